@@ -1,0 +1,195 @@
+/*
+ * mpm.h -- C ABI of the MI355X library for one MPM substep coupled to rigid
+ * bodies (Yu, Du, Zong, Castro, Jiang, Han, "A Convex Formulation of Material
+ * Points and Rigid Bodies with GPU-Accelerated Async-Coupling for Interactive
+ * Simulation", arXiv 2503.05046).
+ *
+ * What one call of mpm_step computes (the asynchronous split of Sec. IV-A,
+ * Eq. (3)-(4)): a host step of N substeps of size h. The rigid pose and twist
+ * are frozen for the host step; each substep (Eq. (5)) is
+ *   1. free motion, Eq. (6): MLS-MPM particle-to-grid transfer with quadratic
+ *      B-splines and the Kirchhoff stress folded into the affine term, then
+ *      v* = p/m + h g on the grid (Sec. V-A);
+ *   2. contact registration: one contact per (particle, rigid primitive) pair
+ *      with the particle strictly inside the primitive (Sec. V-B);
+ *   3. the convex contact problem, Eq. (7)-(8), solved by Algorithm 1: the
+ *      quasi-Newton iteration with the 3x3 block-diagonal Hessian of Sec. IV-C,
+ *      gradient and Hessian of Eq. (9)-(10), exact line search, stopping test
+ *      |grad~| < eps_a + eps_r max(|p~|, |j~|);
+ *   4. grid-to-particle transfer updating v, C (APIC affine matrix), F and x,
+ *      with the Drucker-Prager return map for granular material.
+ * The impulses the substeps apply to each rigid body are summed over the host
+ * step (Eq. (3)) and returned to the caller, who integrates the rigid bodies.
+ *
+ * Conventions: SI units, float32 state, component-major particle arrays
+ * (x[3][P], v[3][P], F[9][P], C[9][P], 3x3 row-major per particle). Grid node
+ * (i, j, k) of an environment sits at origin + (i, j, k) * dx; a particle's
+ * stencil base floor((x - origin)/dx - 1/2) must stay in [0, dims - 3].
+ * All device pointers are HIP device memory of the calling process; every
+ * call is asynchronous on the handle's stream except where stated.
+ *
+ * Errors: no call aborts and no exception crosses the ABI. Each returns an
+ * mpm_status; mpm_last_error() returns a thread-local description of the
+ * last failure on the calling thread.
+ */
+#ifndef MPM_H
+#define MPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MPM_OK = 0,
+    MPM_ENOCONV = 1,  /* warning: a contact solve hit max_iter; state advanced with its last iterate */
+    MPM_EDOMAIN = 2,  /* a particle stencil left the grid; its base was clamped */
+    MPM_ENAN = 3,     /* non-finite particle state produced */
+    MPM_EINVAL = 4,   /* invalid argument; nothing was launched */
+    MPM_ENOMEM = 5,   /* workspace too small, or contact capacity exceeded during a step */
+    MPM_EDEVICE = 6   /* HIP runtime error; see mpm_last_error() */
+} mpm_status;
+
+enum { MPM_FIXED_COROTATED = 0, MPM_DRUCKER_PRAGER = 1 };
+enum { MPM_HALF_SPACE = 0, MPM_BOX = 1 };
+enum { MPM_STATIC = 0, MPM_KINEMATIC = 1 };
+
+/* Step flags (mpm_step_stats.flags) */
+enum {
+    MPM_FLAG_NOCONV = 1,
+    MPM_FLAG_DOMAIN = 2,
+    MPM_FLAG_NAN = 4,
+    MPM_FLAG_CAPACITY = 8
+};
+
+/* One simulation environment: its own grid, material and particle range.
+ * Environments never interact. */
+typedef struct {
+    int32_t dims[3];       /* grid nodes per axis, each >= 4 */
+    float dx;              /* grid spacing [m], > 0 */
+    float origin[3];       /* world position of node (0,0,0) */
+    float gravity[3];      /* [m/s^2] */
+    int32_t material;      /* MPM_FIXED_COROTATED or MPM_DRUCKER_PRAGER */
+    float E;               /* Young's modulus [Pa], > 0 */
+    float nu;              /* Poisson ratio, in (-1, 0.5) */
+    float m_p;             /* particle mass [kg], > 0 */
+    float V0;              /* particle rest volume [m^3], > 0 */
+    float friction_angle;  /* Drucker-Prager friction angle [deg], in [0, 90) */
+    double k;              /* contact stiffness [N/m], > 0 */
+    double d;              /* Hunt-Crossley dissipation [s/m], >= 0 */
+    double eps_s;          /* friction regularisation [m/s], > 0 */
+    int64_t p_begin;       /* first particle of this environment */
+    int64_t p_end;         /* one past its last particle */
+} mpm_env_desc;
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(mpm_desc) */
+    int32_t n_envs;            /* >= 1 */
+    const mpm_env_desc* envs;  /* host array [n_envs], copied; particle ranges must tile [0, n_particles) in order */
+    double h;                  /* substep size [s] = host step / N, > 0 */
+    int32_t N;                 /* substeps per host step, >= 1 */
+    double eps_r, eps_a;       /* Algorithm 1 tolerances, >= 0 */
+    int32_t max_iter;          /* Algorithm 1 iteration cap, >= 1 */
+    int32_t ls_max_rounds;     /* line-search refinement rounds, >= 1 (0 = default 8) */
+    int64_t n_particles;       /* P >= 1 */
+    /* Caller-owned device arrays, borrowed for the life of the handle. The
+     * library reorders particles by grid cell once per host step (a stable
+     * sort, Sec. V-A); pid (may be NULL) is permuted alongside so the caller
+     * can track identity. */
+    float* x;                  /* [3][P] */
+    float* v;                  /* [3][P] */
+    float* F;                  /* [9][P] */
+    float* C;                  /* [9][P] */
+    int32_t* pid;              /* [P] or NULL */
+    int64_t max_contacts;      /* contact capacity per substep (0 = n_particles) */
+    void* workspace;           /* device memory of workspace_bytes, caller-owned, 256-byte aligned */
+    size_t workspace_bytes;
+    void* stream;              /* hipStream_t the handle launches on (NULL = default stream) */
+} mpm_desc;
+
+/* Rigid primitive (body frame) with its initial pose and twist. */
+typedef struct {
+    int32_t shape;             /* MPM_HALF_SPACE or MPM_BOX */
+    double normal[3];          /* half-space: unit outward normal (body frame) */
+    double offset;             /* half-space: sdf(p) = normal . p - offset */
+    double half[3];            /* box: half extents, each > 0 */
+    double mu;                 /* Coulomb friction coefficient, >= 0 */
+    int32_t motion;            /* MPM_STATIC or MPM_KINEMATIC */
+    double R[9];               /* body-to-world rotation, row-major */
+    double t[3];               /* body origin in world */
+    double V[3];               /* linear velocity of the body origin */
+    double w[3];               /* angular velocity (world) */
+} mpm_rigid_desc;
+
+/* Pose and twist of one rigid body, frozen for a host step. */
+typedef struct {
+    double R[9];
+    double t[3];
+    double V[3];
+    double w[3];
+} mpm_rigid_state;
+
+/* Impulse and torque (about the body origin t, world frame) that MPM applied
+ * to one rigid body, summed over the N substeps of a host step; this is minus
+ * the impulse the body applied to the material (Eq. (3)). */
+typedef struct {
+    double impulse[3];
+    double torque[3];
+} mpm_rigid_impulse;
+
+/* Statistics of one host step. Per-substep arrays are caller-owned host
+ * arrays of N entries and may be NULL. */
+typedef struct {
+    int32_t flags;             /* MPM_FLAG_* */
+    int32_t max_iterations;    /* over the substeps */
+    int64_t total_iterations;
+    int32_t max_contacts;
+    int32_t* iterations;       /* [N] Algorithm 1 iterations per substep */
+    int32_t* contacts;         /* [N] registered contact points */
+    int32_t* contact_nodes;    /* [N] grid nodes touched by a contact stencil */
+    double* residual;          /* [N] final |grad~| */
+    double* threshold;         /* [N] eps_a + eps_r max(|p~|, |j~|) at exit */
+} mpm_step_stats;
+
+typedef struct mpm_handle mpm_handle;
+
+/* Bytes of device workspace mpm_create needs for this description (the
+ * caller allocates it). Host only; nothing is launched. */
+mpm_status mpm_workspace_size(const mpm_desc* desc, size_t* bytes);
+
+/* Validate the description, lay out the workspace and upload the environment
+ * tables on desc->stream. The handle keeps the borrowed pointers. */
+mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out);
+
+/* Add a rigid primitive to environment env (Sec. V-B registers contacts
+ * against every primitive of the particle's environment). The descriptor is
+ * copied. *id receives the body's index in the impulse and state arrays
+ * (dense, in order of addition over the whole handle). */
+mpm_status mpm_add_rigid_sdf(mpm_handle* h, int32_t env, const mpm_rigid_desc* r, int32_t* id);
+
+/* Advance one host step of N substeps in place. in: host array of the frozen
+ * pose and twist of every rigid body for this step, or NULL to use the
+ * library's own state (kinematic bodies advanced with their twist after each
+ * step). out: host array, one entry per rigid body (may be NULL). st may be
+ * NULL. Synchronises the handle's stream once, to read impulses and stats.
+ * Returns MPM_OK, a warning (MPM_ENOCONV), or an error (MPM_EDOMAIN, MPM_ENAN,
+ * MPM_ENOMEM when the contact capacity overflowed: the step stops at that
+ * substep with a consistent state). Not thread-safe per handle. */
+mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse* out,
+                    mpm_step_stats* st);
+
+/* Current pose and twist of rigid body id (host). */
+mpm_status mpm_get_rigid_state(const mpm_handle* h, int32_t id, mpm_rigid_state* s);
+
+/* Release the handle (not the borrowed memory). Safe on NULL. */
+void mpm_destroy(mpm_handle* h);
+
+/* Thread-local description of the last error on the calling thread. */
+const char* mpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,496 @@
+// api.hip -- host side of libmpm: argument validation, workspace layout, the
+// rigid-body table and the host-step loop of the asynchronous split
+// (Sec. IV-A, Eq. (3)-(4)): N substeps with the rigid state frozen, impulses
+// summed, then the kinematic bodies advanced on the host.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/mpm.h"
+#include "mpm_internal.h"
+
+using namespace mpm;
+
+namespace {
+
+thread_local std::string g_err;
+
+mpm_status fail(mpm_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(MPM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr int kMaxRigidTotal = 256;
+constexpr int kMaxQnBlocks = 1024;
+constexpr size_t kAlign = 256;
+
+struct Layout {
+    size_t off = 0;
+    char* base = nullptr;
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + kAlign - 1) & ~(kAlign - 1);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (count > 0 ? count : 1);
+        return p;
+    }
+};
+
+struct Sizes {
+    long long P = 0, n_nodes = 0, cap_c = 0, cap_s = 0;
+    int n_tiles = 0, n_envs = 0, N = 1;
+};
+
+mpm_status validate(const mpm_desc* d, Sizes* sz) {
+    if (!d) return fail(MPM_EINVAL, "desc is NULL");
+    if (d->struct_size != sizeof(mpm_desc))
+        return fail(MPM_EINVAL, "desc->struct_size %u != %zu", d->struct_size, sizeof(mpm_desc));
+    if (d->n_envs < 1 || !d->envs) return fail(MPM_EINVAL, "need at least one environment");
+    if (!(d->h > 0.0) || !isfinite(d->h)) return fail(MPM_EINVAL, "h must be > 0");
+    if (d->N < 1) return fail(MPM_EINVAL, "N must be >= 1");
+    if (!(d->eps_r >= 0.0) || !(d->eps_a >= 0.0)) return fail(MPM_EINVAL, "tolerances must be >= 0");
+    if (d->max_iter < 1) return fail(MPM_EINVAL, "max_iter must be >= 1");
+    if (d->ls_max_rounds < 0) return fail(MPM_EINVAL, "ls_max_rounds must be >= 0");
+    if (d->n_particles < 1 || d->n_particles > (1ll << 31) - 1)
+        return fail(MPM_EINVAL, "n_particles out of range");
+    long long expect = 0, nodes = 0;
+    long long tiles = 0;
+    for (int e = 0; e < d->n_envs; ++e) {
+        const mpm_env_desc& E = d->envs[e];
+        if (E.p_begin != expect || E.p_end < E.p_begin)
+            return fail(MPM_EINVAL, "env %d particle range does not continue the previous one", e);
+        expect = E.p_end;
+        for (int a = 0; a < 3; ++a)
+            if (E.dims[a] < 4) return fail(MPM_EINVAL, "env %d dims must be >= 4", e);
+        if (!(E.dx > 0.f)) return fail(MPM_EINVAL, "env %d dx must be > 0", e);
+        if (E.material != MPM_FIXED_COROTATED && E.material != MPM_DRUCKER_PRAGER)
+            return fail(MPM_EINVAL, "env %d unknown material", e);
+        if (!(E.E > 0.f) || !(E.nu > -1.f && E.nu < 0.5f))
+            return fail(MPM_EINVAL, "env %d needs E > 0 and -1 < nu < 0.5", e);
+        if (!(E.m_p > 0.f) || !(E.V0 > 0.f)) return fail(MPM_EINVAL, "env %d needs m_p, V0 > 0", e);
+        if (!(E.friction_angle >= 0.f && E.friction_angle < 90.f))
+            return fail(MPM_EINVAL, "env %d friction angle out of range", e);
+        if (!(E.k > 0.0) || !(E.d >= 0.0) || !(E.eps_s > 0.0))
+            return fail(MPM_EINVAL, "env %d needs k > 0, d >= 0, eps_s > 0", e);
+        nodes += (long long)E.dims[0] * E.dims[1] * E.dims[2];
+        tiles += (long long)((E.dims[0] + 3) / 4) * ((E.dims[1] + 3) / 4) * ((E.dims[2] + 3) / 4);
+    }
+    if (expect != d->n_particles) return fail(MPM_EINVAL, "environments must cover all particles");
+    if (tiles >= (1ll << 26)) return fail(MPM_EINVAL, "too many grid tiles for 32-bit keys");
+    if (nodes >= (1ll << 31) - 1) return fail(MPM_EINVAL, "too many grid nodes");
+    if (d->max_contacts < 0) return fail(MPM_EINVAL, "max_contacts must be >= 0");
+    sz->P = d->n_particles;
+    sz->n_nodes = nodes;
+    sz->n_tiles = (int)tiles;
+    sz->n_envs = d->n_envs;
+    sz->N = d->N;
+    sz->cap_c = d->max_contacts > 0 ? d->max_contacts : d->n_particles;
+    sz->cap_s = std::min<long long>(27 * sz->cap_c, nodes);
+    return MPM_OK;
+}
+
+size_t layout(const Sizes& z, char* base, Work* w) {
+    Layout L;
+    L.base = base;
+    const long long P = z.P;
+    w->key_a = L.take<unsigned>(P);
+    w->key_b = L.take<unsigned>(P);
+    w->idx_a = L.take<unsigned>(P);
+    w->idx_b = L.take<unsigned>(P);
+    w->xs = L.take<float>(3 * P);
+    w->vs = L.take<float>(3 * P);
+    w->Fs = L.take<float>(9 * P);
+    w->Q = L.take<float>(9 * P);
+    w->pids = L.take<int>(P);
+    w->cmask = L.take<unsigned>(P);
+    w->tile_flag = L.take<unsigned>(z.n_tiles);
+    w->active_tiles = L.take<unsigned>(z.n_tiles);
+    w->ptile_id = L.take<unsigned>(z.n_tiles);
+    w->ptile_beg = L.take<unsigned>(z.n_tiles + 1);
+    w->acc = L.take<float4>(z.n_nodes);
+    w->vel = L.take<float4>(z.n_nodes);
+    const long long C = z.cap_c;
+    w->c_pid = L.take<int>(C);
+    w->c_rid = L.take<int>(C);
+    w->c_env = L.take<int>(C);
+    w->c_base = L.take<int>(C);
+    w->c_w = L.take<float>(9 * C);
+    w->c_n = L.take<double>(3 * C);
+    w->c_b = L.take<double>(3 * C);
+    w->c_phi0 = L.take<double>(C);
+    w->c_n0 = L.take<double>(C);
+    w->c_mu = L.take<double>(C);
+    w->c_vc = L.take<double>(6 * C);
+    w->c_uc = L.take<double>(3 * C);
+    w->c_gam = L.take<double>(3 * C);
+    w->c_slot = L.take<int>(27 * C);
+    w->pk_a = L.take<unsigned>(27 * C);
+    w->pk_b = L.take<unsigned>(27 * C);
+    w->pv_a = L.take<unsigned>(27 * C);
+    w->pv_b = L.take<unsigned>(27 * C);
+    const long long S = z.cap_s;
+    w->s_node = L.take<int>(S);
+    w->s_beg = L.take<int>(S + 1);
+    w->s_v = L.take<double>(3 * S);
+    w->s_vstar = L.take<double>(3 * S);
+    w->s_dv = L.take<double>(3 * S);
+    w->s_m = L.take<double>(S);
+    w->blk = L.take<unsigned>(256 * kSortBlocks + 2 * kSortBlocks);
+    w->partial = L.take<double>((size_t)kMaxQnBlocks * (kQnSums + 4 * kLsPoints));
+    w->rigid_acc = L.take<double>(6 * kMaxRigidTotal);
+    w->sstats = L.take<SubstepStats>(z.N);
+    w->cnt = L.take<DevCounters>(1);
+    w->envs = L.take<DevEnv>(z.n_envs);
+    w->rigids = L.take<DevRigid>(kMaxRigidTotal);
+    w->P = z.P;
+    w->n_nodes = z.n_nodes;
+    w->n_tiles = z.n_tiles;
+    w->n_envs = z.n_envs;
+    w->cap_c = z.cap_c;
+    w->cap_s = z.cap_s;
+    return L.off + kAlign;
+}
+
+struct HostRigid {
+    mpm_rigid_desc desc;  // shape, pose and twist (pose/twist updated as the step advances)
+    int env;
+};
+
+void rodrigues_advance(double R[9], const double w[3], double dt) {
+    const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    const double th = wn * dt;
+    if (th == 0.0) return;
+    const double k[3] = {w[0] / wn, w[1] / wn, w[2] / wn};
+    const double K[9] = {0, -k[2], k[1], k[2], 0, -k[0], -k[1], k[0], 0};
+    double K2[9], Rot[9], Rn[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int q = 0; q < 3; ++q) s += K[r * 3 + q] * K[q * 3 + c];
+            K2[r * 3 + c] = s;
+        }
+    for (int i = 0; i < 9; ++i) Rot[i] = sin(th) * K[i] + (1.0 - cos(th)) * K2[i] + (i % 4 == 0 ? 1.0 : 0.0);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0;
+            for (int q = 0; q < 3; ++q) s += Rot[r * 3 + q] * R[q * 3 + c];
+            Rn[r * 3 + c] = s;
+        }
+    memcpy(R, Rn, sizeof(Rn));
+}
+
+}  // namespace
+
+struct mpm_handle {
+    mpm_desc d;
+    std::vector<mpm_env_desc> envs;
+    std::vector<DevEnv> denv;
+    std::vector<HostRigid> rigids;  // in order of addition (user ids)
+    Work w;
+    hipStream_t stream;
+    int key_bits;
+    // pinned host staging
+    DevRigid* h_rigids;
+    double* h_racc;
+    SubstepStats* h_stats;
+    DevCounters* h_cnt;
+};
+
+extern "C" {
+
+const char* mpm_last_error(void) { return g_err.c_str(); }
+
+mpm_status mpm_workspace_size(const mpm_desc* desc, size_t* bytes) {
+    if (!bytes) return fail(MPM_EINVAL, "bytes is NULL");
+    Sizes z;
+    mpm_status st = validate(desc, &z);
+    if (st != MPM_OK) return st;
+    Work w;
+    *bytes = layout(z, nullptr, &w);
+    return MPM_OK;
+}
+
+mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
+    if (!out) return fail(MPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    Sizes z;
+    mpm_status st = validate(desc, &z);
+    if (st != MPM_OK) return st;
+    if (!desc->x || !desc->v || !desc->F || !desc->C) return fail(MPM_EINVAL, "state pointers must be non-NULL");
+    if (!desc->workspace) return fail(MPM_EINVAL, "workspace is NULL");
+    if (((uintptr_t)desc->workspace) % kAlign) return fail(MPM_EINVAL, "workspace must be 256-byte aligned");
+    Work w;
+    const size_t need = layout(z, nullptr, &w);
+    if (desc->workspace_bytes < need)
+        return fail(MPM_ENOMEM, "workspace has %zu bytes, needs %zu", desc->workspace_bytes, need);
+    const int qn_cap = qn_max_blocks();
+    if (qn_cap < 1) return fail(MPM_EDEVICE, "cannot size the cooperative solver launch");
+
+    mpm_handle* h = new mpm_handle();
+    h->d = *desc;
+    h->envs.assign(desc->envs, desc->envs + desc->n_envs);
+    h->d.envs = nullptr;
+    h->stream = (hipStream_t)desc->stream;
+    layout(z, (char*)desc->workspace, &h->w);
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) {
+        delete h;
+        return fail(MPM_EDEVICE, "cannot query the device");
+    }
+    h->w.qn_blocks = std::max(1, std::min({qn_cap, cus, kMaxQnBlocks}));
+    h->w.n_rigid = 0;
+    int tiles = 0;
+    long long nodes = 0;
+    for (int e = 0; e < desc->n_envs; ++e) {
+        const mpm_env_desc& E = h->envs[e];
+        DevEnv D;
+        memset(&D, 0, sizeof(D));
+        for (int a = 0; a < 3; ++a) {
+            D.dims[a] = E.dims[a];
+            D.ntile[a] = (E.dims[a] + 3) / 4;
+            D.origin[a] = E.origin[a];
+            D.gravity[a] = E.gravity[a];
+        }
+        D.tile_base = tiles;
+        D.node_base = nodes;
+        tiles += D.ntile[0] * D.ntile[1] * D.ntile[2];
+        nodes += (long long)E.dims[0] * E.dims[1] * E.dims[2];
+        D.p_begin = E.p_begin;
+        D.p_end = E.p_end;
+        D.dx = E.dx;
+        D.inv_dx = 1.0f / E.dx;
+        D.D = 4.0f / (E.dx * E.dx);
+        D.mat.type = E.material;
+        D.mat.mu = (float)(E.E / (2.0 * (1.0 + E.nu)));
+        D.mat.la = (float)(E.E * E.nu / ((1.0 + E.nu) * (1.0 - 2.0 * E.nu)));
+        const double sphi = sin(E.friction_angle * M_PI / 180.0);
+        D.mat.alpha = (float)(sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi));
+        D.m_p = E.m_p;
+        D.V0 = E.V0;
+        D.k = E.k;
+        D.d = E.d;
+        D.eps_s = E.eps_s;
+        D.rigid_begin = D.rigid_end = 0;
+        h->denv.push_back(D);
+    }
+    int bits = 1;
+    while ((1ll << bits) < (long long)tiles) ++bits;
+    h->key_bits = bits + 6;
+    if (hipHostMalloc((void**)&h->h_rigids, sizeof(DevRigid) * kMaxRigidTotal) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_racc, sizeof(double) * 6 * kMaxRigidTotal) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_stats, sizeof(SubstepStats) * desc->N) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_cnt, sizeof(DevCounters)) != hipSuccess) {
+        mpm_destroy(h);
+        return fail(MPM_EDEVICE, "hipHostMalloc failed");
+    }
+    hipStream_t s = h->stream;
+    const Work& W = h->w;
+    hipError_t e = hipMemsetAsync(W.acc, 0, sizeof(float4) * W.n_nodes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.vel, 0, sizeof(float4) * W.n_nodes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.tile_flag, 0, sizeof(unsigned) * W.n_tiles, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.cnt, 0, sizeof(DevCounters), s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        mpm_destroy(h);
+        return fail(MPM_EDEVICE, "workspace initialisation failed: %s", hipGetErrorString(e));
+    }
+    *out = h;
+    return MPM_OK;
+}
+
+mpm_status mpm_add_rigid_sdf(mpm_handle* h, int32_t env, const mpm_rigid_desc* r, int32_t* id) {
+    if (!h || !r) return fail(MPM_EINVAL, "handle or descriptor is NULL");
+    if (env < 0 || env >= (int)h->envs.size()) return fail(MPM_EINVAL, "env %d out of range", env);
+    if ((int)h->rigids.size() >= kMaxRigidTotal) return fail(MPM_EINVAL, "at most %d rigid bodies", kMaxRigidTotal);
+    int in_env = 0;
+    for (const HostRigid& q : h->rigids) in_env += q.env == env;
+    if (in_env >= kMaxRigidPerEnv) return fail(MPM_EINVAL, "at most %d rigid bodies per environment", kMaxRigidPerEnv);
+    if (r->shape != MPM_HALF_SPACE && r->shape != MPM_BOX) return fail(MPM_EINVAL, "unknown shape");
+    if (r->motion != MPM_STATIC && r->motion != MPM_KINEMATIC) return fail(MPM_EINVAL, "unknown motion");
+    if (!(r->mu >= 0.0) || !isfinite(r->mu)) return fail(MPM_EINVAL, "mu must be >= 0");
+    if (r->shape == MPM_BOX && !(r->half[0] > 0 && r->half[1] > 0 && r->half[2] > 0))
+        return fail(MPM_EINVAL, "degenerate box");
+    if (r->shape == MPM_HALF_SPACE) {
+        const double nn = r->normal[0] * r->normal[0] + r->normal[1] * r->normal[1] + r->normal[2] * r->normal[2];
+        if (!(fabs(nn - 1.0) < 1e-9)) return fail(MPM_EINVAL, "half-space normal must be unit");
+    }
+    double RtR[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0;
+            for (int q = 0; q < 3; ++q) s += r->R[q * 3 + a] * r->R[q * 3 + b];
+            RtR[a * 3 + b] = s;
+        }
+    for (int i = 0; i < 9; ++i)
+        if (fabs(RtR[i] - (i % 4 == 0 ? 1.0 : 0.0)) > 1e-9) return fail(MPM_EINVAL, "R must be a rotation");
+    HostRigid q;
+    q.desc = *r;
+    q.env = env;
+    h->rigids.push_back(q);
+    if (id) *id = (int32_t)h->rigids.size() - 1;
+    return MPM_OK;
+}
+
+mpm_status mpm_get_rigid_state(const mpm_handle* h, int32_t id, mpm_rigid_state* s) {
+    if (!h || !s) return fail(MPM_EINVAL, "handle or output is NULL");
+    if (id < 0 || id >= (int)h->rigids.size()) return fail(MPM_EINVAL, "rigid id %d out of range", id);
+    const mpm_rigid_desc& d = h->rigids[id].desc;
+    memcpy(s->R, d.R, sizeof(s->R));
+    memcpy(s->t, d.t, sizeof(s->t));
+    memcpy(s->V, d.V, sizeof(s->V));
+    memcpy(s->w, d.w, sizeof(s->w));
+    return MPM_OK;
+}
+
+mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse* out, mpm_step_stats* st) {
+    if (!h) return fail(MPM_EINVAL, "handle is NULL");
+    const int nr = (int)h->rigids.size();
+    // frozen rigid state for this host step
+    if (in) {
+        for (int i = 0; i < nr; ++i) {
+            mpm_rigid_desc& d = h->rigids[i].desc;
+            memcpy(d.R, in[i].R, sizeof(d.R));
+            memcpy(d.t, in[i].t, sizeof(d.t));
+            memcpy(d.V, in[i].V, sizeof(d.V));
+            memcpy(d.w, in[i].w, sizeof(d.w));
+        }
+    }
+    // device order: grouped by environment (stable), so each env owns a range
+    std::vector<int> order(nr);
+    for (int i = 0; i < nr; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->rigids[a].env < h->rigids[b].env; });
+    for (DevEnv& D : h->denv) D.rigid_begin = D.rigid_end = 0;
+    for (int k = 0; k < nr; ++k) {
+        const HostRigid& q = h->rigids[order[k]];
+        DevRigid& R = h->h_rigids[k];
+        R.shape = q.desc.shape;
+        R.env = q.env;
+        memcpy(R.normal, q.desc.normal, sizeof(R.normal));
+        R.offset = q.desc.offset;
+        memcpy(R.half, q.desc.half, sizeof(R.half));
+        R.mu = q.desc.mu;
+        memcpy(R.R, q.desc.R, sizeof(R.R));
+        memcpy(R.t, q.desc.t, sizeof(R.t));
+        if (q.desc.motion == MPM_STATIC) {
+            memset(R.V, 0, sizeof(R.V));
+            memset(R.w, 0, sizeof(R.w));
+        } else {
+            memcpy(R.V, q.desc.V, sizeof(R.V));
+            memcpy(R.w, q.desc.w, sizeof(R.w));
+        }
+        DevEnv& D = h->denv[q.env];
+        if (D.rigid_end == D.rigid_begin) D.rigid_begin = D.rigid_end = k;
+        D.rigid_end = k + 1;
+    }
+    Work& W = h->w;
+    W.n_rigid = nr;
+    hipStream_t s = h->stream;
+    const mpm_desc& d = h->d;
+    const int N = d.N;
+    const int ls_rounds = d.ls_max_rounds > 0 ? d.ls_max_rounds : 8;
+    HIP_TRY(hipMemcpyAsync(W.rigids, h->h_rigids, sizeof(DevRigid) * std::max(nr, 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_clear_step(W, N, s));
+    // once per host step: cell keys, stable sort, gather, tile list (Sec. V-A)
+    HIP_TRY(launch_keys(W, d.x, s));
+    unsigned *keys_sorted, *idx_sorted;
+    HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
+    HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
+    HIP_TRY(launch_tile_list(W, keys_sorted, s));
+    for (int k = 0; k < N; ++k) {
+        const bool first = k == 0, last = k == N - 1;
+        const float* x_in = first ? W.xs : d.x;
+        const float* v_in = first ? W.vs : d.v;
+        const float* F_in = first ? W.Fs : d.F;
+        HIP_TRY(launch_clear_substep(W, s));
+        HIP_TRY(launch_p2g(W, x_in, v_in, s));
+        HIP_TRY(launch_grid_update(W, d.h, s));
+        HIP_TRY(launch_registration(W, x_in, v_in, d.h, k, s));
+        HIP_TRY(launch_contact_setup(W, s));
+        HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_rounds, s));
+        HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
+                           (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h, s));
+    }
+    HIP_TRY(hipMemcpyAsync(h->h_cnt, W.cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const unsigned flags = h->h_cnt->flags;
+    if (h->h_cnt->abort_step && h->h_cnt->abort_substep > 0) {
+        // the step stopped early: the caller's C lags the state; rebuild it from Q
+        HIP_TRY(launch_recover_C(W, d.F, d.C, d.h, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    // outputs in user order
+    if (out) {
+        for (int k = 0; k < nr; ++k) {
+            mpm_rigid_impulse& o = out[order[k]];
+            for (int a = 0; a < 3; ++a) {
+                o.impulse[a] = h->h_racc[6 * k + a];
+                o.torque[a] = h->h_racc[6 * k + 3 + a];
+            }
+        }
+    }
+    if (st) {
+        st->flags = (int32_t)(flags & 0xF);
+        st->max_iterations = 0;
+        st->total_iterations = 0;
+        st->max_contacts = 0;
+        for (int k = 0; k < N; ++k) {
+            const SubstepStats& q = h->h_stats[k];
+            st->max_iterations = std::max(st->max_iterations, q.iterations);
+            st->total_iterations += q.iterations;
+            st->max_contacts = std::max(st->max_contacts, q.n_contacts);
+            if (st->iterations) st->iterations[k] = q.iterations;
+            if (st->contacts) st->contacts[k] = q.n_contacts;
+            if (st->contact_nodes) st->contact_nodes[k] = q.n_slots;
+            if (st->residual) st->residual[k] = q.residual;
+            if (st->threshold) st->threshold[k] = q.threshold;
+        }
+    }
+    // host side of the split: advance kinematic bodies with their twist
+    for (HostRigid& q : h->rigids) {
+        if (q.desc.motion != MPM_KINEMATIC) continue;
+        const double dt = N * d.h;
+        for (int a = 0; a < 3; ++a) q.desc.t[a] += dt * q.desc.V[a];
+        rodrigues_advance(q.desc.R, q.desc.w, dt);
+    }
+    if (flags & 16u) return fail(MPM_EDEVICE, "contact solver barrier timed out");
+    if (flags & MPM_FLAG_CAPACITY)
+        return fail(MPM_ENOMEM, "contact capacity %lld exceeded (%u contacts)", (long long)W.cap_c, h->h_cnt->n_contacts);
+    if (flags & MPM_FLAG_NAN) return fail(MPM_ENAN, "non-finite particle state");
+    if (flags & MPM_FLAG_DOMAIN) return fail(MPM_EDOMAIN, "a particle stencil left the grid");
+    if (flags & MPM_FLAG_NOCONV) return fail(MPM_ENOCONV, "contact solve hit max_iter");
+    return MPM_OK;
+}
+
+void mpm_destroy(mpm_handle* h) {
+    if (!h) return;
+    if (h->h_rigids) (void)hipHostFree(h->h_rigids);
+    if (h->h_racc) (void)hipHostFree(h->h_racc);
+    if (h->h_stats) (void)hipHostFree(h->h_stats);
+    if (h->h_cnt) (void)hipHostFree(h->h_cnt);
+    delete h;
+}
+
+}  // extern "C"

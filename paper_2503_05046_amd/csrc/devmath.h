@@ -1,0 +1,245 @@
+// devmath.h -- float32 device math of the MPM substep for gfx950: quadratic
+// B-spline weights, a branch-light 3x3 SVD, the fixed-corotated and Hencky
+// Kirchhoff stresses and the Drucker-Prager return map.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace mpm {
+
+struct M3 {
+    float a[9];  // row-major
+};
+
+__device__ __forceinline__ float sq(float x) { return x * x; }
+
+// Quadratic B-spline weights along one axis for fractional offset f in
+// [0.5, 1.5): nodes base, base+1, base+2 (MLS-MPM transfer, Sec. V-A).
+__device__ __forceinline__ void bspline_w(float f, float w[3]) {
+    w[0] = 0.5f * sq(1.5f - f);
+    w[1] = 0.75f - sq(f - 1.0f);
+    w[2] = 0.5f * sq(f - 0.5f);
+}
+
+// Integer stencil base and fraction of one coordinate. The base is computed
+// with explicitly rounded binary32 operations (no contraction) so that it is
+// bit-identical to the cell index of the sort key.
+__device__ __forceinline__ int cell_base(float x, float origin, float inv_dx, float* frac) {
+    float d = __fsub_rn(x, origin);
+    float t = __fmul_rn(d, inv_dx);
+    float u = __fsub_rn(t, 0.5f);
+    float b = floorf(u);
+    *frac = t - b;
+    return (int)b;
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 SVD, F = U diag(s) V^T with det U = det V = +1, s sorted by decreasing
+// magnitude, s[2] carrying the sign of det F. Method of McAdams, Selle,
+// Tamstorf, Teran, Sifakis (2011): cyclic Jacobi eigen-analysis of F^T F for
+// V, ordering of the columns of F V by norm, then a Givens QR of F V for U and
+// s. Exact Jacobi and Givens rotations (sqrt-based) with a fixed sweep count.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void jacobi_rot(float S[9], float V[9], int p, int q) {
+    float apq = S[p * 3 + q];
+    if (fabsf(apq) < 1e-30f) return;
+    float app = S[p * 3 + p], aqq = S[q * 3 + q];
+    float theta = (aqq - app) / (2.0f * apq);
+    float t = copysignf(1.0f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
+    float c = rsqrtf(t * t + 1.0f);
+    float s = t * c;
+    // S <- J^T S J with J the rotation in the (p, q) plane
+    for (int k = 0; k < 3; ++k) {
+        float skp = S[k * 3 + p], skq = S[k * 3 + q];
+        S[k * 3 + p] = c * skp - s * skq;
+        S[k * 3 + q] = s * skp + c * skq;
+    }
+    for (int k = 0; k < 3; ++k) {
+        float spk = S[p * 3 + k], sqk = S[q * 3 + k];
+        S[p * 3 + k] = c * spk - s * sqk;
+        S[q * 3 + k] = s * spk + c * sqk;
+    }
+    for (int k = 0; k < 3; ++k) {
+        float vkp = V[k * 3 + p], vkq = V[k * 3 + q];
+        V[k * 3 + p] = c * vkp - s * vkq;
+        V[k * 3 + q] = s * vkp + c * vkq;
+    }
+}
+
+__device__ __forceinline__ void swap_cols(float B[9], float V[9], int i, int j, bool negate) {
+    for (int k = 0; k < 3; ++k) {
+        float b = B[k * 3 + i], v = V[k * 3 + i];
+        B[k * 3 + i] = B[k * 3 + j];
+        V[k * 3 + i] = V[k * 3 + j];
+        B[k * 3 + j] = negate ? -b : b;
+        V[k * 3 + j] = negate ? -v : v;
+    }
+}
+
+// Givens rotation acting on rows (i, j) of B chosen to zero B[j][col];
+// accumulates Q^T = G ... so that U = Q.
+__device__ __forceinline__ void givens_qr(float B[9], float U[9], int i, int j, int col) {
+    float a = B[i * 3 + col], b = B[j * 3 + col];
+    float r2 = a * a + b * b;
+    if (r2 < 1e-38f) return;
+    float inv = rsqrtf(r2);
+    float c = a * inv, s = b * inv;
+    for (int k = 0; k < 3; ++k) {
+        float bi = B[i * 3 + k], bj = B[j * 3 + k];
+        B[i * 3 + k] = c * bi + s * bj;
+        B[j * 3 + k] = -s * bi + c * bj;
+    }
+    // U <- U G^T (columns i, j)
+    for (int k = 0; k < 3; ++k) {
+        float ui = U[k * 3 + i], uj = U[k * 3 + j];
+        U[k * 3 + i] = c * ui + s * uj;
+        U[k * 3 + j] = -s * ui + c * uj;
+    }
+}
+
+__device__ inline void svd3(const float F[9], float U[9], float s[3], float V[9]) {
+    // symmetric S = F^T F
+    float S[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            S[r * 3 + c] = F[0 * 3 + r] * F[0 * 3 + c] + F[1 * 3 + r] * F[1 * 3 + c] +
+                           F[2 * 3 + r] * F[2 * 3 + c];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0f : 0.0f;
+#pragma unroll 1
+    for (int sweep = 0; sweep < 6; ++sweep) {
+        jacobi_rot(S, V, 0, 1);
+        jacobi_rot(S, V, 0, 2);
+        jacobi_rot(S, V, 1, 2);
+    }
+    // B = F V; order columns by decreasing norm, keeping det V = +1
+    float B[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            B[r * 3 + c] = F[r * 3 + 0] * V[0 * 3 + c] + F[r * 3 + 1] * V[1 * 3 + c] +
+                           F[r * 3 + 2] * V[2 * 3 + c];
+    float n0 = sq(B[0]) + sq(B[3]) + sq(B[6]);
+    float n1 = sq(B[1]) + sq(B[4]) + sq(B[7]);
+    float n2 = sq(B[2]) + sq(B[5]) + sq(B[8]);
+    if (n0 < n1) { swap_cols(B, V, 0, 1, true); float t = n0; n0 = n1; n1 = t; }
+    if (n0 < n2) { swap_cols(B, V, 0, 2, true); float t = n0; n0 = n2; n2 = t; }
+    if (n1 < n2) { swap_cols(B, V, 1, 2, true); float t = n1; n1 = n2; n2 = t; }
+    // the Jacobi rotations keep det V = +1 and each swap negates one column
+    // QR of B by Givens rotations: zero B[1][0], B[2][0], B[2][1]
+#pragma unroll
+    for (int k = 0; k < 9; ++k) U[k] = (k % 4 == 0) ? 1.0f : 0.0f;
+    givens_qr(B, U, 0, 1, 0);
+    givens_qr(B, U, 0, 2, 0);
+    givens_qr(B, U, 1, 2, 1);
+    s[0] = B[0];
+    s[1] = B[4];
+    s[2] = B[8];
+    // the QR leaves s[0], s[1] >= 0 for full-rank leading columns; flip a
+    // negative s[1] into s[2] to keep det U = +1 with the sign on the last
+    if (s[1] < 0.0f) {
+        s[1] = -s[1];
+        s[2] = -s[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U[k * 3 + 1] = -U[k * 3 + 1];
+            U[k * 3 + 2] = -U[k * 3 + 2];
+        }
+    }
+    if (s[0] < 0.0f) {
+        s[0] = -s[0];
+        s[2] = -s[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            U[k * 3 + 0] = -U[k * 3 + 0];
+            U[k * 3 + 2] = -U[k * 3 + 2];
+        }
+    }
+}
+
+struct Material {
+    int type;      // 0 fixed-corotated, 1 Hencky + Drucker-Prager
+    float mu, la;  // Lame parameters
+    float alpha;   // Drucker-Prager cone coefficient sqrt(2/3) 2 sin(phi) / (3 - sin(phi))
+};
+
+// Kirchhoff stress tau = P F^T from an SVD of F.
+__device__ __forceinline__ void kirchhoff_from_svd(const Material& m, const float F[9],
+                                                   const float U[9], const float s[3],
+                                                   const float V[9], float tau[9]) {
+    if (m.type == 0) {
+        // fixed-corotated: tau = 2 mu (F - R) F^T + la (J - 1) J I, R = U V^T
+        float R[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                R[r * 3 + c] = U[r * 3 + 0] * V[c * 3 + 0] + U[r * 3 + 1] * V[c * 3 + 1] +
+                               U[r * 3 + 2] * V[c * 3 + 2];
+        float J = s[0] * s[1] * s[2];
+        float D[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) D[k] = F[k] - R[k];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                tau[r * 3 + c] = 2.0f * m.mu *
+                                 (D[r * 3 + 0] * F[c * 3 + 0] + D[r * 3 + 1] * F[c * 3 + 1] +
+                                  D[r * 3 + 2] * F[c * 3 + 2]);
+        float vol = m.la * (J - 1.0f) * J;
+        tau[0] += vol;
+        tau[4] += vol;
+        tau[8] += vol;
+    } else {
+        // Hencky: tau = U (2 mu eps + la tr(eps) I) U^T, eps = ln s
+        float e0 = logf(fmaxf(s[0], 1e-6f)), e1 = logf(fmaxf(s[1], 1e-6f)),
+              e2 = logf(fmaxf(s[2], 1e-6f));
+        float tr = e0 + e1 + e2;
+        float d0 = 2.0f * m.mu * e0 + m.la * tr, d1 = 2.0f * m.mu * e1 + m.la * tr,
+              d2 = 2.0f * m.mu * e2 + m.la * tr;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = r; c < 3; ++c) {
+                float v = U[r * 3 + 0] * d0 * U[c * 3 + 0] + U[r * 3 + 1] * d1 * U[c * 3 + 1] +
+                          U[r * 3 + 2] * d2 * U[c * 3 + 2];
+                tau[r * 3 + c] = v;
+                tau[c * 3 + r] = v;
+            }
+    }
+}
+
+// Drucker-Prager return map in Hencky strain (zero cohesion, no hardening),
+// applied to the singular values; F is rebuilt as U exp(eps) V^T.
+__device__ __forceinline__ void dp_return_map(const Material& m, float U[9], float s[3],
+                                              const float V[9], float F[9]) {
+    float e[3] = {logf(fmaxf(s[0], 1e-6f)), logf(fmaxf(s[1], 1e-6f)), logf(fmaxf(s[2], 1e-6f))};
+    float tr = e[0] + e[1] + e[2];
+    if (tr >= 0.0f) {
+        e[0] = e[1] = e[2] = 0.0f;  // tension: cone tip
+    } else {
+        float dv[3] = {e[0] - tr / 3.0f, e[1] - tr / 3.0f, e[2] - tr / 3.0f};
+        float nd = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+        float dg = nd + (3.0f * m.la + 2.0f * m.mu) / (2.0f * m.mu) * tr * m.alpha;
+        if (dg > 0.0f) {
+            float r = dg / nd;
+            e[0] -= r * dv[0];
+            e[1] -= r * dv[1];
+            e[2] -= r * dv[2];
+        }
+    }
+    s[0] = expf(e[0]);
+    s[1] = expf(e[1]);
+    s[2] = expf(e[2]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            F[r * 3 + c] = U[r * 3 + 0] * s[0] * V[c * 3 + 0] + U[r * 3 + 1] * s[1] * V[c * 3 + 1] +
+                           U[r * 3 + 2] * s[2] * V[c * 3 + 2];
+}
+
+}  // namespace mpm

@@ -1,0 +1,146 @@
+// mpm_internal.h -- device tables, workspace layout and kernel entry points
+// shared by the host orchestrator and the HIP kernels of libmpm.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "devmath.h"
+
+namespace mpm {
+
+constexpr int kTile = 4;              // cells per tile edge (4x4x4 = 64 cells)
+constexpr int kBlockNodes = 8;        // LDS node block edge: tile + 2 stencil + 1 drift each side
+constexpr int kMaxRigidPerEnv = 32;   // contact mask width
+constexpr int kLsPoints = 32;         // line-search evaluation points per round
+constexpr int kQnSums = 8;            // per-iteration scalar sums of the node pass
+constexpr int kSortBlocks = 512;      // blocks of the chunked scan / radix passes
+constexpr int kSortThreads = 256;
+
+struct DevEnv {
+    int dims[3];
+    int ntile[3];
+    int tile_base;          // first global tile id of this environment
+    int rigid_begin, rigid_end;
+    long long node_base;    // first global node of this environment
+    long long p_begin, p_end;
+    float dx, inv_dx, D;    // D = 4 / dx^2
+    float origin[3];
+    float gravity[3];
+    Material mat;
+    float m_p, V0;
+    double k, d, eps_s;
+};
+
+struct DevRigid {
+    int shape;
+    int env;
+    double normal[3];
+    double offset;
+    double half[3];
+    double mu;
+    double R[9];
+    double t[3];
+    double V[3];
+    double w[3];
+};
+
+// Per-substep device statistics.
+struct SubstepStats {
+    int n_contacts;
+    int n_slots;
+    int iterations;
+    int converged;
+    double residual;
+    double threshold;
+};
+
+// Device scalars that live in the workspace.
+struct DevCounters {
+    unsigned n_ptiles;       // non-empty particle tiles after the sort
+    unsigned n_active;       // active node tiles this substep
+    unsigned n_contacts;     // registered contacts this substep (may exceed capacity)
+    unsigned n_pairs;        // contact-node pairs
+    unsigned n_slots;        // distinct contact nodes
+    unsigned flags;          // MPM_FLAG_* bits
+    unsigned abort_step;     // set when the step must stop (capacity overflow)
+    unsigned bar_count;      // grid barrier arrival counter
+    unsigned bar_gen;        // grid barrier generation
+    unsigned abort_substep;  // substep at which the step stopped
+    unsigned pad[6];
+    double pnorm_all;        // sum m |v*|^2 over active nodes (FP64)
+};
+
+// Pointers into the caller's workspace.
+struct Work {
+    // particle sort
+    unsigned *key_a, *key_b, *idx_a, *idx_b;
+    float *xs, *vs, *Fs;     // gathered state for the first substep of a host step
+    float* Q;                // fused affine/stress matrix [9][P]
+    int* pids;               // gathered particle ids
+    unsigned* cmask;         // contact bitmask per particle
+    // tiles
+    unsigned* tile_flag;     // [T_all] node-tile activation flags
+    unsigned* active_tiles;  // [T_all]
+    unsigned* ptile_id;      // [T_all] particle tiles (global tile id)
+    unsigned* ptile_beg;     // [T_all + 1]
+    // grid (dense, all envs)
+    float4* acc;             // (m, px, py, pz)
+    float4* vel;             // (vx, vy, vz, m)
+    // contacts (capacity cap_c)
+    int *c_pid, *c_rid, *c_env, *c_base;
+    float* c_w;              // [9][cap] per-axis weights
+    double *c_n, *c_b;       // [3][cap]
+    double *c_phi0, *c_n0, *c_mu;
+    double* c_vc;            // [2][3][cap] contact velocity, double-buffered by iteration parity
+    double* c_uc;            // [3][cap]
+    double* c_gam;           // [3][cap] impulse on MPM at exit (contact frame)
+    int* c_slot;             // [27][cap]
+    // contact-node pairs (capacity 27 cap_c)
+    unsigned *pk_a, *pk_b, *pv_a, *pv_b;
+    // contact-node slots (capacity cap_s)
+    int *s_node, *s_beg;     // s_beg has cap_s + 1 entries
+    double *s_v, *s_vstar, *s_dv, *s_m;  // [3][cap_s] (s_m: [cap_s])
+    // scratch
+    unsigned* blk;           // [kSortBlocks * 256 + 2 * kSortBlocks] histograms / block sums
+    double* partial;         // [qn_blocks][kQnSums + 2 * kLsPoints + 8]
+    double* rigid_acc;       // [n_rigid][6] FP64 impulse accumulators
+    SubstepStats* sstats;    // [N]
+    DevCounters* cnt;
+    DevEnv* envs;
+    DevRigid* rigids;
+    // sizes
+    long long P;
+    long long n_nodes;
+    int n_tiles;
+    int n_envs;
+    int n_rigid;
+    long long cap_c, cap_s;
+    int qn_blocks;
+};
+
+// ---- kernel launchers (return hipError_t of the launch) -------------------
+hipError_t launch_keys(const Work& w, const float* x, hipStream_t s);
+hipError_t radix_sort(const Work& w, unsigned* keys, unsigned* vals, unsigned* keys_tmp,
+                      unsigned* vals_tmp, const unsigned* count_dev, long long count_host,
+                      int bits, hipStream_t s, unsigned** keys_out, unsigned** vals_out);
+hipError_t launch_permute(const Work& w, const unsigned* idx, const float* x, const float* v,
+                          const float* F, const float* C, const int* pid, double h,
+                          hipStream_t s);
+hipError_t launch_recover_C(const Work& w, const float* F, float* C, double h, hipStream_t s);
+hipError_t launch_scan_blocks(unsigned* data, int n_items, unsigned* total, hipStream_t s);
+hipError_t launch_tile_list(const Work& w, const unsigned* sorted_keys, hipStream_t s);
+hipError_t launch_p2g(const Work& w, const float* x, const float* v, hipStream_t s);
+hipError_t launch_grid_update(const Work& w, double h, hipStream_t s);
+hipError_t launch_registration(const Work& w, const float* x, const float* v, double h,
+                               int substep, hipStream_t s);
+hipError_t launch_contact_setup(const Work& w, hipStream_t s);
+hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
+                     double eps_a, int max_iter, int ls_rounds, hipStream_t s);
+int qn_max_blocks();
+hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
+                      float* v_out, float* F_out, float* C_out, const int* pid_in,
+                      int* pid_out, double h, hipStream_t s);
+hipError_t launch_clear_step(const Work& w, int N, hipStream_t s);
+hipError_t launch_clear_substep(const Work& w, hipStream_t s);
+
+}  // namespace mpm

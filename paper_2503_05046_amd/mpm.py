@@ -1,0 +1,281 @@
+"""Python binding of libmpm (the C ABI of include/mpm.h), argument marshalling only.
+
+Every step of the substep runs in the HIP library; PyTorch only provides device
+memory (the caller-owned particle arrays and the workspace) and the stream.
+There is no CPU fallback: importing this module on a machine without the built
+library raises, and creating a simulation without a GPU fails in HIP.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import inputs as _inputs  # noqa: F401  (scene types are the natural input)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmpm.so")
+
+MPM_OK, MPM_ENOCONV, MPM_EDOMAIN, MPM_ENAN, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE = range(7)
+STATUS_NAMES = {0: "MPM_OK", 1: "MPM_ENOCONV", 2: "MPM_EDOMAIN", 3: "MPM_ENAN", 4: "MPM_EINVAL",
+                5: "MPM_ENOMEM", 6: "MPM_EDEVICE"}
+FLAG_NOCONV, FLAG_DOMAIN, FLAG_NAN, FLAG_CAPACITY = 1, 2, 4, 8
+
+EXPORTED = ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
+            "mpm_get_rigid_state", "mpm_destroy", "mpm_last_error")
+
+
+class EnvDesc(ct.Structure):
+    _fields_ = [("dims", ct.c_int32 * 3), ("dx", ct.c_float), ("origin", ct.c_float * 3),
+                ("gravity", ct.c_float * 3), ("material", ct.c_int32), ("E", ct.c_float),
+                ("nu", ct.c_float), ("m_p", ct.c_float), ("V0", ct.c_float),
+                ("friction_angle", ct.c_float), ("k", ct.c_double), ("d", ct.c_double),
+                ("eps_s", ct.c_double), ("p_begin", ct.c_int64), ("p_end", ct.c_int64)]
+
+
+class Desc(ct.Structure):
+    _fields_ = [("struct_size", ct.c_uint32), ("n_envs", ct.c_int32),
+                ("envs", ct.POINTER(EnvDesc)), ("h", ct.c_double), ("N", ct.c_int32),
+                ("eps_r", ct.c_double), ("eps_a", ct.c_double), ("max_iter", ct.c_int32),
+                ("ls_max_rounds", ct.c_int32), ("n_particles", ct.c_int64),
+                ("x", ct.c_void_p), ("v", ct.c_void_p), ("F", ct.c_void_p), ("C", ct.c_void_p),
+                ("pid", ct.c_void_p), ("max_contacts", ct.c_int64), ("workspace", ct.c_void_p),
+                ("workspace_bytes", ct.c_size_t), ("stream", ct.c_void_p)]
+
+
+class RigidDesc(ct.Structure):
+    _fields_ = [("shape", ct.c_int32), ("normal", ct.c_double * 3), ("offset", ct.c_double),
+                ("half", ct.c_double * 3), ("mu", ct.c_double), ("motion", ct.c_int32),
+                ("R", ct.c_double * 9), ("t", ct.c_double * 3), ("V", ct.c_double * 3),
+                ("w", ct.c_double * 3)]
+
+
+class RigidState(ct.Structure):
+    _fields_ = [("R", ct.c_double * 9), ("t", ct.c_double * 3), ("V", ct.c_double * 3),
+                ("w", ct.c_double * 3)]
+
+
+class RigidImpulse(ct.Structure):
+    _fields_ = [("impulse", ct.c_double * 3), ("torque", ct.c_double * 3)]
+
+
+class StepStats(ct.Structure):
+    _fields_ = [("flags", ct.c_int32), ("max_iterations", ct.c_int32),
+                ("total_iterations", ct.c_int64), ("max_contacts", ct.c_int32),
+                ("iterations", ct.POINTER(ct.c_int32)), ("contacts", ct.POINTER(ct.c_int32)),
+                ("contact_nodes", ct.POINTER(ct.c_int32)), ("residual", ct.POINTER(ct.c_double)),
+                ("threshold", ct.POINTER(ct.c_double))]
+
+
+_lib = None
+
+
+def load():
+    """Load libmpm.so (after torch, so both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        import torch  # noqa: F401
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run paper_2503_05046_amd.build.build()")
+        L = ct.CDLL(LIB_PATH)
+        L.mpm_workspace_size.argtypes = [ct.POINTER(Desc), ct.POINTER(ct.c_size_t)]
+        L.mpm_create.argtypes = [ct.POINTER(Desc), ct.POINTER(ct.c_void_p)]
+        L.mpm_add_rigid_sdf.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidDesc),
+                                        ct.POINTER(ct.c_int32)]
+        L.mpm_step.argtypes = [ct.c_void_p, ct.POINTER(RigidState), ct.POINTER(RigidImpulse),
+                               ct.POINTER(StepStats)]
+        L.mpm_get_rigid_state.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidState)]
+        L.mpm_destroy.argtypes = [ct.c_void_p]
+        L.mpm_destroy.restype = None
+        L.mpm_last_error.restype = ct.c_char_p
+        for f in ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
+                  "mpm_get_rigid_state"):
+            getattr(L, f).restype = ct.c_int
+        _lib = L
+    return _lib
+
+
+def mpm_last_error() -> str:
+    return load().mpm_last_error().decode()
+
+
+class MPMError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {mpm_last_error()}")
+
+
+def _check(status: int, where: str, allow=(MPM_OK,)) -> int:
+    if status not in allow:
+        raise MPMError(status, where)
+    return status
+
+
+def env_descs(scene) -> ct.Array:
+    arr = (EnvDesc * len(scene.envs))()
+    for i, e in enumerate(scene.envs):
+        a = arr[i]
+        a.dims[:] = [int(d) for d in e.dims]
+        a.dx = e.dx
+        a.origin[:] = list(e.origin)
+        a.gravity[:] = list(e.gravity)
+        a.material = e.material
+        a.E, a.nu = e.E, e.nu
+        a.m_p, a.V0 = e.rho * e.V0, e.V0
+        a.friction_angle = e.friction_angle
+        a.k, a.d, a.eps_s = e.k, e.d, e.eps_s
+        a.p_begin, a.p_end = e.p_begin, e.p_end
+    return arr
+
+
+def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_rounds: int = 0) -> Desc:
+    d = Desc()
+    d.struct_size = ct.sizeof(Desc)
+    d.n_envs = len(scene.envs)
+    d.envs = ct.cast(envs, ct.POINTER(EnvDesc))
+    d.h, d.N = scene.h, scene.N
+    d.eps_r, d.eps_a = scene.eps_r, scene.eps_a
+    d.max_iter = scene.max_iter
+    d.ls_max_rounds = ls_max_rounds
+    d.n_particles = scene.P
+    d.max_contacts = max_contacts
+    return d
+
+
+def mpm_workspace_size(desc: Desc) -> int:
+    n = ct.c_size_t(0)
+    _check(load().mpm_workspace_size(ct.byref(desc), ct.byref(n)), "mpm_workspace_size")
+    return n.value
+
+
+def mpm_create(desc: Desc) -> ct.c_void_p:
+    h = ct.c_void_p(0)
+    _check(load().mpm_create(ct.byref(desc), ct.byref(h)), "mpm_create")
+    return h
+
+
+def rigid_desc(r) -> RigidDesc:
+    q = RigidDesc()
+    q.shape = r.shape
+    q.normal[:] = list(r.normal)
+    q.offset = r.offset
+    q.half[:] = list(r.half)
+    q.mu = r.mu
+    q.motion = r.motion
+    q.R[:] = list(r.R)
+    q.t[:] = list(r.t)
+    q.V[:] = list(r.V)
+    q.w[:] = list(r.w)
+    return q
+
+
+def mpm_add_rigid_sdf(h, env: int, r: RigidDesc) -> int:
+    rid = ct.c_int32(-1)
+    _check(load().mpm_add_rigid_sdf(h, env, ct.byref(r), ct.byref(rid)), "mpm_add_rigid_sdf")
+    return rid.value
+
+
+def mpm_step(h, n_rigid: int, N: int, states: Optional[Sequence[RigidState]] = None):
+    """One host step. Returns (status, impulses [n_rigid, 6], stats dict)."""
+    imp = (RigidImpulse * max(1, n_rigid))()
+    its = (ct.c_int32 * N)()
+    ncs = (ct.c_int32 * N)()
+    nns = (ct.c_int32 * N)()
+    res = (ct.c_double * N)()
+    thr = (ct.c_double * N)()
+    st = StepStats()
+    st.iterations, st.contacts, st.contact_nodes = its, ncs, nns
+    st.residual, st.threshold = res, thr
+    sin = None
+    if states is not None:
+        sin = (RigidState * max(1, n_rigid))(*states)
+    status = load().mpm_step(h, sin, imp, ct.byref(st))
+    _check(status, "mpm_step", allow=(MPM_OK, MPM_ENOCONV))
+    out = np.array([[*imp[i].impulse, *imp[i].torque] for i in range(n_rigid)]).reshape(n_rigid, 6)
+    stats = dict(flags=st.flags, max_iterations=st.max_iterations,
+                 total_iterations=st.total_iterations, max_contacts=st.max_contacts,
+                 iterations=list(its), contacts=list(ncs), contact_nodes=list(nns),
+                 residual=list(res), threshold=list(thr))
+    return status, out, stats
+
+
+def mpm_get_rigid_state(h, rid: int) -> RigidState:
+    s = RigidState()
+    _check(load().mpm_get_rigid_state(h, rid, ct.byref(s)), "mpm_get_rigid_state")
+    return s
+
+
+def mpm_destroy(h) -> None:
+    if h:
+        load().mpm_destroy(h)
+
+
+class Sim:
+    """A scene resident on one GPU: torch owns the particle arrays and the
+    workspace, the library steps them in place."""
+
+    def __init__(self, scene, device: str = "cuda:0", max_contacts: int = 0,
+                 ls_max_rounds: int = 0, track_ids: bool = True):
+        import torch
+        load()
+        self.torch = torch
+        self.scene = scene
+        self.device = torch.device(device)
+        self.N = scene.N
+        self.P = scene.P
+        dev = self.device
+        self.x = torch.from_numpy(np.ascontiguousarray(scene.x, np.float32)).to(dev)
+        self.v = torch.from_numpy(np.ascontiguousarray(scene.v, np.float32)).to(dev)
+        self.F = torch.from_numpy(np.ascontiguousarray(scene.F, np.float32)).to(dev)
+        self.C = torch.from_numpy(np.ascontiguousarray(scene.C, np.float32)).to(dev)
+        self.pid = torch.arange(self.P, dtype=torch.int32, device=dev) if track_ids else None
+        self._envs = env_descs(scene)
+        self.desc = make_desc(scene, self._envs, max_contacts, ls_max_rounds)
+        self.ws_bytes = mpm_workspace_size(self.desc)
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        base = self.ws.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        d = self.desc
+        d.x, d.v, d.F, d.C = (t.data_ptr() for t in (self.x, self.v, self.F, self.C))
+        d.pid = self.pid.data_ptr() if self.pid is not None else None
+        d.workspace, d.workspace_bytes = aligned, self.ws_bytes
+        self.stream = torch.cuda.current_stream(dev)
+        d.stream = self.stream.cuda_stream
+        self.handle = mpm_create(d)
+        self.rigid_ids = [mpm_add_rigid_sdf(self.handle, r.env, rigid_desc(r)) for r in scene.rigids]
+
+    @property
+    def n_rigid(self) -> int:
+        return len(self.rigid_ids)
+
+    def step(self, states=None):
+        return mpm_step(self.handle, self.n_rigid, self.N, states)
+
+    def state(self, original_order: bool = True) -> dict:
+        """Particle state as float32 numpy arrays (in the caller's original
+        particle order when ids are tracked)."""
+        self.torch.cuda.synchronize(self.device)
+        out = {k: getattr(self, k).cpu().numpy() for k in ("x", "v", "F", "C")}
+        if original_order and self.pid is not None:
+            pid = self.pid.cpu().numpy()
+            inv = np.empty_like(pid)
+            inv[pid] = np.arange(pid.shape[0], dtype=pid.dtype)
+            out = {k: a[:, inv] for k, a in out.items()}
+        return out
+
+    def rigid_state(self, i: int) -> RigidState:
+        return mpm_get_rigid_state(self.handle, self.rigid_ids[i])
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            self.torch.cuda.synchronize(self.device)
+            mpm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

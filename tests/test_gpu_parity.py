@@ -1,0 +1,143 @@
+"""HIP path vs the FP64 oracle, through the C ABI, on seeded scenes.
+
+Run on an MI355X: python -m pytest tests -m gpu
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_05046_amd import inputs as I
+from tests.parity import field_errors, impulse_error, m_norm
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_05046_amd import mpm as M
+    M.load()
+    return M
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run_both(mpm, oracle, scene, host_steps=1, basis=0):
+    """Step the scene on the GPU and in the oracle; returns (gpu state, oracle
+    sim, gpu impulses, oracle impulses, gpu stats, oracle stats)."""
+    sim = mpm.Sim(scene)
+    ora = oracle.OracleSim(scene, basis=basis)
+    imp_g = np.zeros((len(scene.rigids), 6))
+    imp_o = np.zeros((len(scene.rigids), 6))
+    sg, so = [], []
+    for _ in range(host_steps):
+        status, imp, st = sim.step()
+        imp_g += imp
+        sg.append(st)
+        rc, impo, sto = ora.host_step()
+        imp_o += impo
+        so.append(sto)
+    out = sim.state()
+    sim.close()
+    return out, ora, imp_g, imp_o, sg, so
+
+
+def test_sort_is_bit_exact(mpm, oracle):
+    s = I.granular_pour(n_particles=200_000, seed=11)
+    s.N = 1
+    keys = oracle.cell_keys_f32(s.x, s.envs[0].origin, 1.0 / s.envs[0].dx, s.envs[0].dims)
+    ref = oracle.stable_order(keys)
+    _log("sort: 200k particles")
+    sim = mpm.Sim(s)
+    sim.step()
+    pid = sim.pid.cpu().numpy()
+    sim.close()
+    assert np.array_equal(pid, ref)
+
+
+def test_free_fall_one_and_hundred_substeps(mpm, oracle):
+    s = I.plain_cube(contact=False)
+    _log("free fall: plain cube, 1 substep")
+    s1 = s.copy()
+    s1.N = 1
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s1)
+    e = field_errors(g, o, s.envs[0].dx)
+    assert max(e.values()) < 1e-5, e
+    _log("free fall: plain cube, 100 substeps")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s, host_steps=10)
+    e = field_errors(g, o, s.envs[0].dx)
+    assert max(e.values()) < 1e-3, e
+    # and the closed form
+    h, k = s.h, 100
+    gz = -9.81
+    assert np.abs(g["v"][2] - k * h * gz).max() < 1e-5
+    assert all(st["max_contacts"] == 0 for st in sg)
+
+
+@pytest.mark.parametrize("material", [I.FIXED_COROTATED, I.DRUCKER_PRAGER])
+def test_one_substep_random_state(mpm, oracle, material):
+    """Random velocities, deformations and affine matrices; contacts with a
+    half-space and a rotated, moving box; solved tightly so the comparison is
+    at float32 level."""
+    s = I.tiny_random(P=3000, seed=13, material=material, n=32)
+    s.envs[0].eps_s = 1e-2  # softer friction keeps the tight solve short; the machinery is the same
+    s.N = 1
+    s.eps_r = 1e-10
+    s.max_iter = 200000
+    _log(f"random state, material {material}")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s)
+    assert sg[0]["contacts"][0] == so[0][0]["n_contacts"] > 0
+    e = field_errors(g, o, s.envs[0].dx)
+    assert max(e.values()) < 1e-5, (e, sg[0], so[0])
+    m_tot = s.envs[0].m_p * s.P
+    assert impulse_error(ig, io, m_tot, s.h) < 1e-4
+
+
+def _contact_state(oracle, substeps):
+    """C1 contact variant advanced by the oracle into sustained contact; the
+    state is rounded to float32 and handed to both sides."""
+    s = I.plain_cube(contact=True)
+    ora = oracle.OracleSim(s)
+    ora.env.max_iter = 100000
+    for _ in range(substeps):
+        ora.substep()
+    s.x, s.v, s.F, s.C = (a.astype(np.float32) for a in (ora.x, ora.v, ora.F, ora.C))
+    return s
+
+
+def test_contact_substep_metric_tolerance(mpm, oracle):
+    """At the benchmark tolerance (eps_r = 1e-6) the two solves agree within
+    the bound the stopping test guarantees."""
+    s = _contact_state(oracle, 22)
+    s.N = 1
+    s.max_iter = 100000
+    _log("plain cube contact substep at eps_r = 1e-6")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s)
+    st_g, st_o = sg[0], so[0][0]
+    assert st_g["contacts"][0] == st_o["n_contacts"] > 50
+    assert st_g["residual"][0] < st_g["threshold"][0]
+    m_p = s.envs[0].m_p
+    bound = st_g["threshold"][0] + st_o["threshold"] + 1e-6 * math.sqrt(m_p * s.P)
+    assert m_norm(g["v"] - o.v, m_p) <= bound
+    e = field_errors(g, o, s.envs[0].dx)
+    assert e["x"] < 1e-5 and e["F"] < 1e-5, e
+
+
+def test_contact_substep_tight(mpm, oracle):
+    s = _contact_state(oracle, 22)
+    s.N = 1
+    s.eps_r = 1e-10
+    s.max_iter = 400000
+    _log("plain cube contact substep at eps_r = 1e-10")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s)
+    e = field_errors(g, o, s.envs[0].dx)
+    assert max(e.values()) < 1e-5, (e, sg[0], so[0])
+    m_tot = s.envs[0].m_p * s.P
+    assert impulse_error(ig, io, m_tot, s.h) < 1e-4
