@@ -1,0 +1,190 @@
+#!/usr/bin/env python
+"""Throughput of the coupled MPM-rigid host step on one MI355X.
+
+Workload: granular pour, 1,000,000 Drucker-Prager sand particles on a 128^3
+grid (dx = 1/128) falling onto four static rigid boxes (mu = 0.4), substep
+h = 1e-4 s, N = 10 substeps per host step, contact residual eps_r = 1e-6,
+eps_a = FP64 machine epsilon. One benchmark step is one host step: the
+once-per-step cell sort plus ten full substeps (P2G, grid update, contact
+registration, the contact-node table, Algorithm 1 to convergence, G2P with the
+return map). Inputs are seeded and synthetic and resident in HBM before the
+timed region starts.
+
+Prints one JSON line with the metric (particle-substeps/s), a roofline entry
+for the kernel that takes most of the time, per-kernel figures measured with
+HIP events inside the timed region, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes (minimal float32 structure-of-arrays traffic).
+P2G_BYTES_PER_PARTICLE = 60        # reads x, v, Q
+G2P_BYTES_PER_PARTICLE = 144       # reads x, F; writes x, v, F, Q
+SORT_BYTES_PER_PARTICLE = 210      # keys + stable sort passes + gather, once per host step
+SOLVE_BYTES_PER_CONTACT_ITER = 52  # per Algorithm 1 iteration
+SOLVE_BYTES_PER_NODE_ITER = 88
+SOLVE_BYTES_PER_CONTACT_ROUND = 40  # per line-search reduction round
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(state: dict, scene, budget_s: float) -> dict:
+    """The FP64 oracle, as it stands, on one substep of a column of the same
+    state (particles with x, y in [0.36, 0.44], all heights, over one box)."""
+    import numpy as np
+    from oracle import oracle as O
+    O.build(force=not os.path.exists(O.LIB))
+    x = state["x"]
+    sel = np.nonzero((x[0] > 0.36) & (x[0] < 0.44) & (x[1] > 0.36) & (x[1] < 0.44))[0]
+    sub = scene.copy()
+    sub.x, sub.v, sub.F, sub.C = (np.ascontiguousarray(state[k][:, sel]) for k in ("x", "v", "F", "C"))
+    sub.envs[0].p_begin, sub.envs[0].p_end = 0, len(sel)
+    ora = O.OracleSim(sub)
+    t0 = time.perf_counter()
+    rc, st, _ = ora.substep()
+    dt = time.perf_counter() - t0
+    return {"value": len(sel) / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"1 substep of a {len(sel)}-particle column (x, y in [0.36, 0.44]) of the "
+                       f"benchmark state after the timed steps: {st.n_contacts} contacts, "
+                       f"{st.iterations} solver iterations, {dt:.1f} s single-threaded FP64"),
+            "status": rc}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--max-iter", type=int, default=200_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(environments shard by assignment, one slab per GPU for a single scene; "
+              "see the design notes). Run with --gpus 1.", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+
+    scene = I.granular_pour(n_particles=args.particles)
+    scene.max_iter = args.max_iter
+    log(f"scene {scene.name}: P={scene.P}, grid {tuple(scene.envs[0].dims)}, N={scene.N}, "
+        f"h={scene.h}, eps_r={scene.eps_r}")
+    sim = M.Sim(scene, device="cuda:0")
+    P, N = scene.P, scene.N
+
+    def run(k_steps, tag):
+        per = []
+        for i in range(k_steps):
+            t = time.perf_counter()
+            status, imp, st = sim.step()
+            per.append(st)
+            log(f"{tag} step {i}: {1e3 * (time.perf_counter() - t):.1f} ms, contacts max "
+                f"{st['max_contacts']}, iterations/substep {st['iterations']}, flags {st['flags']}")
+        return per
+
+    run(args.warmup, "warmup")
+    sim.profile(True)  # reset and start event timing
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = run(args.steps, "timed")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sim.profile(False)
+    elapsed = t1 - t0
+    value = P * N * args.steps / elapsed
+
+    # per-kernel figures from the live events
+    ms, launches = prof["ms"], prof["launches"]
+    total_ms = sum(ms.values())
+    sub_launches = max(1, launches["p2g"])
+    solve_bytes = (SOLVE_BYTES_PER_CONTACT_ITER * prof["solver_contact_iters"] +
+                   SOLVE_BYTES_PER_NODE_ITER * prof["solver_node_iters"] +
+                   SOLVE_BYTES_PER_CONTACT_ROUND * prof["solver_contact_rounds"])
+    algo_bytes = {
+        "p2g": P2G_BYTES_PER_PARTICLE * P * launches["p2g"],
+        "g2p": G2P_BYTES_PER_PARTICLE * P * launches["g2p"],
+        "sort": SORT_BYTES_PER_PARTICLE * P * launches["sort"],
+        "solve": solve_bytes,
+    }
+    kernels = {}
+    for k in M.KERNEL_CLASSES:
+        if launches[k] == 0:
+            continue
+        e = {"ms_total": round(ms[k], 3), "launches": int(launches[k]),
+             "us_per_launch": round(1e3 * ms[k] / launches[k], 2),
+             "share": round(ms[k] / total_ms, 4) if total_ms > 0 else None}
+        if k in algo_bytes and ms[k] > 0:
+            gbs = algo_bytes[k] / (ms[k] * 1e-3) / 1e9
+            e["algo_GBps"] = round(gbs, 1)
+            e["frac_hbm_peak"] = round(gbs / HBM_PEAK_GBS, 4)
+        kernels[k] = e
+    dominant = max(kernels, key=lambda k: kernels[k]["ms_total"])
+    dom = kernels[dominant]
+    roofline = {"kernel": dominant, "bound": "hbm", "achieved": dom.get("algo_GBps"),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom.get("frac_hbm_peak"),
+                "traffic": None}
+    iters = [i for st in stats for i in st["iterations"]]
+    contacts = [c for st in stats for c in st["contacts"]]
+    nodes = [c for st in stats for c in st["contact_nodes"]]
+    noconv = sum(1 for st in stats if st["flags"] & M.FLAG_NOCONV)
+    solver = {
+        "iterations_per_substep_mean": round(float(np.mean(iters)), 1),
+        "iterations_per_substep_max": int(max(iters)),
+        "contacts_mean": round(float(np.mean(contacts)), 1), "contacts_max": int(max(contacts)),
+        "contact_nodes_mean": round(float(np.mean(nodes)), 1),
+        "us_per_iteration": (round(1e3 * ms["solve"] / prof["solver_iterations"], 2)
+                             if prof["solver_iterations"] else None),
+        "ls_rounds_per_iteration": (round(prof["solver_ls_rounds"] / prof["solver_iterations"], 2)
+                                    if prof["solver_iterations"] else None),
+        "phase_us_per_iteration": ({k: round(v / prof["solver_iterations"], 2)
+                                    for k, v in prof["solver_phase_us"].items()}
+                                   if prof["solver_iterations"] else None),
+        "host_steps_not_converged": noconv,
+        "residual_over_threshold_max": max(
+            (r / t for st in stats for r, t in zip(st["residual"], st["threshold"]) if t > 0),
+            default=None),
+    }
+    out = {
+        "metric": "particle-substeps/s (plain substep at contact residual 1e-6)",
+        "value": value, "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": (f"granular pour: {P} Drucker-Prager sand particles, 128^3 grid, "
+                                f"4 static boxes, h=1e-4 s, {N} substeps per host step, "
+                                f"eps_r=1e-6; one step = one host step"),
+                   "particles": P, "substeps_per_step": N, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "kernels": kernels,
+        "solver": solver,
+    }
+    state = sim.state()
+    sim.close()
+    if not args.no_cpu_baseline:
+        log("cpu baseline: FP64 oracle on a column sample")
+        out["cpu_baseline"] = cpu_baseline(state, scene, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

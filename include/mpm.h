@@ -92,7 +92,7 @@ typedef struct {
     int32_t N;                 /* substeps per host step, >= 1 */
     double eps_r, eps_a;       /* Algorithm 1 tolerances, >= 0 */
     int32_t max_iter;          /* Algorithm 1 iteration cap, >= 1 */
-    int32_t ls_max_rounds;     /* line-search refinement rounds, >= 1 (0 = default 8) */
+    int32_t ls_max_steps;      /* line-search Newton/bisection steps, >= 0 (0 = default 100) */
     int64_t n_particles;       /* P >= 1 */
     /* Caller-owned device arrays, borrowed for the life of the handle. The
      * library reorders particles by grid cell once per host step (a stable
@@ -153,6 +153,32 @@ typedef struct {
     double* threshold;         /* [N] eps_a + eps_r max(|p~|, |j~|) at exit */
 } mpm_step_stats;
 
+/* Kernel classes timed by mpm_profile. */
+enum {
+    MPM_K_SORT = 0,      /* cell keys, radix sort, gather, tile list (once per host step) */
+    MPM_K_P2G = 1,       /* particle-to-grid scatter */
+    MPM_K_GRID = 2,      /* grid update */
+    MPM_K_REGISTER = 3,  /* contact registration */
+    MPM_K_SETUP = 4,     /* contact-node table */
+    MPM_K_SOLVE = 5,     /* Algorithm 1 */
+    MPM_K_G2P = 6,       /* grid-to-particle gather and constitutive update */
+    MPM_K_COUNT = 7
+};
+
+/* Accumulated device time per kernel class, measured with HIP events recorded
+ * on the handle's stream around each launch group. */
+typedef struct {
+    double ms[MPM_K_COUNT];
+    int64_t launches[MPM_K_COUNT];
+    int64_t solver_iterations;    /* Algorithm 1 iterations over the timed steps */
+    int64_t solver_ls_rounds;     /* line-search evaluations (each a pass over the contacts) */
+    int64_t solver_contact_iters; /* sum over iterations of registered contacts */
+    int64_t solver_node_iters;    /* sum over iterations of contact nodes */
+    int64_t solver_contact_rounds;/* sum over line-search evaluations of registered contacts */
+    double solver_phase_us[5];    /* solver time of its first block: node pass, barrier, contact pass,
+                                     barrier, line search */
+} mpm_profile_data;
+
 typedef struct mpm_handle mpm_handle;
 
 /* Bytes of device workspace mpm_create needs for this description (the
@@ -179,6 +205,11 @@ mpm_status mpm_add_rigid_sdf(mpm_handle* h, int32_t env, const mpm_rigid_desc* r
  * substep with a consistent state). Not thread-safe per handle. */
 mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse* out,
                     mpm_step_stats* st);
+
+/* Profiling: enable (1) or disable (0) event timing of the kernel classes
+ * for the following steps. out (may be NULL) receives what was accumulated
+ * since the previous call, and the accumulators are reset. Host only. */
+mpm_status mpm_profile(mpm_handle* h, int32_t enable, mpm_profile_data* out);
 
 /* Current pose and twist of rigid body id (host). */
 mpm_status mpm_get_rigid_state(const mpm_handle* h, int32_t id, mpm_rigid_state* s);

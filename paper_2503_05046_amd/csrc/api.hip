@@ -39,6 +39,8 @@ mpm_status fail(mpm_status st, const char* fmt, ...) {
 
 constexpr int kMaxRigidTotal = 256;
 constexpr int kMaxQnBlocks = 1024;
+constexpr int kQnDefaultBlocks = 32;   // first step, before any problem size is known
+constexpr int kQnItemsPerBlock = 512;  // contact nodes per solver block
 constexpr size_t kAlign = 256;
 
 struct Layout {
@@ -67,7 +69,7 @@ mpm_status validate(const mpm_desc* d, Sizes* sz) {
     if (d->N < 1) return fail(MPM_EINVAL, "N must be >= 1");
     if (!(d->eps_r >= 0.0) || !(d->eps_a >= 0.0)) return fail(MPM_EINVAL, "tolerances must be >= 0");
     if (d->max_iter < 1) return fail(MPM_EINVAL, "max_iter must be >= 1");
-    if (d->ls_max_rounds < 0) return fail(MPM_EINVAL, "ls_max_rounds must be >= 0");
+    if (d->ls_max_steps < 0) return fail(MPM_EINVAL, "ls_max_steps must be >= 0");
     if (d->n_particles < 1 || d->n_particles > (1ll << 31) - 1)
         return fail(MPM_EINVAL, "n_particles out of range");
     long long expect = 0, nodes = 0;
@@ -124,6 +126,10 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->active_tiles = L.take<unsigned>(z.n_tiles);
     w->ptile_id = L.take<unsigned>(z.n_tiles);
     w->ptile_beg = L.take<unsigned>(z.n_tiles + 1);
+    w->ptile_of = L.take<int>(z.n_tiles);
+    w->ntile_list = L.take<unsigned>(z.n_tiles);
+    w->ntile_mark = L.take<unsigned>(z.n_tiles);
+    w->blkbuf = L.take<float4>((size_t)z.n_tiles * 512);
     w->acc = L.take<float4>(z.n_nodes);
     w->vel = L.take<float4>(z.n_nodes);
     const long long C = z.cap_c;
@@ -132,28 +138,20 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->c_env = L.take<int>(C);
     w->c_base = L.take<int>(C);
     w->c_w = L.take<float>(9 * C);
-    w->c_n = L.take<double>(3 * C);
-    w->c_b = L.take<double>(3 * C);
-    w->c_phi0 = L.take<double>(C);
-    w->c_n0 = L.take<double>(C);
-    w->c_mu = L.take<double>(C);
-    w->c_vc = L.take<double>(6 * C);
-    w->c_uc = L.take<double>(3 * C);
-    w->c_gam = L.take<double>(3 * C);
-    w->c_slot = L.take<int>(27 * C);
+    w->c_rec = L.take<ContactRec>(C);
+    w->c_st = L.take<ContactStencil>(C);
+    w->c_dyn = L.take<ContactDyn>(C);
     w->pk_a = L.take<unsigned>(27 * C);
     w->pk_b = L.take<unsigned>(27 * C);
     w->pv_a = L.take<unsigned>(27 * C);
     w->pv_b = L.take<unsigned>(27 * C);
+    w->e_ent = L.take<Entry>(27 * C);
     const long long S = z.cap_s;
     w->s_node = L.take<int>(S);
     w->s_beg = L.take<int>(S + 1);
-    w->s_v = L.take<double>(3 * S);
-    w->s_vstar = L.take<double>(3 * S);
-    w->s_dv = L.take<double>(3 * S);
-    w->s_m = L.take<double>(S);
+    w->s_rec = L.take<SlotRec>(S);
     w->blk = L.take<unsigned>(256 * kSortBlocks + 2 * kSortBlocks);
-    w->partial = L.take<double>((size_t)kMaxQnBlocks * (kQnSums + 4 * kLsPoints));
+    w->partial = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
     w->rigid_acc = L.take<double>(6 * kMaxRigidTotal);
     w->sstats = L.take<SubstepStats>(z.N);
     w->cnt = L.take<DevCounters>(1);
@@ -206,12 +204,44 @@ struct mpm_handle {
     Work w;
     hipStream_t stream;
     int key_bits;
+    int qn_cap;          // co-resident blocks the cooperative solver may use
+    double wall_khz;     // device wall-clock rate
+    int qn_blocks_next;  // blocks for the next step, sized from the last one's problem
     // pinned host staging
     DevRigid* h_rigids;
     double* h_racc;
     SubstepStats* h_stats;
     DevCounters* h_cnt;
+    // profiling
+    bool prof = false;
+    std::vector<hipEvent_t> events;   // pairs (start, stop)
+    std::vector<int> ev_class;        // kernel class of each pair
+    mpm_profile_data acc;
 };
+
+namespace {
+// Event pair around a launch group when profiling is on.
+struct ProfScope {
+    mpm_handle* h;
+    int pair;
+    ProfScope(mpm_handle* hh, int cls, int& next) : h(hh), pair(-1) {
+        if (!h->prof) return;
+        pair = next++;
+        if ((int)h->ev_class.size() <= pair) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) { pair = -1; --next; return; }
+            h->events.push_back(a);
+            h->events.push_back(b);
+            h->ev_class.push_back(cls);
+        }
+        h->ev_class[pair] = cls;
+        (void)hipEventRecord(h->events[2 * pair], h->stream);
+    }
+    ~ProfScope() {
+        if (pair >= 0) (void)hipEventRecord(h->events[2 * pair + 1], h->stream);
+    }
+};
+}  // namespace
 
 extern "C" {
 
@@ -256,6 +286,13 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         return fail(MPM_EDEVICE, "cannot query the device");
     }
     h->w.qn_blocks = std::max(1, std::min({qn_cap, cus, kMaxQnBlocks}));
+    h->qn_cap = h->w.qn_blocks;
+    {
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
+        h->wall_khz = khz;
+    }
+    h->qn_blocks_next = std::min(h->qn_cap, kQnDefaultBlocks);
     h->w.n_rigid = 0;
     int tiles = 0;
     long long nodes = 0;
@@ -306,6 +343,8 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
     hipError_t e = hipMemsetAsync(W.acc, 0, sizeof(float4) * W.n_nodes, s);
     if (e == hipSuccess) e = hipMemsetAsync(W.vel, 0, sizeof(float4) * W.n_nodes, s);
     if (e == hipSuccess) e = hipMemsetAsync(W.tile_flag, 0, sizeof(unsigned) * W.n_tiles, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.ntile_mark, 0, sizeof(unsigned) * W.n_tiles, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.ptile_of, 0xFF, sizeof(int) * W.n_tiles, s);
     if (e == hipSuccess) e = hipMemsetAsync(W.cnt, 0, sizeof(DevCounters), s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s);
@@ -407,35 +446,78 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     hipStream_t s = h->stream;
     const mpm_desc& d = h->d;
     const int N = d.N;
-    const int ls_rounds = d.ls_max_rounds > 0 ? d.ls_max_rounds : 8;
+    const int ls_steps = d.ls_max_steps > 0 ? d.ls_max_steps : 100;
+    const int qn_blocks = h->qn_blocks_next;
     HIP_TRY(hipMemcpyAsync(W.rigids, h->h_rigids, sizeof(DevRigid) * std::max(nr, 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(launch_clear_step(W, N, s));
-    // once per host step: cell keys, stable sort, gather, tile list (Sec. V-A)
-    HIP_TRY(launch_keys(W, d.x, s));
-    unsigned *keys_sorted, *idx_sorted;
-    HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
-    HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
-    HIP_TRY(launch_tile_list(W, keys_sorted, s));
+    int npair = 0;
+    {
+        // once per host step: cell keys, stable sort, gather, tile list (Sec. V-A)
+        ProfScope ps(h, MPM_K_SORT, npair);
+        HIP_TRY(launch_keys(W, d.x, s));
+        unsigned *keys_sorted, *idx_sorted;
+        HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
+        HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
+        HIP_TRY(launch_tile_maps(W, s, true));   // forget the previous step's tiles
+        HIP_TRY(launch_tile_list(W, keys_sorted, s));
+        HIP_TRY(launch_tile_maps(W, s, false));
+        W.keys_sorted = keys_sorted;
+    }
     for (int k = 0; k < N; ++k) {
         const bool first = k == 0, last = k == N - 1;
         const float* x_in = first ? W.xs : d.x;
         const float* v_in = first ? W.vs : d.v;
         const float* F_in = first ? W.Fs : d.F;
         HIP_TRY(launch_clear_substep(W, s));
-        HIP_TRY(launch_p2g(W, x_in, v_in, s));
-        HIP_TRY(launch_grid_update(W, d.h, s));
-        HIP_TRY(launch_registration(W, x_in, v_in, d.h, k, s));
-        HIP_TRY(launch_contact_setup(W, s));
-        HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_rounds, s));
-        HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
-                           (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h, s));
+        {
+            ProfScope ps(h, MPM_K_P2G, npair);
+            HIP_TRY(launch_p2g(W, x_in, v_in, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_GRID, npair);
+            HIP_TRY(launch_grid_update(W, d.h, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_REGISTER, npair);
+            HIP_TRY(launch_registration(W, x_in, v_in, d.h, k, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_SETUP, npair);
+            HIP_TRY(launch_contact_setup(W, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_SOLVE, npair);
+            HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_G2P, npair);
+            HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
+                               (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h, s));
+        }
     }
     HIP_TRY(hipMemcpyAsync(h->h_cnt, W.cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const unsigned flags = h->h_cnt->flags;
+    if (h->prof) {
+        for (int q = 0; q < npair; ++q) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * q], h->events[2 * q + 1]));
+            h->acc.ms[h->ev_class[q]] += ms;
+            h->acc.launches[h->ev_class[q]] += 1;
+        }
+        for (int k = 0; k < N; ++k) {
+            const SubstepStats& q = h->h_stats[k];
+            h->acc.solver_iterations += q.iterations;
+            h->acc.solver_ls_rounds += q.ls_rounds;
+            h->acc.solver_contact_iters += (int64_t)q.iterations * q.n_contacts;
+            h->acc.solver_node_iters += (int64_t)q.iterations * q.n_slots;
+            h->acc.solver_contact_rounds += (int64_t)q.ls_rounds * q.n_contacts;
+            for (int ph = 0; ph < 5; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)q.t_phase[ph] / h->wall_khz;
+        }
+    }
     if (h->h_cnt->abort_step && h->h_cnt->abort_substep > 0) {
         // the step stopped early: the caller's C lags the state; rebuild it from Q
         HIP_TRY(launch_recover_C(W, d.F, d.C, d.h, s));
@@ -468,6 +550,13 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
             if (st->threshold) st->threshold[k] = q.threshold;
         }
     }
+    // size the next step's solver launch from this step's largest problem
+    {
+        int most = 0;
+        for (int k = 0; k < N; ++k) most = std::max(most, h->h_stats[k].n_slots);
+        if (most > 0)
+            h->qn_blocks_next = std::max(1, std::min(h->qn_cap, (most + kQnItemsPerBlock - 1) / kQnItemsPerBlock));
+    }
     // host side of the split: advance kinematic bodies with their twist
     for (HostRigid& q : h->rigids) {
         if (q.desc.motion != MPM_KINEMATIC) continue;
@@ -484,8 +573,17 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     return MPM_OK;
 }
 
+mpm_status mpm_profile(mpm_handle* h, int32_t enable, mpm_profile_data* out) {
+    if (!h) return fail(MPM_EINVAL, "handle is NULL");
+    if (out) *out = h->acc;
+    memset(&h->acc, 0, sizeof(h->acc));
+    h->prof = enable != 0;
+    return MPM_OK;
+}
+
 void mpm_destroy(mpm_handle* h) {
     if (!h) return;
+    for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->h_rigids) (void)hipHostFree(h->h_rigids);
     if (h->h_racc) (void)hipHostFree(h->h_racc);
     if (h->h_stats) (void)hipHostFree(h->h_stats);

@@ -21,13 +21,11 @@
 //               Cholesky, and adds its share of the norms;
 //   barrier     every block reduces the per-block partials in the same order,
 //               so all blocks take the same stopping decision;
-//   contact pass u_c = R_c^T sum w dv, plus the line-search derivatives at a
-//               batch of step lengths;
-//   barrier(s)  the exact line search of Algorithm 1 is solved by rounds that
-//               evaluate phi'(alpha), phi''(alpha) at kLsPoints step lengths
-//               per global reduction (bracketing, then safeguarded Newton
-//               clusters), instead of one sequential 1-D Newton step per
-//               reduction.
+//   contact pass u_c = R_c^T sum w dv;
+//   barrier     then the exact line search of Algorithm 1 (1-D Newton with a
+//               bisection fallback) runs redundantly in every block over all
+//               contacts with block-local reductions, so it needs no global
+//               synchronisation; every block obtains the same step length.
 // Contact velocities are carried as v_c + alpha u_c (the contact velocity is
 // linear in the grid velocity), double-buffered by iteration parity.
 #include "mpm_internal.h"
@@ -41,9 +39,11 @@ constexpr unsigned kFlagNoconv = 1u;
 constexpr unsigned kFlagCapacity = 8u;
 constexpr unsigned kFlagHang = 16u;
 constexpr long long kBarrierTimeoutCycles = 5000000000ll;  // ~2 s: a healthy barrier takes microseconds
-constexpr int kQnThreads = 256;
+constexpr int kQnThreads = 512;
+constexpr int kBlkThreads = 1024;      // single-workgroup solver
+constexpr int kBlkMaxContacts = 2048;  // contacts whose per-iteration terms fit in one CU's LDS
+constexpr int kSlotChunk = 512;     // contact nodes whose accumulators are staged in LDS at once
 constexpr int kMaxRigid = 256;
-constexpr int kPartStride = kQnSums + 4 * kLsPoints;  // node sums + 2 LS buffers (phi', phi'')
 
 __device__ __forceinline__ int env_of_particle_c(const DevEnv* envs, int n_envs, long long p) {
     int lo = 0, hi = n_envs - 1;
@@ -173,9 +173,8 @@ k_reg_write(const float* __restrict__ x, const float* __restrict__ v, long long 
             const DevEnv* __restrict__ envs, int n_envs, const DevRigid* __restrict__ rigids,
             const unsigned* __restrict__ cmask, const unsigned* __restrict__ blk, double h,
             long long cap, int* __restrict__ c_pid, int* __restrict__ c_rid, int* __restrict__ c_env,
-            int* __restrict__ c_base, float* __restrict__ c_w, double* __restrict__ c_n,
-            double* __restrict__ c_b, double* __restrict__ c_phi0, double* __restrict__ c_n0,
-            double* __restrict__ c_mu, int substep, DevCounters* cnt) {
+            int* __restrict__ c_base, float* __restrict__ c_w, ContactRec* __restrict__ c_rec,
+            int substep, DevCounters* cnt) {
     __shared__ unsigned wsum[17];
     if (cnt->abort_step) return;
     long long beg, end;
@@ -217,20 +216,22 @@ k_reg_write(const float* __restrict__ x, const float* __restrict__ v, long long 
                                       R.V[2] + R.w[0] * rel[1] - R.w[1] * rel[0]};
                 double t1[3], t2[3];
                 frame_of(n, t1, t2);
-                c_b[0 * cap + c] = -(t1[0] * vr[0] + t1[1] * vr[1] + t1[2] * vr[2]);
-                c_b[1 * cap + c] = -(t2[0] * vr[0] + t2[1] * vr[1] + t2[2] * vr[2]);
-                c_b[2 * cap + c] = -(n[0] * vr[0] + n[1] * vr[1] + n[2] * vr[2]);
                 const double phi0 = -s;
                 const double vn0 = n[0] * (vp[0] - vr[0]) + n[1] * (vp[1] - vr[1]) + n[2] * (vp[2] - vr[2]);
+                const double n0 = normal_impulse(vn0, phi0, E.k, E.d, h);
+                ContactRec rec;
+                rec.n[0] = n[0]; rec.n[1] = n[1]; rec.n[2] = n[2];
+                rec.phi0 = phi0;
+                rec.mun0 = R.mu * n0;
+                rec.k = E.k; rec.d = E.d; rec.eps_s = E.eps_s;
+                rec.b[0] = -(t1[0] * vr[0] + t1[1] * vr[1] + t1[2] * vr[2]);
+                rec.b[1] = -(t2[0] * vr[0] + t2[1] * vr[1] + t2[2] * vr[2]);
+                rec.b[2] = -(n[0] * vr[0] + n[1] * vr[1] + n[2] * vr[2]);
+                c_rec[c] = rec;
                 c_pid[c] = (int)p;
                 c_rid[c] = r;
                 c_env[c] = e;
                 c_base[c] = (int)node0;
-                c_phi0[c] = phi0;
-                c_n0[c] = normal_impulse(vn0, phi0, E.k, E.d, h);
-                c_mu[c] = R.mu;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) c_n[a * cap + c] = n[a];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     float w3[3];
@@ -258,16 +259,16 @@ hipError_t launch_registration(const Work& w, const float* x, const float* v, do
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reg_write, dim3(kSortBlocks), dim3(256), 0, s, x, v, w.P, w.envs,
                        w.n_envs, w.rigids, w.cmask, w.blk, h, w.cap_c, w.c_pid, w.c_rid, w.c_env,
-                       w.c_base, w.c_w, w.c_n, w.c_b, w.c_phi0, w.c_n0, w.c_mu, substep, w.cnt);
+                       w.c_base, w.c_w, w.c_rec, substep, w.cnt);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
 // Contact-node table
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double stencil_weight(const float* c_w, long long cap, long long c, int o) {
+__device__ __forceinline__ float stencil_weight(const float* c_w, long long cap, long long c, int o) {
     const int a = o % 3, b = (o / 3) % 3, cz = o / 9;
-    return (double)c_w[(0 + a) * cap + c] * (double)c_w[(3 + b) * cap + c] * (double)c_w[(6 + cz) * cap + c];
+    return c_w[(0 + a) * cap + c] * c_w[(3 + b) * cap + c] * c_w[(6 + cz) * cap + c];
 }
 
 __device__ __forceinline__ long long stencil_node(const DevEnv& E, int base, int o) {
@@ -285,8 +286,8 @@ k_pairs(const DevEnv* __restrict__ envs, const int* __restrict__ c_env, const in
          i += (long long)gridDim.x * blockDim.x) {
         const long long c = i / 27;
         const int o = (int)(i % 27);
-        const double w = stencil_weight(c_w, cap, c, o);
-        pk[i] = w > 0.0 ? (unsigned)stencil_node(envs[c_env[c]], c_base[c], o) : invalid_key;
+        const float w = stencil_weight(c_w, cap, c, o);
+        pk[i] = w > 0.f ? (unsigned)stencil_node(envs[c_env[c]], c_base[c], o) : invalid_key;
         pv[i] = (unsigned)i;
     }
 }
@@ -309,8 +310,8 @@ k_csr_count(const unsigned* __restrict__ keys, const DevCounters* cnt, unsigned 
 __global__ void __launch_bounds__(256)
 k_csr_write(const unsigned* __restrict__ keys, const unsigned* __restrict__ vals,
             const DevCounters* cnt, unsigned invalid_key, const unsigned* __restrict__ blk,
-            long long cap, int* __restrict__ s_node, int* __restrict__ s_beg,
-            int* __restrict__ c_slot) {
+            long long cap, const float* __restrict__ c_w, int* __restrict__ s_node,
+            int* __restrict__ s_beg, ContactStencil* __restrict__ c_st, Entry* __restrict__ e_ent) {
     __shared__ unsigned wsum[17];
     const long long n = cnt->n_pairs;
     long long beg, end;
@@ -334,10 +335,19 @@ k_csr_write(const unsigned* __restrict__ keys, const unsigned* __restrict__ vals
                     s_node[slot] = (int)key;
                     s_beg[slot] = (int)i;
                 }
-                c_slot[o * cap + c] = (int)slot;
+                const float w = stencil_weight(c_w, cap, c, o);
+                c_st[c].slot[o] = (int)slot;
+                c_st[c].w[o] = w;
+                Entry en;
+                en.c = (unsigned)c;
+                en.slot = (int)slot;
+                en.w = w;
+                en.pad = 0.f;
+                e_ent[i] = en;
                 if (i + 1 == n || keys[i + 1] == invalid_key) s_beg[cnt->n_slots] = (int)(i + 1);
             } else {
-                c_slot[o * cap + c] = -1;
+                c_st[c].slot[o] = -1;
+                c_st[c].w[o] = 0.f;
             }
         }
         run += tot;
@@ -348,22 +358,32 @@ k_csr_write(const unsigned* __restrict__ keys, const unsigned* __restrict__ vals
 // the free-motion velocity).
 __global__ void __launch_bounds__(256)
 k_slot_init(const int* __restrict__ s_node, const float4* __restrict__ vel, const DevCounters* cnt,
-            long long cap_s, double* __restrict__ s_m, double* __restrict__ s_vstar,
-            double* __restrict__ s_v) {
+            SlotRec* __restrict__ s_rec) {
     const long long ns = cnt->n_slots;
     for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < ns;
          s += (long long)gridDim.x * blockDim.x) {
         const float4 g = vel[s_node[s]];
-        s_m[s] = g.w;
-        s_vstar[0 * cap_s + s] = g.x; s_vstar[1 * cap_s + s] = g.y; s_vstar[2 * cap_s + s] = g.z;
-        s_v[0 * cap_s + s] = g.x; s_v[1 * cap_s + s] = g.y; s_v[2 * cap_s + s] = g.z;
+        SlotRec r;
+        r.m = g.w;
+        r.v[0] = r.vstar[0] = g.x;
+        r.v[1] = r.vstar[1] = g.y;
+        r.v[2] = r.vstar[2] = g.z;
+        r.dv[0] = r.dv[1] = r.dv[2] = 0.0;
+        s_rec[s] = r;
     }
+}
+
+// Key width of the contact-node pairs (node index, or n_nodes for a
+// zero-weight stencil entry).
+static int pair_key_bits(const Work& w) {
+    int bits = 1;
+    while ((1ull << bits) <= (unsigned long long)w.n_nodes) ++bits;
+    return bits;
 }
 
 hipError_t launch_contact_setup(const Work& w, hipStream_t s) {
     const unsigned invalid_key = (unsigned)w.n_nodes;
-    int bits = 1;
-    while ((1ull << bits) <= (unsigned long long)w.n_nodes) ++bits;
+    const int bits = pair_key_bits(w);
     hipLaunchKernelGGL(k_pairs, dim3(2048), dim3(256), 0, s, w.envs, w.c_env, w.c_base, w.c_w,
                        w.cap_c, invalid_key, w.pk_a, w.pv_a, w.cnt);
     unsigned *ks, *vs;
@@ -374,53 +394,66 @@ hipError_t launch_contact_setup(const Work& w, hipStream_t s) {
     e = launch_scan_blocks(w.blk, kSortBlocks, &w.cnt->n_slots, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_csr_write, dim3(kSortBlocks), dim3(256), 0, s, ks, vs,
-                       (const DevCounters*)w.cnt, invalid_key, w.blk, w.cap_c, w.s_node, w.s_beg,
-                       w.c_slot);
+                       (const DevCounters*)w.cnt, invalid_key, w.blk, w.cap_c, w.c_w, w.s_node,
+                       w.s_beg, w.c_st, w.e_ent);
     hipLaunchKernelGGL(k_slot_init, dim3(1024), dim3(256), 0, s, w.s_node, w.vel,
-                       (const DevCounters*)w.cnt, w.cap_s, w.s_m, w.s_vstar, w.s_v);
-    // the sorted pair values are what the solver walks
-    if (vs != w.pv_a) {
-        e = hipMemcpyAsync(w.pv_a, vs, sizeof(unsigned) * 27 * w.cap_c, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return e;
-    }
+                       (const DevCounters*)w.cnt, w.s_rec);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Grid barrier for the cooperative solver (all blocks co-resident). The wait
-// is bounded: on time-out every block sees the broken flag and leaves.
+// Shared pieces of the two solver kernels
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool grid_sync(DevCounters* cnt, unsigned nblocks, unsigned* gen,
-                                          unsigned* s_ok) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned target = *gen + 1u;
-        __threadfence();
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&cnt->bar_count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        bool ok = true;
-        if (arrived == nblocks - 1u) {
-            __hip_atomic_store(&cnt->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&cnt->bar_gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            const long long t0 = clock64();
-            while (__hip_atomic_load(&cnt->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != target) {
-                __builtin_amdgcn_s_sleep(1);
-                if ((__hip_atomic_load(&cnt->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagHang) ||
-                    clock64() - t0 > kBarrierTimeoutCycles) {
-                    atomicOr(&cnt->flags, kFlagHang);
-                    ok = false;
-                    break;
-                }
-            }
-        }
-        __threadfence();
-        if (__hip_atomic_load(&cnt->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagHang) ok = false;
-        *s_ok = ok ? 1u : 0u;
-    }
-    __syncthreads();
-    *gen += 1u;
-    return *s_ok != 0u;
+struct QnArgs {
+    const DevRigid* rigids;
+    const float* x;         // particle positions at substep start (torque arms)
+    long long P;
+    float4* vel;
+    long long cap;
+    const int *c_pid, *c_rid;
+    const ContactRec* c_rec;
+    const ContactStencil* c_st;
+    ContactDyn* c_dyn;
+    const int *s_node, *s_beg;
+    const Entry* e_ent;
+    SlotRec* s_rec;
+    double* partial;
+    double* rigid_acc;
+    int n_rigid;
+    SubstepStats* stats;
+    int substep;
+    double h, eps_r, eps_a;
+    int max_iter, ls_max_steps;
+    DevCounters* cnt;
+};
+
+__device__ __forceinline__ ContactParams params_of(const ContactRec& R, double h) {
+    ContactParams P;
+    P.phi0 = R.phi0;
+    P.mun0 = R.mun0;
+    P.k = R.k;
+    P.d = R.d;
+    P.eps_s = R.eps_s;
+    P.h = h;
+    return P;
+}
+
+// Contact velocity at iteration k: v_c^0 from the initial gather, then
+// v_c^k = v_c^{k-1} + alpha_{k-1} u_c^{k-1} (exact: v_c is linear in v). The
+// iteration that computes u_c^k also stores v_c^k in buffer k&1.
+__device__ __forceinline__ void contact_velocity(const ContactDyn& D, int k, double alpha_prev, double vc[3]) {
+    const int src = k == 0 ? 0 : (k - 1) & 1;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) vc[a] = k == 0 ? D.vc[0][a] : fma(alpha_prev, D.uc[a], D.vc[src][a]);
+}
+
+__device__ __forceinline__ void ls_terms(const ContactParams& P, const double vc[3], const double u[3],
+                                         double alpha, double* d1, double* d2) {
+    double v[3] = {fma(alpha, u[0], vc[0]), fma(alpha, u[1], vc[1]), fma(alpha, u[2], vc[2])};
+    double g[3], g00, g01, g11, gnn;
+    contact_model(P, v, g, &g00, &g01, &g11, &gnn);
+    *d1 = -(g[0] * u[0] + g[1] * u[1] + g[2] * u[2]);
+    *d2 = g00 * u[0] * u[0] + 2.0 * g01 * u[0] * u[1] + g11 * u[1] * u[1] + gnn * u[2] * u[2];
 }
 
 // Block-wide FP64 sum of NV values per thread into out[NV] (thread 0 writes).
@@ -442,414 +475,564 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* 
     __syncthreads();
 }
 
-struct QnArgs {
-    const DevEnv* envs;
-    const DevRigid* rigids;
-    const float* x;         // particle positions at substep start (torque arms)
-    long long P;
-    float4* vel;
-    long long cap, cap_s;
-    const int *c_pid, *c_rid, *c_env, *c_slot;
-    const float* c_w;
-    const double *c_n, *c_b, *c_phi0, *c_n0, *c_mu;
-    double *c_vc, *c_uc, *c_gam;
-    const int *s_node, *s_beg;
-    const unsigned* pv;     // sorted (contact * 27 + offset) per CSR entry
-    double *s_v, *s_vstar, *s_dv, *s_m;
-    double* partial;
-    double* rigid_acc;
-    int n_rigid;
-    SubstepStats* stats;
-    int substep;
-    double h, eps_r, eps_a;
-    int max_iter, ls_rounds;
-    DevCounters* cnt;
-};
-
-__device__ __forceinline__ ContactParams params_of(const QnArgs& A, long long c) {
-    const DevEnv& E = A.envs[A.c_env[c]];
-    ContactParams P;
-    P.phi0 = A.c_phi0[c];
-    P.mun0 = A.c_mu[c] * A.c_n0[c];
-    P.k = E.k;
-    P.d = E.d;
-    P.eps_s = E.eps_s;
-    P.h = A.h;
-    return P;
+// Initial contact velocities v_c^0 = R_c^T sum w v*_i + b_c for contacts
+// [c0, c1) with stride.
+__device__ __forceinline__ void initial_contact_velocity(const QnArgs& A, long long c) {
+    const ContactStencil& st = A.c_st[c];
+    double sacc[3] = {0.0, 0.0, 0.0};
+    for (int o = 0; o < 27; ++o) {
+        const int sl = st.slot[o];
+        if (sl < 0) continue;
+        const double w = st.w[o];
+        const SlotRec& S = A.s_rec[sl];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sacc[a] += w * S.v[a];
+    }
+    const ContactRec& rec = A.c_rec[c];
+    double t1[3], t2[3];
+    frame_of(rec.n, t1, t2);
+    ContactDyn& D = A.c_dyn[c];
+    D.vc[0][0] = t1[0] * sacc[0] + t1[1] * sacc[1] + t1[2] * sacc[2] + rec.b[0];
+    D.vc[0][1] = t2[0] * sacc[0] + t2[1] * sacc[1] + t2[2] * sacc[2] + rec.b[1];
+    D.vc[0][2] = rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2] + rec.b[2];
 }
 
-// Contact velocity at iteration k: v_c^0 from the initial gather, then
-// v_c^k = v_c^{k-1} + alpha_{k-1} u_c^{k-1} (exact: v_c is linear in v).
-__device__ __forceinline__ void contact_velocity(const QnArgs& A, long long c, int k, double alpha_prev,
-                                                 double vc[3]) {
-    const double* src = A.c_vc + (size_t)((k == 0 ? 0 : (k - 1) & 1)) * 3 * A.cap;
+// g, H -> dv by 3x3 Cholesky, and this node's share of the iteration sums.
+__device__ __forceinline__ void node_solve(SlotRec& S, const double j[3], const double Hc[6],
+                                           double sums[kQnSums]) {
+    const double m = S.m;
+    const double H[6] = {m + Hc[0], Hc[1], Hc[2], m + Hc[3], Hc[4], m + Hc[5]};  // 00 01 02 11 12 22
+    double g[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) g[a] = m * (S.v[a] - S.vstar[a]) - j[a];
+    const double l00 = sqrt(H[0]);
+    const double l10 = H[1] / l00, l20 = H[2] / l00;
+    const double l11 = sqrt(H[3] - l10 * l10);
+    const double l21 = (H[4] - l20 * l10) / l11;
+    const double l22 = sqrt(H[5] - l20 * l20 - l21 * l21);
+    const double y0 = -g[0] / l00;
+    const double y1 = (-g[1] - l10 * y0) / l11;
+    const double y2 = (-g[2] - l20 * y0 - l21 * y1) / l22;
+    double dv[3];
+    dv[2] = y2 / l22;
+    dv[1] = (y1 - l21 * dv[2]) / l11;
+    dv[0] = (y0 - l10 * dv[1] - l20 * dv[2]) / l00;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        const double v0 = src[a * A.cap + c];
-        vc[a] = k == 0 ? v0 : fma(alpha_prev, A.c_uc[a * A.cap + c], v0);
+        S.dv[a] = dv[a];
+        sums[0] += g[a] * g[a] / m;                  // |grad~|^2
+        sums[1] += j[a] * j[a] / m;                  // |j~|^2
+        sums[2] += m * S.v[a] * S.v[a];              // contact-node part of |p~|^2
+        sums[3] += m * S.vstar[a] * S.vstar[a];      // same nodes at v*
+        sums[4] += m * dv[a] * dv[a];                // A
+        sums[5] += m * dv[a] * (S.v[a] - S.vstar[a]); // B
+        sums[6] += g[a] * dv[a];                     // phi'(0)
     }
 }
 
-__device__ __forceinline__ void ls_terms(const ContactParams& P, const double vc[3], const double u[3],
-                                         double alpha, double* d1, double* d2) {
-    double v[3] = {fma(alpha, u[0], vc[0]), fma(alpha, u[1], vc[1]), fma(alpha, u[2], vc[2])};
+// R gamma and the upper triangle of R G R^T of one contact at contact velocity vc.
+__device__ __forceinline__ void contact_terms(const ContactRec& rec, double h, const double vc[3],
+                                              double rg[3], double rgr[6]) {
     double g[3], g00, g01, g11, gnn;
-    contact_model(P, v, g, &g00, &g01, &g11, &gnn);
-    *d1 = -(g[0] * u[0] + g[1] * u[1] + g[2] * u[2]);
-    *d2 = g00 * u[0] * u[0] + 2.0 * g01 * u[0] * u[1] + g11 * u[1] * u[1] + gnn * u[2] * u[2];
+    contact_model(params_of(rec, h), vc, g, &g00, &g01, &g11, &gnn);
+    double t1[3], t2[3];
+    frame_of(rec.n, t1, t2);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) rg[a] = t1[a] * g[0] + t2[a] * g[1] + rec.n[a] * g[2];
+    int q = 0;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int cc = r; cc < 3; ++cc)
+            rgr[q++] = g00 * t1[r] * t1[cc] + g01 * (t1[r] * t2[cc] + t2[r] * t1[cc]) + g11 * t2[r] * t2[cc] +
+                       gnn * rec.n[r] * rec.n[cc];
 }
+
+// u_c = R_c^T sum_o w_o dv_slot(o)
+__device__ __forceinline__ void contact_direction(const QnArgs& A, long long c, double u[3]) {
+    const ContactStencil& st = A.c_st[c];
+    double sacc[3] = {0.0, 0.0, 0.0};
+    for (int o = 0; o < 27; ++o) {
+        const int sl = st.slot[o];
+        if (sl < 0) continue;
+        const double w = st.w[o];
+        const SlotRec& S = A.s_rec[sl];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sacc[a] += w * S.dv[a];
+    }
+    const ContactRec& rec = A.c_rec[c];
+    double t1[3], t2[3];
+    frame_of(rec.n, t1, t2);
+    u[0] = t1[0] * sacc[0] + t1[1] * sacc[1] + t1[2] * sacc[2];
+    u[1] = t2[0] * sacc[0] + t2[1] * sacc[1] + t2[2] * sacc[2];
+    u[2] = rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2];
+}
+
+// Impulse on the rigid bodies at the final iterate (minus the impulse on MPM),
+// reduced per body in LDS (racc: 6 doubles per body, zeroed by the caller).
+__device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, int k, double alpha_prev,
+                                                double* racc) {
+    ContactDyn& D = A.c_dyn[c];
+    double vc[3];
+    contact_velocity(D, k, alpha_prev, vc);
+    const ContactRec& rec = A.c_rec[c];
+    double g[3], g00, g01, g11, gnn;
+    contact_model(params_of(rec, A.h), vc, g, &g00, &g01, &g11, &gnn);
+    double t1[3], t2[3];
+    frame_of(rec.n, t1, t2);
+    double rg[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        rg[a] = t1[a] * g[0] + t2[a] * g[1] + rec.n[a] * g[2];
+        D.gam[a] = g[a];
+    }
+    const int r = A.c_rid[c];
+    const long long p = A.c_pid[c];
+    const DevRigid& R = A.rigids[r];
+    const double arm[3] = {(double)A.x[p] - R.t[0], (double)A.x[A.P + p] - R.t[1],
+                           (double)A.x[2 * A.P + p] - R.t[2]};
+    const double tq[3] = {arm[1] * rg[2] - arm[2] * rg[1], arm[2] * rg[0] - arm[0] * rg[2],
+                          arm[0] * rg[1] - arm[1] * rg[0]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        atomicAdd(&racc[r * 6 + a], -rg[a]);
+        atomicAdd(&racc[r * 6 + 3 + a], -tq[a]);
+    }
+}
+
+// Safeguarded 1-D Newton with bisection fallback on phi'(alpha): bracket
+// [lo, hi] with phi'(lo) < 0 <= phi'(hi) found by doubling from the previous
+// step length, Newton from hi, bisection when the iterate leaves the bracket
+// or |phi'| does not halve. EVAL(alpha, &phi'') returns phi'(alpha); it must be
+// called uniformly by the whole block.
+template <typename Eval>
+__device__ double exact_line_search(Eval eval, double alpha0, double d0, int max_steps, int* n_eval) {
+    double lo = 0.0, hi = alpha0, dd;
+    double dh = eval(hi, &dd);
+    ++*n_eval;
+    for (int n = 0; dh < 0.0 && n < 80; ++n) {
+        lo = hi;
+        hi *= 2.0;
+        dh = eval(hi, &dd);
+        ++*n_eval;
+    }
+    double alpha = hi;
+    if (!(dh < 0.0)) {
+        double da = dh, dda = dd, prev = 1e300;
+        for (int it = 0; it < max_steps; ++it) {
+            if (fabs(da) <= 1e-10 * fabs(d0)) break;
+            if (da < 0.0) lo = alpha; else hi = alpha;
+            if (hi - lo <= 1e-12 * hi) break;
+            double an = alpha - da / dda;
+            if (!(an > lo && an < hi) || fabs(da) > 0.5 * prev) an = 0.5 * (lo + hi);
+            prev = fabs(da);
+            alpha = an;
+            da = eval(alpha, &dda);
+            ++*n_eval;
+        }
+    }
+    return alpha;
+}
+
+__device__ __forceinline__ void write_stats(const QnArgs& A, long long nc, long long ns, int k, int converged,
+                                            int ls_total, double res, double thr, const unsigned long long tph[5],
+                                            bool aborted, int kind) {
+    SubstepStats st;
+    st.n_contacts = (int)nc;
+    st.n_slots = (int)ns;
+    st.iterations = k;
+    st.converged = converged;
+    st.ls_rounds = ls_total;
+    st.pad = kind;
+    st.residual = res;
+    st.threshold = thr;
+    for (int q = 0; q < 5; ++q) st.t_phase[q] = tph[q];
+    A.stats[A.substep] = st;
+    if (!converged && !aborted) atomicOr(&A.cnt->flags, kFlagNoconv);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-block solver: persistent cooperative kernel, two grid barriers per
+// iteration (see the file header). Takes problems of more than
+// kBlkMaxContacts contacts.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool grid_sync(DevCounters* cnt, unsigned nblocks, unsigned* gen,
+                                          unsigned* s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned target = *gen + 1u;
+        bool ok = true;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        const unsigned arrived =
+            __hip_atomic_fetch_add(&cnt->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == nblocks - 1u) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
+            __hip_atomic_store(&cnt->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&cnt->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+            const long long t0 = clock64();
+            unsigned polls = 0;
+            while (__hip_atomic_load(&cnt->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+                __builtin_amdgcn_s_sleep(1);
+                if ((++polls & 255u) == 0u &&
+                    ((__hip_atomic_load(&cnt->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagHang) ||
+                     clock64() - t0 > kBarrierTimeoutCycles)) {
+                    atomicOr(&cnt->flags, kFlagHang);
+                    ok = false;
+                    break;
+                }
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_ok = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    *gen += 1u;
+    return *s_ok != 0u;
+}
+
+constexpr int kLsCache = 1024;  // contacts whose line-search data are staged in LDS
+
+struct LsCache {
+    double vc[3][kLsCache];
+    double u[3][kLsCache];
+    double phi0[kLsCache], mun0[kLsCache];
+};
 
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
     __shared__ double lds[16 * 8];
-    __shared__ double tot[kPartStride];
-    __shared__ double ls_acc[kQnThreads / kLsPoints][kLsPoints][2];
-    __shared__ double alphas[kLsPoints];
+    __shared__ double tot[kQnSums];
+    __shared__ double bcast[8];
     __shared__ double racc[kMaxRigid * 6];
     __shared__ unsigned s_ok;
-    __shared__ int s_done;
-    __shared__ double s_alpha;
+    __shared__ LsCache ls_cache;
+    __shared__ double nacc[9][kSlotChunk];     // j (3) and R G R^T (6) of a chunk of owned slots
 
     DevCounters* cnt = A.cnt;
-    const unsigned G = gridDim.x;
-    unsigned gen = __hip_atomic_load(&cnt->bar_gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
     const bool aborted = cnt->abort_step != 0u;
-    const long long nc = aborted ? 0 : std::min<long long>(cnt->n_contacts, A.cap);
-    const long long ns = aborted ? 0 : cnt->n_slots;
-    const int tid = threadIdx.x;
-    // block-contiguous ownership
+    if (aborted || cnt->n_contacts <= (unsigned)kBlkMaxContacts) return;  // k_qn_block's case
+    const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
+    unsigned long long tph[5] = {0, 0, 0, 0, 0};
+    unsigned long long tmark = 0;
+    const unsigned G = gridDim.x;
+    unsigned gen = __hip_atomic_load(&cnt->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long nc = std::min<long long>(cnt->n_contacts, A.cap);
+    const long long ns = cnt->n_slots;
+    const int tid = threadIdx.x, T = blockDim.x;
     const long long sper = (ns + G - 1) / G, cper = (nc + G - 1) / G;
     const long long s0 = std::min<long long>(ns, sper * blockIdx.x), s1 = std::min<long long>(ns, s0 + sper);
     const long long c0 = std::min<long long>(nc, cper * blockIdx.x), c1 = std::min<long long>(nc, c0 + cper);
     const double pnorm_all = cnt->pnorm_all;
 
-    // initial contact velocities v_c^0 = R_c^T sum w v*_i + b_c
-    for (long long c = c0 + tid; c < c1; c += blockDim.x) {
-        double sacc[3] = {0.0, 0.0, 0.0};
-        for (int o = 0; o < 27; ++o) {
-            const int sl = A.c_slot[o * A.cap + c];
-            if (sl < 0) continue;
-            const double w = stencil_weight(A.c_w, A.cap, c, o);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) sacc[a] += w * A.s_v[a * A.cap_s + sl];
-        }
-        const double n[3] = {A.c_n[c], A.c_n[A.cap + c], A.c_n[2 * A.cap + c]};
-        double t1[3], t2[3];
-        frame_of(n, t1, t2);
-        A.c_vc[0 * A.cap + c] = t1[0] * sacc[0] + t1[1] * sacc[1] + t1[2] * sacc[2] + A.c_b[c];
-        A.c_vc[1 * A.cap + c] = t2[0] * sacc[0] + t2[1] * sacc[1] + t2[2] * sacc[2] + A.c_b[A.cap + c];
-        A.c_vc[2 * A.cap + c] = n[0] * sacc[0] + n[1] * sacc[1] + n[2] * sacc[2] + A.c_b[2 * A.cap + c];
-    }
+    for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
 
-    int k = 0;
-    double alpha_prev = 1.0;   // alpha_{k-1}; also the centre of the first line-search round
-    double res = 0.0, thr = 0.0;
-    int converged = 0;
+    int k = 0, ls_total = 0, converged = 0;
+    double alpha_prev = 1.0, res = 0.0, thr = 0.0;
     bool ok = grid_sync(cnt, G, &gen, &s_ok);
-    if (nc == 0) converged = 1;
-    while (ok && nc > 0) {
-        // ---- node pass -----------------------------------------------------
+    while (ok) {
+        if (timer) tmark = wall_clock64();
+        // ---- node pass: CSR entries spread over the threads, FP64 LDS sums ----
         double sums[kQnSums];
 #pragma unroll
         for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
-        for (long long s = s0 + tid; s < s1; s += blockDim.x) {
-            const double m = A.s_m[s];
-            double v[3], vs[3];
+        for (long long sa = s0; sa < s1; sa += kSlotChunk) {
+            const long long sb = std::min<long long>(s1, sa + kSlotChunk);
+            for (int q = tid; q < 9 * kSlotChunk; q += T) (&nacc[0][0])[q] = 0.0;
+            __syncthreads();
+            const int E0 = A.s_beg[sa], E1 = A.s_beg[sb];
+            for (int e = E0 + tid; e < E1; e += T) {
+                const Entry en = A.e_ent[e];
+                const int ls = en.slot - (int)sa;
+                const double w = en.w;
+                double vc[3], rg[3], rgr[6];
+                contact_velocity(A.c_dyn[en.c], k, alpha_prev, vc);
+                contact_terms(A.c_rec[en.c], A.h, vc, rg, rgr);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                v[a] = A.s_v[a * A.cap_s + s];
-                vs[a] = A.s_vstar[a * A.cap_s + s];
+                for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * rg[a]);
+#pragma unroll
+                for (int q = 0; q < 6; ++q) atomicAdd(&nacc[3 + q][ls], w * w * rgr[q]);
             }
-            double j[3] = {0.0, 0.0, 0.0};
-            double H[6] = {m, 0.0, 0.0, m, 0.0, m};  // 00 01 02 11 12 22
-            const int e0 = A.s_beg[s], e1 = A.s_beg[s + 1];
-            for (int e = e0; e < e1; ++e) {
-                const unsigned pv = A.pv[e];
-                const long long c = pv / 27;
-                const int o = (int)(pv % 27);
-                const double w = stencil_weight(A.c_w, A.cap, c, o);
-                double vc[3];
-                contact_velocity(A, c, k, alpha_prev, vc);
-                const ContactParams P = params_of(A, c);
-                double g[3], g00, g01, g11, gnn;
-                contact_model(P, vc, g, &g00, &g01, &g11, &gnn);
-                const double n[3] = {A.c_n[c], A.c_n[A.cap + c], A.c_n[2 * A.cap + c]};
-                double t1[3], t2[3];
-                frame_of(n, t1, t2);
-                // R gamma and R G R^T with R = [t1 t2 n]
-#pragma unroll
-                for (int a = 0; a < 3; ++a) j[a] += w * (t1[a] * g[0] + t2[a] * g[1] + n[a] * g[2]);
-                const double ww = w * w;
-                int q = 0;
-#pragma unroll
-                for (int r = 0; r < 3; ++r)
-#pragma unroll
-                    for (int cc = r; cc < 3; ++cc) {
-                        const double val = g00 * t1[r] * t1[cc] + g01 * (t1[r] * t2[cc] + t2[r] * t1[cc]) +
-                                           g11 * t2[r] * t2[cc] + gnn * n[r] * n[cc];
-                        H[q++] += ww * val;
-                    }
+            __syncthreads();
+            for (long long s = sa + tid; s < sb; s += T) {
+                const int ls = (int)(s - sa);
+                const double j[3] = {nacc[0][ls], nacc[1][ls], nacc[2][ls]};
+                const double Hc[6] = {nacc[3][ls], nacc[4][ls], nacc[5][ls], nacc[6][ls], nacc[7][ls], nacc[8][ls]};
+                node_solve(A.s_rec[s], j, Hc, sums);
             }
-            double g[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) g[a] = m * (v[a] - vs[a]) - j[a];
-            // dv = -H^-1 g by Cholesky
-            const double l00 = sqrt(H[0]);
-            const double l10 = H[1] / l00, l20 = H[2] / l00;
-            const double l11 = sqrt(H[3] - l10 * l10);
-            const double l21 = (H[4] - l20 * l10) / l11;
-            const double l22 = sqrt(H[5] - l20 * l20 - l21 * l21);
-            const double y0 = -g[0] / l00;
-            const double y1 = (-g[1] - l10 * y0) / l11;
-            const double y2 = (-g[2] - l20 * y0 - l21 * y1) / l22;
-            double dv[3];
-            dv[2] = y2 / l22;
-            dv[1] = (y1 - l21 * dv[2]) / l11;
-            dv[0] = (y0 - l10 * dv[1] - l20 * dv[2]) / l00;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                A.s_dv[a * A.cap_s + s] = dv[a];
-                sums[0] += g[a] * g[a] / m;            // |grad~|^2
-                sums[1] += j[a] * j[a] / m;            // |j~|^2
-                sums[2] += m * v[a] * v[a];            // contact-node part of |p~|^2
-                sums[3] += m * vs[a] * vs[a];          // same nodes at v*
-                sums[4] += m * dv[a] * dv[a];          // A
-                sums[5] += m * dv[a] * (v[a] - vs[a]); // B
-                sums[6] += g[a] * dv[a];               // phi'(0)
-            }
+            __syncthreads();
         }
-        block_sum<kQnSums>(sums, lds, A.partial + (size_t)blockIdx.x * kPartStride);
+        block_sum<kQnSums>(sums, lds, A.partial + (size_t)blockIdx.x * kQnSums);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
         ok = grid_sync(cnt, G, &gen, &s_ok);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
         if (!ok) break;
         if (tid < kQnSums) {
             double acc = 0.0;
-            for (unsigned b = 0; b < G; ++b) acc += A.partial[(size_t)b * kPartStride + tid];
+            for (unsigned b = 0; b < G; ++b) acc += A.partial[(size_t)b * kQnSums + tid];
             tot[tid] = acc;
         }
         __syncthreads();
-        const double grad2 = tot[0], j2 = tot[1];
         const double p2 = fmax(pnorm_all - tot[3] + tot[2], 0.0);
-        res = sqrt(grad2);
-        const double pn = sqrt(p2), jn = sqrt(j2);
-        thr = A.eps_a + A.eps_r * fmax(pn, jn);
+        res = sqrt(tot[0]);
+        thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(tot[1]));
         const double Aq = tot[4], Bq = tot[5], d0 = tot[6];
         if (res < thr) { converged = 1; break; }
         if (k >= A.max_iter || !(d0 < 0.0)) break;
-
-        // ---- contact pass: u_c = R_c^T sum w dv_i; store v_c^k ------------
-        for (long long c = c0 + tid; c < c1; c += blockDim.x) {
-            double vc[3];
-            contact_velocity(A, c, k, alpha_prev, vc);
+        // ---- contact pass: store v_c^k, u_c = R_c^T J dv ----------------------
+        for (long long c = c0 + tid; c < c1; c += T) {
+            ContactDyn& D = A.c_dyn[c];
             if (k > 0) {
+                double vc[3];
+                contact_velocity(D, k, alpha_prev, vc);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) A.c_vc[(size_t)(k & 1) * 3 * A.cap + a * A.cap + c] = vc[a];
+                for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
             }
-            double sacc[3] = {0.0, 0.0, 0.0};
-            for (int o = 0; o < 27; ++o) {
-                const int sl = A.c_slot[o * A.cap + c];
-                if (sl < 0) continue;
-                const double w = stencil_weight(A.c_w, A.cap, c, o);
+            double u[3];
+            contact_direction(A, c, u);
 #pragma unroll
-                for (int a = 0; a < 3; ++a) sacc[a] += w * A.s_dv[a * A.cap_s + sl];
-            }
-            const double n[3] = {A.c_n[c], A.c_n[A.cap + c], A.c_n[2 * A.cap + c]};
-            double t1[3], t2[3];
-            frame_of(n, t1, t2);
-            A.c_uc[0 * A.cap + c] = t1[0] * sacc[0] + t1[1] * sacc[1] + t1[2] * sacc[2];
-            A.c_uc[1 * A.cap + c] = t2[0] * sacc[0] + t2[1] * sacc[1] + t2[2] * sacc[2];
-            A.c_uc[2 * A.cap + c] = n[0] * sacc[0] + n[1] * sacc[1] + n[2] * sacc[2];
+            for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
         }
-        __syncthreads();  // this block's u_c are read by its own threads below
-
-        // ---- exact line search by rounds of kLsPoints evaluations ----------
-        // bracket [lo, hi] with phi'(lo) < 0 <= phi'(hi); lo starts at 0.
-        double lo = 0.0, dlo = d0, hi = 0.0, dhi = 0.0, ddhi = 0.0, ddlo = -1.0;
-        bool have_hi = false;
-        double alpha = alpha_prev;
-        double centre = alpha_prev;
-        double best = 0.0, dbest = d0, newton_step = 0.0;
-        for (int round = 0; round < A.ls_rounds; ++round) {
-            if (tid == 0) {
-                for (int jj = 0; jj < kLsPoints; ++jj) {
-                    double a;
-                    if (!have_hi) {
-                        // geometric sweep around the centre (first round: the last step length)
-                        a = centre * exp2((double)(jj - kLsPoints / 2) / 4.0);
-                    } else {
-                        // a cluster of half-width r/2 at the safeguarded Newton
-                        // estimate, r = length of the Newton correction
-                        const double wdt = hi - lo;
-                        double r = fabs(newton_step);
-                        if (!(r > 0.0) || r > wdt) r = wdt;
-                        a = centre + 0.5 * r * ((double)jj - 0.5 * (kLsPoints - 1)) / (0.5 * (kLsPoints - 1));
-                        const double eps = 1e-3 * wdt / kLsPoints;
-                        a = fmin(fmax(a, lo + eps), hi - eps);
-                    }
-                    alphas[jj] = a;
-                }
-            }
-            __syncthreads();
-            // partial phi', phi'' of this block's contacts at every point
-            {
-                const int jj = tid % kLsPoints, lane_c = tid / kLsPoints;
-                const double a = alphas[jj];
-                double d1s = 0.0, d2s = 0.0;
-                for (long long c = c0 + lane_c; c < c1; c += kQnThreads / kLsPoints) {
-                    double vc[3];
-                    const double* src = A.c_vc + (size_t)(k == 0 ? 0 : (k & 1)) * 3 * A.cap;
-#pragma unroll
-                    for (int q = 0; q < 3; ++q) vc[q] = src[q * A.cap + c];
-                    const double u[3] = {A.c_uc[c], A.c_uc[A.cap + c], A.c_uc[2 * A.cap + c]};
-                    double d1, d2;
-                    ls_terms(params_of(A, c), vc, u, a, &d1, &d2);
-                    d1s += d1;
-                    d2s += d2;
-                }
-                ls_acc[lane_c][jj][0] = d1s;
-                ls_acc[lane_c][jj][1] = d2s;
-            }
-            __syncthreads();
-            double* part = A.partial + (size_t)blockIdx.x * kPartStride + kQnSums + (round & 1) * 2 * kLsPoints;
-            if (tid < 2 * kLsPoints) {
-                const int jj = tid >> 1, q = tid & 1;
-                double s = 0.0;
-                for (int l = 0; l < kQnThreads / kLsPoints; ++l) s += ls_acc[l][jj][q];
-                part[tid] = s;
-            }
-            ok = grid_sync(cnt, G, &gen, &s_ok);
-            if (!ok) break;
-            if (tid < 2 * kLsPoints) {
-                double s = 0.0;
-                for (unsigned b = 0; b < G; ++b)
-                    s += A.partial[(size_t)b * kPartStride + kQnSums + (round & 1) * 2 * kLsPoints + tid];
-                tot[kQnSums + tid] = s;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                int done = 0;
-                for (int jj = 0; jj < kLsPoints; ++jj) {
-                    const double a = alphas[jj];
-                    const double d1 = Aq * a + Bq + tot[kQnSums + 2 * jj];
-                    const double d2 = Aq + tot[kQnSums + 2 * jj + 1];
-                    if (fabs(d1) < fabs(dbest)) { best = a; dbest = d1; }
-                    if (d1 < 0.0) {
-                        if (a > lo) { lo = a; dlo = d1; ddlo = d2; }
-                    } else if (!have_hi || a < hi) {
-                        hi = a; dhi = d1; ddhi = d2; have_hi = true;
-                    }
-                }
-                if (have_hi && lo >= hi) { lo = 0.0; dlo = d0; ddlo = -1.0; }  // cannot happen for convex phi
-                if (fabs(dbest) <= 1e-10 * fabs(d0) || (have_hi && hi - lo <= 1e-12 * hi)) done = 1;
-                if (!have_hi) {
-                    centre = alphas[kLsPoints - 1] * 16.0;  // keep expanding
-                } else {
-                    // Newton from the better bracket end, safeguarded to (lo, hi)
-                    double est;
-                    if (fabs(dhi) < fabs(dlo) || ddlo < 0.0) { est = hi - dhi / ddhi; newton_step = dhi / ddhi; }
-                    else { est = lo - dlo / ddlo; newton_step = dlo / ddlo; }
-                    if (!(est > lo && est < hi)) { est = 0.5 * (lo + hi); newton_step = hi - lo; }
-                    centre = est;
-                }
-                alpha = (done || !have_hi) ? best : centre;
-                s_done = done;
-                s_alpha = alpha;
-            }
-            __syncthreads();
-            alpha = s_alpha;
-            if (s_done) break;
-        }
+        __syncthreads();
+        if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
+        ok = grid_sync(cnt, G, &gen, &s_ok);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
         if (!ok) break;
-        // ---- v <- v + alpha dv ---------------------------------------------
-        for (long long s = s0 + tid; s < s1; s += blockDim.x) {
+        // ---- exact line search, redundantly in every block ----------------------
+        const bool use_cache = nc <= kLsCache;
+        if (use_cache) {
+            for (long long c = tid; c < nc; c += T) {
+                const ContactDyn& D = A.c_dyn[c];
+                const ContactRec& R = A.c_rec[c];
+                const int src = k == 0 ? 0 : (k & 1);
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                A.s_v[a * A.cap_s + s] = fma(alpha, A.s_dv[a * A.cap_s + s], A.s_v[a * A.cap_s + s]);
+                for (int a = 0; a < 3; ++a) { ls_cache.vc[a][c] = D.vc[src][a]; ls_cache.u[a][c] = D.uc[a]; }
+                ls_cache.phi0[c] = R.phi0;
+                ls_cache.mun0[c] = R.mun0;
+            }
+            __syncthreads();
+        }
+        auto eval = [&](double alpha, double* d2out) -> double {
+            double acc2[2] = {0.0, 0.0};
+            for (long long c = tid; c < nc; c += T) {
+                double vc[3], u[3], d1, d2;
+                const ContactRec& R = A.c_rec[c];
+                ContactParams P = params_of(R, A.h);
+                if (use_cache) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) { vc[a] = ls_cache.vc[a][c]; u[a] = ls_cache.u[a][c]; }
+                } else {
+                    const ContactDyn& D = A.c_dyn[c];
+                    const int src = k == 0 ? 0 : (k & 1);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) { vc[a] = D.vc[src][a]; u[a] = D.uc[a]; }
+                }
+                ls_terms(P, vc, u, alpha, &d1, &d2);
+                acc2[0] += d1;
+                acc2[1] += d2;
+            }
+            block_sum<2>(acc2, lds, bcast);
+            *d2out = Aq + bcast[1];
+            return fma(Aq, alpha, Bq) + bcast[0];
+        };
+        const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
+        for (long long s = s0 + tid; s < s1; s += T) {
+            SlotRec& S = A.s_rec[s];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, S.dv[a], S.v[a]);
         }
         alpha_prev = alpha;
         ++k;
     }
-
-    // ---- outputs: grid velocity, impulses at the final iterate, stats ------
-    for (long long s = s0 + tid; s < s1; s += blockDim.x) {
+    // ---- outputs --------------------------------------------------------------
+    for (long long s = s0 + tid; s < s1; s += T) {
+        const SlotRec& S = A.s_rec[s];
         float4 g = A.vel[A.s_node[s]];
-        g.x = (float)A.s_v[s];
-        g.y = (float)A.s_v[A.cap_s + s];
-        g.z = (float)A.s_v[2 * A.cap_s + s];
+        g.x = (float)S.v[0]; g.y = (float)S.v[1]; g.z = (float)S.v[2];
         A.vel[A.s_node[s]] = g;
     }
-    for (int q = tid; q < A.n_rigid * 6; q += blockDim.x) racc[q] = 0.0;
+    for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
     __syncthreads();
-    for (long long c = c0 + tid; c < c1; c += blockDim.x) {
-        double vc[3];
-        contact_velocity(A, c, k, alpha_prev, vc);
-        double g[3], g00, g01, g11, gnn;
-        contact_model(params_of(A, c), vc, g, &g00, &g01, &g11, &gnn);
-        const double n[3] = {A.c_n[c], A.c_n[A.cap + c], A.c_n[2 * A.cap + c]};
-        double t1[3], t2[3];
-        frame_of(n, t1, t2);
-        double rg[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            rg[a] = t1[a] * g[0] + t2[a] * g[1] + n[a] * g[2];
-            A.c_gam[a * A.cap + c] = g[a];
-        }
-        const int r = A.c_rid[c];
-        const long long p = A.c_pid[c];
-        const DevRigid& R = A.rigids[r];
-        const double arm[3] = {(double)A.x[p] - R.t[0], (double)A.x[A.P + p] - R.t[1],
-                               (double)A.x[2 * A.P + p] - R.t[2]};
-        const double tq[3] = {arm[1] * rg[2] - arm[2] * rg[1], arm[2] * rg[0] - arm[0] * rg[2],
-                              arm[0] * rg[1] - arm[1] * rg[0]};
-        // impulse on the rigid body is minus the impulse on MPM
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            atomicAdd(&racc[r * 6 + a], -rg[a]);
-            atomicAdd(&racc[r * 6 + 3 + a], -tq[a]);
-        }
-    }
+    for (long long c = c0 + tid; c < c1; c += T) contact_impulse(A, c, k, alpha_prev, racc);
     __syncthreads();
-    for (int q = tid; q < A.n_rigid * 6; q += blockDim.x)
+    for (int q = tid; q < A.n_rigid * 6; q += T)
         if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
-    if (blockIdx.x == 0 && tid == 0) {
-        SubstepStats st;
-        st.n_contacts = (int)nc;
-        st.n_slots = (int)ns;
-        st.iterations = k;
-        st.converged = converged;
-        st.residual = res;
-        st.threshold = thr;
-        A.stats[A.substep] = st;
-        if (!converged && !aborted) atomicOr(&cnt->flags, kFlagNoconv);
+    if (blockIdx.x == 0 && tid == 0) write_stats(A, nc, ns, k, converged, ls_total, res, thr, tph, false, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Algorithm 1 in one workgroup (problems of up to kBlkMaxContacts contacts).
+// Without grid barriers the per-contact work is done once per iteration: the
+// contact pass evaluates each contact's model at v_c^k and stages R gamma and
+// R G R^T in LDS, the node pass gathers them through the CSR, and the line
+// search reads its contact data from LDS. Workgroup barriers only.
+// ---------------------------------------------------------------------------
+struct BlkShared {
+    float gR[3][kBlkMaxContacts];   // R gamma (world frame)
+    float gH[6][kBlkMaxContacts];   // R G R^T (upper triangle)
+    float lv[3][kBlkMaxContacts];   // line search: v_c^k (contact frame)
+    float lu[3][kBlkMaxContacts];   //              u_c^k
+    float lp[2][kBlkMaxContacts];   //              phi0, mu n0
+};
+
+__global__ void __launch_bounds__(kBlkThreads)
+k_qn_block(QnArgs A) {
+    __shared__ BlkShared S;
+    __shared__ double lds[16 * 8];
+    __shared__ double tot[kQnSums];
+    __shared__ double bcast[8];
+    DevCounters* cnt = A.cnt;
+    const bool aborted = cnt->abort_step != 0u;
+    if (!aborted && cnt->n_contacts > (unsigned)kBlkMaxContacts) return;  // k_qn's case
+    const long long nc = aborted ? 0 : cnt->n_contacts;
+    const long long ns = aborted ? 0 : cnt->n_slots;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const double pnorm_all = cnt->pnorm_all;
+    unsigned long long tph[5] = {0, 0, 0, 0, 0}, tmark = 0;
+    const bool timer = tid == 0;
+
+    for (long long c = tid; c < nc; c += T) initial_contact_velocity(A, c);
+    __syncthreads();
+
+    int k = 0, ls_total = 0, converged = nc == 0 ? 1 : 0;
+    double alpha_prev = 1.0, res = 0.0, thr = 0.0;
+    while (nc > 0) {
+        if (timer) tmark = wall_clock64();
+        // ---- contact terms at v^k ---------------------------------------------
+        for (long long c = tid; c < nc; c += T) {
+            ContactDyn& D = A.c_dyn[c];
+            double vc[3], rg[3], rgr[6];
+            contact_velocity(D, k, alpha_prev, vc);
+            if (k > 0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
+            }
+            contact_terms(A.c_rec[c], A.h, vc, rg, rgr);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) S.gR[a][c] = (float)rg[a];
+#pragma unroll
+            for (int q = 0; q < 6; ++q) S.gH[q][c] = (float)rgr[q];
+        }
+        __syncthreads();
+        // ---- node pass ----------------------------------------------------------
+        double sums[kQnSums];
+#pragma unroll
+        for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
+        for (long long s = tid; s < ns; s += T) {
+            double j[3] = {0.0, 0.0, 0.0}, Hc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            const int e0 = A.s_beg[s], e1 = A.s_beg[s + 1];
+            for (int e = e0; e < e1; ++e) {
+                const Entry en = A.e_ent[e];
+                const double w = en.w, ww = w * w;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) j[a] += w * (double)S.gR[a][en.c];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) Hc[q] += ww * (double)S.gH[q][en.c];
+            }
+            node_solve(A.s_rec[s], j, Hc, sums);
+        }
+        block_sum<kQnSums>(sums, lds, tot);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
+        const double p2 = fmax(pnorm_all - tot[3] + tot[2], 0.0);
+        res = sqrt(tot[0]);
+        thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(tot[1]));
+        const double Aq = tot[4], Bq = tot[5], d0 = tot[6];
+        if (res < thr) { converged = 1; break; }
+        if (k >= A.max_iter || !(d0 < 0.0)) break;
+        // ---- u_c = R_c^T J dv; stage the line search ----------------------------
+        for (long long c = tid; c < nc; c += T) {
+            ContactDyn& D = A.c_dyn[c];
+            double u[3];
+            contact_direction(A, c, u);
+            const int src = k == 0 ? 0 : (k & 1);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                D.uc[a] = u[a];
+                S.lu[a][c] = (float)u[a];
+                S.lv[a][c] = (float)D.vc[src][a];
+            }
+            const ContactRec& rec = A.c_rec[c];
+            S.lp[0][c] = (float)rec.phi0;
+            S.lp[1][c] = (float)rec.mun0;
+        }
+        __syncthreads();
+        if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
+        // ---- exact line search ----------------------------------------------------
+        auto eval = [&](double alpha, double* d2out) -> double {
+            double acc2[2] = {0.0, 0.0};
+            for (long long c = tid; c < nc; c += T) {
+                const double vc[3] = {S.lv[0][c], S.lv[1][c], S.lv[2][c]};
+                const double u[3] = {S.lu[0][c], S.lu[1][c], S.lu[2][c]};
+                const ContactRec& R = A.c_rec[c];
+                ContactParams P = params_of(R, A.h);
+                P.phi0 = S.lp[0][c];
+                P.mun0 = S.lp[1][c];
+                double d1, d2;
+                ls_terms(P, vc, u, alpha, &d1, &d2);
+                acc2[0] += d1;
+                acc2[1] += d2;
+            }
+            block_sum<2>(acc2, lds, bcast);
+            *d2out = Aq + bcast[1];
+            return fma(Aq, alpha, Bq) + bcast[0];
+        };
+        const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
+        for (long long s = tid; s < ns; s += T) {
+            SlotRec& R = A.s_rec[s];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) R.v[a] = fma(alpha, R.dv[a], R.v[a]);
+        }
+        __syncthreads();
+        alpha_prev = alpha;
+        ++k;
     }
+    // ---- outputs ----------------------------------------------------------------
+    for (long long s = tid; s < ns; s += T) {
+        const SlotRec& R = A.s_rec[s];
+        float4 g = A.vel[A.s_node[s]];
+        g.x = (float)R.v[0]; g.y = (float)R.v[1]; g.z = (float)R.v[2];
+        A.vel[A.s_node[s]] = g;
+    }
+    double* racc = reinterpret_cast<double*>(&S.gH[0][0]);  // reuse: 6 doubles per rigid body
+    __syncthreads();
+    for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
+    __syncthreads();
+    for (long long c = tid; c < nc; c += T) contact_impulse(A, c, k, alpha_prev, racc);
+    __syncthreads();
+    for (int q = tid; q < A.n_rigid * 6; q += T)
+        if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
+    if (tid == 0) write_stats(A, nc, ns, k, converged, ls_total, res, thr, tph, aborted, 1);
 }
 
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
-                       double eps_a, int max_iter, int ls_rounds, hipStream_t s) {
+                     double eps_a, int max_iter, int ls_max_steps, int blocks, hipStream_t s) {
     QnArgs A;
-    A.envs = w.envs;
     A.rigids = w.rigids;
     A.x = x;
     A.P = w.P;
     A.vel = w.vel;
     A.cap = w.cap_c;
-    A.cap_s = w.cap_s;
-    A.c_pid = w.c_pid; A.c_rid = w.c_rid; A.c_env = w.c_env; A.c_slot = w.c_slot;
-    A.c_w = w.c_w;
-    A.c_n = w.c_n; A.c_b = w.c_b; A.c_phi0 = w.c_phi0; A.c_n0 = w.c_n0; A.c_mu = w.c_mu;
-    A.c_vc = w.c_vc; A.c_uc = w.c_uc; A.c_gam = w.c_gam;
+    A.c_pid = w.c_pid; A.c_rid = w.c_rid;
+    A.c_rec = w.c_rec; A.c_st = w.c_st; A.c_dyn = w.c_dyn;
     A.s_node = w.s_node; A.s_beg = w.s_beg;
-    A.pv = w.pv_a;
-    A.s_v = w.s_v; A.s_vstar = w.s_vstar; A.s_dv = w.s_dv; A.s_m = w.s_m;
+    A.e_ent = w.e_ent;
+    A.s_rec = w.s_rec;
     A.partial = w.partial;
     A.rigid_acc = w.rigid_acc;
     A.n_rigid = w.n_rigid;
     A.stats = w.sstats;
     A.substep = substep;
     A.h = h; A.eps_r = eps_r; A.eps_a = eps_a;
-    A.max_iter = max_iter; A.ls_rounds = ls_rounds;
+    A.max_iter = max_iter; A.ls_max_steps = ls_max_steps;
     A.cnt = w.cnt;
+    // each kernel checks the contact count on the device and leaves the other's case
+    hipLaunchKernelGGL(k_qn_block, dim3(1), dim3(kBlkThreads), 0, s, A);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     void* args[] = {&A};
-    return hipLaunchCooperativeKernel((const void*)k_qn, dim3(w.qn_blocks), dim3(kQnThreads), args, 0, s);
+    return hipLaunchCooperativeKernel((const void*)k_qn, dim3(blocks), dim3(kQnThreads), args, 0, s);
 }
 
 int qn_max_blocks() {

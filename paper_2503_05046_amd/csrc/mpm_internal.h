@@ -11,7 +11,6 @@ namespace mpm {
 constexpr int kTile = 4;              // cells per tile edge (4x4x4 = 64 cells)
 constexpr int kBlockNodes = 8;        // LDS node block edge: tile + 2 stencil + 1 drift each side
 constexpr int kMaxRigidPerEnv = 32;   // contact mask width
-constexpr int kLsPoints = 32;         // line-search evaluation points per round
 constexpr int kQnSums = 8;            // per-iteration scalar sums of the node pass
 constexpr int kSortBlocks = 512;      // blocks of the chunked scan / radix passes
 constexpr int kSortThreads = 256;
@@ -50,8 +49,46 @@ struct SubstepStats {
     int n_slots;
     int iterations;
     int converged;
+    int ls_rounds;
+    int pad;
     double residual;
     double threshold;
+    unsigned long long t_phase[5];  // solver wall-clock ticks: node pass, barrier, contact pass, barrier, line search
+};
+
+// Contact solver data as compact records, so that a gather of one contact or
+// one contact node touches one or two cache lines.
+struct alignas(128) ContactRec {
+    double n[3];     // world normal (third axis of the contact frame)
+    double phi0;     // penetration at substep start
+    double mun0;     // mu times the lagged normal impulse
+    double k, d, eps_s;
+    double b[3];     // bias velocity -R_c^T v_rigid(x_p)
+};
+
+struct alignas(16) ContactStencil {
+    int slot[27];    // contact-node slot of each stencil node, -1 for a zero weight
+    float w[27];     // stencil weights
+};
+
+struct alignas(16) ContactDyn {
+    double vc[2][3];  // contact velocity, double-buffered by iteration parity
+    double uc[3];     // R_c^T J dv of the current iteration
+    double gam[3];    // impulse on MPM at exit (contact frame)
+};
+
+struct alignas(16) SlotRec {
+    double m;
+    double v[3];      // iterate
+    double vstar[3];  // free-motion velocity
+    double dv[3];     // search direction
+};
+
+struct Entry {
+    unsigned c;      // contact
+    int slot;        // contact node
+    float w;         // stencil weight
+    float pad;
 };
 
 // Device scalars that live in the workspace.
@@ -66,7 +103,8 @@ struct DevCounters {
     unsigned bar_count;      // grid barrier arrival counter
     unsigned bar_gen;        // grid barrier generation
     unsigned abort_substep;  // substep at which the step stopped
-    unsigned pad[6];
+    unsigned n_ntiles;       // node tiles adjacent to a particle tile (this host step)
+    unsigned pad[5];
     double pnorm_all;        // sum m |v*|^2 over active nodes (FP64)
 };
 
@@ -83,26 +121,29 @@ struct Work {
     unsigned* active_tiles;  // [T_all]
     unsigned* ptile_id;      // [T_all] particle tiles (global tile id)
     unsigned* ptile_beg;     // [T_all + 1]
+    int* ptile_of;           // [T_all] particle-tile index of a tile, -1 if it holds no particles
+    unsigned* ntile_list;    // [T_all] node tiles within one tile of a particle tile
+    unsigned* ntile_mark;    // [T_all] 1 for tiles in ntile_list
+    float4* blkbuf;          // [T_all][512] per-tile P2G node blocks (m, p)
+    const unsigned* keys_sorted;  // sorted cell keys of the current host step
     // grid (dense, all envs)
     float4* acc;             // (m, px, py, pz)
     float4* vel;             // (vx, vy, vz, m)
     // contacts (capacity cap_c)
     int *c_pid, *c_rid, *c_env, *c_base;
-    float* c_w;              // [9][cap] per-axis weights
-    double *c_n, *c_b;       // [3][cap]
-    double *c_phi0, *c_n0, *c_mu;
-    double* c_vc;            // [2][3][cap] contact velocity, double-buffered by iteration parity
-    double* c_uc;            // [3][cap]
-    double* c_gam;           // [3][cap] impulse on MPM at exit (contact frame)
-    int* c_slot;             // [27][cap]
+    float* c_w;              // [9][cap] per-axis stencil weights (pair generation)
+    ContactRec* c_rec;       // [cap] per-substep contact data
+    ContactStencil* c_st;    // [cap] slots and weights of the 27 stencil nodes
+    ContactDyn* c_dyn;       // [cap] solver state
     // contact-node pairs (capacity 27 cap_c)
     unsigned *pk_a, *pk_b, *pv_a, *pv_b;
+    Entry* e_ent;            // [27 cap] (contact, slot, weight) in slot order
     // contact-node slots (capacity cap_s)
     int *s_node, *s_beg;     // s_beg has cap_s + 1 entries
-    double *s_v, *s_vstar, *s_dv, *s_m;  // [3][cap_s] (s_m: [cap_s])
+    SlotRec* s_rec;          // [cap_s]
     // scratch
     unsigned* blk;           // [kSortBlocks * 256 + 2 * kSortBlocks] histograms / block sums
-    double* partial;         // [qn_blocks][kQnSums + 2 * kLsPoints + 8]
+    double* partial;         // [qn_blocks][kQnSums]
     double* rigid_acc;       // [n_rigid][6] FP64 impulse accumulators
     SubstepStats* sstats;    // [N]
     DevCounters* cnt;
@@ -129,13 +170,14 @@ hipError_t launch_permute(const Work& w, const unsigned* idx, const float* x, co
 hipError_t launch_recover_C(const Work& w, const float* F, float* C, double h, hipStream_t s);
 hipError_t launch_scan_blocks(unsigned* data, int n_items, unsigned* total, hipStream_t s);
 hipError_t launch_tile_list(const Work& w, const unsigned* sorted_keys, hipStream_t s);
+hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old);
 hipError_t launch_p2g(const Work& w, const float* x, const float* v, hipStream_t s);
 hipError_t launch_grid_update(const Work& w, double h, hipStream_t s);
 hipError_t launch_registration(const Work& w, const float* x, const float* v, double h,
                                int substep, hipStream_t s);
 hipError_t launch_contact_setup(const Work& w, hipStream_t s);
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
-                     double eps_a, int max_iter, int ls_rounds, hipStream_t s);
+                     double eps_a, int max_iter, int ls_max_steps, int blocks, hipStream_t s);
 int qn_max_blocks();
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
                       float* v_out, float* F_out, float* C_out, const int* pid_in,

@@ -211,37 +211,112 @@ __device__ __forceinline__ void tile_coords(const DevEnv& E, unsigned gt, int* t
 }
 
 // ---------------------------------------------------------------------------
+// Tile maps, once per host step: the particle-tile index of every tile and
+// the node tiles within one tile of a particle tile (the only node tiles a
+// particle's stencil can reach unless it drifts more than a cell).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_tile_maps_clear(const unsigned* __restrict__ ptile_id, const unsigned* __restrict__ ntile_list,
+                  int* __restrict__ ptile_of, unsigned* __restrict__ ntile_mark, const DevCounters* cnt) {
+    const unsigned np = cnt->n_ptiles, nn = cnt->n_ntiles;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < np || i < nn; i += gridDim.x * blockDim.x) {
+        if (i < np) ptile_of[ptile_id[i]] = -1;
+        if (i < nn) ntile_mark[ntile_list[i]] = 0u;
+    }
+}
+
+__global__ void k_reset_ntiles(DevCounters* cnt) { cnt->n_ntiles = 0u; }
+
+__global__ void __launch_bounds__(256)
+k_tile_maps_build(const unsigned* __restrict__ ptile_id, const DevEnv* __restrict__ envs, int n_envs,
+                  int* __restrict__ ptile_of, unsigned* __restrict__ ntile_list,
+                  unsigned* __restrict__ ntile_mark, DevCounters* cnt) {
+    const unsigned np = cnt->n_ptiles;
+    for (unsigned q = blockIdx.x * blockDim.x + threadIdx.x; q < 27u * np; q += gridDim.x * blockDim.x) {
+        const unsigned t = q / 27u, o = q % 27u;
+        const unsigned gt = ptile_id[t];
+        if (o == 13u) ptile_of[gt] = (int)t;
+        const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
+        int tx, ty, tz;
+        tile_coords(E, gt, &tx, &ty, &tz);
+        const int nx = tx + (int)(o % 3u) - 1, ny = ty + (int)((o / 3u) % 3u) - 1, nz = tz + (int)(o / 9u) - 1;
+        if (nx < 0 || ny < 0 || nz < 0 || nx >= E.ntile[0] || ny >= E.ntile[1] || nz >= E.ntile[2]) continue;
+        const unsigned T = (unsigned)E.tile_base + (unsigned)nx + (unsigned)E.ntile[0] * ((unsigned)ny + (unsigned)E.ntile[1] * (unsigned)nz);
+        if (atomicCAS(&ntile_mark[T], 0u, 1u) == 0u) ntile_list[atomicAdd(&cnt->n_ntiles, 1u)] = T;
+    }
+}
+
+hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old) {
+    if (clear_old) {
+        hipLaunchKernelGGL(k_tile_maps_clear, dim3(512), dim3(256), 0, s, w.ptile_id, w.ntile_list,
+                           w.ptile_of, w.ntile_mark, (const DevCounters*)w.cnt);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_reset_ntiles, dim3(1), dim3(1), 0, s, w.cnt);
+    hipLaunchKernelGGL(k_tile_maps_build, dim3(1024), dim3(256), 0, s, w.ptile_id, w.envs, w.n_envs,
+                       w.ptile_of, w.ntile_list, w.ntile_mark, w.cnt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // P2G: m_i += w m_p, p_i += w (m_p v_p + Q_p (x_i - x_p))
+//
+// One block per particle tile, one thread per (cell of the tile, component):
+// thread q*64 + c sums component q (0: mass, 1-3: momentum) of every particle
+// sorted into cell c over the 27 stencil nodes in registers (the particles of
+// a cell share one stencil), then adds its 27 sums into the tile's 8x8x8 LDS
+// node block; the 64 lanes of a wave hold 64 different cells, so those LDS
+// atomics never collide within an instruction. A particle whose stencil base
+// has drifted from its sort-time cell adds to the LDS block directly, or, if it
+// left the block, to the global accumulator. The block is stored atomic-free to
+// the tile's slot of the block buffer; the grid update sums the 8 blocks that
+// overlap each node in a fixed order.
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ Q,
       long long P, const DevEnv* __restrict__ envs, int n_envs, const unsigned* __restrict__ ptile_id,
-      const unsigned* __restrict__ ptile_beg, float4* __restrict__ acc,
-      unsigned* __restrict__ tile_flag, unsigned* __restrict__ active, DevCounters* cnt) {
+      const unsigned* __restrict__ ptile_beg, const unsigned* __restrict__ keys,
+      float4* __restrict__ blkbuf, float4* __restrict__ acc, unsigned* __restrict__ tile_flag,
+      unsigned* __restrict__ active, DevCounters* cnt) {
     __shared__ float sm[4][kBN3];
-    __shared__ unsigned sflag[27];
+    __shared__ unsigned ccount[64], cstart[64];
     if (cnt->abort_step) return;
     const unsigned n_tiles = cnt->n_ptiles;
+    const int q = threadIdx.x >> 6, cell = threadIdx.x & 63;
+    const int cx = cell & 3, cy = (cell >> 2) & 3, cz = cell >> 4;
     for (unsigned t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         for (int n = threadIdx.x; n < kBN3; n += blockDim.x) {
             sm[0][n] = 0.f; sm[1][n] = 0.f; sm[2][n] = 0.f; sm[3][n] = 0.f;
         }
-        if (threadIdx.x < 27) sflag[threadIdx.x] = 0;
+        if (threadIdx.x < 64) ccount[threadIdx.x] = 0u;
         __syncthreads();
         const unsigned gt = ptile_id[t];
         const long long pb = ptile_beg[t], pe = ptile_beg[t + 1];
+        for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) atomicAdd(&ccount[keys[p] & 63u], 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned run = 0;
+            for (int c = 0; c < 64; ++c) {
+                cstart[c] = run;
+                run += ccount[c];
+            }
+        }
+        __syncthreads();
         const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
         int tx, ty, tz;
         tile_coords(E, gt, &tx, &ty, &tz);
         const int ox = tx * kTile - 1, oy = ty * kTile - 1, oz = tz * kTile - 1;
+        const int nbx = tx * kTile + cx, nby = ty * kTile + cy, nbz = tz * kTile + cz;  // this cell's base
         const float dx = E.dx, mp = E.m_p;
-        bool clamped = false;
-        for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) {
-            float xp[3] = {x[p], x[P + p], x[2 * P + p]};
-            float mv[3] = {mp * v[p], mp * v[P + p], mp * v[2 * P + p]};
-            float Qp[9];
+        float sum[27];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) Qp[k] = Q[k * P + p];
+        for (int o = 0; o < 27; ++o) sum[o] = 0.f;
+        const unsigned cnt_c = ccount[cell];
+        const long long p0 = pb + cstart[cell];
+        bool clamped = false;
+        for (unsigned kk = 0; kk < cnt_c; ++kk) {
+            const long long p = p0 + kk;
+            const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
             int b[3];
             float f[3];
             stencil_base(E, xp, b, f, &clamped);
@@ -249,6 +324,15 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
             bspline_w(f[0], wx);
             bspline_w(f[1], wy);
             bspline_w(f[2], wz);
+            // component q of the particle's contribution: m_p, or m_p v_q + Q_q . (x_i - x_p)
+            float base_val = mp, qr0 = 0.f, qr1 = 0.f, qr2 = 0.f;
+            if (q > 0) {
+                base_val = mp * v[(q - 1) * P + p];
+                qr0 = Q[(3 * (q - 1) + 0) * P + p];
+                qr1 = Q[(3 * (q - 1) + 1) * P + p];
+                qr2 = Q[(3 * (q - 1) + 2) * P + p];
+            }
+            const bool same = b[0] == nbx && b[1] == nby && b[2] == nbz;
             const int lx = b[0] - ox, ly = b[1] - oy, lz = b[2] - oz;
             const bool local = lx >= 0 && lx <= kBN - 3 && ly >= 0 && ly <= kBN - 3 && lz >= 0 && lz <= kBN - 3;
 #pragma unroll
@@ -257,27 +341,20 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                 for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
+                        const int o = (c * 3 + bb) * 3 + a;
                         const float w = wx[a] * wy[bb] * wz[c];
-                        const float d0 = ((float)a - f[0]) * dx, d1 = ((float)bb - f[1]) * dx,
-                                    d2 = ((float)c - f[2]) * dx;
-                        const float p0 = w * (mv[0] + Qp[0] * d0 + Qp[1] * d1 + Qp[2] * d2);
-                        const float p1 = w * (mv[1] + Qp[3] * d0 + Qp[4] * d1 + Qp[5] * d2);
-                        const float p2 = w * (mv[2] + Qp[6] * d0 + Qp[7] * d1 + Qp[8] * d2);
-                        if (local) {
-                            const int n = ((lz + c) * kBN + (ly + bb)) * kBN + (lx + a);
-                            atomicAdd(&sm[0][n], w * mp);
-                            atomicAdd(&sm[1][n], p0);
-                            atomicAdd(&sm[2][n], p1);
-                            atomicAdd(&sm[3][n], p2);
+                        const float val = w * (base_val + qr0 * (((float)a - f[0]) * dx) +
+                                               qr1 * (((float)bb - f[1]) * dx) + qr2 * (((float)c - f[2]) * dx));
+                        if (same) {
+                            sum[o] += val;
+                        } else if (local) {
+                            atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], val);
                         } else {
-                            const long long gi = node_index(E, b[0] + a, b[1] + bb, b[2] + c);
-                            atomicAdd(&acc[gi].x, w * mp);
-                            atomicAdd(&acc[gi].y, p0);
-                            atomicAdd(&acc[gi].z, p1);
-                            atomicAdd(&acc[gi].w, p2);
+                            float* g = reinterpret_cast<float*>(&acc[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]);
+                            atomicAdd(g + q, val);
                         }
                     }
-            if (!local) {
+            if (!local && q == 0) {
                 // the drifted particle's nodes span up to 2x2x2 node tiles
                 for (int c = 0; c < 2; ++c)
                     for (int bb = 0; bb < 2; ++bb)
@@ -286,76 +363,116 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                                           tile_flag, active, cnt);
             }
         }
-        __syncthreads();
-        // flush: one atomic per touched node
-        for (int n = threadIdx.x; n < kBN3; n += blockDim.x) {
-            const float m = sm[0][n];
-            if (m == 0.f) continue;
-            const int i = ox + (n % kBN), j = oy + ((n / kBN) % kBN), k = oz + n / (kBN * kBN);
-            if (i < 0 || j < 0 || k < 0 || i >= E.dims[0] || j >= E.dims[1] || k >= E.dims[2]) continue;
-            const long long gi = node_index(E, i, j, k);
-            atomicAdd(&acc[gi].x, m);
-            atomicAdd(&acc[gi].y, sm[1][n]);
-            atomicAdd(&acc[gi].z, sm[2][n]);
-            atomicAdd(&acc[gi].w, sm[3][n]);
-            const int fx = (i >> 2) - tx + 1, fy = (j >> 2) - ty + 1, fz = (k >> 2) - tz + 1;
-            sflag[(fz * 3 + fy) * 3 + fx] = 1u;
+        if (cnt_c > 0) {
+            const int lx = nbx - ox, ly = nby - oy, lz = nbz - oz;  // in [1, 4]
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], sum[(c * 3 + bb) * 3 + a]);
         }
+        if (clamped) atomicOr(&cnt->flags, kFlagDomain);
         __syncthreads();
-        if (threadIdx.x < 27 && sflag[threadIdx.x]) {
-            const int fx = threadIdx.x % 3, fy = (threadIdx.x / 3) % 3, fz = threadIdx.x / 9;
-            activate_tile(node_tile(E, (tx + fx - 1) * 4, (ty + fy - 1) * 4, (tz + fz - 1) * 4),
-                          tile_flag, active, cnt);
-        }
+        float4* out = blkbuf + (size_t)t * kBN3;
+        for (int n = threadIdx.x; n < kBN3; n += blockDim.x)
+            out[n] = make_float4(sm[0][n], sm[1][n], sm[2][n], sm[3][n]);
         __syncthreads();
     }
 }
 
 hipError_t launch_p2g(const Work& w, const float* x, const float* v, hipStream_t s) {
-    const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 4096);
+    const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 8192);
     hipLaunchKernelGGL(k_p2g, dim3(blocks), dim3(256), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs,
-                       w.ptile_id, w.ptile_beg, w.acc, w.tile_flag, w.active_tiles, w.cnt);
+                       w.ptile_id, w.ptile_beg, w.keys_sorted, w.blkbuf, w.acc, w.tile_flag,
+                       w.active_tiles, w.cnt);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// Grid update: v* = p/m + h g, boundary band, clear the accumulator
+// Grid update: sum the overlapping P2G blocks of every node (fixed order),
+// v* = p/m + h g, boundary band. Node tiles next to a particle tile come from
+// the static list; tiles reached only by drifted particles from the dynamic
+// list, whose accumulator is read and cleared here.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 grid_node_update(const DevEnv& E, int i, int j, int k, float4 a,
+                                                   float hf, double* psum) {
+    float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (a.x > 0.f) {
+        float vv[3] = {a.y / a.x + hf * E.gravity[0], a.z / a.x + hf * E.gravity[1],
+                       a.w / a.x + hf * E.gravity[2]};
+        const int idx[3] = {i, j, k};
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            if (idx[ax] < 3 && vv[ax] < 0.f) vv[ax] = 0.f;
+            if (idx[ax] >= E.dims[ax] - 3 && vv[ax] > 0.f) vv[ax] = 0.f;
+        }
+        out = make_float4(vv[0], vv[1], vv[2], a.x);
+        *psum += (double)a.x * ((double)vv[0] * vv[0] + (double)vv[1] * vv[1] + (double)vv[2] * vv[2]);
+    }
+    return out;
+}
+
 __global__ void __launch_bounds__(64)
-k_grid_update(const DevEnv* __restrict__ envs, int n_envs, double h, float4* __restrict__ acc,
+k_grid_update(const DevEnv* __restrict__ envs, int n_envs, double h, const float4* __restrict__ blkbuf,
+              const int* __restrict__ ptile_of, const unsigned* __restrict__ ntile_list,
+              const unsigned* __restrict__ ntile_mark, float4* __restrict__ acc,
               float4* __restrict__ vel, unsigned* __restrict__ tile_flag,
               const unsigned* __restrict__ active, DevCounters* cnt) {
+    __shared__ int nb[27];
     if (cnt->abort_step) return;
-    const unsigned n_act = cnt->n_active;
+    const unsigned n_static = cnt->n_ntiles, n_dyn = cnt->n_active;
     double psum = 0.0;
     const float hf = (float)h;
-    for (unsigned t = blockIdx.x; t < n_act; t += gridDim.x) {
-        const unsigned gt = active[t];
+    const int rx = threadIdx.x & 3, ry = (threadIdx.x >> 2) & 3, rz = threadIdx.x >> 4;
+    for (unsigned t = blockIdx.x; t < n_static + n_dyn; t += gridDim.x) {
+        const bool is_static = t < n_static;
+        const unsigned gt = is_static ? ntile_list[t] : active[t - n_static];
         const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
         int tx, ty, tz;
         tile_coords(E, gt, &tx, &ty, &tz);
-        const int i = tx * 4 + (threadIdx.x & 3), j = ty * 4 + ((threadIdx.x >> 2) & 3),
-                  k = tz * 4 + (threadIdx.x >> 4);
-        if (i < E.dims[0] && j < E.dims[1] && k < E.dims[2]) {
-            const long long gi = node_index(E, i, j, k);
-            const float4 a = acc[gi];
-            float4 out = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (a.x > 0.f) {
-                float vv[3] = {a.y / a.x + hf * E.gravity[0], a.z / a.x + hf * E.gravity[1],
-                               a.w / a.x + hf * E.gravity[2]};
-                const int idx[3] = {i, j, k};
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) {
-                    if (idx[ax] < 3 && vv[ax] < 0.f) vv[ax] = 0.f;
-                    if (idx[ax] >= E.dims[ax] - 3 && vv[ax] > 0.f) vv[ax] = 0.f;
-                }
-                out = make_float4(vv[0], vv[1], vv[2], a.x);
-                psum += (double)a.x * ((double)vv[0] * vv[0] + (double)vv[1] * vv[1] + (double)vv[2] * vv[2]);
+        if (is_static) {
+            __syncthreads();
+            if (threadIdx.x < 27) {
+                const int nx = tx + (int)(threadIdx.x % 3) - 1, ny = ty + (int)((threadIdx.x / 3) % 3) - 1,
+                          nz = tz + (int)(threadIdx.x / 9) - 1;
+                int pt = -1;
+                if (nx >= 0 && ny >= 0 && nz >= 0 && nx < E.ntile[0] && ny < E.ntile[1] && nz < E.ntile[2])
+                    pt = ptile_of[E.tile_base + nx + E.ntile[0] * (ny + E.ntile[1] * nz)];
+                nb[threadIdx.x] = pt;
             }
-            vel[gi] = out;
+            __syncthreads();
+        } else if (threadIdx.x == 0) {
+            tile_flag[gt] = 0u;
+        }
+        if (!is_static && ntile_mark[gt]) continue;  // already updated through the static list
+        const int i = tx * 4 + rx, j = ty * 4 + ry, k = tz * 4 + rz;
+        if (i >= E.dims[0] || j >= E.dims[1] || k >= E.dims[2]) continue;
+        const long long gi = node_index(E, i, j, k);
+        float4 sum = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (is_static) {
+            // the node lies in the blocks of tiles {T-1, T} (r <= 2) or {T, T+1} (r == 3) per axis
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        const int ofx = (rx == 3 ? a : a - 1), ofy = (ry == 3 ? bb : bb - 1), ofz = (rz == 3 ? c : c - 1);
+                        const int pt = nb[(ofz + 1) * 9 + (ofy + 1) * 3 + (ofx + 1)];
+                        if (pt < 0) continue;
+                        const int lx = i - (4 * (tx + ofx) - 1), ly = j - (4 * (ty + ofy) - 1), lz = k - (4 * (tz + ofz) - 1);
+                        const float4 q = blkbuf[(size_t)pt * kBN3 + (lz * kBN + ly) * kBN + lx];
+                        sum.x += q.x; sum.y += q.y; sum.z += q.z; sum.w += q.w;
+                    }
+        }
+        const float4 ac = acc[gi];
+        if (ac.x != 0.f || ac.y != 0.f || ac.z != 0.f || ac.w != 0.f) {
+            sum.x += ac.x; sum.y += ac.y; sum.z += ac.z; sum.w += ac.w;
             acc[gi] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
-        if (threadIdx.x == 0) tile_flag[gt] = 0u;
+        vel[gi] = grid_node_update(E, i, j, k, sum, hf, &psum);
     }
     // one FP64 atomic per block
 #pragma unroll
@@ -364,9 +481,10 @@ k_grid_update(const DevEnv* __restrict__ envs, int n_envs, double h, float4* __r
 }
 
 hipError_t launch_grid_update(const Work& w, double h, hipStream_t s) {
-    const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 2048);
-    hipLaunchKernelGGL(k_grid_update, dim3(blocks), dim3(64), 0, s, w.envs, w.n_envs, h, w.acc,
-                       w.vel, w.tile_flag, w.active_tiles, w.cnt);
+    const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 4096);
+    hipLaunchKernelGGL(k_grid_update, dim3(blocks), dim3(64), 0, s, w.envs, w.n_envs, h, w.blkbuf,
+                       w.ptile_of, w.ntile_list, w.ntile_mark, w.acc, w.vel, w.tile_flag,
+                       w.active_tiles, w.cnt);
     return hipGetLastError();
 }
 
@@ -531,8 +649,9 @@ __global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, Sub
     for (int i = t; i < n_acc; i += blockDim.x) rigid_acc[i] = 0.0;
     for (int i = t; i < N; i += blockDim.x) {
         SubstepStats z;
-        z.n_contacts = z.n_slots = z.iterations = z.converged = 0;
+        z.n_contacts = z.n_slots = z.iterations = z.converged = z.ls_rounds = z.pad = 0;
         z.residual = z.threshold = 0.0;
+        for (int q = 0; q < 5; ++q) z.t_phase[q] = 0ull;
         st[i] = z;
     }
 }

@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "MPM_OK", 1: "MPM_ENOCONV", 2: "MPM_EDOMAIN", 3: "MPM_ENAN", 
 FLAG_NOCONV, FLAG_DOMAIN, FLAG_NAN, FLAG_CAPACITY = 1, 2, 4, 8
 
 EXPORTED = ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
-            "mpm_get_rigid_state", "mpm_destroy", "mpm_last_error")
+            "mpm_get_rigid_state", "mpm_profile", "mpm_destroy", "mpm_last_error")
+KERNEL_CLASSES = ("sort", "p2g", "grid", "register", "setup", "solve", "g2p")
 
 
 class EnvDesc(ct.Structure):
@@ -39,7 +40,7 @@ class Desc(ct.Structure):
     _fields_ = [("struct_size", ct.c_uint32), ("n_envs", ct.c_int32),
                 ("envs", ct.POINTER(EnvDesc)), ("h", ct.c_double), ("N", ct.c_int32),
                 ("eps_r", ct.c_double), ("eps_a", ct.c_double), ("max_iter", ct.c_int32),
-                ("ls_max_rounds", ct.c_int32), ("n_particles", ct.c_int64),
+                ("ls_max_steps", ct.c_int32), ("n_particles", ct.c_int64),
                 ("x", ct.c_void_p), ("v", ct.c_void_p), ("F", ct.c_void_p), ("C", ct.c_void_p),
                 ("pid", ct.c_void_p), ("max_contacts", ct.c_int64), ("workspace", ct.c_void_p),
                 ("workspace_bytes", ct.c_size_t), ("stream", ct.c_void_p)]
@@ -69,6 +70,13 @@ class StepStats(ct.Structure):
                 ("threshold", ct.POINTER(ct.c_double))]
 
 
+class ProfileData(ct.Structure):
+    _fields_ = [("ms", ct.c_double * 7), ("launches", ct.c_int64 * 7),
+                ("solver_iterations", ct.c_int64), ("solver_ls_rounds", ct.c_int64),
+                ("solver_contact_iters", ct.c_int64), ("solver_node_iters", ct.c_int64),
+                ("solver_contact_rounds", ct.c_int64), ("solver_phase_us", ct.c_double * 5)]
+
+
 _lib = None
 
 
@@ -87,11 +95,12 @@ def load():
         L.mpm_step.argtypes = [ct.c_void_p, ct.POINTER(RigidState), ct.POINTER(RigidImpulse),
                                ct.POINTER(StepStats)]
         L.mpm_get_rigid_state.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidState)]
+        L.mpm_profile.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ProfileData)]
         L.mpm_destroy.argtypes = [ct.c_void_p]
         L.mpm_destroy.restype = None
         L.mpm_last_error.restype = ct.c_char_p
         for f in ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
-                  "mpm_get_rigid_state"):
+                  "mpm_get_rigid_state", "mpm_profile"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -130,7 +139,7 @@ def env_descs(scene) -> ct.Array:
     return arr
 
 
-def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_rounds: int = 0) -> Desc:
+def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 0) -> Desc:
     d = Desc()
     d.struct_size = ct.sizeof(Desc)
     d.n_envs = len(scene.envs)
@@ -138,7 +147,7 @@ def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_rounds: int =
     d.h, d.N = scene.h, scene.N
     d.eps_r, d.eps_a = scene.eps_r, scene.eps_a
     d.max_iter = scene.max_iter
-    d.ls_max_rounds = ls_max_rounds
+    d.ls_max_steps = ls_max_steps
     d.n_particles = scene.P
     d.max_contacts = max_contacts
     return d
@@ -207,6 +216,20 @@ def mpm_get_rigid_state(h, rid: int) -> RigidState:
     return s
 
 
+def mpm_profile(h, enable: bool) -> dict:
+    """Switch kernel-class event timing on/off; returns what was accumulated."""
+    p = ProfileData()
+    _check(load().mpm_profile(h, 1 if enable else 0, ct.byref(p)), "mpm_profile")
+    return dict(ms={k: p.ms[i] for i, k in enumerate(KERNEL_CLASSES)},
+                launches={k: p.launches[i] for i, k in enumerate(KERNEL_CLASSES)},
+                solver_iterations=p.solver_iterations, solver_ls_rounds=p.solver_ls_rounds,
+                solver_contact_iters=p.solver_contact_iters,
+                solver_node_iters=p.solver_node_iters,
+                solver_contact_rounds=p.solver_contact_rounds,
+                solver_phase_us=dict(zip(("node", "barrier1", "contact", "barrier2", "line_search"),
+                                         list(p.solver_phase_us))))
+
+
 def mpm_destroy(h) -> None:
     if h:
         load().mpm_destroy(h)
@@ -217,7 +240,7 @@ class Sim:
     workspace, the library steps them in place."""
 
     def __init__(self, scene, device: str = "cuda:0", max_contacts: int = 0,
-                 ls_max_rounds: int = 0, track_ids: bool = True):
+                 ls_max_steps: int = 0, track_ids: bool = True):
         import torch
         load()
         self.torch = torch
@@ -232,7 +255,7 @@ class Sim:
         self.C = torch.from_numpy(np.ascontiguousarray(scene.C, np.float32)).to(dev)
         self.pid = torch.arange(self.P, dtype=torch.int32, device=dev) if track_ids else None
         self._envs = env_descs(scene)
-        self.desc = make_desc(scene, self._envs, max_contacts, ls_max_rounds)
+        self.desc = make_desc(scene, self._envs, max_contacts, ls_max_steps)
         self.ws_bytes = mpm_workspace_size(self.desc)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
@@ -264,6 +287,9 @@ class Sim:
             inv[pid] = np.arange(pid.shape[0], dtype=pid.dtype)
             out = {k: a[:, inv] for k, a in out.items()}
         return out
+
+    def profile(self, enable: bool) -> dict:
+        return mpm_profile(self.handle, enable)
 
     def rigid_state(self, i: int) -> RigidState:
         return mpm_get_rigid_state(self.handle, self.rigid_ids[i])
