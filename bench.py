@@ -187,4 +187,6 @@ def main() -> int:
 
 
 if __name__ == "__main__":
-    sys.exit(main())
+    rc = main()
+    if rc:
+        sys.exit(rc)

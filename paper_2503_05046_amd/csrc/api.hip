@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -206,6 +207,8 @@ struct mpm_handle {
     int key_bits;
     int qn_cap;          // co-resident blocks the cooperative solver may use
     double wall_khz;     // device wall-clock rate
+    int blk_max;         // contact count up to which one workgroup runs the solver
+    int slots_per_block; // contact nodes per block of the multi-block solver
     int qn_blocks_next;  // blocks for the next step, sized from the last one's problem
     // pinned host staging
     DevRigid* h_rigids;
@@ -293,6 +296,14 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         h->wall_khz = khz;
     }
     h->qn_blocks_next = std::min(h->qn_cap, kQnDefaultBlocks);
+    {
+        // tuning override of the single-workgroup solver threshold
+        const char* env = getenv("MPM_SOLVER_BLOCK_MAX");
+        h->blk_max = env ? atoi(env) : 256;
+        // and of the contact nodes per solver block
+        const char* spb = getenv("MPM_SOLVER_SLOTS_PER_BLOCK");
+        h->slots_per_block = spb ? std::max(1, atoi(spb)) : kQnItemsPerBlock;
+    }
     h->w.n_rigid = 0;
     int tiles = 0;
     long long nodes = 0;
@@ -488,7 +499,8 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         }
         {
             ProfScope ps(h, MPM_K_SOLVE, npair);
-            HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks, s));
+            HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
+                              h->blk_max, s));
         }
         {
             ProfScope ps(h, MPM_K_G2P, npair);
@@ -555,7 +567,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         int most = 0;
         for (int k = 0; k < N; ++k) most = std::max(most, h->h_stats[k].n_slots);
         if (most > 0)
-            h->qn_blocks_next = std::max(1, std::min(h->qn_cap, (most + kQnItemsPerBlock - 1) / kQnItemsPerBlock));
+            h->qn_blocks_next = std::max(1, std::min(h->qn_cap, (most + h->slots_per_block - 1) / h->slots_per_block));
     }
     // host side of the split: advance kinematic bodies with their twist
     for (HostRigid& q : h->rigids) {

@@ -32,6 +32,7 @@
 #include "sort_util.h"
 
 #include <algorithm>
+#include <cstddef>
 
 namespace mpm {
 
@@ -116,27 +117,29 @@ struct ContactParams {
     double phi0, mun0, k, d, eps_s, h;
 };
 
+// The normal impulse is active while both factors (phi0 - h vn) and
+// (1 - d vn) are positive; the friction terms share one reciprocal square root.
 __device__ __forceinline__ void contact_model(const ContactParams& P, const double vc[3],
                                               double gam[3], double* g00, double* g01,
                                               double* g11, double* gnn) {
-    double vbar = P.phi0 / P.h;
-    if (P.d > 0.0 && 1.0 / P.d < vbar) vbar = 1.0 / P.d;
     const double vn = vc[2];
-    if (vn < vbar) {
-        gam[2] = P.h * P.k * (P.phi0 - P.h * vn) * (1.0 - P.d * vn);
-        *gnn = P.h * P.k * (P.h * (1.0 - P.d * vn) + P.d * (P.phi0 - P.h * vn));
+    const double a = P.phi0 - P.h * vn, b = 1.0 - P.d * vn;
+    if (a > 0.0 && b > 0.0) {
+        gam[2] = P.h * P.k * a * b;
+        *gnn = P.h * P.k * (P.h * b + P.d * a);
     } else {
         gam[2] = 0.0;
         *gnn = 0.0;
     }
     const double s2 = vc[0] * vc[0] + vc[1] * vc[1] + P.eps_s * P.eps_s;
-    const double s = sqrt(s2);
-    const double cs = P.mun0 / s;
+    const double inv_s = 1.0 / sqrt(s2);
+    const double inv_s2 = inv_s * inv_s;
+    const double cs = P.mun0 * inv_s;
     gam[0] = -cs * vc[0];
     gam[1] = -cs * vc[1];
-    *g00 = cs * (1.0 - vc[0] * vc[0] / s2);
-    *g01 = -cs * vc[0] * vc[1] / s2;
-    *g11 = cs * (1.0 - vc[1] * vc[1] / s2);
+    *g00 = cs * (1.0 - vc[0] * vc[0] * inv_s2);
+    *g01 = -cs * vc[0] * vc[1] * inv_s2;
+    *g11 = cs * (1.0 - vc[1] * vc[1] * inv_s2);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,6 +427,7 @@ struct QnArgs {
     int substep;
     double h, eps_r, eps_a;
     int max_iter, ls_max_steps;
+    int blk_max;            // largest contact count solved by the single-workgroup kernel
     DevCounters* cnt;
 };
 
@@ -475,19 +479,45 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* 
     __syncthreads();
 }
 
-// Initial contact velocities v_c^0 = R_c^T sum w v*_i + b_c for contacts
-// [c0, c1) with stride.
-__device__ __forceinline__ void initial_contact_velocity(const QnArgs& A, long long c) {
+// Sum over the 27 stencil nodes of a contact of w times a 3-vector of the
+// node's slot record (kField: offset in doubles inside SlotRec). The loads of
+// a 9-node layer are issued together; a node with no slot (zero weight) reads
+// slot 0 with weight 0.
+template <int kField>
+__device__ __forceinline__ void stencil_sum(const QnArgs& A, long long c, double acc[3]) {
     const ContactStencil& st = A.c_st[c];
-    double sacc[3] = {0.0, 0.0, 0.0};
-    for (int o = 0; o < 27; ++o) {
-        const int sl = st.slot[o];
-        if (sl < 0) continue;
-        const double w = st.w[o];
-        const SlotRec& S = A.s_rec[sl];
+    acc[0] = acc[1] = acc[2] = 0.0;
+#pragma unroll 1
+    for (int g = 0; g < 3; ++g) {
+        int sl[9];
+        double w[9];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) sacc[a] += w * S.v[a];
+        for (int o = 0; o < 9; ++o) {
+            const int q = st.slot[9 * g + o];
+            sl[o] = q < 0 ? 0 : q;
+            w[o] = q < 0 ? 0.0 : (double)st.w[9 * g + o];
+        }
+        double val[9][3];
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+            const double* r = &A.s_rec[sl[o]].m + kField;
+            val[o][0] = r[0]; val[o][1] = r[1]; val[o][2] = r[2];
+        }
+#pragma unroll
+        for (int o = 0; o < 9; ++o)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) acc[a] += w[o] * val[o][a];
     }
+}
+constexpr int kSlotV = 1;   // SlotRec::v
+constexpr int kSlotDv = 7;  // SlotRec::dv
+static_assert(offsetof(SlotRec, v) == kSlotV * sizeof(double), "SlotRec layout");
+static_assert(offsetof(SlotRec, dv) == kSlotDv * sizeof(double), "SlotRec layout");
+
+// Initial contact velocity v_c^0 = R_c^T sum w v*_i + b_c.
+__device__ __forceinline__ void initial_contact_velocity(const QnArgs& A, long long c) {
+    double sacc[3];
+    stencil_sum<kSlotV>(A, c, sacc);
     const ContactRec& rec = A.c_rec[c];
     double t1[3], t2[3];
     frame_of(rec.n, t1, t2);
@@ -531,35 +561,31 @@ __device__ __forceinline__ void node_solve(SlotRec& S, const double j[3], const 
 }
 
 // R gamma and the upper triangle of R G R^T of one contact at contact velocity vc.
-__device__ __forceinline__ void contact_terms(const ContactRec& rec, double h, const double vc[3],
+__device__ __forceinline__ void contact_terms(const double n[3], const ContactParams& P, const double vc[3],
                                               double rg[3], double rgr[6]) {
     double g[3], g00, g01, g11, gnn;
-    contact_model(params_of(rec, h), vc, g, &g00, &g01, &g11, &gnn);
+    contact_model(P, vc, g, &g00, &g01, &g11, &gnn);
     double t1[3], t2[3];
-    frame_of(rec.n, t1, t2);
+    frame_of(n, t1, t2);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) rg[a] = t1[a] * g[0] + t2[a] * g[1] + rec.n[a] * g[2];
+    for (int a = 0; a < 3; ++a) rg[a] = t1[a] * g[0] + t2[a] * g[1] + n[a] * g[2];
     int q = 0;
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll
         for (int cc = r; cc < 3; ++cc)
             rgr[q++] = g00 * t1[r] * t1[cc] + g01 * (t1[r] * t2[cc] + t2[r] * t1[cc]) + g11 * t2[r] * t2[cc] +
-                       gnn * rec.n[r] * rec.n[cc];
+                       gnn * n[r] * n[cc];
+}
+__device__ __forceinline__ void contact_terms(const ContactRec& rec, double h, const double vc[3],
+                                              double rg[3], double rgr[6]) {
+    contact_terms(rec.n, params_of(rec, h), vc, rg, rgr);
 }
 
 // u_c = R_c^T sum_o w_o dv_slot(o)
 __device__ __forceinline__ void contact_direction(const QnArgs& A, long long c, double u[3]) {
-    const ContactStencil& st = A.c_st[c];
-    double sacc[3] = {0.0, 0.0, 0.0};
-    for (int o = 0; o < 27; ++o) {
-        const int sl = st.slot[o];
-        if (sl < 0) continue;
-        const double w = st.w[o];
-        const SlotRec& S = A.s_rec[sl];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) sacc[a] += w * S.dv[a];
-    }
+    double sacc[3];
+    stencil_sum<kSlotDv>(A, c, sacc);
     const ContactRec& rec = A.c_rec[c];
     double t1[3], t2[3];
     frame_of(rec.n, t1, t2);
@@ -691,13 +717,11 @@ __device__ __forceinline__ bool grid_sync(DevCounters* cnt, unsigned nblocks, un
     return *s_ok != 0u;
 }
 
-constexpr int kLsCache = 1024;  // contacts whose line-search data are staged in LDS
-
-struct LsCache {
-    double vc[3][kLsCache];
-    double u[3][kLsCache];
-    double phi0[kLsCache], mun0[kLsCache];
-};
+constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
+constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
+constexpr int kLsLdsFields = 11; // v_c, u_c, phi0, mu n0, k, d, eps_s of one more contact per thread in LDS
+constexpr int kQnMaxBlocks = 64; // grid size limit of k_qn (per-block partials staged in LDS)
+static_assert(kQnMaxBlocks * kQnSums <= kQnThreads, "one partial per thread");
 
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
@@ -706,12 +730,13 @@ k_qn(QnArgs A) {
     __shared__ double bcast[8];
     __shared__ double racc[kMaxRigid * 6];
     __shared__ unsigned s_ok;
-    __shared__ LsCache ls_cache;
+    __shared__ double red[kQnMaxBlocks * kQnSums];
+    __shared__ double ls_ovf[kLsLdsFields][kQnThreads];  // line-search contacts beyond the registers
     __shared__ double nacc[9][kSlotChunk];     // j (3) and R G R^T (6) of a chunk of owned slots
 
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
-    if (aborted || cnt->n_contacts <= (unsigned)kBlkMaxContacts) return;  // k_qn_block's case
+    if (aborted || cnt->n_contacts <= (unsigned)A.blk_max) return;  // k_qn_block's case
     const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
     unsigned long long tph[5] = {0, 0, 0, 0, 0};
     unsigned long long tmark = 0;
@@ -741,17 +766,35 @@ k_qn(QnArgs A) {
             for (int q = tid; q < 9 * kSlotChunk; q += T) (&nacc[0][0])[q] = 0.0;
             __syncthreads();
             const int E0 = A.s_beg[sa], E1 = A.s_beg[sb];
-            for (int e = E0 + tid; e < E1; e += T) {
-                const Entry en = A.e_ent[e];
-                const int ls = en.slot - (int)sa;
-                const double w = en.w;
-                double vc[3], rg[3], rgr[6];
-                contact_velocity(A.c_dyn[en.c], k, alpha_prev, vc);
-                contact_terms(A.c_rec[en.c], A.h, vc, rg, rgr);
+            for (int eb = E0; eb < E1; eb += T * kEntBatch) {
+                // all loads of a batch of entries first, then the model and the LDS sums
+                Entry en[kEntBatch];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * rg[a]);
+                for (int u = 0; u < kEntBatch; ++u) {
+                    const int e = eb + tid + u * T;
+                    en[u] = A.e_ent[e < E1 ? e : E0];
+                }
+                double vc[kEntBatch][3], nrm[kEntBatch][3];
+                ContactParams P[kEntBatch];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) atomicAdd(&nacc[3 + q][ls], w * w * rgr[q]);
+                for (int u = 0; u < kEntBatch; ++u) {
+                    contact_velocity(A.c_dyn[en[u].c], k, alpha_prev, vc[u]);
+                    const ContactRec& R = A.c_rec[en[u].c];
+                    nrm[u][0] = R.n[0]; nrm[u][1] = R.n[1]; nrm[u][2] = R.n[2];
+                    P[u] = params_of(R, A.h);
+                }
+#pragma unroll
+                for (int u = 0; u < kEntBatch; ++u) {
+                    if (eb + tid + u * T >= E1) continue;
+                    const int ls = en[u].slot - (int)sa;
+                    const double w = en[u].w;
+                    double rg[3], rgr[6];
+                    contact_terms(nrm[u], P[u], vc[u], rg, rgr);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * rg[a]);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) atomicAdd(&nacc[3 + q][ls], w * w * rgr[q]);
+                }
             }
             __syncthreads();
             for (long long s = sa + tid; s < sb; s += T) {
@@ -767,9 +810,12 @@ k_qn(QnArgs A) {
         ok = grid_sync(cnt, G, &gen, &s_ok);
         if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
         if (!ok) break;
+        // every block sums the per-block partials in the same order
+        if (tid < (int)G * kQnSums) red[tid] = A.partial[tid];
+        __syncthreads();
         if (tid < kQnSums) {
             double acc = 0.0;
-            for (unsigned b = 0; b < G; ++b) acc += A.partial[(size_t)b * kQnSums + tid];
+            for (unsigned b = 0; b < G; ++b) acc += red[b * kQnSums + tid];
             tot[tid] = acc;
         }
         __syncthreads();
@@ -799,37 +845,66 @@ k_qn(QnArgs A) {
         if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
         if (!ok) break;
         // ---- exact line search, redundantly in every block ----------------------
-        const bool use_cache = nc <= kLsCache;
-        if (use_cache) {
-            for (long long c = tid; c < nc; c += T) {
-                const ContactDyn& D = A.c_dyn[c];
-                const ContactRec& R = A.c_rec[c];
-                const int src = k == 0 ? 0 : (k & 1);
+        // Contact c is taken by thread c mod T. The first kLsPer*T contacts
+        // stay in registers for all the evaluations, the next T in LDS, and
+        // any beyond are read from memory at each evaluation.
+        const int src = k == 0 ? 0 : (k & 1);
+        double lv[kLsPer][3], lu[kLsPer][3], lphi[kLsPer], lmun[kLsPer], lk[kLsPer], ld[kLsPer], leps[kLsPer];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) { ls_cache.vc[a][c] = D.vc[src][a]; ls_cache.u[a][c] = D.uc[a]; }
-                ls_cache.phi0[c] = R.phi0;
-                ls_cache.mun0[c] = R.mun0;
+        for (int u = 0; u < kLsPer; ++u) {
+            const long long c = tid + (long long)u * T;
+            const bool valid = c < nc;
+            const ContactDyn& D = A.c_dyn[valid ? c : 0];
+            const ContactRec& R = A.c_rec[valid ? c : 0];
+            lphi[u] = R.phi0; lmun[u] = R.mun0; lk[u] = R.k; ld[u] = R.d; leps[u] = R.eps_s;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                lv[u][a] = D.vc[src][a];
+                lu[u][a] = valid ? D.uc[a] : 0.0;  // a zero direction adds exactly nothing
             }
-            __syncthreads();
+        }
+        const long long c_lds = tid + (long long)kLsPer * T;
+        const bool use_lds = (long long)kLsPer * T < nc;
+        if (use_lds) {
+            const bool valid = c_lds < nc;
+            const ContactDyn& D = A.c_dyn[valid ? c_lds : 0];
+            const ContactRec& R = A.c_rec[valid ? c_lds : 0];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ls_ovf[a][tid] = D.vc[src][a];
+                ls_ovf[3 + a][tid] = valid ? D.uc[a] : 0.0;
+            }
+            ls_ovf[6][tid] = R.phi0; ls_ovf[7][tid] = R.mun0; ls_ovf[8][tid] = R.k;
+            ls_ovf[9][tid] = R.d; ls_ovf[10][tid] = R.eps_s;
         }
         auto eval = [&](double alpha, double* d2out) -> double {
             double acc2[2] = {0.0, 0.0};
-            for (long long c = tid; c < nc; c += T) {
-                double vc[3], u[3], d1, d2;
-                const ContactRec& R = A.c_rec[c];
-                ContactParams P = params_of(R, A.h);
-                if (use_cache) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) { vc[a] = ls_cache.vc[a][c]; u[a] = ls_cache.u[a][c]; }
-                } else {
-                    const ContactDyn& D = A.c_dyn[c];
-                    const int src = k == 0 ? 0 : (k & 1);
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) { vc[a] = D.vc[src][a]; u[a] = D.uc[a]; }
-                }
+            for (int u = 0; u < kLsPer; ++u) {
+                const ContactParams P = {lphi[u], lmun[u], lk[u], ld[u], leps[u], A.h};
+                double d1, d2;
+                ls_terms(P, lv[u], lu[u], alpha, &d1, &d2);
+                acc2[0] += d1;
+                acc2[1] += d2;
+            }
+            if (use_lds) {
+                const double vc[3] = {ls_ovf[0][tid], ls_ovf[1][tid], ls_ovf[2][tid]};
+                const double u[3] = {ls_ovf[3][tid], ls_ovf[4][tid], ls_ovf[5][tid]};
+                const ContactParams P = {ls_ovf[6][tid], ls_ovf[7][tid], ls_ovf[8][tid],
+                                         ls_ovf[9][tid], ls_ovf[10][tid], A.h};
+                double d1, d2;
                 ls_terms(P, vc, u, alpha, &d1, &d2);
                 acc2[0] += d1;
                 acc2[1] += d2;
+                for (long long c = c_lds + T; c < nc; c += T) {
+                    double vc[3], u[3], d1, d2;
+                    const ContactDyn& D = A.c_dyn[c];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) { vc[a] = D.vc[src][a]; u[a] = D.uc[a]; }
+                    ls_terms(params_of(A.c_rec[c], A.h), vc, u, alpha, &d1, &d2);
+                    acc2[0] += d1;
+                    acc2[1] += d2;
+                }
             }
             block_sum<2>(acc2, lds, bcast);
             *d2out = Aq + bcast[1];
@@ -884,7 +959,7 @@ k_qn_block(QnArgs A) {
     __shared__ double bcast[8];
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
-    if (!aborted && cnt->n_contacts > (unsigned)kBlkMaxContacts) return;  // k_qn's case
+    if (!aborted && cnt->n_contacts > (unsigned)A.blk_max) return;  // k_qn's case
     const long long nc = aborted ? 0 : cnt->n_contacts;
     const long long ns = aborted ? 0 : cnt->n_slots;
     const int tid = threadIdx.x, T = blockDim.x;
@@ -1007,8 +1082,10 @@ k_qn_block(QnArgs A) {
 }
 
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
-                     double eps_a, int max_iter, int ls_max_steps, int blocks, hipStream_t s) {
+                     double eps_a, int max_iter, int ls_max_steps, int blocks, int blk_max,
+                     hipStream_t s) {
     QnArgs A;
+    A.blk_max = std::min(blk_max, kBlkMaxContacts);
     A.rigids = w.rigids;
     A.x = x;
     A.P = w.P;
@@ -1042,7 +1119,7 @@ int qn_max_blocks() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    return per_cu * cus;
+    return std::min(per_cu * cus, kQnMaxBlocks);
 }
 
 }  // namespace mpm

@@ -177,7 +177,8 @@ hipError_t launch_registration(const Work& w, const float* x, const float* v, do
                                int substep, hipStream_t s);
 hipError_t launch_contact_setup(const Work& w, hipStream_t s);
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
-                     double eps_a, int max_iter, int ls_max_steps, int blocks, hipStream_t s);
+                     double eps_a, int max_iter, int ls_max_steps, int blocks, int blk_max,
+                     hipStream_t s);
 int qn_max_blocks();
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
                       float* v_out, float* F_out, float* C_out, const int* pid_in,

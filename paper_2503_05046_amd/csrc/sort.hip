@@ -5,8 +5,11 @@
 // so the element count may live in device memory (it is read by every kernel
 // at start) and nothing needs a host round trip. Per 8-bit digit pass:
 //   hist:    per-block digit histogram in LDS -> hist[digit][block]
-//   scan:    one block scans the digit-major table (digit, then block order)
-//   scatter: each block walks its chunk in order in 256-element rounds; the
+//   rowscan: one block per digit scans its row of block counts (coalesced)
+//            and stores the digit's total
+//   scatter: each block first turns the 256 digit totals into digit offsets
+//            (one block scan), then walks its chunk in order in 256-element
+//            rounds; the
 //            rank of an element among equal digits of its wave comes from
 //            eight ballots, ranks across the block's four waves from a small
 //            LDS table, so the pass is stable and the result bit-exact.
@@ -30,8 +33,21 @@ k_rs_hist(const unsigned* __restrict__ keys, const unsigned* count_dev, long lon
     hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
+// Exclusive scan of one digit's row of per-block counts, in place; the row
+// total goes to totals[digit]. One block of kSortBlocks threads per digit.
+__global__ void __launch_bounds__(kSortBlocks)
+k_rs_rowscan(unsigned* __restrict__ hist, unsigned* __restrict__ totals) {
+    __shared__ unsigned wsum[17];
+    unsigned* row = hist + (size_t)blockIdx.x * kSortBlocks;
+    const unsigned v = row[threadIdx.x];
+    unsigned total;
+    const unsigned ex = block_exclusive_scan_total(v, wsum, &total);
+    row[threadIdx.x] = ex;
+    if (threadIdx.x == 0) totals[blockIdx.x] = total;
+}
+
 // Exclusive scan of n_items unsigned values in place by one block of 1024
-// threads; optionally stores the total.
+// threads (used for n_items <= a few thousand); optionally stores the total.
 __global__ void __launch_bounds__(1024)
 k_scan_one_block(unsigned* __restrict__ data, int n_items, unsigned* total) {
     __shared__ unsigned wsum[16];
@@ -55,16 +71,19 @@ __global__ void __launch_bounds__(kSortThreads)
 k_rs_scatter(const unsigned* __restrict__ kin, const unsigned* __restrict__ vin,
              unsigned* __restrict__ kout, unsigned* __restrict__ vout,
              const unsigned* count_dev, long long count_host, int shift,
-             const unsigned* __restrict__ hist) {
+             const unsigned* __restrict__ hist, const unsigned* __restrict__ totals) {
+    static_assert(kSortThreads == 256, "one thread per digit");
     __shared__ unsigned running[256];
     __shared__ unsigned wcnt[kSortThreads / 64][256];
+    __shared__ unsigned wsum[16];
     const long long n = count_dev ? (long long)*count_dev : count_host;
     long long beg, end;
     chunk_range(n, blockIdx.x, gridDim.x, &beg, &end);
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int lane = tid & 63;
-    running[tid] = hist[tid * gridDim.x + blockIdx.x];
+    const unsigned digit_off = block_exclusive_scan_1024(totals[tid], wsum);
+    running[tid] = digit_off + hist[tid * gridDim.x + blockIdx.x];
     for (long long base = beg; base < end; base += kSortThreads) {
         for (int w = 0; w < kSortThreads / 64; ++w) wcnt[w][tid] = 0;
         __syncthreads();
@@ -112,10 +131,10 @@ hipError_t radix_sort(const Work& w, unsigned* keys, unsigned* vals, unsigned* k
         const int shift = 8 * p;
         hipLaunchKernelGGL(k_rs_hist, dim3(kSortBlocks), dim3(kSortThreads), 0, s, ki, count_dev,
                            count_host, shift, w.blk);
-        hipLaunchKernelGGL(k_scan_one_block, dim3(1), dim3(1024), 0, s, w.blk, 256 * kSortBlocks,
-                           (unsigned*)nullptr);
+        unsigned* totals = w.blk + 256 * kSortBlocks;
+        hipLaunchKernelGGL(k_rs_rowscan, dim3(256), dim3(kSortBlocks), 0, s, w.blk, totals);
         hipLaunchKernelGGL(k_rs_scatter, dim3(kSortBlocks), dim3(kSortThreads), 0, s, ki, vi, ko,
-                           vo, count_dev, count_host, shift, w.blk);
+                           vo, count_dev, count_host, shift, w.blk, (const unsigned*)totals);
         unsigned* t = ki; ki = ko; ko = t;
         t = vi; vi = vo; vo = t;
     }
