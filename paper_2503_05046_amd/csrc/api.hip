@@ -41,7 +41,7 @@ mpm_status fail(mpm_status st, const char* fmt, ...) {
 constexpr int kMaxRigidTotal = 256;
 constexpr int kMaxQnBlocks = 1024;
 constexpr int kQnDefaultBlocks = 32;   // first step, before any problem size is known
-constexpr int kQnItemsPerBlock = 512;  // contact nodes per solver block
+constexpr int kQnItemsPerBlock = 256;  // contact nodes per solver block
 constexpr size_t kAlign = 256;
 
 struct Layout {
@@ -527,7 +527,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
             h->acc.solver_contact_iters += (int64_t)q.iterations * q.n_contacts;
             h->acc.solver_node_iters += (int64_t)q.iterations * q.n_slots;
             h->acc.solver_contact_rounds += (int64_t)q.ls_rounds * q.n_contacts;
-            for (int ph = 0; ph < 5; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)q.t_phase[ph] / h->wall_khz;
+            for (int ph = 0; ph < 6; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)q.t_phase[ph] / h->wall_khz;
         }
     }
     if (h->h_cnt->abort_step && h->h_cnt->abort_substep > 0) {

@@ -42,7 +42,7 @@ constexpr unsigned kFlagHang = 16u;
 constexpr long long kBarrierTimeoutCycles = 5000000000ll;  // ~2 s: a healthy barrier takes microseconds
 constexpr int kQnThreads = 512;
 constexpr int kBlkThreads = 1024;      // single-workgroup solver
-constexpr int kBlkMaxContacts = 2048;  // contacts whose per-iteration terms fit in one CU's LDS
+constexpr int kBlkMaxContacts = 512;   // contacts whose per-iteration terms fit in one CU's LDS
 constexpr int kSlotChunk = 512;     // contact nodes whose accumulators are staged in LDS at once
 constexpr int kMaxRigid = 256;
 
@@ -117,6 +117,16 @@ struct ContactParams {
     double phi0, mun0, k, d, eps_s, h;
 };
 
+// 1/sqrt(x) for normal x > 0: the hardware estimate refined by two Newton
+// steps y <- y (3/2 - x y^2 / 2) (each step squares the relative error).
+__device__ __forceinline__ double inv_sqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double hx = 0.5 * x;
+    y = y * fma(-hx * y, y, 1.5);
+    y = y * fma(-hx * y, y, 1.5);
+    return y;
+}
+
 // The normal impulse is active while both factors (phi0 - h vn) and
 // (1 - d vn) are positive; the friction terms share one reciprocal square root.
 __device__ __forceinline__ void contact_model(const ContactParams& P, const double vc[3],
@@ -132,7 +142,7 @@ __device__ __forceinline__ void contact_model(const ContactParams& P, const doub
         *gnn = 0.0;
     }
     const double s2 = vc[0] * vc[0] + vc[1] * vc[1] + P.eps_s * P.eps_s;
-    const double inv_s = 1.0 / sqrt(s2);
+    const double inv_s = inv_sqrt(s2);
     const double inv_s2 = inv_s * inv_s;
     const double cs = P.mun0 * inv_s;
     gam[0] = -cs * vc[0];
@@ -140,6 +150,63 @@ __device__ __forceinline__ void contact_model(const ContactParams& P, const doub
     *g00 = cs * (1.0 - vc[0] * vc[0] * inv_s2);
     *g01 = -cs * vc[0] * vc[1] * inv_s2;
     *g11 = cs * (1.0 - vc[1] * vc[1] * inv_s2);
+}
+
+// Line search along v_c(alpha) = v_c + alpha u_c: the contact's terms of
+// phi'(alpha) = -gamma(v_c(alpha)) . u_c and phi''(alpha) = u_c^T G u_c in
+// closed form. With v_t, u_t the tangential parts,
+//   s^2(alpha) = |v_t + alpha u_t|^2 + eps_s^2 = q0 + 2 p0 alpha + q2 alpha^2,
+//   friction:  phi'  += mu n0 (p0 + alpha q2) / s,
+//              phi'' += mu n0 / s (q2 - (p0 + alpha q2)^2 / s^2);
+//   normal, while a = phi0 - h v_n(alpha) > 0 and b = 1 - d v_n(alpha) > 0:
+//              phi'  -= h k u_n a b,   phi'' += h k u_n^2 (h b + d a).
+struct LsCoef {
+    double q0, p0, q2, mun0;  // friction
+    double a0, a1, b0, b1;    // a = a0 - alpha a1, b = b0 - alpha b1
+    double kn, eh, ed;        // h k u_n, h k u_n^2 h, h k u_n^2 d
+};
+
+__device__ __forceinline__ LsCoef ls_coef(const ContactParams& P, const double vc[3], const double u[3]) {
+    LsCoef L;
+    L.q0 = vc[0] * vc[0] + vc[1] * vc[1] + P.eps_s * P.eps_s;
+    L.p0 = vc[0] * u[0] + vc[1] * u[1];
+    L.q2 = u[0] * u[0] + u[1] * u[1];
+    L.mun0 = P.mun0;
+    L.a0 = P.phi0 - P.h * vc[2];
+    L.a1 = P.h * u[2];
+    L.b0 = 1.0 - P.d * vc[2];
+    L.b1 = P.d * u[2];
+    const double hk = P.h * P.k, hkuu = hk * u[2] * u[2];
+    L.kn = hk * u[2];
+    L.eh = hkuu * P.h;
+    L.ed = hkuu * P.d;
+    return L;
+}
+
+// Coefficients that contribute exactly zero (padding lanes).
+__device__ __forceinline__ LsCoef ls_coef_zero() {
+    LsCoef L;
+    L.q0 = 1.0; L.p0 = L.q2 = L.mun0 = 0.0;
+    L.a0 = -1.0; L.a1 = L.b0 = L.b1 = 0.0;
+    L.kn = L.eh = L.ed = 0.0;
+    return L;
+}
+
+__device__ __forceinline__ void ls_eval(const LsCoef& L, double alpha, double* d1, double* d2) {
+    const double pa = fma(alpha, L.q2, L.p0);
+    const double s2 = fma(alpha, pa + L.p0, L.q0);
+    const double is = inv_sqrt(s2);
+    const double cs = L.mun0 * is;
+    const double pis = pa * is;
+    double e1 = cs * pa;
+    double e2 = cs * fma(-pis, pis, L.q2);
+    const double a = fma(-alpha, L.a1, L.a0), b = fma(-alpha, L.b1, L.b0);
+    if (a > 0.0 && b > 0.0) {
+        e1 -= L.kn * a * b;
+        e2 += fma(L.eh, b, L.ed * a);
+    }
+    *d1 = e1;
+    *d2 = e2;
 }
 
 // ---------------------------------------------------------------------------
@@ -177,7 +244,7 @@ k_reg_write(const float* __restrict__ x, const float* __restrict__ v, long long 
             const unsigned* __restrict__ cmask, const unsigned* __restrict__ blk, double h,
             long long cap, int* __restrict__ c_pid, int* __restrict__ c_rid, int* __restrict__ c_env,
             int* __restrict__ c_base, float* __restrict__ c_w, ContactRec* __restrict__ c_rec,
-            int substep, DevCounters* cnt) {
+            ContactDyn* __restrict__ c_dyn, int substep, DevCounters* cnt) {
     __shared__ unsigned wsum[17];
     if (cnt->abort_step) return;
     long long beg, end;
@@ -223,14 +290,16 @@ k_reg_write(const float* __restrict__ x, const float* __restrict__ v, long long 
                 const double vn0 = n[0] * (vp[0] - vr[0]) + n[1] * (vp[1] - vr[1]) + n[2] * (vp[2] - vr[2]);
                 const double n0 = normal_impulse(vn0, phi0, E.k, E.d, h);
                 ContactRec rec;
-                rec.n[0] = n[0]; rec.n[1] = n[1]; rec.n[2] = n[2];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) { rec.t1[a] = t1[a]; rec.t2[a] = t2[a]; rec.n[a] = n[a]; }
                 rec.phi0 = phi0;
                 rec.mun0 = R.mu * n0;
                 rec.k = E.k; rec.d = E.d; rec.eps_s = E.eps_s;
-                rec.b[0] = -(t1[0] * vr[0] + t1[1] * vr[1] + t1[2] * vr[2]);
-                rec.b[1] = -(t2[0] * vr[0] + t2[1] * vr[1] + t2[2] * vr[2]);
-                rec.b[2] = -(n[0] * vr[0] + n[1] * vr[1] + n[2] * vr[2]);
                 c_rec[c] = rec;
+                ContactDyn& D = c_dyn[c];
+                D.b[0] = -(t1[0] * vr[0] + t1[1] * vr[1] + t1[2] * vr[2]);
+                D.b[1] = -(t2[0] * vr[0] + t2[1] * vr[1] + t2[2] * vr[2]);
+                D.b[2] = -(n[0] * vr[0] + n[1] * vr[1] + n[2] * vr[2]);
                 c_pid[c] = (int)p;
                 c_rid[c] = r;
                 c_env[c] = e;
@@ -262,7 +331,7 @@ hipError_t launch_registration(const Work& w, const float* x, const float* v, do
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_reg_write, dim3(kSortBlocks), dim3(256), 0, s, x, v, w.P, w.envs,
                        w.n_envs, w.rigids, w.cmask, w.blk, h, w.cap_c, w.c_pid, w.c_rid, w.c_env,
-                       w.c_base, w.c_w, w.c_rec, substep, w.cnt);
+                       w.c_base, w.c_w, w.c_rec, w.c_dyn, substep, w.cnt);
     return hipGetLastError();
 }
 
@@ -451,32 +520,57 @@ __device__ __forceinline__ void contact_velocity(const ContactDyn& D, int k, dou
     for (int a = 0; a < 3; ++a) vc[a] = k == 0 ? D.vc[0][a] : fma(alpha_prev, D.uc[a], D.vc[src][a]);
 }
 
-__device__ __forceinline__ void ls_terms(const ContactParams& P, const double vc[3], const double u[3],
-                                         double alpha, double* d1, double* d2) {
-    double v[3] = {fma(alpha, u[0], vc[0]), fma(alpha, u[1], vc[1]), fma(alpha, u[2], vc[2])};
-    double g[3], g00, g01, g11, gnn;
-    contact_model(P, v, g, &g00, &g01, &g11, &gnn);
-    *d1 = -(g[0] * u[0] + g[1] * u[1] + g[2] * u[2]);
-    *d2 = g00 * u[0] * u[0] + 2.0 * g01 * u[0] * u[1] + g11 * u[1] * u[1] + gnn * u[2] * u[2];
+// Sum of x over the 64 lanes of a wave, the same bits in every lane: DPP
+// exchanges inside each row of 16 lanes (pairs, quads, half rows, rows; each
+// step adds two equal partial sums in either order, so the lanes stay equal),
+// then the four row sums read back and added in row order. Every lane of the
+// wave must be active.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, kCtrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum(double x) {
+    x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_move<0x141>(x);  // row_half_mirror
+    x += dpp_move<0x140>(x);  // row_mirror
+    const long long b = __builtin_bit_cast(long long, x);
+    double r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int lo = __builtin_amdgcn_readlane((int)b, 16 * q);
+        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * q);
+        r[q] = __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
+    }
+    return (r[0] + r[1]) + (r[2] + r[3]);
 }
 
-// Block-wide FP64 sum of NV values per thread into out[NV] (thread 0 writes).
+// Block-wide FP64 sums of NV values per thread, returned in every thread with
+// the same bits in every thread (and in every block that sums the same
+// values): wave sums, one workgroup barrier, then each thread adds the wave
+// sums in wave order. buf holds 2 x 16 x NV doubles used alternately, so a
+// wave that runs ahead cannot overwrite sums another wave is still reading.
 template <int NV>
-__device__ __forceinline__ void block_sum(double (&v)[NV], double* lds, double* out) {
+__device__ __forceinline__ void block_allsum(double (&v)[NV], double* buf, unsigned& parity) {
+    double* b = buf + (parity & 1u) * 16 * NV;
+    parity ^= 1u;
+    const int wave = threadIdx.x >> 6;
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
-        double x = v[k];
+        const double ws = wave_sum(v[k]);
+        if ((threadIdx.x & 63) == 0) b[wave * NV + k] = ws;
+    }
+    __syncthreads();
+    const int nw = blockDim.x >> 6;
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
-        if ((threadIdx.x & 63) == 0) lds[(threadIdx.x >> 6) * NV + k] = x;
+    for (int k = 0; k < NV; ++k) {
+        double t = 0.0;
+        for (int w = 0; w < nw; ++w) t += b[w * NV + k];
+        v[k] = t;
     }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        double s = 0.0;
-        for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) s += lds[wv * NV + threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    __syncthreads();
 }
 
 // Sum over the 27 stencil nodes of a contact of w times a 3-vector of the
@@ -519,12 +613,10 @@ __device__ __forceinline__ void initial_contact_velocity(const QnArgs& A, long l
     double sacc[3];
     stencil_sum<kSlotV>(A, c, sacc);
     const ContactRec& rec = A.c_rec[c];
-    double t1[3], t2[3];
-    frame_of(rec.n, t1, t2);
     ContactDyn& D = A.c_dyn[c];
-    D.vc[0][0] = t1[0] * sacc[0] + t1[1] * sacc[1] + t1[2] * sacc[2] + rec.b[0];
-    D.vc[0][1] = t2[0] * sacc[0] + t2[1] * sacc[1] + t2[2] * sacc[2] + rec.b[1];
-    D.vc[0][2] = rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2] + rec.b[2];
+    D.vc[0][0] = rec.t1[0] * sacc[0] + rec.t1[1] * sacc[1] + rec.t1[2] * sacc[2] + D.b[0];
+    D.vc[0][1] = rec.t2[0] * sacc[0] + rec.t2[1] * sacc[1] + rec.t2[2] * sacc[2] + D.b[1];
+    D.vc[0][2] = rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2] + D.b[2];
 }
 
 // g, H -> dv by 3x3 Cholesky, and this node's share of the iteration sums.
@@ -561,12 +653,11 @@ __device__ __forceinline__ void node_solve(SlotRec& S, const double j[3], const 
 }
 
 // R gamma and the upper triangle of R G R^T of one contact at contact velocity vc.
-__device__ __forceinline__ void contact_terms(const double n[3], const ContactParams& P, const double vc[3],
+__device__ __forceinline__ void contact_terms(const double t1[3], const double t2[3], const double n[3],
+                                              const ContactParams& P, const double vc[3],
                                               double rg[3], double rgr[6]) {
     double g[3], g00, g01, g11, gnn;
     contact_model(P, vc, g, &g00, &g01, &g11, &gnn);
-    double t1[3], t2[3];
-    frame_of(n, t1, t2);
 #pragma unroll
     for (int a = 0; a < 3; ++a) rg[a] = t1[a] * g[0] + t2[a] * g[1] + n[a] * g[2];
     int q = 0;
@@ -579,7 +670,7 @@ __device__ __forceinline__ void contact_terms(const double n[3], const ContactPa
 }
 __device__ __forceinline__ void contact_terms(const ContactRec& rec, double h, const double vc[3],
                                               double rg[3], double rgr[6]) {
-    contact_terms(rec.n, params_of(rec, h), vc, rg, rgr);
+    contact_terms(rec.t1, rec.t2, rec.n, params_of(rec, h), vc, rg, rgr);
 }
 
 // u_c = R_c^T sum_o w_o dv_slot(o)
@@ -587,10 +678,8 @@ __device__ __forceinline__ void contact_direction(const QnArgs& A, long long c, 
     double sacc[3];
     stencil_sum<kSlotDv>(A, c, sacc);
     const ContactRec& rec = A.c_rec[c];
-    double t1[3], t2[3];
-    frame_of(rec.n, t1, t2);
-    u[0] = t1[0] * sacc[0] + t1[1] * sacc[1] + t1[2] * sacc[2];
-    u[1] = t2[0] * sacc[0] + t2[1] * sacc[1] + t2[2] * sacc[2];
+    u[0] = rec.t1[0] * sacc[0] + rec.t1[1] * sacc[1] + rec.t1[2] * sacc[2];
+    u[1] = rec.t2[0] * sacc[0] + rec.t2[1] * sacc[1] + rec.t2[2] * sacc[2];
     u[2] = rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2];
 }
 
@@ -604,12 +693,10 @@ __device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, in
     const ContactRec& rec = A.c_rec[c];
     double g[3], g00, g01, g11, gnn;
     contact_model(params_of(rec, A.h), vc, g, &g00, &g01, &g11, &gnn);
-    double t1[3], t2[3];
-    frame_of(rec.n, t1, t2);
     double rg[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        rg[a] = t1[a] * g[0] + t2[a] * g[1] + rec.n[a] * g[2];
+        rg[a] = rec.t1[a] * g[0] + rec.t2[a] * g[1] + rec.n[a] * g[2];
         D.gam[a] = g[a];
     }
     const int r = A.c_rid[c];
@@ -661,7 +748,7 @@ __device__ double exact_line_search(Eval eval, double alpha0, double d0, int max
 }
 
 __device__ __forceinline__ void write_stats(const QnArgs& A, long long nc, long long ns, int k, int converged,
-                                            int ls_total, double res, double thr, const unsigned long long tph[5],
+                                            int ls_total, double res, double thr, const unsigned long long tph[6],
                                             bool aborted, int kind) {
     SubstepStats st;
     st.n_contacts = (int)nc;
@@ -672,7 +759,7 @@ __device__ __forceinline__ void write_stats(const QnArgs& A, long long nc, long 
     st.pad = kind;
     st.residual = res;
     st.threshold = thr;
-    for (int q = 0; q < 5; ++q) st.t_phase[q] = tph[q];
+    for (int q = 0; q < 6; ++q) st.t_phase[q] = tph[q];
     A.stats[A.substep] = st;
     if (!converged && !aborted) atomicOr(&A.cnt->flags, kFlagNoconv);
 }
@@ -719,29 +806,28 @@ __device__ __forceinline__ bool grid_sync(DevCounters* cnt, unsigned nblocks, un
 
 constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
 constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
-constexpr int kLsLdsFields = 11; // v_c, u_c, phi0, mu n0, k, d, eps_s of one more contact per thread in LDS
 constexpr int kQnMaxBlocks = 64; // grid size limit of k_qn (per-block partials staged in LDS)
 static_assert(kQnMaxBlocks * kQnSums <= kQnThreads, "one partial per thread");
 
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
-    __shared__ double lds[16 * 8];
+    __shared__ double rbuf[2 * 16 * kQnSums];
     __shared__ double tot[kQnSums];
-    __shared__ double bcast[8];
     __shared__ double racc[kMaxRigid * 6];
     __shared__ unsigned s_ok;
     __shared__ double red[kQnMaxBlocks * kQnSums];
-    __shared__ double ls_ovf[kLsLdsFields][kQnThreads];  // line-search contacts beyond the registers
+    __shared__ LsCoef ls_ovf[kQnThreads];  // line-search contacts beyond the registers
     __shared__ double nacc[9][kSlotChunk];     // j (3) and R G R^T (6) of a chunk of owned slots
 
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
     if (aborted || cnt->n_contacts <= (unsigned)A.blk_max) return;  // k_qn_block's case
     const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
-    unsigned long long tph[5] = {0, 0, 0, 0, 0};
+    unsigned long long tph[6] = {0, 0, 0, 0, 0, 0};
     unsigned long long tmark = 0;
     const unsigned G = gridDim.x;
     unsigned gen = __hip_atomic_load(&cnt->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned rpar = 0;  // parity of the block-sum buffer
     const long long nc = std::min<long long>(cnt->n_contacts, A.cap);
     const long long ns = cnt->n_slots;
     const int tid = threadIdx.x, T = blockDim.x;
@@ -774,13 +860,14 @@ k_qn(QnArgs A) {
                     const int e = eb + tid + u * T;
                     en[u] = A.e_ent[e < E1 ? e : E0];
                 }
-                double vc[kEntBatch][3], nrm[kEntBatch][3];
+                double vc[kEntBatch][3], fr[kEntBatch][9];
                 ContactParams P[kEntBatch];
 #pragma unroll
                 for (int u = 0; u < kEntBatch; ++u) {
                     contact_velocity(A.c_dyn[en[u].c], k, alpha_prev, vc[u]);
                     const ContactRec& R = A.c_rec[en[u].c];
-                    nrm[u][0] = R.n[0]; nrm[u][1] = R.n[1]; nrm[u][2] = R.n[2];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) { fr[u][a] = R.t1[a]; fr[u][3 + a] = R.t2[a]; fr[u][6 + a] = R.n[a]; }
                     P[u] = params_of(R, A.h);
                 }
 #pragma unroll
@@ -789,7 +876,7 @@ k_qn(QnArgs A) {
                     const int ls = en[u].slot - (int)sa;
                     const double w = en[u].w;
                     double rg[3], rgr[6];
-                    contact_terms(nrm[u], P[u], vc[u], rg, rgr);
+                    contact_terms(fr[u], fr[u] + 3, fr[u] + 6, P[u], vc[u], rg, rgr);
 #pragma unroll
                     for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * rg[a]);
 #pragma unroll
@@ -797,6 +884,7 @@ k_qn(QnArgs A) {
                 }
             }
             __syncthreads();
+            if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
             for (long long s = sa + tid; s < sb; s += T) {
                 const int ls = (int)(s - sa);
                 const double j[3] = {nacc[0][ls], nacc[1][ls], nacc[2][ls]};
@@ -805,10 +893,14 @@ k_qn(QnArgs A) {
             }
             __syncthreads();
         }
-        block_sum<kQnSums>(sums, lds, A.partial + (size_t)blockIdx.x * kQnSums);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
-        ok = grid_sync(cnt, G, &gen, &s_ok);
+        block_allsum<kQnSums>(sums, rbuf, rpar);
+        if (tid == 0) {
+#pragma unroll
+            for (int q = 0; q < kQnSums; ++q) A.partial[(size_t)blockIdx.x * kQnSums + q] = sums[q];
+        }
         if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
+        ok = grid_sync(cnt, G, &gen, &s_ok);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
         if (!ok) break;
         // every block sums the per-block partials in the same order
         if (tid < (int)G * kQnSums) red[tid] = A.partial[tid];
@@ -840,78 +932,56 @@ k_qn(QnArgs A) {
             for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
         }
         __syncthreads();
-        if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
-        ok = grid_sync(cnt, G, &gen, &s_ok);
         if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
+        ok = grid_sync(cnt, G, &gen, &s_ok);
+        if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
         if (!ok) break;
         // ---- exact line search, redundantly in every block ----------------------
-        // Contact c is taken by thread c mod T. The first kLsPer*T contacts
-        // stay in registers for all the evaluations, the next T in LDS, and
-        // any beyond are read from memory at each evaluation.
+        // Contact c is taken by thread c mod T. The closed-form coefficients of
+        // the first kLsPer*T contacts stay in registers for all the
+        // evaluations, the next T in LDS, and any beyond are formed from
+        // memory at each evaluation.
         const int src = k == 0 ? 0 : (k & 1);
-        double lv[kLsPer][3], lu[kLsPer][3], lphi[kLsPer], lmun[kLsPer], lk[kLsPer], ld[kLsPer], leps[kLsPer];
+        LsCoef lc[kLsPer];
 #pragma unroll
         for (int u = 0; u < kLsPer; ++u) {
             const long long c = tid + (long long)u * T;
-            const bool valid = c < nc;
-            const ContactDyn& D = A.c_dyn[valid ? c : 0];
-            const ContactRec& R = A.c_rec[valid ? c : 0];
-            lphi[u] = R.phi0; lmun[u] = R.mun0; lk[u] = R.k; ld[u] = R.d; leps[u] = R.eps_s;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                lv[u][a] = D.vc[src][a];
-                lu[u][a] = valid ? D.uc[a] : 0.0;  // a zero direction adds exactly nothing
-            }
+            lc[u] = c < nc ? ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc)
+                           : ls_coef_zero();
         }
         const long long c_lds = tid + (long long)kLsPer * T;
         const bool use_lds = (long long)kLsPer * T < nc;
-        if (use_lds) {
-            const bool valid = c_lds < nc;
-            const ContactDyn& D = A.c_dyn[valid ? c_lds : 0];
-            const ContactRec& R = A.c_rec[valid ? c_lds : 0];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                ls_ovf[a][tid] = D.vc[src][a];
-                ls_ovf[3 + a][tid] = valid ? D.uc[a] : 0.0;
-            }
-            ls_ovf[6][tid] = R.phi0; ls_ovf[7][tid] = R.mun0; ls_ovf[8][tid] = R.k;
-            ls_ovf[9][tid] = R.d; ls_ovf[10][tid] = R.eps_s;
-        }
+        if (use_lds)
+            ls_ovf[tid] = c_lds < nc ? ls_coef(params_of(A.c_rec[c_lds], A.h), A.c_dyn[c_lds].vc[src],
+                                               A.c_dyn[c_lds].uc)
+                                     : ls_coef_zero();
         auto eval = [&](double alpha, double* d2out) -> double {
             double acc2[2] = {0.0, 0.0};
 #pragma unroll
             for (int u = 0; u < kLsPer; ++u) {
-                const ContactParams P = {lphi[u], lmun[u], lk[u], ld[u], leps[u], A.h};
                 double d1, d2;
-                ls_terms(P, lv[u], lu[u], alpha, &d1, &d2);
+                ls_eval(lc[u], alpha, &d1, &d2);
                 acc2[0] += d1;
                 acc2[1] += d2;
             }
             if (use_lds) {
-                const double vc[3] = {ls_ovf[0][tid], ls_ovf[1][tid], ls_ovf[2][tid]};
-                const double u[3] = {ls_ovf[3][tid], ls_ovf[4][tid], ls_ovf[5][tid]};
-                const ContactParams P = {ls_ovf[6][tid], ls_ovf[7][tid], ls_ovf[8][tid],
-                                         ls_ovf[9][tid], ls_ovf[10][tid], A.h};
                 double d1, d2;
-                ls_terms(P, vc, u, alpha, &d1, &d2);
+                ls_eval(ls_ovf[tid], alpha, &d1, &d2);
                 acc2[0] += d1;
                 acc2[1] += d2;
                 for (long long c = c_lds + T; c < nc; c += T) {
-                    double vc[3], u[3], d1, d2;
-                    const ContactDyn& D = A.c_dyn[c];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) { vc[a] = D.vc[src][a]; u[a] = D.uc[a]; }
-                    ls_terms(params_of(A.c_rec[c], A.h), vc, u, alpha, &d1, &d2);
+                    ls_eval(ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc), alpha,
+                            &d1, &d2);
                     acc2[0] += d1;
                     acc2[1] += d2;
                 }
             }
-            block_sum<2>(acc2, lds, bcast);
-            *d2out = Aq + bcast[1];
-            return fma(Aq, alpha, Bq) + bcast[0];
+            block_allsum<2>(acc2, rbuf, rpar);
+            *d2out = Aq + acc2[1];
+            return fma(Aq, alpha, Bq) + acc2[0];
         };
         const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
+        if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
         for (long long s = s0 + tid; s < s1; s += T) {
             SlotRec& S = A.s_rec[s];
 #pragma unroll
@@ -944,19 +1014,15 @@ k_qn(QnArgs A) {
 // search reads its contact data from LDS. Workgroup barriers only.
 // ---------------------------------------------------------------------------
 struct BlkShared {
-    float gR[3][kBlkMaxContacts];   // R gamma (world frame)
-    float gH[6][kBlkMaxContacts];   // R G R^T (upper triangle)
-    float lv[3][kBlkMaxContacts];   // line search: v_c^k (contact frame)
-    float lu[3][kBlkMaxContacts];   //              u_c^k
-    float lp[2][kBlkMaxContacts];   //              phi0, mu n0
+    double gR[3][kBlkMaxContacts];  // R gamma (world frame)
+    double gH[6][kBlkMaxContacts];  // R G R^T (upper triangle)
+    LsCoef lc[kBlkMaxContacts];     // line-search coefficients
 };
 
 __global__ void __launch_bounds__(kBlkThreads)
 k_qn_block(QnArgs A) {
     __shared__ BlkShared S;
-    __shared__ double lds[16 * 8];
-    __shared__ double tot[kQnSums];
-    __shared__ double bcast[8];
+    __shared__ double rbuf[2 * 16 * kQnSums];
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
     if (!aborted && cnt->n_contacts > (unsigned)A.blk_max) return;  // k_qn's case
@@ -964,7 +1030,8 @@ k_qn_block(QnArgs A) {
     const long long ns = aborted ? 0 : cnt->n_slots;
     const int tid = threadIdx.x, T = blockDim.x;
     const double pnorm_all = cnt->pnorm_all;
-    unsigned long long tph[5] = {0, 0, 0, 0, 0}, tmark = 0;
+    unsigned long long tph[6] = {0, 0, 0, 0, 0, 0}, tmark = 0;
+    unsigned rpar = 0;  // parity of the block-sum buffer
     const bool timer = tid == 0;
 
     for (long long c = tid; c < nc; c += T) initial_contact_velocity(A, c);
@@ -985,9 +1052,9 @@ k_qn_block(QnArgs A) {
             }
             contact_terms(A.c_rec[c], A.h, vc, rg, rgr);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) S.gR[a][c] = (float)rg[a];
+            for (int a = 0; a < 3; ++a) S.gR[a][c] = rg[a];
 #pragma unroll
-            for (int q = 0; q < 6; ++q) S.gH[q][c] = (float)rgr[q];
+            for (int q = 0; q < 6; ++q) S.gH[q][c] = rgr[q];
         }
         __syncthreads();
         // ---- node pass ----------------------------------------------------------
@@ -1001,18 +1068,18 @@ k_qn_block(QnArgs A) {
                 const Entry en = A.e_ent[e];
                 const double w = en.w, ww = w * w;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) j[a] += w * (double)S.gR[a][en.c];
+                for (int a = 0; a < 3; ++a) j[a] += w * S.gR[a][en.c];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) Hc[q] += ww * (double)S.gH[q][en.c];
+                for (int q = 0; q < 6; ++q) Hc[q] += ww * S.gH[q][en.c];
             }
             node_solve(A.s_rec[s], j, Hc, sums);
         }
-        block_sum<kQnSums>(sums, lds, tot);
+        block_allsum<kQnSums>(sums, rbuf, rpar);
         if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
-        const double p2 = fmax(pnorm_all - tot[3] + tot[2], 0.0);
-        res = sqrt(tot[0]);
-        thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(tot[1]));
-        const double Aq = tot[4], Bq = tot[5], d0 = tot[6];
+        const double p2 = fmax(pnorm_all - sums[3] + sums[2], 0.0);
+        res = sqrt(sums[0]);
+        thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(sums[1]));
+        const double Aq = sums[4], Bq = sums[5], d0 = sums[6];
         if (res < thr) { converged = 1; break; }
         if (k >= A.max_iter || !(d0 < 0.0)) break;
         // ---- u_c = R_c^T J dv; stage the line search ----------------------------
@@ -1022,38 +1089,26 @@ k_qn_block(QnArgs A) {
             contact_direction(A, c, u);
             const int src = k == 0 ? 0 : (k & 1);
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                D.uc[a] = u[a];
-                S.lu[a][c] = (float)u[a];
-                S.lv[a][c] = (float)D.vc[src][a];
-            }
-            const ContactRec& rec = A.c_rec[c];
-            S.lp[0][c] = (float)rec.phi0;
-            S.lp[1][c] = (float)rec.mun0;
+            for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
+            S.lc[c] = ls_coef(params_of(A.c_rec[c], A.h), D.vc[src], u);
         }
         __syncthreads();
-        if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
+        if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
         // ---- exact line search ----------------------------------------------------
         auto eval = [&](double alpha, double* d2out) -> double {
             double acc2[2] = {0.0, 0.0};
             for (long long c = tid; c < nc; c += T) {
-                const double vc[3] = {S.lv[0][c], S.lv[1][c], S.lv[2][c]};
-                const double u[3] = {S.lu[0][c], S.lu[1][c], S.lu[2][c]};
-                const ContactRec& R = A.c_rec[c];
-                ContactParams P = params_of(R, A.h);
-                P.phi0 = S.lp[0][c];
-                P.mun0 = S.lp[1][c];
                 double d1, d2;
-                ls_terms(P, vc, u, alpha, &d1, &d2);
+                ls_eval(S.lc[c], alpha, &d1, &d2);
                 acc2[0] += d1;
                 acc2[1] += d2;
             }
-            block_sum<2>(acc2, lds, bcast);
-            *d2out = Aq + bcast[1];
-            return fma(Aq, alpha, Bq) + bcast[0];
+            block_allsum<2>(acc2, rbuf, rpar);
+            *d2out = Aq + acc2[1];
+            return fma(Aq, alpha, Bq) + acc2[0];
         };
         const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
+        if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
         for (long long s = tid; s < ns; s += T) {
             SlotRec& R = A.s_rec[s];
 #pragma unroll

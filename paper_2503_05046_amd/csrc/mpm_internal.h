@@ -53,17 +53,18 @@ struct SubstepStats {
     int pad;
     double residual;
     double threshold;
-    unsigned long long t_phase[5];  // solver wall-clock ticks: node pass, barrier, contact pass, barrier, line search
+    unsigned long long t_phase[6];  // solver wall-clock ticks: node gather, node solve, barrier, contact pass,
+                                    // barrier, line search
 };
 
 // Contact solver data as compact records, so that a gather of one contact or
 // one contact node touches one or two cache lines.
 struct alignas(128) ContactRec {
-    double n[3];     // world normal (third axis of the contact frame)
-    double phi0;     // penetration at substep start
-    double mun0;     // mu times the lagged normal impulse
+    double t1[3], t2[3];  // tangent axes of the contact frame R_c = [t1 t2 n] (world)
+    double n[3];          // world normal
+    double phi0;          // penetration at substep start
+    double mun0;          // mu times the lagged normal impulse
     double k, d, eps_s;
-    double b[3];     // bias velocity -R_c^T v_rigid(x_p)
 };
 
 struct alignas(16) ContactStencil {
@@ -71,10 +72,11 @@ struct alignas(16) ContactStencil {
     float w[27];     // stencil weights
 };
 
-struct alignas(16) ContactDyn {
+struct alignas(128) ContactDyn {
     double vc[2][3];  // contact velocity, double-buffered by iteration parity
     double uc[3];     // R_c^T J dv of the current iteration
     double gam[3];    // impulse on MPM at exit (contact frame)
+    double b[3];      // bias velocity -R_c^T v_rigid(x_p)
 };
 
 struct alignas(16) SlotRec {

@@ -17,6 +17,11 @@ synthetic scenes of the same kind stand in for them, larger and denser):
 * ``gripper``        250k-particle elastic ellipsoid (E=5e4, nu=0.4) on a 96^3
                      grid between two kinematic jaw boxes closing at 0.05 m/s,
                      mu=0.8, h=1e-4, 10 substeps per rigid step.
+* ``batched``        many independent environments in one handle: particle
+                     counts log-uniform in [p_min, p_max], each env with its own
+                     n^3 grid (dx = 1/n), elastic or sand at random, a block of
+                     particles falling at 1 m/s onto 1-3 random static boxes
+                     with mu uniform in [0.2, 0.9].
 * ``tiny_block`` / ``tiny_random``: small scenes for exhaustive checks.
 
 Units are SI, z is up, gravity is (0, 0, -9.81). The domain of every env is
@@ -192,6 +197,44 @@ def gripper(n_particles: int = 250_000, seed: int = 2, n: int = 96) -> Scene:
             for s in (-1.0, 1.0)]
     x, v, F, C = _state(pos, (0.0, 0.0, 0.0))
     return Scene("gripper", 1e-4, 10, [env], jaws, x, v, F, C)
+
+
+def batched(n_envs: int = 64, seed: int = 4, p_min: int = 5_000, p_max: int = 100_000,
+            n: int = 64, h: float = 1e-4, N: int = 10) -> Scene:
+    """Independent environments of uneven size, each a particle block
+    (2 particles per cell per axis on average, uniform random positions) just
+    above 1-3 static boxes, falling at 1 m/s; materials alternate at random
+    between fixed-corotated (E=1e5, nu=0.3) and Drucker-Prager sand
+    (E=3.5e5, nu=0.3, 30 deg)."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n
+    counts = np.exp(rng.uniform(math.log(p_min), math.log(p_max), n_envs)).astype(np.int64)
+    envs, rigids, xs = [], [], []
+    p0 = 0
+    for e in range(n_envs):
+        cnt = int(counts[e])
+        side = max(4.0 * dx, cnt ** (1.0 / 3.0) * 0.5 * dx)
+        n_box = int(rng.integers(1, 4))
+        top = 0.12
+        # boxes side by side under the block, tops at z = top
+        half_x = 0.5 * side / n_box + 2.0 * dx
+        cx0 = 0.5 - 0.5 * side
+        for b in range(n_box):
+            cx = cx0 + (b + 0.5) * side / n_box
+            rigids.append(RigidSpec(env=e, shape=BOX, mu=float(rng.uniform(0.2, 0.9)),
+                                    half=(half_x, 0.5 * side + 2.0 * dx, 0.04),
+                                    t=(cx, 0.5, top - 0.04)))
+        lo = np.array([0.5 - 0.5 * side, 0.5 - 0.5 * side, top + 0.5 * dx])
+        xs.append(lo + rng.uniform(0.0, side, (cnt, 3)))
+        V0 = side ** 3 / cnt
+        sand = bool(rng.integers(0, 2))
+        E_mod = 3.5e5 if sand else 1e5
+        envs.append(EnvSpec(dims=(n, n, n), dx=dx, material=DRUCKER_PRAGER if sand else FIXED_COROTATED,
+                            E=E_mod, nu=0.3, rho=1000.0, V0=V0, friction_angle=30.0,
+                            k=_stiffness(E_mod, V0), p_begin=p0, p_end=p0 + cnt))
+        p0 += cnt
+    x, v, F, C = _state(np.concatenate(xs), (0.0, 0.0, -1.0))
+    return Scene("batched", h, N, envs, rigids, x, v, F, C)
 
 
 def tiny_block(n_side: int = 3, seed: int = 5, vel=(0.3, 0.1, -0.5), mu: float = 0.5,
