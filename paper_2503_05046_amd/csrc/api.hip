@@ -40,7 +40,6 @@ mpm_status fail(mpm_status st, const char* fmt, ...) {
 
 constexpr int kMaxRigidTotal = 256;
 constexpr int kMaxQnBlocks = 1024;
-constexpr int kQnDefaultBlocks = 32;   // first step, before any problem size is known
 constexpr int kQnItemsPerBlock = 256;  // contact nodes per solver block
 constexpr size_t kAlign = 256;
 
@@ -154,7 +153,12 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->blk = L.take<unsigned>(256 * kSortBlocks + 2 * kSortBlocks);
     w->partial = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
     w->rigid_acc = L.take<double>(6 * kMaxRigidTotal);
-    w->sstats = L.take<SubstepStats>(z.N);
+    w->sstats = L.take<SubstepStats>((size_t)z.N * z.n_envs);
+    w->env_pnorm = L.take<double>(z.n_envs);
+    w->env_range = L.take<int>(4 * (size_t)z.n_envs);
+    w->qn_map = L.take<int2>(kMaxQnBlocks);
+    w->env_qn = L.take<int>(2 * (size_t)z.n_envs);
+    w->env_bar = L.take<unsigned>((size_t)kBarStride * z.n_envs);
     w->cnt = L.take<DevCounters>(1);
     w->envs = L.take<DevEnv>(z.n_envs);
     w->rigids = L.take<DevRigid>(kMaxRigidTotal);
@@ -207,14 +211,15 @@ struct mpm_handle {
     int key_bits;
     int qn_cap;          // co-resident blocks the cooperative solver may use
     double wall_khz;     // device wall-clock rate
-    int blk_max;         // contact count up to which one workgroup runs the solver
-    int slots_per_block; // contact nodes per block of the multi-block solver
-    int qn_blocks_next;  // blocks for the next step, sized from the last one's problem
+    int slots_per_block; // contact nodes per solver block
+    std::vector<int> env_slots;  // per environment: most contact nodes in a substep of the last step
     // pinned host staging
     DevRigid* h_rigids;
     double* h_racc;
-    SubstepStats* h_stats;
+    SubstepStats* h_stats;  // [N][n_envs]
     DevCounters* h_cnt;
+    int2* h_qn_map;         // solver plan staging
+    int* h_env_qn;
     // profiling
     bool prof = false;
     std::vector<hipEvent_t> events;   // pairs (start, stop)
@@ -244,6 +249,54 @@ struct ProfScope {
         if (pair >= 0) (void)hipEventRecord(h->events[2 * pair + 1], h->stream);
     }
 };
+// Environment with the most solver iterations in one substep's stats.
+int longest_solve(const SubstepStats* q, int n_envs) {
+    int best = 0;
+    for (int e = 1; e < n_envs; ++e)
+        if (q[e].iterations > q[best].iterations) best = e;
+    return best;
+}
+
+// Solver plan for one host step: a group of blocks per environment, sized by
+// the environment's contact nodes in the previous step (at least one block,
+// at most kQnMaxGroup, all groups co-resident). With more environments than
+// co-resident blocks every block takes environments in turn. Fills the pinned
+// staging tables; returns the number of blocks.
+int plan_solver(mpm_handle* h, int* env_stride) {
+    const int n_envs = (int)h->envs.size();
+    const int cap = h->qn_cap;
+    if (n_envs > cap) {
+        for (int b = 0; b < cap; ++b) h->h_qn_map[b] = make_int2(b, 0);
+        for (int e = 0; e < n_envs; ++e) {
+            h->h_env_qn[2 * e] = e % cap;
+            h->h_env_qn[2 * e + 1] = 1;
+        }
+        *env_stride = cap;
+        return cap;
+    }
+    std::vector<int> g(n_envs);
+    int total = 0;
+    for (int e = 0; e < n_envs; ++e) {
+        g[e] = std::max(1, std::min(kQnMaxGroup, (h->env_slots[e] + h->slots_per_block - 1) / h->slots_per_block));
+        total += g[e];
+    }
+    while (total > cap) {  // shrink the largest groups until all fit
+        int big = 0;
+        for (int e = 1; e < n_envs; ++e)
+            if (g[e] > g[big]) big = e;
+        --g[big];
+        --total;
+    }
+    int b = 0;
+    for (int e = 0; e < n_envs; ++e) {
+        h->h_env_qn[2 * e] = b;
+        h->h_env_qn[2 * e + 1] = g[e];
+        for (int r = 0; r < g[e]; ++r) h->h_qn_map[b++] = make_int2(e, r);
+    }
+    *env_stride = 0;
+    return total;
+}
+
 }  // namespace
 
 extern "C" {
@@ -288,21 +341,21 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         delete h;
         return fail(MPM_EDEVICE, "cannot query the device");
     }
-    h->w.qn_blocks = std::max(1, std::min({qn_cap, cus, kMaxQnBlocks}));
+    h->w.qn_blocks = std::max(1, std::min(qn_cap, kMaxQnBlocks));
     h->qn_cap = h->w.qn_blocks;
+    h->env_slots.assign(desc->n_envs, 0);
     {
         int khz = 0;
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
         h->wall_khz = khz;
     }
-    h->qn_blocks_next = std::min(h->qn_cap, kQnDefaultBlocks);
     {
-        // tuning override of the single-workgroup solver threshold
-        const char* env = getenv("MPM_SOLVER_BLOCK_MAX");
-        h->blk_max = env ? atoi(env) : 256;
-        // and of the contact nodes per solver block
+        // tuning override of the contact nodes per solver block
         const char* spb = getenv("MPM_SOLVER_SLOTS_PER_BLOCK");
         h->slots_per_block = spb ? std::max(1, atoi(spb)) : kQnItemsPerBlock;
+        // and a cap on the solver's blocks (below it, environments share blocks)
+        const char* mb = getenv("MPM_SOLVER_MAX_BLOCKS");
+        if (mb && atoi(mb) > 0) h->qn_cap = std::min(h->qn_cap, atoi(mb));
     }
     h->w.n_rigid = 0;
     int tiles = 0;
@@ -344,8 +397,10 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
     h->key_bits = bits + 6;
     if (hipHostMalloc((void**)&h->h_rigids, sizeof(DevRigid) * kMaxRigidTotal) != hipSuccess ||
         hipHostMalloc((void**)&h->h_racc, sizeof(double) * 6 * kMaxRigidTotal) != hipSuccess ||
-        hipHostMalloc((void**)&h->h_stats, sizeof(SubstepStats) * desc->N) != hipSuccess ||
-        hipHostMalloc((void**)&h->h_cnt, sizeof(DevCounters)) != hipSuccess) {
+        hipHostMalloc((void**)&h->h_stats, sizeof(SubstepStats) * desc->N * desc->n_envs) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_cnt, sizeof(DevCounters)) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_qn_map, sizeof(int2) * kMaxQnBlocks) != hipSuccess ||
+        hipHostMalloc((void**)&h->h_env_qn, sizeof(int) * 2 * desc->n_envs) != hipSuccess) {
         mpm_destroy(h);
         return fail(MPM_EDEVICE, "hipHostMalloc failed");
     }
@@ -357,6 +412,7 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
     if (e == hipSuccess) e = hipMemsetAsync(W.ntile_mark, 0, sizeof(unsigned) * W.n_tiles, s);
     if (e == hipSuccess) e = hipMemsetAsync(W.ptile_of, 0xFF, sizeof(int) * W.n_tiles, s);
     if (e == hipSuccess) e = hipMemsetAsync(W.cnt, 0, sizeof(DevCounters), s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.env_bar, 0, sizeof(unsigned) * kBarStride * W.n_envs, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -458,9 +514,13 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     const mpm_desc& d = h->d;
     const int N = d.N;
     const int ls_steps = d.ls_max_steps > 0 ? d.ls_max_steps : 100;
-    const int qn_blocks = h->qn_blocks_next;
+    const int n_envs = (int)h->envs.size();
+    int env_stride = 0;
+    const int qn_blocks = plan_solver(h, &env_stride);
     HIP_TRY(hipMemcpyAsync(W.rigids, h->h_rigids, sizeof(DevRigid) * std::max(nr, 1), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.qn_map, h->h_qn_map, sizeof(int2) * qn_blocks, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.env_qn, h->h_env_qn, sizeof(int) * 2 * n_envs, hipMemcpyHostToDevice, s));
     HIP_TRY(launch_clear_step(W, N, s));
     int npair = 0;
     {
@@ -500,7 +560,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         {
             ProfScope ps(h, MPM_K_SOLVE, npair);
             HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
-                              h->blk_max, s));
+                              env_stride, s));
         }
         {
             ProfScope ps(h, MPM_K_G2P, npair);
@@ -509,7 +569,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         }
     }
     HIP_TRY(hipMemcpyAsync(h->h_cnt, W.cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N * n_envs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const unsigned flags = h->h_cnt->flags;
@@ -521,13 +581,16 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
             h->acc.launches[h->ev_class[q]] += 1;
         }
         for (int k = 0; k < N; ++k) {
-            const SubstepStats& q = h->h_stats[k];
-            h->acc.solver_iterations += q.iterations;
-            h->acc.solver_ls_rounds += q.ls_rounds;
-            h->acc.solver_contact_iters += (int64_t)q.iterations * q.n_contacts;
-            h->acc.solver_node_iters += (int64_t)q.iterations * q.n_slots;
-            h->acc.solver_contact_rounds += (int64_t)q.ls_rounds * q.n_contacts;
-            for (int ph = 0; ph < 6; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)q.t_phase[ph] / h->wall_khz;
+            const SubstepStats* q = h->h_stats + (size_t)k * n_envs;
+            const SubstepStats& lead = q[longest_solve(q, n_envs)];
+            h->acc.solver_iterations += lead.iterations;
+            h->acc.solver_ls_rounds += lead.ls_rounds;
+            for (int e = 0; e < n_envs; ++e) {
+                h->acc.solver_contact_iters += (int64_t)q[e].iterations * q[e].n_contacts;
+                h->acc.solver_node_iters += (int64_t)q[e].iterations * q[e].n_slots;
+                h->acc.solver_contact_rounds += (int64_t)q[e].ls_rounds * q[e].n_contacts;
+            }
+            for (int ph = 0; ph < 6; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)lead.t_phase[ph] / h->wall_khz;
         }
     }
     if (h->h_cnt->abort_step && h->h_cnt->abort_substep > 0) {
@@ -551,23 +614,32 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         st->total_iterations = 0;
         st->max_contacts = 0;
         for (int k = 0; k < N; ++k) {
-            const SubstepStats& q = h->h_stats[k];
-            st->max_iterations = std::max(st->max_iterations, q.iterations);
-            st->total_iterations += q.iterations;
-            st->max_contacts = std::max(st->max_contacts, q.n_contacts);
-            if (st->iterations) st->iterations[k] = q.iterations;
-            if (st->contacts) st->contacts[k] = q.n_contacts;
-            if (st->contact_nodes) st->contact_nodes[k] = q.n_slots;
-            if (st->residual) st->residual[k] = q.residual;
-            if (st->threshold) st->threshold[k] = q.threshold;
+            // over the environments: the longest solve, all contacts, the worst residual
+            const SubstepStats* q = h->h_stats + (size_t)k * n_envs;
+            const SubstepStats& lead = q[longest_solve(q, n_envs)];
+            int contacts = 0, nodes = 0, worst = 0;
+            for (int e = 0; e < n_envs; ++e) {
+                contacts += q[e].n_contacts;
+                nodes += q[e].n_slots;
+                if (q[e].threshold > 0.0 &&
+                    (q[worst].threshold <= 0.0 || q[e].residual * q[worst].threshold > q[worst].residual * q[e].threshold))
+                    worst = e;
+            }
+            st->max_iterations = std::max(st->max_iterations, lead.iterations);
+            st->total_iterations += lead.iterations;
+            st->max_contacts = std::max(st->max_contacts, contacts);
+            if (st->iterations) st->iterations[k] = lead.iterations;
+            if (st->contacts) st->contacts[k] = contacts;
+            if (st->contact_nodes) st->contact_nodes[k] = nodes;
+            if (st->residual) st->residual[k] = q[worst].residual;
+            if (st->threshold) st->threshold[k] = q[worst].threshold;
         }
     }
-    // size the next step's solver launch from this step's largest problem
-    {
+    // size the next step's solver groups from this step's problems
+    for (int e = 0; e < n_envs; ++e) {
         int most = 0;
-        for (int k = 0; k < N; ++k) most = std::max(most, h->h_stats[k].n_slots);
-        if (most > 0)
-            h->qn_blocks_next = std::max(1, std::min(h->qn_cap, (most + h->slots_per_block - 1) / h->slots_per_block));
+        for (int k = 0; k < N; ++k) most = std::max(most, h->h_stats[(size_t)k * n_envs + e].n_slots);
+        h->env_slots[e] = most;
     }
     // host side of the split: advance kinematic bodies with their twist
     for (HostRigid& q : h->rigids) {
@@ -600,6 +672,8 @@ void mpm_destroy(mpm_handle* h) {
     if (h->h_racc) (void)hipHostFree(h->h_racc);
     if (h->h_stats) (void)hipHostFree(h->h_stats);
     if (h->h_cnt) (void)hipHostFree(h->h_cnt);
+    if (h->h_qn_map) (void)hipHostFree(h->h_qn_map);
+    if (h->h_env_qn) (void)hipHostFree(h->h_env_qn);
     delete h;
 }
 

@@ -12,20 +12,22 @@
 // contact order: a deterministic CSR with no atomics.
 //
 // Solver: one persistent cooperative kernel runs Algorithm 1 to convergence
-// with the iterate, gradient, block Hessian, search direction, contact
-// velocities and every reduction in double precision. Per iteration:
+// for every environment, each environment's problem on its own group of
+// blocks, with the iterate, gradient, block Hessian, search direction,
+// contact velocities and every reduction in double precision. Per iteration:
 //   node pass   each slot gathers its contacts' impulses and Hessians (each
 //               contact's model is re-evaluated by its 27 nodes instead of
 //               being scattered, which saves a barrier and all atomics),
 //               forms g = m (v - v*) - j and H, solves the 3x3 block by
 //               Cholesky, and adds its share of the norms;
-//   barrier     every block reduces the per-block partials in the same order,
-//               so all blocks take the same stopping decision;
+//   barrier     every block of the group reduces the per-block partials in
+//               the same order, so all take the same stopping decision;
 //   contact pass u_c = R_c^T sum w dv;
 //   barrier     then the exact line search of Algorithm 1 (1-D Newton with a
-//               bisection fallback) runs redundantly in every block over all
-//               contacts with block-local reductions, so it needs no global
-//               synchronisation; every block obtains the same step length.
+//               bisection fallback) runs redundantly in every block of the
+//               group over the environment's contacts with block-local
+//               reductions, so it needs no further synchronisation; every
+//               block obtains the same step length.
 // Contact velocities are carried as v_c + alpha u_c (the contact velocity is
 // linear in the grid velocity), double-buffered by iteration parity.
 #include "mpm_internal.h"
@@ -41,8 +43,6 @@ constexpr unsigned kFlagCapacity = 8u;
 constexpr unsigned kFlagHang = 16u;
 constexpr long long kBarrierTimeoutCycles = 5000000000ll;  // ~2 s: a healthy barrier takes microseconds
 constexpr int kQnThreads = 512;
-constexpr int kBlkThreads = 1024;      // single-workgroup solver
-constexpr int kBlkMaxContacts = 512;   // contacts whose per-iteration terms fit in one CU's LDS
 constexpr int kSlotChunk = 512;     // contact nodes whose accumulators are staged in LDS at once
 constexpr int kMaxRigid = 256;
 
@@ -445,6 +445,35 @@ k_slot_init(const int* __restrict__ s_node, const float4* __restrict__ vel, cons
     }
 }
 
+// First index in a[0, n) whose value is >= key (a ascending).
+__device__ __forceinline__ long long lower_bound_i(const int* a, long long n, long long key) {
+    long long lo = 0, hi = n;
+    while (lo < hi) {
+        const long long mid = (lo + hi) >> 1;
+        if ((long long)a[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Contacts and contact nodes of every environment: contacts are numbered in
+// particle order and contact nodes in global node order, and both orders
+// group the environments, so each environment owns one range of each.
+__global__ void __launch_bounds__(256)
+k_env_ranges(const DevEnv* __restrict__ envs, int n_envs, const int* __restrict__ c_env,
+             const int* __restrict__ s_node, const DevCounters* cnt, long long cap, int* __restrict__ range) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_envs) return;
+    const bool aborted = cnt->abort_step != 0u;
+    const long long nc = aborted ? 0 : std::min<long long>(cnt->n_contacts, cap);
+    const long long ns = aborted ? 0 : (long long)cnt->n_slots;
+    const DevEnv& E = envs[e];
+    const long long n0 = E.node_base, n1 = n0 + (long long)E.dims[0] * E.dims[1] * E.dims[2];
+    range[4 * e + 0] = (int)lower_bound_i(c_env, nc, e);
+    range[4 * e + 1] = (int)lower_bound_i(c_env, nc, e + 1);
+    range[4 * e + 2] = (int)lower_bound_i(s_node, ns, n0);
+    range[4 * e + 3] = (int)lower_bound_i(s_node, ns, n1);
+}
+
 // Key width of the contact-node pairs (node index, or n_nodes for a
 // zero-weight stencil entry).
 static int pair_key_bits(const Work& w) {
@@ -470,6 +499,8 @@ hipError_t launch_contact_setup(const Work& w, hipStream_t s) {
                        w.s_beg, w.c_st, w.e_ent);
     hipLaunchKernelGGL(k_slot_init, dim3(1024), dim3(256), 0, s, w.s_node, w.vel,
                        (const DevCounters*)w.cnt, w.s_rec);
+    hipLaunchKernelGGL(k_env_ranges, dim3((w.n_envs + 255) / 256), dim3(256), 0, s, w.envs, w.n_envs,
+                       w.c_env, w.s_node, (const DevCounters*)w.cnt, w.cap_c, w.env_range);
     return hipGetLastError();
 }
 
@@ -496,7 +527,13 @@ struct QnArgs {
     int substep;
     double h, eps_r, eps_a;
     int max_iter, ls_max_steps;
-    int blk_max;            // largest contact count solved by the single-workgroup kernel
+    const int2* qn_map;        // per block: (environment, rank in its group)
+    const int* env_qn;         // per environment: first block and size of its group
+    const int* env_range;      // per environment: contacts [c0, c1), contact nodes [s0, s1)
+    const double* env_pnorm;   // per environment: sum m |v*|^2 over its active nodes
+    unsigned* env_bar;         // per environment: barrier count and generation
+    int n_envs;
+    int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
     DevCounters* cnt;
 };
 
@@ -747,9 +784,9 @@ __device__ double exact_line_search(Eval eval, double alpha0, double d0, int max
     return alpha;
 }
 
-__device__ __forceinline__ void write_stats(const QnArgs& A, long long nc, long long ns, int k, int converged,
-                                            int ls_total, double res, double thr, const unsigned long long tph[6],
-                                            bool aborted, int kind) {
+__device__ __forceinline__ void write_stats(const QnArgs& A, int env, long long nc, long long ns, int k,
+                                            int converged, int ls_total, double res, double thr,
+                                            const unsigned long long tph[6], bool aborted, int kind) {
     SubstepStats st;
     st.n_contacts = (int)nc;
     st.n_slots = (int)ns;
@@ -760,32 +797,43 @@ __device__ __forceinline__ void write_stats(const QnArgs& A, long long nc, long 
     st.residual = res;
     st.threshold = thr;
     for (int q = 0; q < 6; ++q) st.t_phase[q] = tph[q];
-    A.stats[A.substep] = st;
+    A.stats[(size_t)A.substep * A.n_envs + env] = st;
     if (!converged && !aborted) atomicOr(&A.cnt->flags, kFlagNoconv);
 }
 
 // ---------------------------------------------------------------------------
-// Multi-block solver: persistent cooperative kernel, two grid barriers per
-// iteration (see the file header). Takes problems of more than
-// kBlkMaxContacts contacts.
+// Solver: one persistent cooperative kernel for every environment. Each
+// environment's contact problem is independent (its own stopping test and
+// line search) and is solved by a group of blocks: the group splits the
+// environment's contact nodes and contacts evenly and meets at two group
+// barriers per iteration; a group of one block needs workgroup barriers only.
+// With more environments than co-resident blocks, every block solves
+// environments b, b + stride, ... one after the other, alone.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool grid_sync(DevCounters* cnt, unsigned nblocks, unsigned* gen,
-                                          unsigned* s_ok) {
+
+// Barrier of the G blocks of one group (bar[0]: arrivals, bar[1]: generation).
+// Returns false when a member did not arrive within the time limit (the
+// kernel then stops and the step reports a device error).
+__device__ __forceinline__ bool group_sync(unsigned* bar, unsigned G, unsigned* gen, unsigned* s_ok,
+                                           DevCounters* cnt) {
+    if (G == 1u) {
+        __syncthreads();
+        return true;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned target = *gen + 1u;
         bool ok = true;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const unsigned arrived =
-            __hip_atomic_fetch_add(&cnt->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == nblocks - 1u) {
+        const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (arrived == G - 1u) {
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "agent");
-            __hip_atomic_store(&cnt->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&cnt->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&bar[1], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             const long long t0 = clock64();
             unsigned polls = 0;
-            while (__hip_atomic_load(&cnt->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
+            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != target) {
                 __builtin_amdgcn_s_sleep(1);
                 if ((++polls & 255u) == 0u &&
                     ((__hip_atomic_load(&cnt->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagHang) ||
@@ -806,8 +854,7 @@ __device__ __forceinline__ bool grid_sync(DevCounters* cnt, unsigned nblocks, un
 
 constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
 constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
-constexpr int kQnMaxBlocks = 64; // grid size limit of k_qn (per-block partials staged in LDS)
-static_assert(kQnMaxBlocks * kQnSums <= kQnThreads, "one partial per thread");
+static_assert(kQnMaxGroup * kQnSums <= kQnThreads, "one partial per thread");
 
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
@@ -815,332 +862,218 @@ k_qn(QnArgs A) {
     __shared__ double tot[kQnSums];
     __shared__ double racc[kMaxRigid * 6];
     __shared__ unsigned s_ok;
-    __shared__ double red[kQnMaxBlocks * kQnSums];
+    __shared__ double red[kQnMaxGroup * kQnSums];
     __shared__ LsCoef ls_ovf[kQnThreads];  // line-search contacts beyond the registers
-    __shared__ double nacc[9][kSlotChunk];     // j (3) and R G R^T (6) of a chunk of owned slots
+    __shared__ double nacc[9][kSlotChunk];  // j (3) and R G R^T (6) of a chunk of owned slots
 
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
-    if (aborted || cnt->n_contacts <= (unsigned)A.blk_max) return;  // k_qn_block's case
-    const bool timer = blockIdx.x == 0 && threadIdx.x == 0;
-    unsigned long long tph[6] = {0, 0, 0, 0, 0, 0};
-    unsigned long long tmark = 0;
-    const unsigned G = gridDim.x;
-    unsigned gen = __hip_atomic_load(&cnt->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    unsigned rpar = 0;  // parity of the block-sum buffer
-    const long long nc = std::min<long long>(cnt->n_contacts, A.cap);
-    const long long ns = cnt->n_slots;
     const int tid = threadIdx.x, T = blockDim.x;
-    const long long sper = (ns + G - 1) / G, cper = (nc + G - 1) / G;
-    const long long s0 = std::min<long long>(ns, sper * blockIdx.x), s1 = std::min<long long>(ns, s0 + sper);
-    const long long c0 = std::min<long long>(nc, cper * blockIdx.x), c1 = std::min<long long>(nc, c0 + cper);
-    const double pnorm_all = cnt->pnorm_all;
+    const int2 me = A.qn_map[blockIdx.x];
+    unsigned rpar = 0;  // parity of the block-sum buffer
+    for (int env = me.x; env < A.n_envs; env += A.env_stride > 0 ? A.env_stride : A.n_envs) {
+        const int first = A.env_stride > 0 ? (int)blockIdx.x : A.env_qn[2 * env];
+        const unsigned G = A.env_stride > 0 ? 1u : (unsigned)A.env_qn[2 * env + 1];
+        const int rank = A.env_stride > 0 ? 0 : me.y;
+        const bool timer = rank == 0 && tid == 0;
+        unsigned long long tph[6] = {0, 0, 0, 0, 0, 0};
+        unsigned long long tmark = 0;
+        if (aborted) {
+            if (timer) write_stats(A, env, 0, 0, 0, 1, 0, 0.0, 0.0, tph, true, 0);
+            continue;
+        }
+        unsigned* bar = A.env_bar + (size_t)env * kBarStride;
+        unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long ec0 = A.env_range[4 * env], ec1 = A.env_range[4 * env + 1];
+        const long long es0 = A.env_range[4 * env + 2], es1 = A.env_range[4 * env + 3];
+        const long long nc = ec1 - ec0, ns = es1 - es0;
+        const long long sper = (ns + G - 1) / G, cper = (nc + G - 1) / G;
+        const long long s0 = es0 + std::min<long long>(ns, sper * rank), s1 = std::min<long long>(es1, s0 + sper);
+        const long long c0 = ec0 + std::min<long long>(nc, cper * rank), c1 = std::min<long long>(ec1, c0 + cper);
+        const double pnorm_env = A.env_pnorm[env];
+        double* partial = A.partial + (size_t)first * kQnSums;
 
-    for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
+        for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
 
-    int k = 0, ls_total = 0, converged = 0;
-    double alpha_prev = 1.0, res = 0.0, thr = 0.0;
-    bool ok = grid_sync(cnt, G, &gen, &s_ok);
-    while (ok) {
-        if (timer) tmark = wall_clock64();
-        // ---- node pass: CSR entries spread over the threads, FP64 LDS sums ----
-        double sums[kQnSums];
+        int k = 0, ls_total = 0, converged = 0;
+        double alpha_prev = 1.0, res = 0.0, thr = 0.0;
+        bool ok = group_sync(bar, G, &gen, &s_ok, cnt);
+        while (ok) {
+            if (timer) tmark = wall_clock64();
+            // ---- node pass: CSR entries spread over the threads, FP64 LDS sums ----
+            double sums[kQnSums];
 #pragma unroll
-        for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
-        for (long long sa = s0; sa < s1; sa += kSlotChunk) {
-            const long long sb = std::min<long long>(s1, sa + kSlotChunk);
-            for (int q = tid; q < 9 * kSlotChunk; q += T) (&nacc[0][0])[q] = 0.0;
-            __syncthreads();
-            const int E0 = A.s_beg[sa], E1 = A.s_beg[sb];
-            for (int eb = E0; eb < E1; eb += T * kEntBatch) {
-                // all loads of a batch of entries first, then the model and the LDS sums
-                Entry en[kEntBatch];
+            for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
+            for (long long sa = s0; sa < s1; sa += kSlotChunk) {
+                const long long sb = std::min<long long>(s1, sa + kSlotChunk);
+                for (int q = tid; q < 9 * kSlotChunk; q += T) (&nacc[0][0])[q] = 0.0;
+                __syncthreads();
+                const int E0 = A.s_beg[sa], E1 = A.s_beg[sb];
+                for (int eb = E0; eb < E1; eb += T * kEntBatch) {
+                    // all loads of a batch of entries first, then the model and the LDS sums
+                    Entry en[kEntBatch];
 #pragma unroll
-                for (int u = 0; u < kEntBatch; ++u) {
-                    const int e = eb + tid + u * T;
-                    en[u] = A.e_ent[e < E1 ? e : E0];
+                    for (int u = 0; u < kEntBatch; ++u) {
+                        const int e = eb + tid + u * T;
+                        en[u] = A.e_ent[e < E1 ? e : E0];
+                    }
+                    double vc[kEntBatch][3], fr[kEntBatch][9];
+                    ContactParams P[kEntBatch];
+#pragma unroll
+                    for (int u = 0; u < kEntBatch; ++u) {
+                        contact_velocity(A.c_dyn[en[u].c], k, alpha_prev, vc[u]);
+                        const ContactRec& R = A.c_rec[en[u].c];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) { fr[u][a] = R.t1[a]; fr[u][3 + a] = R.t2[a]; fr[u][6 + a] = R.n[a]; }
+                        P[u] = params_of(R, A.h);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kEntBatch; ++u) {
+                        if (eb + tid + u * T >= E1) continue;
+                        const int ls = en[u].slot - (int)sa;
+                        const double w = en[u].w;
+                        double rg[3], rgr[6];
+                        contact_terms(fr[u], fr[u] + 3, fr[u] + 6, P[u], vc[u], rg, rgr);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * rg[a]);
+#pragma unroll
+                        for (int q = 0; q < 6; ++q) atomicAdd(&nacc[3 + q][ls], w * w * rgr[q]);
+                    }
                 }
-                double vc[kEntBatch][3], fr[kEntBatch][9];
-                ContactParams P[kEntBatch];
-#pragma unroll
-                for (int u = 0; u < kEntBatch; ++u) {
-                    contact_velocity(A.c_dyn[en[u].c], k, alpha_prev, vc[u]);
-                    const ContactRec& R = A.c_rec[en[u].c];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) { fr[u][a] = R.t1[a]; fr[u][3 + a] = R.t2[a]; fr[u][6 + a] = R.n[a]; }
-                    P[u] = params_of(R, A.h);
+                __syncthreads();
+                if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
+                for (long long s = sa + tid; s < sb; s += T) {
+                    const int ls = (int)(s - sa);
+                    const double j[3] = {nacc[0][ls], nacc[1][ls], nacc[2][ls]};
+                    const double Hc[6] = {nacc[3][ls], nacc[4][ls], nacc[5][ls], nacc[6][ls], nacc[7][ls], nacc[8][ls]};
+                    node_solve(A.s_rec[s], j, Hc, sums);
                 }
+                __syncthreads();
+            }
+            block_allsum<kQnSums>(sums, rbuf, rpar);
+            if (G > 1u && tid == 0) {
 #pragma unroll
-                for (int u = 0; u < kEntBatch; ++u) {
-                    if (eb + tid + u * T >= E1) continue;
-                    const int ls = en[u].slot - (int)sa;
-                    const double w = en[u].w;
-                    double rg[3], rgr[6];
-                    contact_terms(fr[u], fr[u] + 3, fr[u] + 6, P[u], vc[u], rg, rgr);
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * rg[a]);
-#pragma unroll
-                    for (int q = 0; q < 6; ++q) atomicAdd(&nacc[3 + q][ls], w * w * rgr[q]);
+                for (int q = 0; q < kQnSums; ++q) partial[(size_t)rank * kQnSums + q] = sums[q];
+            }
+            if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
+            ok = group_sync(bar, G, &gen, &s_ok, cnt);
+            if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
+            if (!ok) break;
+            if (G > 1u) {
+                // every block of the group sums the partials in the same order
+                if (tid < (int)G * kQnSums) red[tid] = partial[tid];
+                __syncthreads();
+                if (tid < kQnSums) {
+                    double acc = 0.0;
+                    for (unsigned b = 0; b < G; ++b) acc += red[b * kQnSums + tid];
+                    tot[tid] = acc;
                 }
+                __syncthreads();
+#pragma unroll
+                for (int q = 0; q < kQnSums; ++q) sums[q] = tot[q];
+            }
+            const double p2 = fmax(pnorm_env - sums[3] + sums[2], 0.0);
+            res = sqrt(sums[0]);
+            thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(sums[1]));
+            const double Aq = sums[4], Bq = sums[5], d0 = sums[6];
+            if (res < thr) { converged = 1; break; }
+            if (k >= A.max_iter || !(d0 < 0.0)) break;
+            // ---- contact pass: store v_c^k, u_c = R_c^T J dv ----------------------
+            for (long long c = c0 + tid; c < c1; c += T) {
+                ContactDyn& D = A.c_dyn[c];
+                if (k > 0) {
+                    double vc[3];
+                    contact_velocity(D, k, alpha_prev, vc);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
+                }
+                double u[3];
+                contact_direction(A, c, u);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
             }
             __syncthreads();
-            if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
-            for (long long s = sa + tid; s < sb; s += T) {
-                const int ls = (int)(s - sa);
-                const double j[3] = {nacc[0][ls], nacc[1][ls], nacc[2][ls]};
-                const double Hc[6] = {nacc[3][ls], nacc[4][ls], nacc[5][ls], nacc[6][ls], nacc[7][ls], nacc[8][ls]};
-                node_solve(A.s_rec[s], j, Hc, sums);
-            }
-            __syncthreads();
-        }
-        block_allsum<kQnSums>(sums, rbuf, rpar);
-        if (tid == 0) {
-#pragma unroll
-            for (int q = 0; q < kQnSums; ++q) A.partial[(size_t)blockIdx.x * kQnSums + q] = sums[q];
-        }
-        if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
-        ok = grid_sync(cnt, G, &gen, &s_ok);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
-        if (!ok) break;
-        // every block sums the per-block partials in the same order
-        if (tid < (int)G * kQnSums) red[tid] = A.partial[tid];
-        __syncthreads();
-        if (tid < kQnSums) {
-            double acc = 0.0;
-            for (unsigned b = 0; b < G; ++b) acc += red[b * kQnSums + tid];
-            tot[tid] = acc;
-        }
-        __syncthreads();
-        const double p2 = fmax(pnorm_all - tot[3] + tot[2], 0.0);
-        res = sqrt(tot[0]);
-        thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(tot[1]));
-        const double Aq = tot[4], Bq = tot[5], d0 = tot[6];
-        if (res < thr) { converged = 1; break; }
-        if (k >= A.max_iter || !(d0 < 0.0)) break;
-        // ---- contact pass: store v_c^k, u_c = R_c^T J dv ----------------------
-        for (long long c = c0 + tid; c < c1; c += T) {
-            ContactDyn& D = A.c_dyn[c];
-            if (k > 0) {
-                double vc[3];
-                contact_velocity(D, k, alpha_prev, vc);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
-            }
-            double u[3];
-            contact_direction(A, c, u);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
-        }
-        __syncthreads();
-        if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
-        ok = grid_sync(cnt, G, &gen, &s_ok);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
-        if (!ok) break;
-        // ---- exact line search, redundantly in every block ----------------------
-        // Contact c is taken by thread c mod T. The closed-form coefficients of
-        // the first kLsPer*T contacts stay in registers for all the
-        // evaluations, the next T in LDS, and any beyond are formed from
-        // memory at each evaluation.
-        const int src = k == 0 ? 0 : (k & 1);
-        LsCoef lc[kLsPer];
-#pragma unroll
-        for (int u = 0; u < kLsPer; ++u) {
-            const long long c = tid + (long long)u * T;
-            lc[u] = c < nc ? ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc)
-                           : ls_coef_zero();
-        }
-        const long long c_lds = tid + (long long)kLsPer * T;
-        const bool use_lds = (long long)kLsPer * T < nc;
-        if (use_lds)
-            ls_ovf[tid] = c_lds < nc ? ls_coef(params_of(A.c_rec[c_lds], A.h), A.c_dyn[c_lds].vc[src],
-                                               A.c_dyn[c_lds].uc)
-                                     : ls_coef_zero();
-        auto eval = [&](double alpha, double* d2out) -> double {
-            double acc2[2] = {0.0, 0.0};
+            if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
+            ok = group_sync(bar, G, &gen, &s_ok, cnt);
+            if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
+            if (!ok) break;
+            // ---- exact line search, redundantly in every block of the group -------
+            // Contact ec0 + i is taken by thread i mod T. The closed-form
+            // coefficients of the first kLsPer*T contacts stay in registers for
+            // all the evaluations, the next T in LDS, and any beyond are formed
+            // from memory at each evaluation.
+            const int src = k == 0 ? 0 : (k & 1);
+            LsCoef lc[kLsPer];
 #pragma unroll
             for (int u = 0; u < kLsPer; ++u) {
-                double d1, d2;
-                ls_eval(lc[u], alpha, &d1, &d2);
-                acc2[0] += d1;
-                acc2[1] += d2;
+                const long long c = ec0 + tid + (long long)u * T;
+                lc[u] = c < ec1 ? ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc)
+                                : ls_coef_zero();
             }
-            if (use_lds) {
-                double d1, d2;
-                ls_eval(ls_ovf[tid], alpha, &d1, &d2);
-                acc2[0] += d1;
-                acc2[1] += d2;
-                for (long long c = c_lds + T; c < nc; c += T) {
-                    ls_eval(ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc), alpha,
-                            &d1, &d2);
+            const long long c_lds = ec0 + tid + (long long)kLsPer * T;
+            const bool use_lds = (long long)kLsPer * T < nc;
+            if (use_lds)
+                ls_ovf[tid] = c_lds < ec1 ? ls_coef(params_of(A.c_rec[c_lds], A.h), A.c_dyn[c_lds].vc[src],
+                                                    A.c_dyn[c_lds].uc)
+                                          : ls_coef_zero();
+            auto eval = [&](double alpha, double* d2out) -> double {
+                double acc2[2] = {0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < kLsPer; ++u) {
+                    double d1, d2;
+                    ls_eval(lc[u], alpha, &d1, &d2);
                     acc2[0] += d1;
                     acc2[1] += d2;
                 }
+                if (use_lds) {
+                    double d1, d2;
+                    ls_eval(ls_ovf[tid], alpha, &d1, &d2);
+                    acc2[0] += d1;
+                    acc2[1] += d2;
+                    for (long long c = c_lds + T; c < ec1; c += T) {
+                        ls_eval(ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc), alpha,
+                                &d1, &d2);
+                        acc2[0] += d1;
+                        acc2[1] += d2;
+                    }
+                }
+                block_allsum<2>(acc2, rbuf, rpar);
+                *d2out = Aq + acc2[1];
+                return fma(Aq, alpha, Bq) + acc2[0];
+            };
+            const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
+            if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
+            for (long long s = s0 + tid; s < s1; s += T) {
+                SlotRec& S = A.s_rec[s];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, S.dv[a], S.v[a]);
             }
-            block_allsum<2>(acc2, rbuf, rpar);
-            *d2out = Aq + acc2[1];
-            return fma(Aq, alpha, Bq) + acc2[0];
-        };
-        const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
+            alpha_prev = alpha;
+            ++k;
+        }
+        // ---- outputs ----------------------------------------------------------------
         for (long long s = s0 + tid; s < s1; s += T) {
-            SlotRec& S = A.s_rec[s];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, S.dv[a], S.v[a]);
+            const SlotRec& S = A.s_rec[s];
+            float4 g = A.vel[A.s_node[s]];
+            g.x = (float)S.v[0]; g.y = (float)S.v[1]; g.z = (float)S.v[2];
+            A.vel[A.s_node[s]] = g;
         }
-        alpha_prev = alpha;
-        ++k;
-    }
-    // ---- outputs --------------------------------------------------------------
-    for (long long s = s0 + tid; s < s1; s += T) {
-        const SlotRec& S = A.s_rec[s];
-        float4 g = A.vel[A.s_node[s]];
-        g.x = (float)S.v[0]; g.y = (float)S.v[1]; g.z = (float)S.v[2];
-        A.vel[A.s_node[s]] = g;
-    }
-    for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
-    __syncthreads();
-    for (long long c = c0 + tid; c < c1; c += T) contact_impulse(A, c, k, alpha_prev, racc);
-    __syncthreads();
-    for (int q = tid; q < A.n_rigid * 6; q += T)
-        if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
-    if (blockIdx.x == 0 && tid == 0) write_stats(A, nc, ns, k, converged, ls_total, res, thr, tph, false, 0);
-}
-
-// ---------------------------------------------------------------------------
-// Algorithm 1 in one workgroup (problems of up to kBlkMaxContacts contacts).
-// Without grid barriers the per-contact work is done once per iteration: the
-// contact pass evaluates each contact's model at v_c^k and stages R gamma and
-// R G R^T in LDS, the node pass gathers them through the CSR, and the line
-// search reads its contact data from LDS. Workgroup barriers only.
-// ---------------------------------------------------------------------------
-struct BlkShared {
-    double gR[3][kBlkMaxContacts];  // R gamma (world frame)
-    double gH[6][kBlkMaxContacts];  // R G R^T (upper triangle)
-    LsCoef lc[kBlkMaxContacts];     // line-search coefficients
-};
-
-__global__ void __launch_bounds__(kBlkThreads)
-k_qn_block(QnArgs A) {
-    __shared__ BlkShared S;
-    __shared__ double rbuf[2 * 16 * kQnSums];
-    DevCounters* cnt = A.cnt;
-    const bool aborted = cnt->abort_step != 0u;
-    if (!aborted && cnt->n_contacts > (unsigned)A.blk_max) return;  // k_qn's case
-    const long long nc = aborted ? 0 : cnt->n_contacts;
-    const long long ns = aborted ? 0 : cnt->n_slots;
-    const int tid = threadIdx.x, T = blockDim.x;
-    const double pnorm_all = cnt->pnorm_all;
-    unsigned long long tph[6] = {0, 0, 0, 0, 0, 0}, tmark = 0;
-    unsigned rpar = 0;  // parity of the block-sum buffer
-    const bool timer = tid == 0;
-
-    for (long long c = tid; c < nc; c += T) initial_contact_velocity(A, c);
-    __syncthreads();
-
-    int k = 0, ls_total = 0, converged = nc == 0 ? 1 : 0;
-    double alpha_prev = 1.0, res = 0.0, thr = 0.0;
-    while (nc > 0) {
-        if (timer) tmark = wall_clock64();
-        // ---- contact terms at v^k ---------------------------------------------
-        for (long long c = tid; c < nc; c += T) {
-            ContactDyn& D = A.c_dyn[c];
-            double vc[3], rg[3], rgr[6];
-            contact_velocity(D, k, alpha_prev, vc);
-            if (k > 0) {
-#pragma unroll
-                for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
-            }
-            contact_terms(A.c_rec[c], A.h, vc, rg, rgr);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) S.gR[a][c] = rg[a];
-#pragma unroll
-            for (int q = 0; q < 6; ++q) S.gH[q][c] = rgr[q];
-        }
+        for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
         __syncthreads();
-        // ---- node pass ----------------------------------------------------------
-        double sums[kQnSums];
-#pragma unroll
-        for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
-        for (long long s = tid; s < ns; s += T) {
-            double j[3] = {0.0, 0.0, 0.0}, Hc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            const int e0 = A.s_beg[s], e1 = A.s_beg[s + 1];
-            for (int e = e0; e < e1; ++e) {
-                const Entry en = A.e_ent[e];
-                const double w = en.w, ww = w * w;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) j[a] += w * S.gR[a][en.c];
-#pragma unroll
-                for (int q = 0; q < 6; ++q) Hc[q] += ww * S.gH[q][en.c];
-            }
-            node_solve(A.s_rec[s], j, Hc, sums);
-        }
-        block_allsum<kQnSums>(sums, rbuf, rpar);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
-        const double p2 = fmax(pnorm_all - sums[3] + sums[2], 0.0);
-        res = sqrt(sums[0]);
-        thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(sums[1]));
-        const double Aq = sums[4], Bq = sums[5], d0 = sums[6];
-        if (res < thr) { converged = 1; break; }
-        if (k >= A.max_iter || !(d0 < 0.0)) break;
-        // ---- u_c = R_c^T J dv; stage the line search ----------------------------
-        for (long long c = tid; c < nc; c += T) {
-            ContactDyn& D = A.c_dyn[c];
-            double u[3];
-            contact_direction(A, c, u);
-            const int src = k == 0 ? 0 : (k & 1);
-#pragma unroll
-            for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
-            S.lc[c] = ls_coef(params_of(A.c_rec[c], A.h), D.vc[src], u);
-        }
+        for (long long c = c0 + tid; c < c1; c += T) contact_impulse(A, c, k, alpha_prev, racc);
         __syncthreads();
-        if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
-        // ---- exact line search ----------------------------------------------------
-        auto eval = [&](double alpha, double* d2out) -> double {
-            double acc2[2] = {0.0, 0.0};
-            for (long long c = tid; c < nc; c += T) {
-                double d1, d2;
-                ls_eval(S.lc[c], alpha, &d1, &d2);
-                acc2[0] += d1;
-                acc2[1] += d2;
-            }
-            block_allsum<2>(acc2, rbuf, rpar);
-            *d2out = Aq + acc2[1];
-            return fma(Aq, alpha, Bq) + acc2[0];
-        };
-        const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
-        if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
-        for (long long s = tid; s < ns; s += T) {
-            SlotRec& R = A.s_rec[s];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) R.v[a] = fma(alpha, R.dv[a], R.v[a]);
-        }
-        __syncthreads();
-        alpha_prev = alpha;
-        ++k;
+        for (int q = tid; q < A.n_rigid * 6; q += T)
+            if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
+        if (timer) write_stats(A, env, nc, ns, k, converged, ls_total, res, thr, tph, false, (int)G);
+        __syncthreads();  // racc and the block sums are reused by the next environment
+        if (!ok) break;
     }
-    // ---- outputs ----------------------------------------------------------------
-    for (long long s = tid; s < ns; s += T) {
-        const SlotRec& R = A.s_rec[s];
-        float4 g = A.vel[A.s_node[s]];
-        g.x = (float)R.v[0]; g.y = (float)R.v[1]; g.z = (float)R.v[2];
-        A.vel[A.s_node[s]] = g;
-    }
-    double* racc = reinterpret_cast<double*>(&S.gH[0][0]);  // reuse: 6 doubles per rigid body
-    __syncthreads();
-    for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
-    __syncthreads();
-    for (long long c = tid; c < nc; c += T) contact_impulse(A, c, k, alpha_prev, racc);
-    __syncthreads();
-    for (int q = tid; q < A.n_rigid * 6; q += T)
-        if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
-    if (tid == 0) write_stats(A, nc, ns, k, converged, ls_total, res, thr, tph, aborted, 1);
 }
 
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
-                     double eps_a, int max_iter, int ls_max_steps, int blocks, int blk_max,
+                     double eps_a, int max_iter, int ls_max_steps, int blocks, int env_stride,
                      hipStream_t s) {
     QnArgs A;
-    A.blk_max = std::min(blk_max, kBlkMaxContacts);
     A.rigids = w.rigids;
     A.x = x;
     A.P = w.P;
@@ -1158,15 +1091,19 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.substep = substep;
     A.h = h; A.eps_r = eps_r; A.eps_a = eps_a;
     A.max_iter = max_iter; A.ls_max_steps = ls_max_steps;
+    A.qn_map = w.qn_map;
+    A.env_qn = w.env_qn;
+    A.env_range = w.env_range;
+    A.env_pnorm = w.env_pnorm;
+    A.env_bar = w.env_bar;
+    A.n_envs = w.n_envs;
+    A.env_stride = env_stride;
     A.cnt = w.cnt;
-    // each kernel checks the contact count on the device and leaves the other's case
-    hipLaunchKernelGGL(k_qn_block, dim3(1), dim3(kBlkThreads), 0, s, A);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     void* args[] = {&A};
     return hipLaunchCooperativeKernel((const void*)k_qn, dim3(blocks), dim3(kQnThreads), args, 0, s);
 }
 
+// Blocks of k_qn that can be resident at once (the cooperative launch limit).
 int qn_max_blocks() {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_qn, kQnThreads, 0) != hipSuccess)
@@ -1174,7 +1111,8 @@ int qn_max_blocks() {
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    return std::min(per_cu * cus, kQnMaxBlocks);
+    return per_cu * cus;
 }
+
 
 }  // namespace mpm

@@ -102,13 +102,12 @@ struct DevCounters {
     unsigned n_slots;        // distinct contact nodes
     unsigned flags;          // MPM_FLAG_* bits
     unsigned abort_step;     // set when the step must stop (capacity overflow)
-    unsigned bar_count;      // grid barrier arrival counter
-    unsigned bar_gen;        // grid barrier generation
     unsigned abort_substep;  // substep at which the step stopped
     unsigned n_ntiles;       // node tiles adjacent to a particle tile (this host step)
-    unsigned pad[5];
-    double pnorm_all;        // sum m |v*|^2 over active nodes (FP64)
+    unsigned pad[7];
 };
+
+constexpr int kBarStride = 16;  // unsigned words between the barrier counters of two environments
 
 // Pointers into the caller's workspace.
 struct Work {
@@ -145,9 +144,15 @@ struct Work {
     SlotRec* s_rec;          // [cap_s]
     // scratch
     unsigned* blk;           // [kSortBlocks * 256 + 2 * kSortBlocks] histograms / block sums
-    double* partial;         // [qn_blocks][kQnSums]
+    double* partial;         // [solver blocks][kQnSums]
     double* rigid_acc;       // [n_rigid][6] FP64 impulse accumulators
-    SubstepStats* sstats;    // [N]
+    SubstepStats* sstats;    // [N][n_envs]
+    // per-environment contact solve
+    double* env_pnorm;       // [n_envs] sum m |v*|^2 over the env's active nodes (FP64)
+    int* env_range;          // [n_envs][4] contacts [c0, c1) and contact nodes [s0, s1)
+    int2* qn_map;            // [solver blocks] (env, rank in the env's block group)
+    int* env_qn;             // [n_envs][2] first block and block count of the env's group
+    unsigned* env_bar;       // [n_envs][kBarStride] barrier arrival count and generation
     DevCounters* cnt;
     DevEnv* envs;
     DevRigid* rigids;
@@ -158,7 +163,7 @@ struct Work {
     int n_envs;
     int n_rigid;
     long long cap_c, cap_s;
-    int qn_blocks;
+    int qn_blocks;           // co-resident solver blocks (capacity of partial and qn_map)
 };
 
 // ---- kernel launchers (return hipError_t of the launch) -------------------
@@ -179,9 +184,10 @@ hipError_t launch_registration(const Work& w, const float* x, const float* v, do
                                int substep, hipStream_t s);
 hipError_t launch_contact_setup(const Work& w, hipStream_t s);
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
-                     double eps_a, int max_iter, int ls_max_steps, int blocks, int blk_max,
+                     double eps_a, int max_iter, int ls_max_steps, int blocks, int env_stride,
                      hipStream_t s);
 int qn_max_blocks();
+constexpr int kQnMaxGroup = 64;  // blocks of one environment's group (partials staged in LDS)
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
                       float* v_out, float* F_out, float* C_out, const int* pid_in,
                       int* pid_out, double h, hipStream_t s);

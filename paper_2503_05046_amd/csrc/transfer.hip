@@ -488,22 +488,36 @@ __device__ __forceinline__ float4 grid_node_update(const DevEnv& E, int i, int j
     return out;
 }
 
+// One FP64 atomic per block and environment (the block is one wave).
+__device__ __forceinline__ void flush_env_sum(double psum, double* dst) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) psum += __shfl_down(psum, o, 64);
+    if (threadIdx.x == 0 && psum != 0.0) atomicAdd(dst, psum);
+}
+
 __global__ void __launch_bounds__(64)
 k_grid_update(const DevEnv* __restrict__ envs, int n_envs, double h, const float4* __restrict__ blkbuf,
               const int* __restrict__ ptile_of, const unsigned* __restrict__ ntile_list,
               const unsigned* __restrict__ ntile_mark, float4* __restrict__ acc,
               float4* __restrict__ vel, unsigned* __restrict__ tile_flag,
-              const unsigned* __restrict__ active, DevCounters* cnt) {
+              const unsigned* __restrict__ active, double* __restrict__ env_pnorm, DevCounters* cnt) {
     __shared__ int nb[27];
     if (cnt->abort_step) return;
     const unsigned n_static = cnt->n_ntiles, n_dyn = cnt->n_active;
-    double psum = 0.0;
+    double psum = 0.0;  // sum m |v*|^2 of environment psum_env, flushed when the environment changes
+    int psum_env = -1;
     const float hf = (float)h;
     const int rx = threadIdx.x & 3, ry = (threadIdx.x >> 2) & 3, rz = threadIdx.x >> 4;
     for (unsigned t = blockIdx.x; t < n_static + n_dyn; t += gridDim.x) {
         const bool is_static = t < n_static;
         const unsigned gt = is_static ? ntile_list[t] : active[t - n_static];
-        const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
+        const int env = env_of_tile(envs, n_envs, (int)gt);
+        if (env != psum_env) {  // uniform over the block (one tile at a time)
+            if (psum_env >= 0) flush_env_sum(psum, env_pnorm + psum_env);
+            psum = 0.0;
+            psum_env = env;
+        }
+        const DevEnv& E = envs[env];
         int tx, ty, tz;
         tile_coords(E, gt, &tx, &ty, &tz);
         if (is_static) {
@@ -548,17 +562,14 @@ k_grid_update(const DevEnv* __restrict__ envs, int n_envs, double h, const float
         }
         vel[gi] = grid_node_update(E, i, j, k, sum, hf, &psum);
     }
-    // one FP64 atomic per block
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) psum += __shfl_down(psum, o, 64);
-    if (threadIdx.x == 0 && psum != 0.0) atomicAdd(&cnt->pnorm_all, psum);
+    if (psum_env >= 0) flush_env_sum(psum, env_pnorm + psum_env);
 }
 
 hipError_t launch_grid_update(const Work& w, double h, hipStream_t s) {
     const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 4096);
     hipLaunchKernelGGL(k_grid_update, dim3(blocks), dim3(64), 0, s, w.envs, w.n_envs, h, w.blkbuf,
                        w.ptile_of, w.ntile_list, w.ntile_mark, w.acc, w.vel, w.tile_flag,
-                       w.active_tiles, w.cnt);
+                       w.active_tiles, w.env_pnorm, w.cnt);
     return hipGetLastError();
 }
 
@@ -713,7 +724,7 @@ hipError_t launch_recover_C(const Work& w, const float* F, float* C, double h, h
 }
 
 // Start of a host step: flags, impulse accumulators and per-substep stats.
-__global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, SubstepStats* st, int N) {
+__global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, SubstepStats* st, int n_st) {
     const int t = threadIdx.x;
     if (t == 0) {
         cnt->flags = 0u;
@@ -721,33 +732,35 @@ __global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, Sub
         cnt->abort_substep = 0u;
     }
     for (int i = t; i < n_acc; i += blockDim.x) rigid_acc[i] = 0.0;
-    for (int i = t; i < N; i += blockDim.x) {
+    for (int i = t; i < n_st; i += blockDim.x) {
         SubstepStats z;
         z.n_contacts = z.n_slots = z.iterations = z.converged = z.ls_rounds = z.pad = 0;
         z.residual = z.threshold = 0.0;
-        for (int q = 0; q < 5; ++q) z.t_phase[q] = 0ull;
+        for (int q = 0; q < 6; ++q) z.t_phase[q] = 0ull;
         st[i] = z;
     }
 }
 
 // Start of a substep: counters rebuilt every substep (a fill kernel rather
 // than a memset, so the sequence can be captured in a graph).
-__global__ void k_clear_substep(DevCounters* cnt) {
-    cnt->n_active = 0u;
-    cnt->n_contacts = 0u;
-    cnt->n_pairs = 0u;
-    cnt->n_slots = 0u;
-    cnt->pnorm_all = 0.0;
+__global__ void k_clear_substep(DevCounters* cnt, double* env_pnorm, int n_envs) {
+    if (threadIdx.x == 0) {
+        cnt->n_active = 0u;
+        cnt->n_contacts = 0u;
+        cnt->n_pairs = 0u;
+        cnt->n_slots = 0u;
+    }
+    for (int e = threadIdx.x; e < n_envs; e += blockDim.x) env_pnorm[e] = 0.0;
 }
 
 hipError_t launch_clear_step(const Work& w, int N, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_step, dim3(1), dim3(256), 0, s, w.cnt, w.rigid_acc, 6 * 256,
-                       w.sstats, N);
+                       w.sstats, N * w.n_envs);
     return hipGetLastError();
 }
 
 hipError_t launch_clear_substep(const Work& w, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_substep, dim3(1), dim3(1), 0, s, w.cnt);
+    hipLaunchKernelGGL(k_clear_substep, dim3(1), dim3(256), 0, s, w.cnt, w.env_pnorm, w.n_envs);
     return hipGetLastError();
 }
 

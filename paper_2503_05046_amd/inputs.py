@@ -119,6 +119,17 @@ class Scene:
         return s
 
 
+def single_env(scene: Scene, e: int) -> Scene:
+    """Environment e of a scene as a scene of its own (same state and rigids)."""
+    env = dataclasses.replace(scene.envs[e])
+    sl = slice(env.p_begin, env.p_end)
+    env.p_begin, env.p_end = 0, env.p_end - env.p_begin
+    rig = [dataclasses.replace(r, env=0) for r in scene.rigids if r.env == e]
+    out = dataclasses.replace(scene, name=f"{scene.name}[{e}]", envs=[env], rigids=rig)
+    out.x, out.v, out.F, out.C = (np.ascontiguousarray(a[:, sl]) for a in (scene.x, scene.v, scene.F, scene.C))
+    return out
+
+
 def _stiffness(E: float, V0: float) -> float:
     return KAPPA * E * V0 ** (1.0 / 3.0)
 

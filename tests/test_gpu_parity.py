@@ -141,3 +141,59 @@ def test_contact_substep_tight(mpm, oracle):
     assert max(e.values()) < 1e-5, (e, sg[0], so[0])
     m_tot = s.envs[0].m_p * s.P
     assert impulse_error(ig, io, m_tot, s.h) < 1e-4
+
+
+def _batched_contact_scene(n_envs, seed, penetrating):
+    """Independent environments in one handle; the particle blocks of the
+    environments in `penetrating` start 1.5 dx inside their boxes, the others
+    just above them (no contact in the first substeps)."""
+    s = I.batched(n_envs=n_envs, seed=seed, p_min=300, p_max=1500, n=24, N=2)
+    for e in penetrating:
+        env = s.envs[e]
+        s.x[2, env.p_begin:env.p_end] -= np.float32(1.5 * env.dx)
+    for env in s.envs:
+        env.eps_s = 1e-2  # softer friction keeps the tight solves short
+    s.eps_r = 1e-10
+    s.max_iter = 200000
+    return s
+
+
+def _compare_envs(mpm, oracle, s):
+    sim = mpm.Sim(s)
+    status, imp, st = sim.step()
+    out = sim.state()
+    sim.close()
+    contacts = np.zeros(s.N, np.int64)
+    for e, env in enumerate(s.envs):
+        _log(f"  env {e}: {env.p_end - env.p_begin} particles, oracle")
+        ora = oracle.OracleSim(s, env=e)
+        rc, impo, sto = ora.host_step()
+        contacts += np.array([q["n_contacts"] for q in sto])
+        sl = slice(env.p_begin, env.p_end)
+        g = {k: out[k][:, sl] for k in ("x", "v", "F", "C")}
+        err = field_errors(g, ora, env.dx)
+        assert max(err.values()) < 1e-5, (e, err)
+        rid = [i for i, r in enumerate(s.rigids) if r.env == e]
+        m_tot = env.m_p * (env.p_end - env.p_begin)
+        assert impulse_error(imp[rid], impo, m_tot, s.h) < 1e-4, e
+    assert list(st["contacts"]) == list(contacts)
+    return contacts
+
+
+def test_batched_envs_solve_independently(mpm, oracle):
+    """Four environments of different size and material in one handle, one of
+    them without contact: each matches the oracle run on it alone (its own
+    stopping test and line search)."""
+    s = _batched_contact_scene(4, 21, penetrating=(0, 1, 3))
+    _log("batched: 4 environments, 2 substeps")
+    contacts = _compare_envs(mpm, oracle, s)
+    assert contacts.min() > 0
+
+
+def test_batched_envs_sharing_blocks(mpm, oracle, monkeypatch):
+    """More environments than solver blocks: blocks take environments in turn."""
+    monkeypatch.setenv("MPM_SOLVER_MAX_BLOCKS", "2")
+    s = _batched_contact_scene(5, 22, penetrating=(0, 2, 3, 4))
+    _log("batched: 5 environments on 2 solver blocks, 2 substeps")
+    contacts = _compare_envs(mpm, oracle, s)
+    assert contacts.min() > 0
