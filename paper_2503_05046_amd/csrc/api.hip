@@ -40,7 +40,7 @@ mpm_status fail(mpm_status st, const char* fmt, ...) {
 
 constexpr int kMaxRigidTotal = 256;
 constexpr int kMaxQnBlocks = 1024;
-constexpr int kQnItemsPerBlock = 256;  // contact nodes per solver block
+constexpr int kQnItemsPerBlock = 128;  // contact nodes per solver block
 constexpr size_t kAlign = 256;
 
 struct Layout {
@@ -152,6 +152,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->s_rec = L.take<SlotRec>(S);
     w->blk = L.take<unsigned>(256 * kSortBlocks + 2 * kSortBlocks);
     w->partial = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
+    w->partial2 = L.take<double>(kMaxQnBlocks);
     w->rigid_acc = L.take<double>(6 * kMaxRigidTotal);
     w->sstats = L.take<SubstepStats>((size_t)z.N * z.n_envs);
     w->env_pnorm = L.take<double>(z.n_envs);

@@ -520,7 +520,8 @@ struct QnArgs {
     const int *s_node, *s_beg;
     const Entry* e_ent;
     SlotRec* s_rec;
-    double* partial;
+    double* partial;        // per block: the node pass's sums
+    double* partial2;       // per block: the contact pass's share of phi''(0)
     double* rigid_acc;
     int n_rigid;
     SubstepStats* stats;
@@ -641,9 +642,7 @@ __device__ __forceinline__ void stencil_sum(const QnArgs& A, long long c, double
     }
 }
 constexpr int kSlotV = 1;   // SlotRec::v
-constexpr int kSlotDv = 7;  // SlotRec::dv
 static_assert(offsetof(SlotRec, v) == kSlotV * sizeof(double), "SlotRec layout");
-static_assert(offsetof(SlotRec, dv) == kSlotDv * sizeof(double), "SlotRec layout");
 
 // Initial contact velocity v_c^0 = R_c^T sum w v*_i + b_c.
 __device__ __forceinline__ void initial_contact_velocity(const QnArgs& A, long long c) {
@@ -710,16 +709,6 @@ __device__ __forceinline__ void contact_terms(const ContactRec& rec, double h, c
     contact_terms(rec.t1, rec.t2, rec.n, params_of(rec, h), vc, rg, rgr);
 }
 
-// u_c = R_c^T sum_o w_o dv_slot(o)
-__device__ __forceinline__ void contact_direction(const QnArgs& A, long long c, double u[3]) {
-    double sacc[3];
-    stencil_sum<kSlotDv>(A, c, sacc);
-    const ContactRec& rec = A.c_rec[c];
-    u[0] = rec.t1[0] * sacc[0] + rec.t1[1] * sacc[1] + rec.t1[2] * sacc[2];
-    u[1] = rec.t2[0] * sacc[0] + rec.t2[1] * sacc[1] + rec.t2[2] * sacc[2];
-    u[2] = rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2];
-}
-
 // Impulse on the rigid bodies at the final iterate (minus the impulse on MPM),
 // reduced per body in LDS (racc: 6 doubles per body, zeroed by the caller).
 __device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, int k, double alpha_prev,
@@ -750,36 +739,37 @@ __device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, in
     }
 }
 
-// Safeguarded 1-D Newton with bisection fallback on phi'(alpha): bracket
-// [lo, hi] with phi'(lo) < 0 <= phi'(hi) found by doubling from the previous
-// step length, Newton from hi, bisection when the iterate leaves the bracket
-// or |phi'| does not halve. EVAL(alpha, &phi'') returns phi'(alpha); it must be
-// called uniformly by the whole block.
+// Exact line search: the root of phi'(alpha) for alpha > 0 (phi is convex
+// with phi'(0) = d0 < 0). Safeguarded 1-D Newton from alpha0: while no point
+// with phi' >= 0 is known the step only grows (Newton, or doubling when
+// Newton does not advance); once the root is bracketed, a Newton step that
+// leaves the bracket or does not halve |phi'| is replaced by bisection. Stops
+// at |phi'| <= 1e-10 |d0| or a bracket narrower than 1e-12 of its upper end.
+// EVAL(alpha, &phi'') returns phi'(alpha); it must be called uniformly by
+// the whole block.
 template <typename Eval>
 __device__ double exact_line_search(Eval eval, double alpha0, double d0, int max_steps, int* n_eval) {
-    double lo = 0.0, hi = alpha0, dd;
-    double dh = eval(hi, &dd);
-    ++*n_eval;
-    for (int n = 0; dh < 0.0 && n < 80; ++n) {
-        lo = hi;
-        hi *= 2.0;
-        dh = eval(hi, &dd);
+    double lo = 0.0, hi = 0.0, alpha = alpha0, prev = fabs(d0), dd;
+    bool bracketed = false;
+    for (int it = 0; it < max_steps + 80; ++it) {
+        const double da = eval(alpha, &dd);
         ++*n_eval;
-    }
-    double alpha = hi;
-    if (!(dh < 0.0)) {
-        double da = dh, dda = dd, prev = 1e300;
-        for (int it = 0; it < max_steps; ++it) {
-            if (fabs(da) <= 1e-10 * fabs(d0)) break;
-            if (da < 0.0) lo = alpha; else hi = alpha;
-            if (hi - lo <= 1e-12 * hi) break;
-            double an = alpha - da / dda;
-            if (!(an > lo && an < hi) || fabs(da) > 0.5 * prev) an = 0.5 * (lo + hi);
-            prev = fabs(da);
-            alpha = an;
-            da = eval(alpha, &dda);
-            ++*n_eval;
+        if (fabs(da) <= 1e-10 * fabs(d0)) break;
+        if (da < 0.0) {
+            lo = alpha;
+        } else {
+            hi = alpha;
+            bracketed = true;
         }
+        if (bracketed && hi - lo <= 1e-12 * hi) break;
+        double an = dd > 0.0 ? alpha - da / dd : -1.0;
+        if (bracketed) {
+            if (!(an > lo && an < hi) || fabs(da) > 0.5 * prev) an = 0.5 * (lo + hi);
+        } else if (!(an > alpha)) {
+            an = 2.0 * alpha;
+        }
+        prev = fabs(da);
+        alpha = an;
     }
     return alpha;
 }
@@ -854,7 +844,6 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, unsigned G, unsigned* 
 
 constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
 constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
-static_assert(kQnMaxGroup * kQnSums <= kQnThreads, "one partial per thread");
 
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
@@ -887,11 +876,19 @@ k_qn(QnArgs A) {
         const long long ec0 = A.env_range[4 * env], ec1 = A.env_range[4 * env + 1];
         const long long es0 = A.env_range[4 * env + 2], es1 = A.env_range[4 * env + 3];
         const long long nc = ec1 - ec0, ns = es1 - es0;
-        const long long sper = (ns + G - 1) / G, cper = (nc + G - 1) / G;
-        const long long s0 = es0 + std::min<long long>(ns, sper * rank), s1 = std::min<long long>(es1, s0 + sper);
+        // contact nodes split so that every block gets about the same number of
+        // CSR entries (the node pass's work); contacts split evenly
+        long long s0 = es0, s1 = es1;
+        if (G > 1u) {
+            const long long e_lo = A.s_beg[es0], e_n = (long long)A.s_beg[es1] - e_lo;
+            s0 = rank == 0 ? es0 : es0 + lower_bound_i(A.s_beg + es0, ns, e_lo + (e_n * rank + G - 1) / G);
+            s1 = rank + 1 == (int)G ? es1 : es0 + lower_bound_i(A.s_beg + es0, ns, e_lo + (e_n * (rank + 1) + G - 1) / G);
+        }
+        const long long cper = (nc + G - 1) / G;
         const long long c0 = ec0 + std::min<long long>(nc, cper * rank), c1 = std::min<long long>(ec1, c0 + cper);
         const double pnorm_env = A.env_pnorm[env];
         double* partial = A.partial + (size_t)first * kQnSums;
+        double* partial2 = A.partial2 + first;
 
         for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
 
@@ -961,7 +958,7 @@ k_qn(QnArgs A) {
             if (!ok) break;
             if (G > 1u) {
                 // every block of the group sums the partials in the same order
-                if (tid < (int)G * kQnSums) red[tid] = partial[tid];
+                for (int i = tid; i < (int)G * kQnSums; i += T) red[i] = partial[i];
                 __syncthreads();
                 if (tid < kQnSums) {
                     double acc = 0.0;
@@ -978,25 +975,78 @@ k_qn(QnArgs A) {
             const double Aq = sums[4], Bq = sums[5], d0 = sums[6];
             if (res < thr) { converged = 1; break; }
             if (k >= A.max_iter || !(d0 < 0.0)) break;
-            // ---- contact pass: store v_c^k, u_c = R_c^T J dv ----------------------
-            for (long long c = c0 + tid; c < c1; c += T) {
-                ContactDyn& D = A.c_dyn[c];
-                if (k > 0) {
-                    double vc[3];
-                    contact_velocity(D, k, alpha_prev, vc);
+            // ---- contact pass: store v_c^k, u_c = R_c^T J dv, and u_c^T G(v_c^k) u_c
+            // (this block's share of phi''(0)). Eight lanes gather one contact's
+            // 27 stencil nodes and combine their sums by shuffles.
+            double curv[1] = {0.0};
+            {
+                const int part = tid & 7;
+                for (long long cb = c0; cb < c1; cb += T / 8) {
+                    const long long c = cb + (tid >> 3);
+                    const bool valid = c < c1;
+                    const long long cc = valid ? c : c0;
+                    const ContactStencil& st = A.c_st[cc];
+                    int sl[4];
+                    double w[4];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
+                    for (int j = 0; j < 4; ++j) {
+                        const int o = part + 8 * j;
+                        const int q = (o < 27 && valid) ? st.slot[o] : -1;
+                        sl[j] = q < 0 ? 0 : q;
+                        w[j] = q < 0 ? 0.0 : (double)st.w[o];
+                    }
+                    double dvs[4][3];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const SlotRec& S = A.s_rec[sl[j]];
+                        dvs[j][0] = S.dv[0]; dvs[j][1] = S.dv[1]; dvs[j][2] = S.dv[2];
+                    }
+                    double sacc[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) sacc[a] += w[j] * dvs[j][a];
+#pragma unroll
+                    for (int m = 4; m >= 1; m >>= 1)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) sacc[a] += __shfl_xor(sacc[a], m, 64);
+                    if (valid && part == 0) {
+                        ContactDyn& D = A.c_dyn[c];
+                        const ContactRec& R = A.c_rec[c];
+                        double vc[3];
+                        contact_velocity(D, k, alpha_prev, vc);
+                        if (k > 0) {
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
+                        }
+                        double u[3];
+                        u[0] = R.t1[0] * sacc[0] + R.t1[1] * sacc[1] + R.t1[2] * sacc[2];
+                        u[1] = R.t2[0] * sacc[0] + R.t2[1] * sacc[1] + R.t2[2] * sacc[2];
+                        u[2] = R.n[0] * sacc[0] + R.n[1] * sacc[1] + R.n[2] * sacc[2];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
+                        double g[3], g00, g01, g11, gnn;
+                        contact_model(params_of(R, A.h), vc, g, &g00, &g01, &g11, &gnn);
+                        curv[0] += g00 * u[0] * u[0] + 2.0 * g01 * u[0] * u[1] + g11 * u[1] * u[1] + gnn * u[2] * u[2];
+                    }
                 }
-                double u[3];
-                contact_direction(A, c, u);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
             }
-            __syncthreads();
+            block_allsum<1>(curv, rbuf, rpar);
+            if (G > 1u && tid == 0) partial2[rank] = curv[0];
             if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
             ok = group_sync(bar, G, &gen, &s_ok, cnt);
             if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
             if (!ok) break;
+            double curv0 = curv[0];  // phi''(0) - A
+            if (G > 1u) {
+                for (int i = tid; i < (int)G; i += T) red[i] = partial2[i];
+                __syncthreads();
+                curv0 = 0.0;
+                for (unsigned b = 0; b < G; ++b) curv0 += red[b];
+                __syncthreads();
+            }
+            // first trial step: the Newton step of phi' from alpha = 0
+            const double alpha0 = Aq + curv0 > 0.0 ? -d0 / (Aq + curv0) : alpha_prev;
             // ---- exact line search, redundantly in every block of the group -------
             // Contact ec0 + i is taken by thread i mod T. The closed-form
             // coefficients of the first kLsPer*T contacts stay in registers for
@@ -1041,7 +1091,7 @@ k_qn(QnArgs A) {
                 *d2out = Aq + acc2[1];
                 return fma(Aq, alpha, Bq) + acc2[0];
             };
-            const double alpha = exact_line_search(eval, alpha_prev, d0, A.ls_max_steps, &ls_total);
+            const double alpha = exact_line_search(eval, alpha0, d0, A.ls_max_steps, &ls_total);
             if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
             for (long long s = s0 + tid; s < s1; s += T) {
                 SlotRec& S = A.s_rec[s];
@@ -1085,6 +1135,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.e_ent = w.e_ent;
     A.s_rec = w.s_rec;
     A.partial = w.partial;
+    A.partial2 = w.partial2;
     A.rigid_acc = w.rigid_acc;
     A.n_rigid = w.n_rigid;
     A.stats = w.sstats;

@@ -145,6 +145,7 @@ struct Work {
     // scratch
     unsigned* blk;           // [kSortBlocks * 256 + 2 * kSortBlocks] histograms / block sums
     double* partial;         // [solver blocks][kQnSums]
+    double* partial2;        // [solver blocks]
     double* rigid_acc;       // [n_rigid][6] FP64 impulse accumulators
     SubstepStats* sstats;    // [N][n_envs]
     // per-environment contact solve
@@ -187,7 +188,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
                      double eps_a, int max_iter, int ls_max_steps, int blocks, int env_stride,
                      hipStream_t s);
 int qn_max_blocks();
-constexpr int kQnMaxGroup = 64;  // blocks of one environment's group (partials staged in LDS)
+constexpr int kQnMaxGroup = 128;  // blocks of one environment's group (partials staged in LDS)
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
                       float* v_out, float* F_out, float* C_out, const int* pid_in,
                       int* pid_out, double h, hipStream_t s);

@@ -272,185 +272,122 @@ hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old) {
 // the tile's slot of the block buffer; the grid update sums the 8 blocks that
 // overlap each node in a fixed order.
 // ---------------------------------------------------------------------------
-// Contributions of one particle to its 27 stencil nodes: component 0 is the
-// mass w m_p, components 1..3 the momentum w (m_p v + Q (x_i - x_p)) (Eq. (6)
-// with the MLS affine/stress matrix Q). SINK(o, a, b, c, val[4]) receives node
-// (base + (a, b, c)), o = (c * 3 + b) * 3 + a.
-template <typename Sink>
-__device__ __forceinline__ void p2g_particle(const float f[3], float dx, float mp, const float v[3],
-                                             const float Qm[9], Sink sink) {
-    float wx[3], wy[3], wz[3];
-    bspline_w(f[0], wx);
-    bspline_w(f[1], wy);
-    bspline_w(f[2], wz);
-    float d0[3], d1[3], d2[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        d0[a] = ((float)a - f[0]) * dx;
-        d1[a] = ((float)a - f[1]) * dx;
-        d2[a] = ((float)a - f[2]) * dx;
-    }
-    const float mv[3] = {mp * v[0], mp * v[1], mp * v[2]};
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const float w = wx[a] * wy[bb] * wz[c];
-                float val[4];
-                val[0] = w * mp;
-#pragma unroll
-                for (int q = 0; q < 3; ++q)
-                    val[q + 1] = w * (mv[q] + Qm[3 * q + 0] * d0[a] + Qm[3 * q + 1] * d1[bb] + Qm[3 * q + 2] * d2[c]);
-                sink((c * 3 + bb) * 3 + a, a, bb, c, val);
-            }
-}
-
-// P2G, one particle tile per block iteration. The tile's particles are staged
-// in LDS in chunks with coalesced loads. Lane l of every wave owns cell l of
-// the tile and accumulates, in registers, all four components of the particles
-// of that cell whose stencil base is still the cell (the sort key's), taking
-// the cell's particles in turn with the other waves; the lanes then add their
-// sums into the LDS node block, one atomic per node and component, and since
-// the 64 lanes own 64 different cells, the atomics of one instruction never
-// collide. Particles that drifted to another base since the sort are listed
-// and scattered one per thread: into LDS when their stencil lies inside the
-// block, else into the global accumulator (activating the node tiles). The
-// block is then stored without atomics; the grid update sums the overlapping
-// blocks of every node.
-constexpr int kP2gThreads = 256;
-constexpr int kP2gChunk = 512;  // particles staged at once (15 floats each)
-
-__global__ void __launch_bounds__(kP2gThreads)
+// P2G, one particle tile per block: 256 threads, thread (q, cell) with
+// component q = tid / 64 (mass, then the three momentum components) and cell
+// = tid % 64 of the 4x4x4 tile. Each thread walks the particles of its cell
+// (contiguous after the sort) and keeps in registers its component of the
+// contributions of those whose stencil base is still the cell; it then adds
+// its 27 sums into the tile's 8x8x8-node LDS block. The 64 lanes of a wave
+// own 64 different cells, so those atomics never collide. Particles that
+// drifted to another base since the sort are scattered directly, into LDS
+// when their stencil lies inside the block, else into the global accumulator
+// (activating the node tiles). The block is stored without atomics; the grid
+// update sums the overlapping blocks of every node.
+__global__ void __launch_bounds__(256)
 k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ Q,
       long long P, const DevEnv* __restrict__ envs, int n_envs, const unsigned* __restrict__ ptile_id,
       const unsigned* __restrict__ ptile_beg, const unsigned* __restrict__ keys,
       float4* __restrict__ blkbuf, float4* __restrict__ acc, unsigned* __restrict__ tile_flag,
       unsigned* __restrict__ active, DevCounters* cnt) {
-    static_assert(kP2gThreads == 256, "four waves, one lane per cell of a 4x4x4 tile");
     __shared__ float sm[4][kBN3];
-    __shared__ float st[15][kP2gChunk];        // x (3), v (3), Q (9) of the chunk
-    __shared__ unsigned short dlist[kP2gChunk];  // drifted particles of the chunk
-    __shared__ unsigned ccount[64], cstart[64], ndrift;
+    __shared__ unsigned ccount[64], cstart[64];
     if (cnt->abort_step) return;
     const unsigned n_tiles = cnt->n_ptiles;
-    const int wave = threadIdx.x >> 6, cell = threadIdx.x & 63;
+    const int q = threadIdx.x >> 6, cell = threadIdx.x & 63;
     const int cx = cell & 3, cy = (cell >> 2) & 3, cz = cell >> 4;
     for (unsigned t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-        for (int n = threadIdx.x; n < kBN3; n += kP2gThreads) {
+        for (int n = threadIdx.x; n < kBN3; n += blockDim.x) {
             sm[0][n] = 0.f; sm[1][n] = 0.f; sm[2][n] = 0.f; sm[3][n] = 0.f;
         }
+        if (threadIdx.x < 64) ccount[threadIdx.x] = 0u;
+        __syncthreads();
         const unsigned gt = ptile_id[t];
         const long long pb = ptile_beg[t], pe = ptile_beg[t + 1];
+        for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) atomicAdd(&ccount[keys[p] & 63u], 1u);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned run = 0;
+            for (int c = 0; c < 64; ++c) {
+                cstart[c] = run;
+                run += ccount[c];
+            }
+        }
+        __syncthreads();
         const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
         int tx, ty, tz;
         tile_coords(E, gt, &tx, &ty, &tz);
         const int ox = tx * kTile - 1, oy = ty * kTile - 1, oz = tz * kTile - 1;
         const int nbx = tx * kTile + cx, nby = ty * kTile + cy, nbz = tz * kTile + cz;  // this cell's base
         const float dx = E.dx, mp = E.m_p;
-        float sum[4][27];
+        float sum[27];
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int o = 0; o < 27; ++o) sum[q][o] = 0.f;
-        bool any = false, clamped = false;
-        for (long long q0 = pb; q0 < pe; q0 += kP2gChunk) {
-            const int n = (int)std::min<long long>(kP2gChunk, pe - q0);
-            __syncthreads();  // the block is zeroed and the previous chunk is consumed
-            if (threadIdx.x < 64) ccount[threadIdx.x] = 0u;
-            if (threadIdx.x == 0) ndrift = 0u;
-            for (int i = threadIdx.x; i < n; i += kP2gThreads) {
-                const long long p = q0 + i;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    st[a][i] = x[a * P + p];
-                    st[3 + a][i] = v[a * P + p];
-                }
-#pragma unroll
-                for (int k = 0; k < 9; ++k) st[6 + k][i] = Q[k * P + p];
+        for (int o = 0; o < 27; ++o) sum[o] = 0.f;
+        const unsigned cnt_c = ccount[cell];
+        const long long p0 = pb + cstart[cell];
+        bool clamped = false;
+        for (unsigned kk = 0; kk < cnt_c; ++kk) {
+            const long long p = p0 + kk;
+            const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
+            int b[3];
+            float f[3];
+            stencil_base(E, xp, b, f, &clamped);
+            float wx[3], wy[3], wz[3];
+            bspline_w(f[0], wx);
+            bspline_w(f[1], wy);
+            bspline_w(f[2], wz);
+            // component q of the particle's contribution: m_p, or m_p v_q + Q_q . (x_i - x_p)
+            float base_val = mp, qr0 = 0.f, qr1 = 0.f, qr2 = 0.f;
+            if (q > 0) {
+                base_val = mp * v[(q - 1) * P + p];
+                qr0 = Q[(3 * (q - 1) + 0) * P + p];
+                qr1 = Q[(3 * (q - 1) + 1) * P + p];
+                qr2 = Q[(3 * (q - 1) + 2) * P + p];
             }
-            __syncthreads();
-            for (int i = threadIdx.x; i < n; i += kP2gThreads) atomicAdd(&ccount[keys[q0 + i] & 63u], 1u);
-            __syncthreads();
-            if (threadIdx.x < 64) {
-                const unsigned c = ccount[threadIdx.x];
-                cstart[threadIdx.x] = wave_inclusive_scan(c) - c;
-            }
-            __syncthreads();
-            const int n_cell = (int)ccount[cell], c0 = (int)cstart[cell];
-            for (int k = wave; k < n_cell; k += 4) {
-                const int i = c0 + k;
-                const float xp[3] = {st[0][i], st[1][i], st[2][i]};
-                int b[3];
-                float f[3];
-                stencil_base(E, xp, b, f, &clamped);
-                if (b[0] == nbx && b[1] == nby && b[2] == nbz) {
-                    any = true;
-                    const float vp[3] = {st[3][i], st[4][i], st[5][i]};
-                    float Qm[9];
-#pragma unroll
-                    for (int m = 0; m < 9; ++m) Qm[m] = st[6 + m][i];
-                    p2g_particle(f, dx, mp, vp, Qm, [&](int o, int, int, int, const float (&val)[4]) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) sum[q][o] += val[q];
-                    });
-                } else {
-                    dlist[atomicAdd(&ndrift, 1u)] = (unsigned short)i;
-                }
-            }
-            __syncthreads();
-            const unsigned nd = ndrift;
-            for (unsigned j = threadIdx.x; j < nd; j += kP2gThreads) {
-                const int i = dlist[j];
-                const float xp[3] = {st[0][i], st[1][i], st[2][i]};
-                int b[3];
-                float f[3];
-                stencil_base(E, xp, b, f, &clamped);
-                const float vp[3] = {st[3][i], st[4][i], st[5][i]};
-                float Qm[9];
-#pragma unroll
-                for (int m = 0; m < 9; ++m) Qm[m] = st[6 + m][i];
-                const int lx = b[0] - ox, ly = b[1] - oy, lz = b[2] - oz;
-                const bool local = lx >= 0 && lx <= kBN - 3 && ly >= 0 && ly <= kBN - 3 && lz >= 0 && lz <= kBN - 3;
-                if (local) {
-                    p2g_particle(f, dx, mp, vp, Qm, [&](int, int a, int bb, int c, const float (&val)[4]) {
-                        const int nn = ((lz + c) * kBN + (ly + bb)) * kBN + (lx + a);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) atomicAdd(&sm[q][nn], val[q]);
-                    });
-                } else {
-                    p2g_particle(f, dx, mp, vp, Qm, [&](int, int a, int bb, int c, const float (&val)[4]) {
-                        float* g = reinterpret_cast<float*>(&acc[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) atomicAdd(g + q, val[q]);
-                    });
-                    // the drifted particle's nodes span up to 2x2x2 node tiles
-                    for (int c = 0; c < 2; ++c)
-                        for (int bb = 0; bb < 2; ++bb)
-                            for (int a = 0; a < 2; ++a)
-                                activate_tile(node_tile(E, b[0] + 2 * a, b[1] + 2 * bb, b[2] + 2 * c),
-                                              tile_flag, active, cnt);
-                }
-            }
-        }
-        if (any) {
-            const int lx = nbx - ox, ly = nby - oy, lz = nbz - oz;  // in [1, 4]
+            const bool same = b[0] == nbx && b[1] == nby && b[2] == nbz;
+            const int lx = b[0] - ox, ly = b[1] - oy, lz = b[2] - oz;
+            const bool local = lx >= 0 && lx <= kBN - 3 && ly >= 0 && ly <= kBN - 3 && lz >= 0 && lz <= kBN - 3;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
                 for (int bb = 0; bb < 3; ++bb)
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        const int nn = ((lz + c) * kBN + (ly + bb)) * kBN + (lx + a);
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) atomicAdd(&sm[q][nn], sum[q][(c * 3 + bb) * 3 + a]);
+                        const int o = (c * 3 + bb) * 3 + a;
+                        const float w = wx[a] * wy[bb] * wz[c];
+                        const float val = w * (base_val + qr0 * (((float)a - f[0]) * dx) +
+                                               qr1 * (((float)bb - f[1]) * dx) + qr2 * (((float)c - f[2]) * dx));
+                        if (same) {
+                            sum[o] += val;
+                        } else if (local) {
+                            atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], val);
+                        } else {
+                            float* g = reinterpret_cast<float*>(&acc[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]);
+                            atomicAdd(g + q, val);
+                        }
                     }
+            if (!local && q == 0) {
+                // the drifted particle's nodes span up to 2x2x2 node tiles
+                for (int c = 0; c < 2; ++c)
+                    for (int bb = 0; bb < 2; ++bb)
+                        for (int a = 0; a < 2; ++a)
+                            activate_tile(node_tile(E, b[0] + 2 * a, b[1] + 2 * bb, b[2] + 2 * c),
+                                          tile_flag, active, cnt);
+            }
+        }
+        if (cnt_c > 0) {
+            const int lx = nbx - ox, ly = nby - oy, lz = nbz - oz;  // in [1, 4]
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], sum[(c * 3 + bb) * 3 + a]);
         }
         if (clamped) atomicOr(&cnt->flags, kFlagDomain);
         __syncthreads();
         float4* out = blkbuf + (size_t)t * kBN3;
-        for (int n = threadIdx.x; n < kBN3; n += kP2gThreads)
+        for (int n = threadIdx.x; n < kBN3; n += blockDim.x)
             out[n] = make_float4(sm[0][n], sm[1][n], sm[2][n], sm[3][n]);
         __syncthreads();
     }
@@ -458,7 +395,7 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
 
 hipError_t launch_p2g(const Work& w, const float* x, const float* v, hipStream_t s) {
     const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 8192);
-    hipLaunchKernelGGL(k_p2g, dim3(blocks), dim3(kP2gThreads), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs,
+    hipLaunchKernelGGL(k_p2g, dim3(blocks), dim3(256), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs,
                        w.ptile_id, w.ptile_beg, w.keys_sorted, w.blkbuf, w.acc, w.tile_flag,
                        w.active_tiles, w.cnt);
     return hipGetLastError();
