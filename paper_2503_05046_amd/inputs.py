@@ -19,9 +19,9 @@ synthetic scenes of the same kind stand in for them, larger and denser):
                      mu=0.8, h=1e-4, 10 substeps per rigid step.
 * ``batched``        many independent environments in one handle: particle
                      counts log-uniform in [p_min, p_max], each env with its own
-                     n^3 grid (dx = 1/n), elastic or sand at random, a block of
-                     particles falling at 1 m/s onto 1-3 random static boxes
-                     with mu uniform in [0.2, 0.9].
+                     n^3 grid (dx = 1/n), elastic or sand at random, a particle
+                     cube resting on a floor slab and moving down at 0.5 m/s,
+                     0-2 more boxes beside it, mu uniform in [0.2, 0.9].
 * ``tiny_block`` / ``tiny_random``: small scenes for exhaustive checks.
 
 Units are SI, z is up, gravity is (0, 0, -9.81). The domain of every env is
@@ -211,40 +211,51 @@ def gripper(n_particles: int = 250_000, seed: int = 2, n: int = 96) -> Scene:
 
 
 def batched(n_envs: int = 64, seed: int = 4, p_min: int = 5_000, p_max: int = 100_000,
-            n: int = 64, h: float = 1e-4, N: int = 10) -> Scene:
-    """Independent environments of uneven size, each a particle block
-    (2 particles per cell per axis on average, uniform random positions) just
-    above 1-3 static boxes, falling at 1 m/s; materials alternate at random
-    between fixed-corotated (E=1e5, nu=0.3) and Drucker-Prager sand
-    (E=3.5e5, nu=0.3, 30 deg)."""
+            n: int = 64, h: float = 1e-4, N: int = 10, z_floor: float = 0.2,
+            v0: float = -0.5) -> Scene:
+    """Independent environments of uneven size: particle counts log-uniform in
+    [p_min, p_max]; each env is elastic (fixed-corotated, E=1e5, nu=0.3,
+    particles on a lattice of spacing dx/2 with +-0.1 dx jitter) or sand
+    (Drucker-Prager 30 deg, E=3.5e5, nu=0.3, uniform random positions) with
+    probability 1/2, a cube of side (P_e/8)^(1/3) dx centred in x and y whose
+    bottom rests on a static floor slab (top at z_floor), falling at v0, and
+    0-2 more static boxes beside the cube; mu uniform in [0.2, 0.9] per box."""
     rng = np.random.default_rng(seed)
     dx = 1.0 / n
-    counts = np.exp(rng.uniform(math.log(p_min), math.log(p_max), n_envs)).astype(np.int64)
+    counts = np.exp(rng.uniform(math.log(p_min), math.log(p_max), n_envs)).round().astype(np.int64)
     envs, rigids, xs = [], [], []
     p0 = 0
     for e in range(n_envs):
         cnt = int(counts[e])
-        side = max(4.0 * dx, cnt ** (1.0 / 3.0) * 0.5 * dx)
-        n_box = int(rng.integers(1, 4))
-        top = 0.12
-        # boxes side by side under the block, tops at z = top
-        half_x = 0.5 * side / n_box + 2.0 * dx
-        cx0 = 0.5 - 0.5 * side
-        for b in range(n_box):
-            cx = cx0 + (b + 0.5) * side / n_box
-            rigids.append(RigidSpec(env=e, shape=BOX, mu=float(rng.uniform(0.2, 0.9)),
-                                    half=(half_x, 0.5 * side + 2.0 * dx, 0.04),
-                                    t=(cx, 0.5, top - 0.04)))
-        lo = np.array([0.5 - 0.5 * side, 0.5 - 0.5 * side, top + 0.5 * dx])
-        xs.append(lo + rng.uniform(0.0, side, (cnt, 3)))
-        V0 = side ** 3 / cnt
         sand = bool(rng.integers(0, 2))
+        m = max(2, int(round((cnt / 8.0) ** (1.0 / 3.0) * 2.0)))  # lattice points per side (spacing dx/2)
+        side = m * 0.5 * dx
+        lo = np.array([0.5 - 0.5 * side, 0.5 - 0.5 * side, z_floor])
+        if sand:
+            pos = lo + rng.uniform(0.0, side, (cnt, 3))
+        else:
+            g = (np.arange(m) + 0.5) * 0.5 * dx
+            lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+            lat = lat[rng.permutation(lat.shape[0])[:cnt]] if lat.shape[0] >= cnt else lat
+            cnt = lat.shape[0]
+            pos = lo + lat + rng.uniform(-0.1 * dx, 0.1 * dx, lat.shape)
+        xs.append(pos)
+        V0 = side ** 3 / cnt
         E_mod = 3.5e5 if sand else 1e5
         envs.append(EnvSpec(dims=(n, n, n), dx=dx, material=DRUCKER_PRAGER if sand else FIXED_COROTATED,
                             E=E_mod, nu=0.3, rho=1000.0, V0=V0, friction_angle=30.0,
                             k=_stiffness(E_mod, V0), p_begin=p0, p_end=p0 + cnt))
         p0 += cnt
-    x, v, F, C = _state(np.concatenate(xs), (0.0, 0.0, -1.0))
+        # the floor slab, then boxes beside the cube (alternately at -x and +x)
+        rigids.append(RigidSpec(env=e, shape=BOX, mu=float(rng.uniform(0.2, 0.9)),
+                                half=(0.4, 0.4, 0.05), t=(0.5, 0.5, z_floor - 0.05)))
+        for b in range(int(rng.integers(0, 3))):
+            hx, hy, hz = rng.uniform(0.02, 0.06, 3)
+            sgn = -1.0 if b == 0 else 1.0
+            cx = 0.5 + sgn * (0.5 * side + hx + 0.02)
+            rigids.append(RigidSpec(env=e, shape=BOX, mu=float(rng.uniform(0.2, 0.9)),
+                                    half=(hx, hy, hz), t=(cx, 0.5 + rng.uniform(-0.1, 0.1), z_floor + hz)))
+    x, v, F, C = _state(np.concatenate(xs), (0.0, 0.0, v0))
     return Scene("batched", h, N, envs, rigids, x, v, F, C)
 
 
