@@ -107,6 +107,9 @@ typedef struct {
     void* workspace;           /* device memory of workspace_bytes, caller-owned, 256-byte aligned */
     size_t workspace_bytes;
     void* stream;              /* hipStream_t the handle launches on (NULL = default stream) */
+    int32_t tape_substeps;     /* substeps the differentiation tape can hold (0 = no tape); a
+                                  multiple of N. The workspace grows by about
+                                  tape_substeps x (96 P + 32 grid nodes) bytes. */
 } mpm_desc;
 
 /* Rigid primitive (body frame) with its initial pose and twist. */
@@ -216,6 +219,39 @@ mpm_status mpm_get_rigid_state(const mpm_handle* h, int32_t id, mpm_rigid_state*
 
 /* Release the handle (not the borrowed memory). Safe on NULL. */
 void mpm_destroy(mpm_handle* h);
+
+/* ---- Differentiation (reverse mode through recorded host steps) ----------
+ * With desc->tape_substeps > 0, every mpm_step after mpm_tape_reset records
+ * what the reverse pass needs (the state at each substep start, the grid
+ * before and after the contact solve, the sort permutation of each host
+ * step) until the tape is full; mpm_step returns MPM_ENOMEM, with nothing
+ * advanced, when a host step would not fit. mpm_step_backward then maps the
+ * adjoint of the state after the recorded steps to the adjoint of the state
+ * before them, and returns the adjoints of the Lame parameters as adjoints of
+ * each environment's E and nu (with k, V0 and rho held fixed). This is the
+ * reverse mode of the free-motion substep of Eq. (6) (P2G, grid update, G2P
+ * with the fixed-corotated stress): host steps with registered contacts, or
+ * environments of Drucker-Prager material, are refused with MPM_EINVAL. */
+
+/* Adjoints of one environment's material parameters. */
+typedef struct {
+    double dE;
+    double dnu;
+} mpm_env_grad;
+
+/* Empty the tape; the following mpm_step calls record. Host only. */
+mpm_status mpm_tape_reset(mpm_handle* h);
+
+/* Reverse pass over the recorded host steps, on the handle's stream (the call
+ * synchronises it once at the end). gx [3][P], gv [3][P], gF [9][P], gC [9][P]:
+ * device arrays, on entry dL/d(x, v, F, C) of the state after the last recorded
+ * step, in the particle order the state has then; on return dL/d(x, v, F, C) of
+ * the state before the first recorded step, in the particle order it had then
+ * (the pid array permuted by the steps maps between the two). env_grads: host
+ * array of n_envs entries (may be NULL), overwritten. The tape is kept, so the
+ * call may be repeated with other adjoints. */
+mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, float* gC,
+                             mpm_env_grad* env_grads);
 
 /* Thread-local description of the last error on the calling thread. */
 const char* mpm_last_error(void);

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmpm.so")
-SOURCES = ["api.hip", "sort.hip", "transfer.hip", "contact.hip"]
+SOURCES = ["api.hip", "sort.hip", "transfer.hip", "contact.hip", "adjoint.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -57,7 +57,7 @@ struct Layout {
 
 struct Sizes {
     long long P = 0, n_nodes = 0, cap_c = 0, cap_s = 0;
-    int n_tiles = 0, n_envs = 0, N = 1;
+    int n_tiles = 0, n_envs = 0, N = 1, tape_cap = 0;
 };
 
 mpm_status validate(const mpm_desc* d, Sizes* sz) {
@@ -98,6 +98,8 @@ mpm_status validate(const mpm_desc* d, Sizes* sz) {
     if (tiles >= (1ll << 26)) return fail(MPM_EINVAL, "too many grid tiles for 32-bit keys");
     if (nodes >= (1ll << 31) - 1) return fail(MPM_EINVAL, "too many grid nodes");
     if (d->max_contacts < 0) return fail(MPM_EINVAL, "max_contacts must be >= 0");
+    if (d->tape_substeps < 0 || d->tape_substeps % d->N != 0)
+        return fail(MPM_EINVAL, "tape_substeps must be a non-negative multiple of N");
     sz->P = d->n_particles;
     sz->n_nodes = nodes;
     sz->n_tiles = (int)tiles;
@@ -105,6 +107,7 @@ mpm_status validate(const mpm_desc* d, Sizes* sz) {
     sz->N = d->N;
     sz->cap_c = d->max_contacts > 0 ? d->max_contacts : d->n_particles;
     sz->cap_s = std::min<long long>(27 * sz->cap_c, nodes);
+    sz->tape_cap = d->tape_substeps;
     return MPM_OK;
 }
 
@@ -160,6 +163,14 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->qn_map = L.take<int2>(kMaxQnBlocks);
     w->env_qn = L.take<int>(2 * (size_t)z.n_envs);
     w->env_bar = L.take<unsigned>((size_t)kBarStride * z.n_envs);
+    const long long T = z.tape_cap;
+    w->tape_p = T ? L.take<float>((size_t)T * 24 * P) : nullptr;
+    w->tape_g = T ? L.take<float4>((size_t)T * 2 * z.n_nodes) : nullptr;
+    w->tape_idx = T ? L.take<unsigned>((size_t)(T / z.N) * P) : nullptr;
+    w->adj = T ? L.take<float>((size_t)2 * 24 * P) : nullptr;
+    w->gbar = T ? L.take<float4>(z.n_nodes) : nullptr;
+    w->lame = T ? L.take<double>(2 * (size_t)z.n_envs) : nullptr;
+    w->tape_cap = (int)T;
     w->cnt = L.take<DevCounters>(1);
     w->envs = L.take<DevEnv>(z.n_envs);
     w->rigids = L.take<DevRigid>(kMaxRigidTotal);
@@ -214,6 +225,10 @@ struct mpm_handle {
     double wall_khz;     // device wall-clock rate
     int slots_per_block; // contact nodes per solver block
     std::vector<int> env_slots;  // per environment: most contact nodes in a substep of the last step
+    // differentiation tape
+    bool tape_on = false;  // recording since mpm_tape_reset
+    int tape_len = 0;      // substeps recorded
+    bool tape_contact = false;  // a recorded substep had contacts
     // pinned host staging
     DevRigid* h_rigids;
     double* h_racc;
@@ -471,6 +486,9 @@ mpm_status mpm_get_rigid_state(const mpm_handle* h, int32_t id, mpm_rigid_state*
 
 mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse* out, mpm_step_stats* st) {
     if (!h) return fail(MPM_EINVAL, "handle is NULL");
+    const bool rec = h->tape_on;
+    if (rec && h->tape_len + h->d.N > h->w.tape_cap)
+        return fail(MPM_ENOMEM, "the differentiation tape is full (%d substeps)", h->w.tape_cap);
     const int nr = (int)h->rigids.size();
     // frozen rigid state for this host step
     if (in) {
@@ -531,6 +549,9 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         unsigned *keys_sorted, *idx_sorted;
         HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
         HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
+        if (rec)
+            HIP_TRY(hipMemcpyAsync(W.tape_idx + (size_t)(h->tape_len / N) * W.P, idx_sorted,
+                                   sizeof(unsigned) * W.P, hipMemcpyDeviceToDevice, s));
         HIP_TRY(launch_tile_maps(W, s, true));   // forget the previous step's tiles
         HIP_TRY(launch_tile_list(W, keys_sorted, s));
         HIP_TRY(launch_tile_maps(W, s, false));
@@ -542,6 +563,15 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         const float* v_in = first ? W.vs : d.v;
         const float* F_in = first ? W.Fs : d.F;
         HIP_TRY(launch_clear_substep(W, s));
+        float* tp = rec ? W.tape_p + (size_t)(h->tape_len + k) * 24 * W.P : nullptr;
+        float4* tg = rec ? W.tape_g + (size_t)(h->tape_len + k) * 2 * W.n_nodes : nullptr;
+        if (rec) {
+            const size_t P = W.P;
+            HIP_TRY(hipMemcpyAsync(tp, x_in, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(tp + 3 * P, v_in, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(tp + 6 * P, F_in, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(tp + 15 * P, W.Q, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+        }
         {
             ProfScope ps(h, MPM_K_P2G, npair);
             HIP_TRY(launch_p2g(W, x_in, v_in, s));
@@ -550,6 +580,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
             ProfScope ps(h, MPM_K_GRID, npair);
             HIP_TRY(launch_grid_update(W, d.h, s));
         }
+        if (rec) HIP_TRY(hipMemcpyAsync(tg, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
         {
             ProfScope ps(h, MPM_K_REGISTER, npair);
             HIP_TRY(launch_registration(W, x_in, v_in, d.h, k, s));
@@ -563,6 +594,8 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
             HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
                               env_stride, s));
         }
+        if (rec)
+            HIP_TRY(hipMemcpyAsync(tg + W.n_nodes, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
         {
             ProfScope ps(h, MPM_K_G2P, npair);
             HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
@@ -574,6 +607,10 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const unsigned flags = h->h_cnt->flags;
+    if (rec) {
+        h->tape_len += N;
+        for (int q = 0; q < N * n_envs; ++q) h->tape_contact |= h->h_stats[q].n_contacts > 0;
+    }
     if (h->prof) {
         for (int q = 0; q < npair; ++q) {
             float ms = 0.f;
@@ -655,6 +692,82 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     if (flags & MPM_FLAG_NAN) return fail(MPM_ENAN, "non-finite particle state");
     if (flags & MPM_FLAG_DOMAIN) return fail(MPM_EDOMAIN, "a particle stencil left the grid");
     if (flags & MPM_FLAG_NOCONV) return fail(MPM_ENOCONV, "contact solve hit max_iter");
+    return MPM_OK;
+}
+
+mpm_status mpm_tape_reset(mpm_handle* h) {
+    if (!h) return fail(MPM_EINVAL, "handle is NULL");
+    if (h->w.tape_cap <= 0) return fail(MPM_EINVAL, "the handle was created without a tape (tape_substeps = 0)");
+    h->tape_on = true;
+    h->tape_len = 0;
+    h->tape_contact = false;
+    return MPM_OK;
+}
+
+mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, float* gC, mpm_env_grad* env_grads) {
+    if (!h) return fail(MPM_EINVAL, "handle is NULL");
+    if (!gx || !gv || !gF || !gC) return fail(MPM_EINVAL, "adjoint arrays must be non-NULL");
+    if (h->tape_len <= 0) return fail(MPM_EINVAL, "nothing recorded: call mpm_tape_reset, then mpm_step");
+    if (h->tape_contact)
+        return fail(MPM_EINVAL, "the reverse pass does not cover substeps with registered contacts");
+    for (const mpm_env_desc& E : h->envs)
+        if (E.material != MPM_FIXED_COROTATED)
+            return fail(MPM_EINVAL, "the reverse pass covers the fixed-corotated material only");
+    Work& W = h->w;
+    hipStream_t s = h->stream;
+    const int N = h->d.N, n_envs = (int)h->envs.size();
+    const size_t P = W.P;
+    const float hf = (float)h->d.h;
+    // two particle-adjoint buffers (x 3, v 3, F 9, C or Q 9 per particle)
+    float* bufs[2] = {W.adj, W.adj + 24 * P};
+    float* A = bufs[0];
+    HIP_TRY(hipMemcpyAsync(A, gx, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + 3 * P, gv, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + 6 * P, gF, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(A + 15 * P, gC, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemsetAsync(W.lame, 0, sizeof(double) * 2 * n_envs, s));
+    int cur = 0;
+    for (int j = h->tape_len / N - 1; j >= 0; --j) {
+        A = bufs[cur];
+        float *ax = A, *av = A + 3 * P, *aF = A + 6 * P, *aCQ = A + 15 * P;
+        for (int k = N - 1; k >= 0; --k) {
+            const int r = j * N + k;
+            const float* tp = W.tape_p + (size_t)r * 24 * P;
+            const float4* tg = W.tape_g + (size_t)r * 2 * W.n_nodes;
+            const TapeStep t = {tp, tp + 3 * P, tp + 6 * P, tp + 15 * P, tg, tg + W.n_nodes};
+            HIP_TRY(hipMemsetAsync(W.gbar, 0, sizeof(float4) * W.n_nodes, s));
+            // the host step's last substep produces C; the others produce Q
+            HIP_TRY(launch_g2p_adj(W, t, hf, ax, av, aF, k == N - 1 ? nullptr : aCQ, k == N - 1 ? aCQ : nullptr,
+                                   W.gbar, W.lame, s));
+            HIP_TRY(launch_grid_adj(W, t, hf, W.gbar, s));
+            HIP_TRY(launch_p2g_adj(W, t, W.gbar, ax, av, aCQ, s));
+        }
+        // the host step's gather (Q from F and C, then the sort) in reverse
+        const float* tp0 = W.tape_p + (size_t)(j * N) * 24 * P;
+        const TapeStep t0 = {tp0, tp0 + 3 * P, tp0 + 6 * P, tp0 + 15 * P, nullptr, nullptr};
+        float* B = bufs[1 - cur];
+        HIP_TRY(launch_permute_adj(W, t0, hf, W.tape_idx + (size_t)j * P, ax, av, aF, aCQ, B, B + 3 * P, B + 6 * P,
+                                   B + 15 * P, W.lame, s));
+        cur = 1 - cur;
+    }
+    A = bufs[cur];
+    HIP_TRY(hipMemcpyAsync(gx, A, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(gv, A + 3 * P, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(gF, A + 6 * P, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(gC, A + 15 * P, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+    std::vector<double> lame(2 * n_envs);
+    HIP_TRY(hipMemcpyAsync(lame.data(), W.lame, sizeof(double) * 2 * n_envs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (env_grads) {
+        for (int e = 0; e < n_envs; ++e) {
+            // mu = E / (2 (1 + nu)), la = E nu / ((1 + nu)(1 - 2 nu)), both from double E, nu
+            const double E = h->envs[e].E, nu = h->envs[e].nu;
+            const double mub = lame[2 * e], lab = lame[2 * e + 1];
+            const double a = 1.0 + nu, b = 1.0 - 2.0 * nu;
+            env_grads[e].dE = mub / (2.0 * a) + lab * nu / (a * b);
+            env_grads[e].dnu = -mub * E / (2.0 * a * a) + lab * E * (1.0 + 2.0 * nu * nu) / (a * a * b * b);
+        }
+    }
     return MPM_OK;
 }
 

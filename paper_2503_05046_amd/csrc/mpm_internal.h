@@ -154,6 +154,14 @@ struct Work {
     int2* qn_map;            // [solver blocks] (env, rank in the env's block group)
     int* env_qn;             // [n_envs][2] first block and block count of the env's group
     unsigned* env_bar;       // [n_envs][kBarStride] barrier arrival count and generation
+    // differentiation tape and reverse-pass buffers (tape_cap substeps; empty when 0)
+    float* tape_p;           // [tape_cap][24][P] x, v, F, Q at each substep start
+    float4* tape_g;          // [tape_cap][2][n_nodes] grid after the update and after the solve
+    unsigned* tape_idx;      // [tape_cap / N][P] sort permutation of each host step
+    float* adj;              // [2][24][P] particle adjoints, two orders
+    float4* gbar;            // [n_nodes] node adjoints
+    double* lame;            // [n_envs][2] adjoints of mu and lambda
+    int tape_cap;
     DevCounters* cnt;
     DevEnv* envs;
     DevRigid* rigids;
@@ -165,6 +173,13 @@ struct Work {
     int n_rigid;
     long long cap_c, cap_s;
     int qn_blocks;           // co-resident solver blocks (capacity of partial and qn_map)
+};
+
+// One recorded substep of the differentiation tape.
+struct TapeStep {
+    const float *x, *v, *F, *Q;  // state at the substep start, [3|9][P], in its host step's sorted order
+    const float4* vstar;         // grid after the update (v*, m)
+    const float4* vel;           // grid after the contact solve (v, m)
 };
 
 // ---- kernel launchers (return hipError_t of the launch) -------------------
@@ -193,6 +208,15 @@ hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float
                       float* v_out, float* F_out, float* C_out, const int* pid_in,
                       int* pid_out, double h, hipStream_t s);
 hipError_t launch_clear_step(const Work& w, int N, hipStream_t s);
+// reverse mode (adjoint.hip)
+hipError_t launch_g2p_adj(const Work& w, const TapeStep& t, float h, float* ax, const float* av, float* aF,
+                          const float* aQ, const float* aC, float4* gbar, double* lame, hipStream_t s);
+hipError_t launch_grid_adj(const Work& w, const TapeStep& t, float h, float4* gbar, hipStream_t s);
+hipError_t launch_p2g_adj(const Work& w, const TapeStep& t, const float4* gbar, float* ax, float* av, float* aQ,
+                          hipStream_t s);
+hipError_t launch_permute_adj(const Work& w, const TapeStep& t, float h, const unsigned* idx, const float* ax,
+                              const float* av, const float* aF, const float* aQ, float* ox, float* ov, float* oF,
+                              float* oC, double* lame, hipStream_t s);
 hipError_t launch_clear_substep(const Work& w, hipStream_t s);
 
 }  // namespace mpm

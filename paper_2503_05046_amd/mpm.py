@@ -24,7 +24,8 @@ STATUS_NAMES = {0: "MPM_OK", 1: "MPM_ENOCONV", 2: "MPM_EDOMAIN", 3: "MPM_ENAN", 
 FLAG_NOCONV, FLAG_DOMAIN, FLAG_NAN, FLAG_CAPACITY = 1, 2, 4, 8
 
 EXPORTED = ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
-            "mpm_get_rigid_state", "mpm_profile", "mpm_destroy", "mpm_last_error")
+            "mpm_get_rigid_state", "mpm_profile", "mpm_destroy", "mpm_tape_reset",
+            "mpm_step_backward", "mpm_last_error")
 KERNEL_CLASSES = ("sort", "p2g", "grid", "register", "setup", "solve", "g2p")
 
 
@@ -43,7 +44,12 @@ class Desc(ct.Structure):
                 ("ls_max_steps", ct.c_int32), ("n_particles", ct.c_int64),
                 ("x", ct.c_void_p), ("v", ct.c_void_p), ("F", ct.c_void_p), ("C", ct.c_void_p),
                 ("pid", ct.c_void_p), ("max_contacts", ct.c_int64), ("workspace", ct.c_void_p),
-                ("workspace_bytes", ct.c_size_t), ("stream", ct.c_void_p)]
+                ("workspace_bytes", ct.c_size_t), ("stream", ct.c_void_p),
+                ("tape_substeps", ct.c_int32)]
+
+
+class EnvGrad(ct.Structure):
+    _fields_ = [("dE", ct.c_double), ("dnu", ct.c_double)]
 
 
 class RigidDesc(ct.Structure):
@@ -96,6 +102,9 @@ def load():
                                ct.POINTER(StepStats)]
         L.mpm_get_rigid_state.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidState)]
         L.mpm_profile.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ProfileData)]
+        L.mpm_tape_reset.argtypes = [ct.c_void_p]
+        L.mpm_step_backward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                        ct.POINTER(EnvGrad)]
         L.mpm_destroy.argtypes = [ct.c_void_p]
         L.mpm_destroy.restype = None
         L.mpm_last_error.restype = ct.c_char_p
@@ -139,7 +148,8 @@ def env_descs(scene) -> ct.Array:
     return arr
 
 
-def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 0) -> Desc:
+def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 0,
+              tape_substeps: int = 0) -> Desc:
     d = Desc()
     d.struct_size = ct.sizeof(Desc)
     d.n_envs = len(scene.envs)
@@ -150,6 +160,7 @@ def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 
     d.ls_max_steps = ls_max_steps
     d.n_particles = scene.P
     d.max_contacts = max_contacts
+    d.tape_substeps = tape_substeps
     return d
 
 
@@ -230,6 +241,18 @@ def mpm_profile(h, enable: bool) -> dict:
                                          list(p.solver_phase_us))))
 
 
+def mpm_tape_reset(h) -> None:
+    _check(load().mpm_tape_reset(h), "mpm_tape_reset")
+
+
+def mpm_step_backward(h, gx: int, gv: int, gF: int, gC: int, n_envs: int) -> list:
+    """Device pointers of the four adjoint arrays (updated in place); returns
+    [(dL/dE, dL/dnu)] per environment."""
+    g = (EnvGrad * n_envs)()
+    _check(load().mpm_step_backward(h, gx, gv, gF, gC, g), "mpm_step_backward")
+    return [(e.dE, e.dnu) for e in g]
+
+
 def mpm_destroy(h) -> None:
     if h:
         load().mpm_destroy(h)
@@ -240,7 +263,7 @@ class Sim:
     workspace, the library steps them in place."""
 
     def __init__(self, scene, device: str = "cuda:0", max_contacts: int = 0,
-                 ls_max_steps: int = 0, track_ids: bool = True):
+                 ls_max_steps: int = 0, track_ids: bool = True, tape_substeps: int = 0):
         import torch
         load()
         self.torch = torch
@@ -255,7 +278,7 @@ class Sim:
         self.C = torch.from_numpy(np.ascontiguousarray(scene.C, np.float32)).to(dev)
         self.pid = torch.arange(self.P, dtype=torch.int32, device=dev) if track_ids else None
         self._envs = env_descs(scene)
-        self.desc = make_desc(scene, self._envs, max_contacts, ls_max_steps)
+        self.desc = make_desc(scene, self._envs, max_contacts, ls_max_steps, tape_substeps)
         self.ws_bytes = mpm_workspace_size(self.desc)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
@@ -287,6 +310,21 @@ class Sim:
             inv[pid] = np.arange(pid.shape[0], dtype=pid.dtype)
             out = {k: a[:, inv] for k, a in out.items()}
         return out
+
+    def tape_reset(self) -> None:
+        mpm_tape_reset(self.handle)
+
+    def backward(self, gx, gv, gF, gC) -> list:
+        """Reverse pass over the recorded steps. gx, gv, gF, gC: contiguous
+        float32 tensors on the device, [3|9, P], the adjoint of the current
+        state in its current particle order; overwritten in place with the
+        adjoint of the state at the tape start, in the order it had then.
+        Returns [(dL/dE, dL/dnu)] per environment."""
+        for t in (gx, gv, gF, gC):
+            if t.device != self.device or t.dtype != self.torch.float32 or not t.is_contiguous():
+                raise ValueError("adjoints must be contiguous float32 tensors on the simulation device")
+        return mpm_step_backward(self.handle, gx.data_ptr(), gv.data_ptr(), gF.data_ptr(), gC.data_ptr(),
+                                 len(self.scene.envs))
 
     def profile(self, enable: bool) -> dict:
         return mpm_profile(self.handle, enable)
