@@ -228,16 +228,29 @@ void mpm_destroy(mpm_handle* h);
  * advanced, when a host step would not fit. mpm_step_backward then maps the
  * adjoint of the state after the recorded steps to the adjoint of the state
  * before them, and returns the adjoints of the Lame parameters as adjoints of
- * each environment's E and nu (with k, V0 and rho held fixed). This is the
- * reverse mode of the free-motion substep of Eq. (6) (P2G, grid update, G2P
- * with the fixed-corotated stress): host steps with registered contacts, or
- * environments of Drucker-Prager material, are refused with MPM_EINVAL. */
+ * each environment's E and nu (with k, V0 and rho held fixed) and of each
+ * rigid body's linear velocity. It covers the substep of Eq. (5)-(8): P2G,
+ * grid update, the contact solve (implicit differentiation at its optimum:
+ * the full Hessian system by preconditioned conjugate gradients), contact
+ * registration (penetration, lagged normal impulse and bias of every
+ * contact) and G2P with the fixed-corotated stress. Environments of
+ * Drucker-Prager material are refused with MPM_EINVAL (the return map has no
+ * reverse mode here). The set of registered contacts is held fixed. */
 
 /* Adjoints of one environment's material parameters. */
 typedef struct {
     double dE;
     double dnu;
 } mpm_env_grad;
+
+/* Adjoints of one rigid body's motion (zero for static bodies). */
+typedef struct {
+    double dV[3];            /* through the velocity V used in every recorded host step */
+    double dt[3];            /* through the position t, as a common shift of every recorded pose */
+    double dV_kinematic[3];  /* dV plus the library's own kinematic update of t (t advances
+                                by N h V after each host step), i.e. the full derivative when
+                                mpm_step was called with in = NULL */
+} mpm_rigid_grad;
 
 /* Empty the tape; the following mpm_step calls record. Host only. */
 mpm_status mpm_tape_reset(mpm_handle* h);
@@ -248,10 +261,12 @@ mpm_status mpm_tape_reset(mpm_handle* h);
  * step, in the particle order the state has then; on return dL/d(x, v, F, C) of
  * the state before the first recorded step, in the particle order it had then
  * (the pid array permuted by the steps maps between the two). env_grads: host
- * array of n_envs entries (may be NULL), overwritten. The tape is kept, so the
- * call may be repeated with other adjoints. */
+ * array of n_envs entries, rigid_grads: host array of one entry per rigid body
+ * in id order (either may be NULL), overwritten. The tape is kept, so the
+ * call may be repeated with other adjoints. MPM_ENOCONV if a conjugate-gradient
+ * solve stopped at its iteration cap (relative residual target 1e-7). */
 mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, float* gC,
-                             mpm_env_grad* env_grads);
+                             mpm_env_grad* env_grads, mpm_rigid_grad* rigid_grads);
 
 /* Thread-local description of the last error on the calling thread. */
 const char* mpm_last_error(void);

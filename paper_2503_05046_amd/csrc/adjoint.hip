@@ -20,6 +20,21 @@
 // Particle adjoints live in component-major float32 arrays like the state;
 // node adjoints are scattered with float atomics into a float4 grid array.
 // The Lame-parameter adjoints are reduced per environment in FP64.
+//
+// Contact solve (Eq. (8)): at the optimum M (v - v*) + sum_c J_c^T R_c dl_c = 0
+// with v_c = R_c^T J_c v + b_c. Differentiating, an adjoint vb on the contact
+// nodes becomes vb* = M lam with H lam = vb, H = M + sum_c J_c^T R_c G_c R_c^T J_c
+// the full Hessian (solved by preconditioned conjugate gradients in FP64 with
+// the 3x3 node blocks of H as preconditioner). With y_c = R_c^T J_c lam:
+//   bias          bb_c   = -G_c y_c
+//   penetration   phib_c = -y_c . d(dl_c)/dphi0
+//   friction      mun0b  = -y_c . d(dl_c)/d(mu n0)
+//   weights       wb_ic  = -(R_c G_c y_c) . v_i + lam_i . (R_c gamma_c)
+// and through registration: phi0 = -sdf(x_p), n0 = gamma_n(n . (v_p - v_r)),
+// b_c = -R_c^T v_r with v_r = V + w x (x_p - t) the rigid velocity at x_p. The
+// normal of a half-space or of the inside of a box does not vary with x_p,
+// so the frame R_c carries no adjoint to the particle.
+#include "contact_model.h"
 #include "mpm_internal.h"
 
 namespace mpm {
@@ -319,14 +334,15 @@ k_g2p_adj(long long P, const DevEnv* __restrict__ envs, int n_envs, float h, con
 }
 
 // Adjoint of the grid update, in place on gbar: dL/dv*_i -> (dL/dp_i, dL/dm_i)
-// at nodes with mass; components zeroed by the boundary band pass nothing.
+// at nodes with mass (plus the direct dL/dm_i already in the fourth
+// component); components zeroed by the boundary band pass nothing.
 __global__ void __launch_bounds__(256)
 k_grid_adj(long long n_nodes, const DevEnv* __restrict__ envs, int n_envs, float h,
            const float4* __restrict__ vstar, float4* __restrict__ gbar) {
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= n_nodes) return;
-    const float4 g = gbar[n];
-    if (g.x == 0.f && g.y == 0.f && g.z == 0.f) return;
+    const float4 g = gbar[n];  // dL/dv* (xyz) and a direct dL/dm from the contact solve (w)
+    if (g.x == 0.f && g.y == 0.f && g.z == 0.f && g.w == 0.f) return;
     const float4 vs = vstar[n];
     if (!(vs.w > 0.f)) {
         gbar[n] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -345,7 +361,7 @@ k_grid_adj(long long n_nodes, const DevEnv* __restrict__ envs, int n_envs, float
         mb -= gb[a] * (vv[a] - h * E.gravity[a]);
     }
     const float inv_m = 1.0f / vs.w;
-    gbar[n] = make_float4(gb[0] * inv_m, gb[1] * inv_m, gb[2] * inv_m, mb * inv_m);
+    gbar[n] = make_float4(gb[0] * inv_m, gb[1] * inv_m, gb[2] * inv_m, mb * inv_m + g.w);
 }
 
 // Adjoint of P2G: from (dL/dp_i, dL/dm_i) in gbar to dL/dv_p, dL/dQ_p and the
@@ -353,7 +369,8 @@ k_grid_adj(long long n_nodes, const DevEnv* __restrict__ envs, int n_envs, float
 __global__ void __launch_bounds__(256)
 k_p2g_adj(long long P, const DevEnv* __restrict__ envs, int n_envs, const float* __restrict__ x,
           const float* __restrict__ v, const float* __restrict__ Q, const float4* __restrict__ gbar,
-          float* __restrict__ ax, float* __restrict__ av, float* __restrict__ aQ) {
+          const float* __restrict__ cx, const float* __restrict__ cv, float* __restrict__ ax,
+          float* __restrict__ av, float* __restrict__ aQ) {
     const long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
     const DevEnv& E = envs[env_of_particle_a(envs, n_envs, p)];
@@ -396,8 +413,8 @@ k_p2g_adj(long long P, const DevEnv* __restrict__ envs, int n_envs, const float*
     for (int a = 0; a < 3; ++a) xo[a] -= Qm[0 * 3 + a] * sp[0] + Qm[1 * 3 + a] * sp[1] + Qm[2 * 3 + a] * sp[2];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        ax[a * P + p] = xo[a];
-        av[a * P + p] = E.m_p * sp[a];
+        ax[a * P + p] = xo[a] + (cx ? cx[a * P + p] : 0.f);
+        av[a * P + p] = E.m_p * sp[a] + (cv ? cv[a * P + p] : 0.f);
     }
 #pragma unroll
     for (int k = 0; k < 9; ++k) aQ[k * P + p] = sq[k];
@@ -443,6 +460,369 @@ k_permute_adj(long long P, const DevEnv* __restrict__ envs, int n_envs, float h,
     add_env_pair(lame, env, live ? (double)mub : 0.0, live ? (double)lab : 0.0);
 }
 
+// ---------------------------------------------------------------------------
+// Contact solve in reverse
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ ContactParams params_a(const ContactRec& R, double h) {
+    ContactParams P;
+    P.phi0 = R.phi0; P.mun0 = R.mun0; P.k = R.k; P.d = R.d; P.eps_s = R.eps_s; P.h = h;
+    return P;
+}
+
+// world vector w -> contact frame, and back
+__device__ __forceinline__ void to_frame(const ContactRec& R, const double w[3], double c[3]) {
+    c[0] = R.t1[0] * w[0] + R.t1[1] * w[1] + R.t1[2] * w[2];
+    c[1] = R.t2[0] * w[0] + R.t2[1] * w[1] + R.t2[2] * w[2];
+    c[2] = R.n[0] * w[0] + R.n[1] * w[1] + R.n[2] * w[2];
+}
+__device__ __forceinline__ void from_frame(const ContactRec& R, const double c[3], double w[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w[a] = R.t1[a] * c[0] + R.t2[a] * c[1] + R.n[a] * c[2];
+}
+__device__ __forceinline__ void apply_G(double g00, double g01, double g11, double gnn, const double u[3], double o[3]) {
+    o[0] = g00 * u[0] + g01 * u[1];
+    o[1] = g01 * u[0] + g11 * u[1];
+    o[2] = gnn * u[2];
+}
+
+// v_c at the optimum from the recorded node velocities (slot nodes of the grid
+// after the solve), kept in ContactDyn::vc[0].
+__global__ void __launch_bounds__(256)
+k_cadj_vc(const DevCounters* cnt, long long cap, const ContactRec* __restrict__ rec,
+          const ContactStencil* __restrict__ st, const int* __restrict__ s_node, const float4* __restrict__ vel,
+          ContactDyn* __restrict__ dyn) {
+    const long long nc = std::min<long long>(cnt->n_contacts, cap);
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int o = 0; o < 27; ++o) {
+            const int sl = st[c].slot[o];
+            if (sl < 0) continue;
+            const float4 g = vel[s_node[sl]];
+            const double w = st[c].w[o];
+            acc[0] += w * g.x; acc[1] += w * g.y; acc[2] += w * g.z;
+        }
+        double vc[3];
+        to_frame(rec[c], acc, vc);
+        ContactDyn& D = dyn[c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) D.vc[0][a] = vc[a] + D.b[a];
+    }
+}
+
+// Per contact node: the inverse of its 3x3 block m I + sum w^2 R G R^T
+// (symmetric, 6 entries), the right-hand side vb (from the node adjoints), and
+// the CG start lam = 0, r = vb, z = P r, p = z; sums r.z and r.r.
+__global__ void __launch_bounds__(256)
+k_cadj_start(const DevCounters* cnt, double h, const ContactRec* __restrict__ rec, const ContactDyn* __restrict__ dyn,
+             const int* __restrict__ s_node, const int* __restrict__ s_beg, const Entry* __restrict__ ent,
+             const SlotRec* __restrict__ srec, const float4* __restrict__ gbar, double* __restrict__ pinv,
+             double3* __restrict__ lam, double3* __restrict__ r, double3* __restrict__ z, double3* __restrict__ p,
+             double* __restrict__ sc) {
+    const long long ns = cnt->n_slots;
+    double rz = 0.0, rr = 0.0;
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (long long)gridDim.x * blockDim.x) {
+        const double m = srec[s].m;
+        double H[6] = {m, 0.0, 0.0, m, 0.0, m};  // 00 01 02 11 12 22
+        for (int e = s_beg[s]; e < s_beg[s + 1]; ++e) {
+            const Entry en = ent[e];
+            const ContactRec& R = rec[en.c];
+            double gam[3], g00, g01, g11, gnn;
+            contact_model(params_a(R, h), dyn[en.c].vc[0], gam, &g00, &g01, &g11, &gnn);
+            const double ww = (double)en.w * en.w;
+            const double* t1 = R.t1; const double* t2 = R.t2; const double* n = R.n;
+            int q = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = a; b < 3; ++b)
+                    H[q++] += ww * (g00 * t1[a] * t1[b] + g01 * (t1[a] * t2[b] + t2[a] * t1[b]) + g11 * t2[a] * t2[b] +
+                                    gnn * n[a] * n[b]);
+        }
+        // inverse by cofactors (H is SPD)
+        const double c00 = H[3] * H[5] - H[4] * H[4], c01 = H[2] * H[4] - H[1] * H[5], c02 = H[1] * H[4] - H[2] * H[3];
+        const double c11 = H[0] * H[5] - H[2] * H[2], c12 = H[1] * H[2] - H[0] * H[4], c22 = H[0] * H[3] - H[1] * H[1];
+        const double det = H[0] * c00 + H[1] * c01 + H[2] * c02;
+        const double id = 1.0 / det;
+        double* Pi = pinv + 6 * s;
+        Pi[0] = c00 * id; Pi[1] = c01 * id; Pi[2] = c02 * id; Pi[3] = c11 * id; Pi[4] = c12 * id; Pi[5] = c22 * id;
+        const float4 g = gbar[s_node[s]];
+        const double rv[3] = {g.x, g.y, g.z};
+        const double zv[3] = {Pi[0] * rv[0] + Pi[1] * rv[1] + Pi[2] * rv[2], Pi[1] * rv[0] + Pi[3] * rv[1] + Pi[4] * rv[2],
+                              Pi[2] * rv[0] + Pi[4] * rv[1] + Pi[5] * rv[2]};
+        lam[s] = make_double3(0.0, 0.0, 0.0);
+        r[s] = make_double3(rv[0], rv[1], rv[2]);
+        z[s] = make_double3(zv[0], zv[1], zv[2]);
+        p[s] = make_double3(zv[0], zv[1], zv[2]);
+        rz += rv[0] * zv[0] + rv[1] * zv[1] + rv[2] * zv[2];
+        rr += rv[0] * rv[0] + rv[1] * rv[1] + rv[2] * rv[2];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        rz += __shfl_down(rz, o, 64);
+        rr += __shfl_down(rr, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&sc[0], rz);
+        atomicAdd(&sc[5], rr);  // |r0|^2
+    }
+}
+
+// q_c = R G R^T J_c p (world frame)
+__global__ void __launch_bounds__(256)
+k_cg_q(const DevCounters* cnt, long long cap, double h, const ContactRec* __restrict__ rec,
+       const ContactDyn* __restrict__ dyn, const ContactStencil* __restrict__ st, const double3* __restrict__ p,
+       double3* __restrict__ q) {
+    const long long nc = std::min<long long>(cnt->n_contacts, cap);
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x) {
+        double acc[3] = {0.0, 0.0, 0.0};
+        for (int o = 0; o < 27; ++o) {
+            const int sl = st[c].slot[o];
+            if (sl < 0) continue;
+            const double w = st[c].w[o];
+            const double3 pv = p[sl];
+            acc[0] += w * pv.x; acc[1] += w * pv.y; acc[2] += w * pv.z;
+        }
+        const ContactRec& R = rec[c];
+        double u[3], gu[3], out[3], gam[3], g00, g01, g11, gnn;
+        to_frame(R, acc, u);
+        contact_model(params_a(R, h), dyn[c].vc[0], gam, &g00, &g01, &g11, &gnn);
+        apply_G(g00, g01, g11, gnn, u, gu);
+        from_frame(R, gu, out);
+        q[c] = make_double3(out[0], out[1], out[2]);
+    }
+}
+
+// Hp_s = m p_s + sum_e w_e q_c(e); sums p.Hp into sc[2]
+__global__ void __launch_bounds__(256)
+k_cg_hp(const DevCounters* cnt, const int* __restrict__ s_beg, const Entry* __restrict__ ent,
+        const SlotRec* __restrict__ srec, const double3* __restrict__ p, const double3* __restrict__ q,
+        double3* __restrict__ hp, double* __restrict__ sc) {
+    const long long ns = cnt->n_slots;
+    double php = 0.0;
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (long long)gridDim.x * blockDim.x) {
+        const double m = srec[s].m;
+        const double3 pv = p[s];
+        double a[3] = {m * pv.x, m * pv.y, m * pv.z};
+        for (int e = s_beg[s]; e < s_beg[s + 1]; ++e) {
+            const Entry en = ent[e];
+            const double3 qv = q[en.c];
+            a[0] += en.w * qv.x; a[1] += en.w * qv.y; a[2] += en.w * qv.z;
+        }
+        hp[s] = make_double3(a[0], a[1], a[2]);
+        php += pv.x * a[0] + pv.y * a[1] + pv.z * a[2];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) php += __shfl_down(php, o, 64);
+    if ((threadIdx.x & 63) == 0) atomicAdd(&sc[2], php);
+}
+
+// alpha = rz / pHp; lam += alpha p; r -= alpha Hp; z = P r; sums r.z (sc[1]) and r.r (sc[3])
+__global__ void __launch_bounds__(256)
+k_cg_update(const DevCounters* cnt, const double* __restrict__ pinv, const double3* __restrict__ p,
+            const double3* __restrict__ hp, double3* __restrict__ lam, double3* __restrict__ r,
+            double3* __restrict__ z, double* __restrict__ sc) {
+    const long long ns = cnt->n_slots;
+    const double alpha = sc[2] > 0.0 ? sc[0] / sc[2] : 0.0;
+    double rz = 0.0, rr = 0.0;
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (long long)gridDim.x * blockDim.x) {
+        const double3 pv = p[s], hv = hp[s];
+        double3 l = lam[s], rv = r[s];
+        l.x += alpha * pv.x; l.y += alpha * pv.y; l.z += alpha * pv.z;
+        rv.x -= alpha * hv.x; rv.y -= alpha * hv.y; rv.z -= alpha * hv.z;
+        lam[s] = l;
+        r[s] = rv;
+        const double* Pi = pinv + 6 * s;
+        const double3 zv = make_double3(Pi[0] * rv.x + Pi[1] * rv.y + Pi[2] * rv.z,
+                                        Pi[1] * rv.x + Pi[3] * rv.y + Pi[4] * rv.z,
+                                        Pi[2] * rv.x + Pi[4] * rv.y + Pi[5] * rv.z);
+        z[s] = zv;
+        rz += rv.x * zv.x + rv.y * zv.y + rv.z * zv.z;
+        rr += rv.x * rv.x + rv.y * rv.y + rv.z * rv.z;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        rz += __shfl_down(rz, o, 64);
+        rr += __shfl_down(rr, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd(&sc[1], rz);
+        atomicAdd(&sc[3], rr);
+    }
+}
+
+// p = z + beta p with beta = rz_new / rz
+__global__ void __launch_bounds__(256)
+k_cg_dir(const DevCounters* cnt, const double3* __restrict__ z, double3* __restrict__ p, const double* __restrict__ sc) {
+    const long long ns = cnt->n_slots;
+    const double beta = sc[0] > 0.0 ? sc[1] / sc[0] : 0.0;
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (long long)gridDim.x * blockDim.x) {
+        const double3 zv = z[s];
+        double3 pv = p[s];
+        pv.x = zv.x + beta * pv.x; pv.y = zv.y + beta * pv.y; pv.z = zv.z + beta * pv.z;
+        p[s] = pv;
+    }
+}
+
+// scalars for the next iteration: sc[4] = last |r|^2, rz = rz_new, the sums cleared
+__global__ void k_cg_next(double* sc) {
+    sc[4] = sc[3];
+    sc[0] = sc[1];
+    sc[1] = 0.0;
+    sc[2] = 0.0;
+    sc[3] = 0.0;
+}
+
+// Per contact: the adjoints of the contact's parameters, chained through
+// registration to the particle (x, v at the substep start: into cx, cv) and
+// to the rigid body (twist V and position t: into rg, 6 doubles per body).
+__global__ void __launch_bounds__(256)
+k_cadj_params(const DevCounters* cnt, long long cap, long long P, double h, const DevEnv* __restrict__ envs,
+              const DevRigid* __restrict__ rigids, const ContactRec* __restrict__ rec,
+              const ContactDyn* __restrict__ dyn, const ContactStencil* __restrict__ st,
+              const int* __restrict__ c_pid, const int* __restrict__ c_rid, const int* __restrict__ c_env,
+              const int* __restrict__ s_node, const float4* __restrict__ vel, const double3* __restrict__ lam,
+              const float* __restrict__ x, const float* __restrict__ v, float* __restrict__ cx,
+              float* __restrict__ cv, double* __restrict__ rg) {
+    const long long nc = std::min<long long>(cnt->n_contacts, cap);
+    for (long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (long long)gridDim.x * blockDim.x) {
+        const ContactRec& R = rec[c];
+        const double* vcf = dyn[c].vc[0];
+        double ly[3] = {0.0, 0.0, 0.0};
+        for (int o = 0; o < 27; ++o) {
+            const int sl = st[c].slot[o];
+            if (sl < 0) continue;
+            const double w = st[c].w[o];
+            const double3 l = lam[sl];
+            ly[0] += w * l.x; ly[1] += w * l.y; ly[2] += w * l.z;
+        }
+        double y[3];
+        to_frame(R, ly, y);
+        const ContactParams Pm = params_a(R, h);
+        double gam[3], g00, g01, g11, gnn;
+        contact_model(Pm, vcf, gam, &g00, &g01, &g11, &gnn);
+        double Gy[3];
+        apply_G(g00, g01, g11, gnn, y, Gy);
+        // parameters of the contact
+        double bb[3] = {-Gy[0], -Gy[1], -Gy[2]};
+        const double an = Pm.phi0 - h * vcf[2], bn = 1.0 - Pm.d * vcf[2];
+        double phib = (an > 0.0 && bn > 0.0) ? h * Pm.k * bn * y[2] : 0.0;
+        const double s2 = vcf[0] * vcf[0] + vcf[1] * vcf[1] + Pm.eps_s * Pm.eps_s;
+        const double mun0b = -(y[0] * vcf[0] + y[1] * vcf[1]) * inv_sqrt(s2);
+        // weights of the stencil
+        const long long p = c_pid[c];
+        const DevEnv& E = envs[c_env[c]];
+        const DevRigid& B = rigids[c_rid[c]];
+        const float xf[3] = {x[p], x[P + p], x[2 * P + p]};
+        Stencil S;
+        stencil_of(E, xf, S);
+        double RGy[3], Rg[3];
+        from_frame(R, Gy, RGy);
+        from_frame(R, gam, Rg);
+        double xb[3] = {0.0, 0.0, 0.0}, vb[3] = {0.0, 0.0, 0.0};
+        for (int o = 0; o < 27; ++o) {
+            const int sl = st[c].slot[o];
+            if (sl < 0) continue;
+            const float4 g = vel[s_node[sl]];
+            const double3 l = lam[sl];
+            const double wb = -(RGy[0] * g.x + RGy[1] * g.y + RGy[2] * g.z) + (l.x * Rg[0] + l.y * Rg[1] + l.z * Rg[2]);
+            const int a = o % 3, bq = (o / 3) % 3, cz = o / 9;
+            xb[0] += wb * (double)(S.dw[0][a] * S.w[1][bq] * S.w[2][cz] * E.inv_dx);
+            xb[1] += wb * (double)(S.w[0][a] * S.dw[1][bq] * S.w[2][cz] * E.inv_dx);
+            xb[2] += wb * (double)(S.w[0][a] * S.w[1][bq] * S.dw[2][cz] * E.inv_dx);
+        }
+        // registration: n0 = gamma_n(n . (v_p - v_r)), lagged
+        const double xp[3] = {xf[0], xf[1], xf[2]};
+        const double rel[3] = {xp[0] - B.t[0], xp[1] - B.t[1], xp[2] - B.t[2]};
+        const double vr[3] = {B.V[0] + B.w[1] * rel[2] - B.w[2] * rel[1], B.V[1] + B.w[2] * rel[0] - B.w[0] * rel[2],
+                              B.V[2] + B.w[0] * rel[1] - B.w[1] * rel[0]};
+        const double vp[3] = {v[p], v[P + p], v[2 * P + p]};
+        const double vn0 = R.n[0] * (vp[0] - vr[0]) + R.n[1] * (vp[1] - vr[1]) + R.n[2] * (vp[2] - vr[2]);
+        const double a0 = Pm.phi0 - h * vn0, b0 = 1.0 - Pm.d * vn0;
+        double vrb[3];
+        {
+            double rbb[3];
+            from_frame(R, bb, rbb);  // b = -R^T v_r
+            vrb[0] = -rbb[0]; vrb[1] = -rbb[1]; vrb[2] = -rbb[2];
+        }
+        if (a0 > 0.0 && b0 > 0.0) {
+            const double n0b = B.mu * mun0b;
+            phib += n0b * h * Pm.k * b0;
+            const double vn0b = n0b * h * Pm.k * (-h * b0 - Pm.d * a0);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                vb[q] += vn0b * R.n[q];
+                vrb[q] -= vn0b * R.n[q];
+            }
+        }
+        // phi0 = -sdf(x_p; pose): d/dx = -n, d/dt = n
+        // v_r = V + w x (x_p - t): d/dx = [w]x, d/dt = -[w]x
+        const double wx[3] = {vrb[1] * B.w[2] - vrb[2] * B.w[1], vrb[2] * B.w[0] - vrb[0] * B.w[2],
+                              vrb[0] * B.w[1] - vrb[1] * B.w[0]};  // vrb x w
+#pragma unroll
+        for (int q = 0; q < 3; ++q) xb[q] += -phib * R.n[q] + wx[q];
+        const int rid = c_rid[c];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+            atomicAdd(&cx[q * P + p], (float)xb[q]);
+            atomicAdd(&cv[q * P + p], (float)vb[q]);
+            atomicAdd(&rg[6 * rid + q], vrb[q]);
+            atomicAdd(&rg[6 * rid + 3 + q], phib * R.n[q] - wx[q]);
+        }
+    }
+}
+
+// Contact nodes: the node adjoint becomes the adjoint of v*, m lam, and the
+// solve's own dependence on the node mass (M (v - v*) in its optimality
+// condition) gives dL/dm = -lam . (v - v*), kept in the fourth component for
+// the grid update's reverse pass.
+__global__ void __launch_bounds__(256)
+k_cadj_vstar(const DevCounters* cnt, const int* __restrict__ s_node, const SlotRec* __restrict__ srec,
+             const double3* __restrict__ lam, const float4* __restrict__ vel, const float4* __restrict__ vstar,
+             float4* __restrict__ gbar) {
+    const long long ns = cnt->n_slots;
+    for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < ns; s += (long long)gridDim.x * blockDim.x) {
+        const double m = srec[s].m;
+        const double3 l = lam[s];
+        const long long n = s_node[s];
+        const float4 v = vel[n], vs = vstar[n];
+        const double mb = -(l.x * ((double)v.x - vs.x) + l.y * ((double)v.y - vs.y) + l.z * ((double)v.z - vs.z));
+        gbar[n] = make_float4((float)(m * l.x), (float)(m * l.y), (float)(m * l.z), (float)mb);
+    }
+}
+
+hipError_t launch_cadj_start(const Work& w, double h, const float4* vel, hipStream_t s) {
+    const DevCounters* cnt = w.cnt;
+    hipLaunchKernelGGL(k_cadj_vc, dim3(256), dim3(256), 0, s, cnt, w.cap_c, w.c_rec, w.c_st, w.s_node, vel, w.c_dyn);
+    double3* V = reinterpret_cast<double3*>(w.cg_vec);
+    const size_t S = w.cap_s;
+    hipLaunchKernelGGL(k_cadj_start, dim3(256), dim3(256), 0, s, cnt, h, w.c_rec, w.c_dyn, w.s_node, w.s_beg,
+                       w.e_ent, w.s_rec, w.gbar, w.cg_pinv, V, V + S, V + 2 * S, V + 3 * S, w.cg_sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_iteration(const Work& w, double h, hipStream_t s) {
+    const DevCounters* cnt = w.cnt;
+    double3* V = reinterpret_cast<double3*>(w.cg_vec);
+    const size_t S = w.cap_s;
+    double3 *lam = V, *r = V + S, *z = V + 2 * S, *p = V + 3 * S, *hp = V + 4 * S;
+    hipLaunchKernelGGL(k_cg_q, dim3(256), dim3(256), 0, s, cnt, w.cap_c, h, w.c_rec, w.c_dyn, w.c_st, p,
+                       reinterpret_cast<double3*>(w.cg_q));
+    hipLaunchKernelGGL(k_cg_hp, dim3(256), dim3(256), 0, s, cnt, w.s_beg, w.e_ent, w.s_rec, p,
+                       reinterpret_cast<const double3*>(w.cg_q), hp, w.cg_sc);
+    hipLaunchKernelGGL(k_cg_update, dim3(256), dim3(256), 0, s, cnt, w.cg_pinv, p, hp, lam, r, z, w.cg_sc);
+    hipLaunchKernelGGL(k_cg_dir, dim3(256), dim3(256), 0, s, cnt, z, p, w.cg_sc);
+    hipLaunchKernelGGL(k_cg_next, dim3(1), dim3(1), 0, s, w.cg_sc);
+    return hipGetLastError();
+}
+
+hipError_t launch_cadj_finish(const Work& w, double h, const TapeStep& t, const float4* vel, float* cx, float* cv,
+                              double* rg, hipStream_t s) {
+    const DevCounters* cnt = w.cnt;
+    const double3* lam = reinterpret_cast<const double3*>(w.cg_vec);
+    hipLaunchKernelGGL(k_cadj_params, dim3(256), dim3(256), 0, s, cnt, w.cap_c, w.P, h, w.envs, w.rigids, w.c_rec,
+                       w.c_dyn, w.c_st, w.c_pid, w.c_rid, w.c_env, w.s_node, vel, lam, t.x, t.v, cx, cv, rg);
+    hipLaunchKernelGGL(k_cadj_vstar, dim3(256), dim3(256), 0, s, cnt, w.s_node, w.s_rec, lam, vel, t.vstar, w.gbar);
+    return hipGetLastError();
+}
+
 hipError_t launch_g2p_adj(const Work& w, const TapeStep& t, float h, float* ax, const float* av, float* aF,
                           const float* aQ, const float* aC, float4* gbar, double* lame, hipStream_t s) {
     const unsigned blocks = (unsigned)((w.P + 255) / 256);
@@ -457,11 +837,11 @@ hipError_t launch_grid_adj(const Work& w, const TapeStep& t, float h, float4* gb
     return hipGetLastError();
 }
 
-hipError_t launch_p2g_adj(const Work& w, const TapeStep& t, const float4* gbar, float* ax, float* av, float* aQ,
-                          hipStream_t s) {
+hipError_t launch_p2g_adj(const Work& w, const TapeStep& t, const float4* gbar, const float* cx, const float* cv,
+                          float* ax, float* av, float* aQ, hipStream_t s) {
     const unsigned blocks = (unsigned)((w.P + 255) / 256);
-    hipLaunchKernelGGL(k_p2g_adj, dim3(blocks), dim3(256), 0, s, w.P, w.envs, w.n_envs, t.x, t.v, t.Q, gbar, ax,
-                       av, aQ);
+    hipLaunchKernelGGL(k_p2g_adj, dim3(blocks), dim3(256), 0, s, w.P, w.envs, w.n_envs, t.x, t.v, t.Q, gbar, cx, cv,
+                       ax, av, aQ);
     return hipGetLastError();
 }
 

@@ -170,6 +170,14 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->adj = T ? L.take<float>((size_t)2 * 24 * P) : nullptr;
     w->gbar = T ? L.take<float4>(z.n_nodes) : nullptr;
     w->lame = T ? L.take<double>(2 * (size_t)z.n_envs) : nullptr;
+    w->tape_rig = T ? L.take<DevRigid>((size_t)(T / z.N) * kMaxRigidTape) : nullptr;
+    w->tape_env = T ? L.take<DevEnv>((size_t)(T / z.N) * z.n_envs) : nullptr;
+    w->cg_vec = T ? L.take<double>((size_t)5 * 3 * z.cap_s) : nullptr;
+    w->cg_pinv = T ? L.take<double>((size_t)6 * z.cap_s) : nullptr;
+    w->cg_q = T ? L.take<double>((size_t)3 * z.cap_c) : nullptr;
+    w->cg_sc = T ? L.take<double>(8) : nullptr;
+    w->cxv = T ? L.take<float>((size_t)6 * P) : nullptr;
+    w->rgrad = T ? L.take<double>((size_t)(T / z.N) * kMaxRigidTape * 6) : nullptr;
     w->tape_cap = (int)T;
     w->cnt = L.take<DevCounters>(1);
     w->envs = L.take<DevEnv>(z.n_envs);
@@ -228,7 +236,7 @@ struct mpm_handle {
     // differentiation tape
     bool tape_on = false;  // recording since mpm_tape_reset
     int tape_len = 0;      // substeps recorded
-    bool tape_contact = false;  // a recorded substep had contacts
+    std::vector<int> tape_ncon;  // contacts of each recorded substep (all environments)
     // pinned host staging
     DevRigid* h_rigids;
     double* h_racc;
@@ -549,9 +557,15 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         unsigned *keys_sorted, *idx_sorted;
         HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
         HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
-        if (rec)
-            HIP_TRY(hipMemcpyAsync(W.tape_idx + (size_t)(h->tape_len / N) * W.P, idx_sorted,
-                                   sizeof(unsigned) * W.P, hipMemcpyDeviceToDevice, s));
+        if (rec) {
+            const size_t j = (size_t)(h->tape_len / N);
+            HIP_TRY(hipMemcpyAsync(W.tape_idx + j * W.P, idx_sorted, sizeof(unsigned) * W.P,
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(W.tape_rig + j * kMaxRigidTape, W.rigids, sizeof(DevRigid) * std::max(nr, 1),
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(W.tape_env + j * n_envs, W.envs, sizeof(DevEnv) * n_envs,
+                                   hipMemcpyDeviceToDevice, s));
+        }
         HIP_TRY(launch_tile_maps(W, s, true));   // forget the previous step's tiles
         HIP_TRY(launch_tile_list(W, keys_sorted, s));
         HIP_TRY(launch_tile_maps(W, s, false));
@@ -609,7 +623,11 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     const unsigned flags = h->h_cnt->flags;
     if (rec) {
         h->tape_len += N;
-        for (int q = 0; q < N * n_envs; ++q) h->tape_contact |= h->h_stats[q].n_contacts > 0;
+        for (int k = 0; k < N; ++k) {
+            int nc = 0;
+            for (int e = 0; e < n_envs; ++e) nc += h->h_stats[(size_t)k * n_envs + e].n_contacts;
+            h->tape_ncon.push_back(nc);
+        }
     }
     if (h->prof) {
         for (int q = 0; q < npair; ++q) {
@@ -700,24 +718,29 @@ mpm_status mpm_tape_reset(mpm_handle* h) {
     if (h->w.tape_cap <= 0) return fail(MPM_EINVAL, "the handle was created without a tape (tape_substeps = 0)");
     h->tape_on = true;
     h->tape_len = 0;
-    h->tape_contact = false;
+    h->tape_ncon.clear();
     return MPM_OK;
 }
 
-mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, float* gC, mpm_env_grad* env_grads) {
+mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, float* gC, mpm_env_grad* env_grads,
+                             mpm_rigid_grad* rigid_grads) {
     if (!h) return fail(MPM_EINVAL, "handle is NULL");
     if (!gx || !gv || !gF || !gC) return fail(MPM_EINVAL, "adjoint arrays must be non-NULL");
     if (h->tape_len <= 0) return fail(MPM_EINVAL, "nothing recorded: call mpm_tape_reset, then mpm_step");
-    if (h->tape_contact)
-        return fail(MPM_EINVAL, "the reverse pass does not cover substeps with registered contacts");
     for (const mpm_env_desc& E : h->envs)
         if (E.material != MPM_FIXED_COROTATED)
             return fail(MPM_EINVAL, "the reverse pass covers the fixed-corotated material only");
     Work& W = h->w;
     hipStream_t s = h->stream;
-    const int N = h->d.N, n_envs = (int)h->envs.size();
+    const int N = h->d.N, n_envs = (int)h->envs.size(), nr = (int)h->rigids.size();
+    const int n_host = h->tape_len / N;
     const size_t P = W.P;
-    const float hf = (float)h->d.h;
+    const double hd = h->d.h;
+    const float hf = (float)hd;
+    constexpr int kCgCheck = 16;        // CG iterations between convergence checks
+    constexpr int kCgMax = 200000;      // iteration cap per solve
+    constexpr double kCgTol = 1e-7;     // relative residual target
+    bool cg_capped = false;
     // two particle-adjoint buffers (x 3, v 3, F 9, C or Q 9 per particle)
     float* bufs[2] = {W.adj, W.adj + 24 * P};
     float* A = bufs[0];
@@ -726,21 +749,58 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
     HIP_TRY(hipMemcpyAsync(A + 6 * P, gF, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(A + 15 * P, gC, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemsetAsync(W.lame, 0, sizeof(double) * 2 * n_envs, s));
+    HIP_TRY(hipMemsetAsync(W.rgrad, 0, sizeof(double) * 6 * kMaxRigidTape * n_host, s));
+    HIP_TRY(launch_clear_step(W, N, s));
+    W.n_rigid = nr;
     int cur = 0;
-    for (int j = h->tape_len / N - 1; j >= 0; --j) {
+    for (int j = n_host - 1; j >= 0; --j) {
         A = bufs[cur];
         float *ax = A, *av = A + 3 * P, *aF = A + 6 * P, *aCQ = A + 15 * P;
+        // the host step's rigid and environment tables, for re-running registration
+        HIP_TRY(hipMemcpyAsync(W.rigids, W.tape_rig + (size_t)j * kMaxRigidTape, sizeof(DevRigid) * std::max(nr, 1),
+                               hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(W.envs, W.tape_env + (size_t)j * n_envs, sizeof(DevEnv) * n_envs,
+                               hipMemcpyDeviceToDevice, s));
         for (int k = N - 1; k >= 0; --k) {
             const int r = j * N + k;
             const float* tp = W.tape_p + (size_t)r * 24 * P;
             const float4* tg = W.tape_g + (size_t)r * 2 * W.n_nodes;
             const TapeStep t = {tp, tp + 3 * P, tp + 6 * P, tp + 15 * P, tg, tg + W.n_nodes};
+            const bool contact = h->tape_ncon[r] > 0;
+            if (contact) {
+                // registration and the contact-node table of this substep, again
+                HIP_TRY(launch_clear_substep(W, s));
+                HIP_TRY(launch_registration(W, t.x, t.v, hd, k, s));
+                Work Wv = W;
+                Wv.vel = const_cast<float4*>(t.vstar);
+                HIP_TRY(launch_contact_setup(Wv, s));
+            }
             HIP_TRY(hipMemsetAsync(W.gbar, 0, sizeof(float4) * W.n_nodes, s));
             // the host step's last substep produces C; the others produce Q
             HIP_TRY(launch_g2p_adj(W, t, hf, ax, av, aF, k == N - 1 ? nullptr : aCQ, k == N - 1 ? aCQ : nullptr,
                                    W.gbar, W.lame, s));
+            float *cx = nullptr, *cv = nullptr;
+            if (contact) {
+                HIP_TRY(hipMemsetAsync(W.cg_sc, 0, sizeof(double) * 8, s));
+                HIP_TRY(launch_cadj_start(W, hd, t.vel, s));
+                double sc[8];
+                int it = 0;
+                for (;;) {
+                    HIP_TRY(hipMemcpyAsync(sc, W.cg_sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+                    HIP_TRY(hipStreamSynchronize(s));
+                    const double r0 = sc[5], rr = it == 0 ? r0 : sc[4];
+                    if (!(rr > kCgTol * kCgTol * r0)) break;
+                    if (it >= kCgMax) { cg_capped = true; break; }
+                    for (int q = 0; q < kCgCheck; ++q) HIP_TRY(launch_cg_iteration(W, hd, s));
+                    it += kCgCheck;
+                }
+                cx = W.cxv;
+                cv = W.cxv + 3 * P;
+                HIP_TRY(hipMemsetAsync(W.cxv, 0, sizeof(float) * 6 * P, s));
+                HIP_TRY(launch_cadj_finish(W, hd, t, t.vel, cx, cv, W.rgrad + (size_t)j * kMaxRigidTape * 6, s));
+            }
             HIP_TRY(launch_grid_adj(W, t, hf, W.gbar, s));
-            HIP_TRY(launch_p2g_adj(W, t, W.gbar, ax, av, aCQ, s));
+            HIP_TRY(launch_p2g_adj(W, t, W.gbar, cx, cv, ax, av, aCQ, s));
         }
         // the host step's gather (Q from F and C, then the sort) in reverse
         const float* tp0 = W.tape_p + (size_t)(j * N) * 24 * P;
@@ -755,8 +815,9 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
     HIP_TRY(hipMemcpyAsync(gv, A + 3 * P, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(gF, A + 6 * P, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(gC, A + 15 * P, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
-    std::vector<double> lame(2 * n_envs);
+    std::vector<double> lame(2 * n_envs), rg((size_t)6 * kMaxRigidTape * n_host);
     HIP_TRY(hipMemcpyAsync(lame.data(), W.lame, sizeof(double) * 2 * n_envs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(rg.data(), W.rgrad, sizeof(double) * rg.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (env_grads) {
         for (int e = 0; e < n_envs; ++e) {
@@ -768,6 +829,27 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
             env_grads[e].dnu = -mub * E / (2.0 * a * a) + lab * E * (1.0 + 2.0 * nu * nu) / (a * a * b * b);
         }
     }
+    if (rigid_grads) {
+        // device order groups the bodies by environment (stable), as in mpm_step
+        std::vector<int> order(nr);
+        for (int i = 0; i < nr; ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->rigids[a].env < h->rigids[b].env; });
+        const double dT = N * hd;
+        for (int k = 0; k < nr; ++k) {
+            mpm_rigid_grad& g = rigid_grads[order[k]];
+            memset(&g, 0, sizeof(g));
+            if (h->rigids[order[k]].desc.motion == MPM_STATIC) continue;
+            for (int j = 0; j < n_host; ++j) {
+                const double* q = rg.data() + ((size_t)j * kMaxRigidTape + k) * 6;
+                for (int a = 0; a < 3; ++a) {
+                    g.dV[a] += q[a];
+                    g.dt[a] += q[3 + a];
+                    g.dV_kinematic[a] += q[a] + j * dT * q[3 + a];
+                }
+            }
+        }
+    }
+    if (cg_capped) return fail(MPM_ENOCONV, "a contact adjoint solve hit its iteration cap");
     return MPM_OK;
 }
 

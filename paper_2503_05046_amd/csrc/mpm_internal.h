@@ -107,7 +107,8 @@ struct DevCounters {
     unsigned pad[7];
 };
 
-constexpr int kBarStride = 16;  // unsigned words between the barrier counters of two environments
+constexpr int kBarStride = 16;
+constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps each host step's table)  // unsigned words between the barrier counters of two environments
 
 // Pointers into the caller's workspace.
 struct Work {
@@ -161,6 +162,14 @@ struct Work {
     float* adj;              // [2][24][P] particle adjoints, two orders
     float4* gbar;            // [n_nodes] node adjoints
     double* lame;            // [n_envs][2] adjoints of mu and lambda
+    DevRigid* tape_rig;      // [tape_cap / N][kMaxRigidTape] rigid table of each recorded host step
+    DevEnv* tape_env;        // [tape_cap / N][n_envs] environment table of each recorded host step
+    double* cg_vec;          // [5][cap_s][3] conjugate gradients: lam, r, z, p, Hp
+    double* cg_pinv;         // [cap_s][6] inverse node blocks
+    double* cg_q;            // [cap_c][3]
+    double* cg_sc;           // [8] scalars
+    float* cxv;              // [6][P] particle adjoints from the contact solve (x, v)
+    double* rgrad;           // [tape_cap / N][n_rigid][6] rigid adjoints (V, t) per host step
     int tape_cap;
     DevCounters* cnt;
     DevEnv* envs;
@@ -212,8 +221,12 @@ hipError_t launch_clear_step(const Work& w, int N, hipStream_t s);
 hipError_t launch_g2p_adj(const Work& w, const TapeStep& t, float h, float* ax, const float* av, float* aF,
                           const float* aQ, const float* aC, float4* gbar, double* lame, hipStream_t s);
 hipError_t launch_grid_adj(const Work& w, const TapeStep& t, float h, float4* gbar, hipStream_t s);
-hipError_t launch_p2g_adj(const Work& w, const TapeStep& t, const float4* gbar, float* ax, float* av, float* aQ,
-                          hipStream_t s);
+hipError_t launch_p2g_adj(const Work& w, const TapeStep& t, const float4* gbar, const float* cx, const float* cv,
+                          float* ax, float* av, float* aQ, hipStream_t s);
+hipError_t launch_cadj_start(const Work& w, double h, const float4* vel, hipStream_t s);
+hipError_t launch_cg_iteration(const Work& w, double h, hipStream_t s);
+hipError_t launch_cadj_finish(const Work& w, double h, const TapeStep& t, const float4* vel, float* cx, float* cv,
+                              double* rg, hipStream_t s);
 hipError_t launch_permute_adj(const Work& w, const TapeStep& t, float h, const unsigned* idx, const float* ax,
                               const float* av, const float* aF, const float* aQ, float* ox, float* ov, float* oF,
                               float* oC, double* lame, hipStream_t s);

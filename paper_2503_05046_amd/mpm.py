@@ -52,6 +52,10 @@ class EnvGrad(ct.Structure):
     _fields_ = [("dE", ct.c_double), ("dnu", ct.c_double)]
 
 
+class RigidGrad(ct.Structure):
+    _fields_ = [("dV", ct.c_double * 3), ("dt", ct.c_double * 3), ("dV_kinematic", ct.c_double * 3)]
+
+
 class RigidDesc(ct.Structure):
     _fields_ = [("shape", ct.c_int32), ("normal", ct.c_double * 3), ("offset", ct.c_double),
                 ("half", ct.c_double * 3), ("mu", ct.c_double), ("motion", ct.c_int32),
@@ -104,7 +108,7 @@ def load():
         L.mpm_profile.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ProfileData)]
         L.mpm_tape_reset.argtypes = [ct.c_void_p]
         L.mpm_step_backward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
-                                        ct.POINTER(EnvGrad)]
+                                        ct.POINTER(EnvGrad), ct.POINTER(RigidGrad)]
         L.mpm_destroy.argtypes = [ct.c_void_p]
         L.mpm_destroy.restype = None
         L.mpm_last_error.restype = ct.c_char_p
@@ -245,12 +249,16 @@ def mpm_tape_reset(h) -> None:
     _check(load().mpm_tape_reset(h), "mpm_tape_reset")
 
 
-def mpm_step_backward(h, gx: int, gv: int, gF: int, gC: int, n_envs: int) -> list:
+def mpm_step_backward(h, gx: int, gv: int, gF: int, gC: int, n_envs: int, n_rigid: int):
     """Device pointers of the four adjoint arrays (updated in place); returns
-    [(dL/dE, dL/dnu)] per environment."""
+    ([(dL/dE, dL/dnu)] per environment, {"dV", "dt", "dV_kinematic"} arrays of
+    shape [n_rigid, 3])."""
     g = (EnvGrad * n_envs)()
-    _check(load().mpm_step_backward(h, gx, gv, gF, gC, g), "mpm_step_backward")
-    return [(e.dE, e.dnu) for e in g]
+    r = (RigidGrad * max(1, n_rigid))()
+    _check(load().mpm_step_backward(h, gx, gv, gF, gC, g, r), "mpm_step_backward")
+    rig = {k: np.array([list(getattr(q, k)) for q in r[:n_rigid]]).reshape(n_rigid, 3)
+           for k in ("dV", "dt", "dV_kinematic")}
+    return [(e.dE, e.dnu) for e in g], rig
 
 
 def mpm_destroy(h) -> None:
@@ -319,12 +327,12 @@ class Sim:
         float32 tensors on the device, [3|9, P], the adjoint of the current
         state in its current particle order; overwritten in place with the
         adjoint of the state at the tape start, in the order it had then.
-        Returns [(dL/dE, dL/dnu)] per environment."""
+        Returns ([(dL/dE, dL/dnu)] per environment, rigid adjoints)."""
         for t in (gx, gv, gF, gC):
             if t.device != self.device or t.dtype != self.torch.float32 or not t.is_contiguous():
                 raise ValueError("adjoints must be contiguous float32 tensors on the simulation device")
         return mpm_step_backward(self.handle, gx.data_ptr(), gv.data_ptr(), gF.data_ptr(), gC.data_ptr(),
-                                 len(self.scene.envs))
+                                 len(self.scene.envs), self.n_rigid)
 
     def profile(self, enable: bool) -> dict:
         return mpm_profile(self.handle, enable)

@@ -1,8 +1,10 @@
 """Reverse pass of the HIP library against central finite differences of the
 FP64 oracle.
 
-The scene has no contact: the reverse pass covers P2G, the grid update, G2P
-with the fixed-corotated stress and the host step's sort. Loss functionals
+Two scenes: one without contact (P2G, the grid update, G2P with the
+fixed-corotated stress and the host step's sort in reverse), and one in
+contact with a half-space and a rotating, moving box (adding the contact
+solve, differentiated at its optimum, and contact registration). Loss functionals
 L_a = <W_a, a_final> (a in x, v, F, C, random weights W_a) after two host steps
 of two substeps; for every pair (loss a, input field b) the directional
 derivative of L_a along a random direction in b from mpm_step_backward is
@@ -80,8 +82,8 @@ def reverse(mpm):
     for a, _ in FIELDS:
         g = {b: torch.zeros((n, scene.P), dtype=torch.float32, device=sim.device) for b, n in FIELDS}
         g[a].copy_(torch.from_numpy(W[a][:, pid].astype(np.float32)))
-        grads = sim.backward(g["x"], g["v"], g["F"], g["C"])
-        out[a] = ({b: g[b].cpu().numpy().astype(np.float64) for b, _ in FIELDS}, grads[0])
+        env_grads, _ = sim.backward(g["x"], g["v"], g["F"], g["C"])
+        out[a] = ({b: g[b].cpu().numpy().astype(np.float64) for b, _ in FIELDS}, env_grads[0])
     sim.close()
     return scene, W, out
 
@@ -119,16 +121,95 @@ def test_youngs_modulus_gradient(oracle, reverse, a):
     assert abs(gpu - fd) <= 1e-3 * abs(fd) + 1e-12, (gpu, fd)
 
 
-def test_backward_refuses_contact(mpm):
-    """Substeps with registered contacts are outside the reverse pass: the
-    call fails with a clear status instead of returning a wrong gradient."""
-    import torch
+def _contact_scene():
+    """Random elastic state over a half-space, under a rotating box moving at
+    (0.1, -0.05, 0) m/s: 60-65 contacts per substep. Soft friction (eps_s =
+    1e-2) and tight solves keep the finite differences clean."""
     s = I.tiny_random(P=300, seed=13, n=16, material=I.FIXED_COROTATED, with_box=True)
-    s.N = 1
-    sim = mpm.Sim(s, tape_substeps=1)
+    s.envs[0].eps_s = 1e-2
+    s.N = 2
+    s.eps_r = 1e-12
+    s.max_iter = 400000
+    return s
+
+
+def _oracle_final_rigid(oracle, scene, dV):
+    s = scene.copy()
+    r = s.rigids[1]
+    s.rigids[1] = type(r)(**{**r.__dict__, "V": tuple(np.array(r.V) + dV)})
+    return _oracle_final(oracle, s)
+
+
+@pytest.fixture(scope="module")
+def reverse_contact(mpm):
+    import torch
+    scene = _contact_scene()
+    rng = np.random.default_rng(8)
+    W = {a: rng.normal(size=(n, scene.P)) for a, n in FIELDS}
+    gpu_scene = scene.copy()
+    gpu_scene.eps_r = 1e-10
+    sim = mpm.Sim(gpu_scene, tape_substeps=scene.N * HOST_STEPS)
     sim.tape_reset()
-    sim.step()
-    g = [torch.zeros((n, s.P), dtype=torch.float32, device=sim.device) for _, n in FIELDS]
-    with pytest.raises(RuntimeError, match="contacts"):
-        sim.backward(*g)
+    for _ in range(HOST_STEPS):
+        status, _, st = sim.step()
+        assert status == 0 and st["max_contacts"] > 0
+    pid = sim.pid.cpu().numpy()
+    out = {}
+    for a, _ in FIELDS:
+        g = {b: torch.zeros((n, scene.P), dtype=torch.float32, device=sim.device) for b, n in FIELDS}
+        g[a].copy_(torch.from_numpy(W[a][:, pid].astype(np.float32)))
+        env_grads, rig = sim.backward(g["x"], g["v"], g["F"], g["C"])
+        out[a] = ({b: g[b].cpu().numpy().astype(np.float64) for b, _ in FIELDS}, env_grads[0], rig)
     sim.close()
+    return scene, W, out
+
+
+@pytest.mark.parametrize("a", [f for f, _ in FIELDS])
+@pytest.mark.parametrize("b", [f for f, _ in FIELDS])
+def test_contact_state_gradient_matches_finite_differences(oracle, reverse_contact, a, b):
+    scene, W, out = reverse_contact
+    grad = out[a][0][b]
+    names = [f for f, _ in FIELDS]
+    rng = np.random.default_rng(200 + 10 * names.index(a) + names.index(b))
+    d = rng.normal(size=grad.shape)
+    eps = 1e-6 * (scene.envs[0].dx if b == "x" else 1.0)
+    lp = (W[a] * _oracle_final(oracle, scene, (b, d), eps)[a]).sum()
+    lm = (W[a] * _oracle_final(oracle, scene, (b, d), -eps)[a]).sum()
+    fd = (lp - lm) / (2 * eps)
+    gpu = float((grad * d).sum())
+    if a == b and a in ("x", "F"):
+        ident = float((W[a] * d).sum())
+        fd, gpu = fd - ident, gpu - ident
+    _log(f"contact: L_{a} along d{b}: gpu {gpu:.6e} fd {fd:.6e}")
+    assert abs(gpu - fd) <= 1e-3 * abs(fd) + 1e-7 * np.sqrt((W[a] ** 2).sum() * (d ** 2).sum()), (gpu, fd)
+
+
+@pytest.mark.parametrize("a", [f for f, _ in FIELDS])
+def test_contact_youngs_modulus_gradient(oracle, reverse_contact, a):
+    scene, W, out = reverse_contact
+    E = scene.envs[0].E
+    eps = 1e-6 * E
+    lp = (W[a] * _oracle_final(oracle, scene, dE=eps)[a]).sum()
+    lm = (W[a] * _oracle_final(oracle, scene, dE=-eps)[a]).sum()
+    fd = (lp - lm) / (2 * eps)
+    gpu = out[a][1][0]
+    _log(f"contact: dL_{a}/dE: gpu {gpu:.6e} fd {fd:.6e}")
+    assert abs(gpu - fd) <= 1e-3 * abs(fd) + 1e-12, (gpu, fd)
+
+
+@pytest.mark.parametrize("a", [f for f, _ in FIELDS])
+def test_box_velocity_gradient(oracle, reverse_contact, a):
+    """d L / d V of the kinematic box, through the contact bias, the lagged
+    normal impulse and the box's advance between host steps."""
+    scene, W, out = reverse_contact
+    gpu = out[a][2]["dV_kinematic"][1]
+    fd = np.zeros(3)
+    for k in range(3):
+        dv = np.zeros(3)
+        dv[k] = 1e-6
+        lp = (W[a] * _oracle_final_rigid(oracle, scene, dv)[a]).sum()
+        lm = (W[a] * _oracle_final_rigid(oracle, scene, -dv)[a]).sum()
+        fd[k] = (lp - lm) / 2e-6
+    _log(f"contact: dL_{a}/dV: gpu {gpu} fd {fd}")
+    assert np.abs(gpu - fd).max() <= 1e-3 * np.abs(fd).max() + 1e-9, (gpu, fd)
+    assert np.all(out[a][2]["dV"][0] == 0.0)  # the half-space is static
