@@ -134,12 +134,73 @@ def run_batched(args) -> int:
     return 0
 
 
+def run_differentiable(args) -> int:
+    """The backward form: 200k-particle elastic cube pushed by a box (C5), 50
+    substeps (5 host steps) with a checkpoint every host step; the loss is the
+    x coordinate of the final centre of mass, differentiated with respect to a
+    uniform offset of the initial velocity, Young's modulus and the box
+    velocity. Reports the forward-plus-backward rate and its cost relative to
+    the plain forward."""
+    import numpy as np
+    import torch
+    from paper_2503_05046_amd import diff
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+
+    scene = I.differentiable()
+    scene.max_iter = args.max_iter
+    P, N, steps = scene.P, scene.N, 5
+    log(f"differentiable: P={P}, {steps} host steps of {N} substeps, checkpoint every host step")
+    sim = M.Sim(scene, tape_substeps=N)
+    path = diff.RigidPath(scene)
+    dev = sim.device
+    x0, v0, F0, C0 = (torch.from_numpy(a).to(dev) for a in (scene.x, scene.v, scene.F, scene.C))
+    V0 = torch.tensor([list(r.V) for r in scene.rigids], dtype=torch.float64)
+    E0 = torch.tensor([scene.envs[0].E], dtype=torch.float64)
+    # plain forward (no tape, no autograd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diff._run(sim, path, steps, 0, x0, v0, F0, C0, V0, record=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    log(f"forward: {t_fwd:.2f} s")
+    # forward + backward through the checkpointed segments
+    u = torch.zeros(3, dtype=torch.float32, device=dev, requires_grad=True)
+    E = E0.clone().requires_grad_(True)
+    V = V0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, v, F, C = diff.simulate(sim, path, steps, 1, x0, v0 + u[:, None], F0, C0, E, V)
+    loss = x[0].mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    log(f"forward + backward: {t_fb:.2f} s")
+    sim.close()
+    out = {
+        "metric": "particle-substeps/s (forward + backward, contact residual 1e-6)",
+        "value": P * N * steps / t_fb, "unit": "particle-substeps/s", "n_gpus": 1, "steps": 1,
+        "warmup": 0, "ms_per_step": 1e3 * t_fb, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": (f"differentiable: {P}-particle elastic cube, 96^3 grid, pushed by a box at "
+                                f"0.5 m/s, {N * steps} substeps, checkpoint every {N} substeps, "
+                                f"eps_r=1e-6; one step = the whole forward-plus-backward run"),
+                   "particles": P, "substeps": N * steps},
+        "forward_s": t_fwd, "forward_backward_s": t_fb, "fwd_bwd_over_fwd": t_fb / t_fwd,
+        "gradient": {"d_com_x/d_v0": u.grad.cpu().tolist(), "d_com_x/d_E": float(E.grad[0]),
+                     "d_com_x/d_V_box": V.grad[0].tolist()},
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=("granular_pour", "batched"), default="granular_pour")
+    ap.add_argument("--workload", choices=("granular_pour", "batched", "differentiable"),
+                    default="granular_pour")
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--max-iter", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -156,6 +217,8 @@ def main() -> int:
         return 2
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "differentiable":
+        return run_differentiable(args)
 
     import numpy as np
     import torch

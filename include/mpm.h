@@ -221,7 +221,7 @@ mpm_status mpm_get_rigid_state(const mpm_handle* h, int32_t id, mpm_rigid_state*
 void mpm_destroy(mpm_handle* h);
 
 /* ---- Differentiation (reverse mode through recorded host steps) ----------
- * With desc->tape_substeps > 0, every mpm_step after mpm_tape_reset records
+ * With desc->tape_substeps > 0, every mpm_step after mpm_tape_reset(h, 1) records
  * what the reverse pass needs (the state at each substep start, the grid
  * before and after the contact solve, the sort permutation of each host
  * step) until the tape is full; mpm_step returns MPM_ENOMEM, with nothing
@@ -252,8 +252,9 @@ typedef struct {
                                 mpm_step was called with in = NULL */
 } mpm_rigid_grad;
 
-/* Empty the tape; the following mpm_step calls record. Host only. */
-mpm_status mpm_tape_reset(mpm_handle* h);
+/* Empty the tape; with record = 1 the following mpm_step calls record, with
+ * record = 0 they do not. Host only. */
+mpm_status mpm_tape_reset(mpm_handle* h, int32_t record);
 
 /* Reverse pass over the recorded host steps, on the handle's stream (the call
  * synchronises it once at the end). gx [3][P], gv [3][P], gF [9][P], gC [9][P]:

@@ -713,10 +713,10 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     return MPM_OK;
 }
 
-mpm_status mpm_tape_reset(mpm_handle* h) {
+mpm_status mpm_tape_reset(mpm_handle* h, int32_t record) {
     if (!h) return fail(MPM_EINVAL, "handle is NULL");
     if (h->w.tape_cap <= 0) return fail(MPM_EINVAL, "the handle was created without a tape (tape_substeps = 0)");
-    h->tape_on = true;
+    h->tape_on = record != 0;
     h->tape_len = 0;
     h->tape_ncon.clear();
     return MPM_OK;

@@ -22,6 +22,8 @@ synthetic scenes of the same kind stand in for them, larger and denser):
                      n^3 grid (dx = 1/n), elastic or sand at random, a particle
                      cube resting on a floor slab and moving down at 0.5 m/s,
                      0-2 more boxes beside it, mu uniform in [0.2, 0.9].
+* ``differentiable`` 200k-particle elastic cube on a 96^3 grid pushed by a
+                     kinematic box at 0.5 m/s (the backward-form workload).
 * ``tiny_block`` / ``tiny_random``: small scenes for exhaustive checks.
 
 Units are SI, z is up, gravity is (0, 0, -9.81). The domain of every env is
@@ -257,6 +259,24 @@ def batched(n_envs: int = 64, seed: int = 4, p_min: int = 5_000, p_max: int = 10
                                     half=(hx, hy, hz), t=(cx, 0.5 + rng.uniform(-0.1, 0.1), z_floor + hz)))
     x, v, F, C = _state(np.concatenate(xs), (0.0, 0.0, v0))
     return Scene("batched", h, N, envs, rigids, x, v, F, C)
+
+
+def differentiable(n_particles: int = 200_000, seed: int = 5, n: int = 96) -> Scene:
+    """Elastic cube (fixed-corotated, E=1e5, nu=0.3, rho=1000) of side 0.3046 m
+    (about 8 particles per cell, uniform random) centred at 0.5 on a 96^3
+    grid, pushed along +x by a kinematic box (half extents 0.02, 0.2, 0.2)
+    touching its -x face and moving at 0.5 m/s, mu = 0.5; gravity on."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n
+    side = 0.3046
+    pos = 0.5 - 0.5 * side + rng.uniform(0.0, side, (n_particles, 3))
+    V0 = side ** 3 / n_particles
+    env = EnvSpec(dims=(n, n, n), dx=dx, E=1e5, nu=0.3, rho=1000.0, V0=V0, k=_stiffness(1e5, V0),
+                  p_begin=0, p_end=n_particles)
+    box = RigidSpec(env=0, shape=BOX, mu=0.5, motion=KINEMATIC, half=(0.02, 0.2, 0.2),
+                    t=(0.5 - 0.5 * side - 0.02, 0.5, 0.5), V=(0.5, 0.0, 0.0))
+    x, v, F, C = _state(pos, (0.0, 0.0, 0.0))
+    return Scene("differentiable", 1e-4, 10, [env], [box], x, v, F, C)
 
 
 def tiny_block(n_side: int = 3, seed: int = 5, vel=(0.3, 0.1, -0.5), mu: float = 0.5,

@@ -106,7 +106,7 @@ def load():
                                ct.POINTER(StepStats)]
         L.mpm_get_rigid_state.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidState)]
         L.mpm_profile.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ProfileData)]
-        L.mpm_tape_reset.argtypes = [ct.c_void_p]
+        L.mpm_tape_reset.argtypes = [ct.c_void_p, ct.c_int32]
         L.mpm_step_backward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                         ct.POINTER(EnvGrad), ct.POINTER(RigidGrad)]
         L.mpm_destroy.argtypes = [ct.c_void_p]
@@ -245,8 +245,8 @@ def mpm_profile(h, enable: bool) -> dict:
                                          list(p.solver_phase_us))))
 
 
-def mpm_tape_reset(h) -> None:
-    _check(load().mpm_tape_reset(h), "mpm_tape_reset")
+def mpm_tape_reset(h, record: bool = True) -> None:
+    _check(load().mpm_tape_reset(h, 1 if record else 0), "mpm_tape_reset")
 
 
 def mpm_step_backward(h, gx: int, gv: int, gF: int, gC: int, n_envs: int, n_rigid: int):
@@ -319,8 +319,23 @@ class Sim:
             out = {k: a[:, inv] for k, a in out.items()}
         return out
 
-    def tape_reset(self) -> None:
-        mpm_tape_reset(self.handle)
+    def tape_reset(self, record: bool = True) -> None:
+        mpm_tape_reset(self.handle, record)
+
+    def load_state(self, x, v, F, C) -> None:
+        """Replace the state by (x, v, F, C) (tensors [3|9, P], any float dtype)
+        in the caller's particle order, and reset the particle ids."""
+        with self.torch.no_grad():
+            for dst, src in ((self.x, x), (self.v, v), (self.F, F), (self.C, C)):
+                dst.copy_(src.detach().to(device=self.device, dtype=self.torch.float32))
+            if self.pid is not None:
+                self.pid.copy_(self.torch.arange(self.P, dtype=self.torch.int32, device=self.device))
+
+    def state_tensors(self):
+        """(x, v, F, C) as new float32 tensors on the device in the order of the
+        last load_state (or creation)."""
+        inv = self.torch.argsort(self.pid.long())
+        return tuple(t[:, inv].clone() for t in (self.x, self.v, self.F, self.C))
 
     def backward(self, gx, gv, gF, gC) -> list:
         """Reverse pass over the recorded steps. gx, gv, gF, gC: contiguous

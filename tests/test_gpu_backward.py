@@ -73,7 +73,7 @@ def reverse(mpm):
     rng = np.random.default_rng(7)
     W = {a: rng.normal(size=(n, scene.P)) for a, n in FIELDS}
     sim = mpm.Sim(scene, tape_substeps=scene.N * HOST_STEPS)
-    sim.tape_reset()
+    sim.tape_reset(True)
     for _ in range(HOST_STEPS):
         status, _, st = sim.step()
         assert status == 0 and st["max_contacts"] == 0
@@ -149,7 +149,7 @@ def reverse_contact(mpm):
     gpu_scene = scene.copy()
     gpu_scene.eps_r = 1e-10
     sim = mpm.Sim(gpu_scene, tape_substeps=scene.N * HOST_STEPS)
-    sim.tape_reset()
+    sim.tape_reset(True)
     for _ in range(HOST_STEPS):
         status, _, st = sim.step()
         assert status == 0 and st["max_contacts"] > 0
