@@ -45,6 +45,7 @@ constexpr unsigned kFlagHang = 16u;
 constexpr long long kBarrierTimeoutCycles = 5000000000ll;  // ~2 s: a healthy barrier takes microseconds
 constexpr int kQnThreads = 512;
 constexpr int kSlotChunk = 512;     // contact nodes whose accumulators are staged in LDS at once
+static_assert(kSlotChunk <= kQnThreads, "one contact node of a chunk per thread");
 constexpr int kMaxRigid = 256;
 
 __device__ __forceinline__ int env_of_particle_c(const DevEnv* envs, int n_envs, long long p) {
@@ -609,34 +610,47 @@ __device__ __forceinline__ void initial_contact_velocity(const QnArgs& A, long l
 }
 
 // g, H -> dv by 3x3 Cholesky, and this node's share of the iteration sums.
-__device__ __forceinline__ void node_solve(SlotRec& S, const double j[3], const double Hc[6],
-                                           double sums[kQnSums]) {
-    const double m = S.m;
+// A contact node's mass, iterate and free-motion velocity.
+struct SlotVals {
+    double m, v[3], vs[3];
+};
+
+__device__ __forceinline__ SlotVals slot_vals(const SlotRec& S) {
+    SlotVals o;
+    o.m = S.m;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) { o.v[a] = S.v[a]; o.vs[a] = S.vstar[a]; }
+    return o;
+}
+
+// g, H -> dv = -H^{-1} g by 3x3 Cholesky (reciprocal square roots), and this
+// node's share of the iteration sums.
+__device__ __forceinline__ void node_solve(const SlotVals& S, const double j[3], const double Hc[6],
+                                           double sums[kQnSums], double dv[3]) {
+    const double m = S.m, inv_m = 1.0 / m;
     const double H[6] = {m + Hc[0], Hc[1], Hc[2], m + Hc[3], Hc[4], m + Hc[5]};  // 00 01 02 11 12 22
     double g[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) g[a] = m * (S.v[a] - S.vstar[a]) - j[a];
-    const double l00 = sqrt(H[0]);
-    const double l10 = H[1] / l00, l20 = H[2] / l00;
-    const double l11 = sqrt(H[3] - l10 * l10);
-    const double l21 = (H[4] - l20 * l10) / l11;
-    const double l22 = sqrt(H[5] - l20 * l20 - l21 * l21);
-    const double y0 = -g[0] / l00;
-    const double y1 = (-g[1] - l10 * y0) / l11;
-    const double y2 = (-g[2] - l20 * y0 - l21 * y1) / l22;
-    double dv[3];
-    dv[2] = y2 / l22;
-    dv[1] = (y1 - l21 * dv[2]) / l11;
-    dv[0] = (y0 - l10 * dv[1] - l20 * dv[2]) / l00;
+    for (int a = 0; a < 3; ++a) g[a] = m * (S.v[a] - S.vs[a]) - j[a];
+    const double i00 = inv_sqrt(H[0]);
+    const double l10 = H[1] * i00, l20 = H[2] * i00;
+    const double i11 = inv_sqrt(H[3] - l10 * l10);
+    const double l21 = (H[4] - l20 * l10) * i11;
+    const double i22 = inv_sqrt(H[5] - l20 * l20 - l21 * l21);
+    const double y0 = -g[0] * i00;
+    const double y1 = (-g[1] - l10 * y0) * i11;
+    const double y2 = (-g[2] - l20 * y0 - l21 * y1) * i22;
+    dv[2] = y2 * i22;
+    dv[1] = (y1 - l21 * dv[2]) * i11;
+    dv[0] = (y0 - l10 * dv[1] - l20 * dv[2]) * i00;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        S.dv[a] = dv[a];
-        sums[0] += g[a] * g[a] / m;                  // |grad~|^2
-        sums[1] += j[a] * j[a] / m;                  // |j~|^2
+        sums[0] += g[a] * g[a] * inv_m;              // |grad~|^2
+        sums[1] += j[a] * j[a] * inv_m;              // |j~|^2
         sums[2] += m * S.v[a] * S.v[a];              // contact-node part of |p~|^2
-        sums[3] += m * S.vstar[a] * S.vstar[a];      // same nodes at v*
+        sums[3] += m * S.vs[a] * S.vs[a];            // same nodes at v*
         sums[4] += m * dv[a] * dv[a];                // A
-        sums[5] += m * dv[a] * (S.v[a] - S.vstar[a]); // B
+        sums[5] += m * dv[a] * (S.v[a] - S.vs[a]);   // B
         sums[6] += g[a] * dv[a];                     // phi'(0)
     }
 }
@@ -804,7 +818,6 @@ k_qn(QnArgs A) {
     __shared__ double tot[kQnSums];
     __shared__ double racc[kMaxRigid * 6];
     __shared__ unsigned s_ok;
-    __shared__ double red[kQnMaxGroup * kQnSums];
     __shared__ LsCoef ls_ovf[kQnThreads];  // line-search contacts beyond the registers
     __shared__ double nacc[9][kSlotChunk];  // j (3) and R G R^T (6) of a chunk of owned slots
 
@@ -856,6 +869,9 @@ k_qn(QnArgs A) {
             for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
             for (long long sa = s0; sa < s1; sa += kSlotChunk) {
                 const long long sb = std::min<long long>(s1, sa + kSlotChunk);
+                // this thread's contact node of the chunk, loaded before the gather
+                const bool own = tid < sb - sa;
+                const SlotVals sv = slot_vals(A.s_rec[own ? sa + tid : sa]);
                 for (int q = tid; q < 9 * kSlotChunk; q += T) (&nacc[0][0])[q] = 0.0;
                 __syncthreads();
                 const int E0 = A.s_beg[sa], E1 = A.s_beg[sb];
@@ -892,11 +908,14 @@ k_qn(QnArgs A) {
                 }
                 __syncthreads();
                 if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
-                for (long long s = sa + tid; s < sb; s += T) {
-                    const int ls = (int)(s - sa);
+                if (own) {
+                    const int ls = tid;
                     const double j[3] = {nacc[0][ls], nacc[1][ls], nacc[2][ls]};
                     const double Hc[6] = {nacc[3][ls], nacc[4][ls], nacc[5][ls], nacc[6][ls], nacc[7][ls], nacc[8][ls]};
-                    node_solve(A.s_rec[s], j, Hc, sums);
+                    double dv[3];
+                    node_solve(sv, j, Hc, sums, dv);
+                    SlotRec& S = A.s_rec[sa + tid];
+                    S.dv[0] = dv[0]; S.dv[1] = dv[1]; S.dv[2] = dv[2];
                 }
                 __syncthreads();
             }
@@ -910,13 +929,13 @@ k_qn(QnArgs A) {
             if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
             if (!ok) break;
             if (G > 1u) {
-                // every block of the group sums the partials in the same order
-                for (int i = tid; i < (int)G * kQnSums; i += T) red[i] = partial[i];
-                __syncthreads();
-                if (tid < kQnSums) {
-                    double acc = 0.0;
-                    for (unsigned b = 0; b < G; ++b) acc += red[b * kQnSums + tid];
-                    tot[tid] = acc;
+                // wave q adds sum q of the group's blocks (the same bits in every block)
+                const int wv = tid >> 6, lane = tid & 63;
+                if (wv < kQnSums) {
+                    double a = 0.0;
+                    for (unsigned b = lane; b < G; b += 64) a += partial[(size_t)b * kQnSums + wv];
+                    a = wave_sum(a);
+                    if (lane == 0) tot[wv] = a;
                 }
                 __syncthreads();
 #pragma unroll
@@ -938,6 +957,14 @@ k_qn(QnArgs A) {
                     const long long c = cb + (tid >> 3);
                     const bool valid = c < c1;
                     const long long cc = valid ? c : c0;
+                    // the contact's records, loaded before the stencil gather
+                    ContactDyn& D = A.c_dyn[cc];
+                    const ContactRec& R = A.c_rec[cc];
+                    double vc[3], fr[9];
+                    contact_velocity(D, k, alpha_prev, vc);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) { fr[a] = R.t1[a]; fr[3 + a] = R.t2[a]; fr[6 + a] = R.n[a]; }
+                    const ContactParams Pc = params_of(R, A.h);
                     const ContactStencil& st = A.c_st[cc];
                     int sl[4];
                     double w[4];
@@ -964,22 +991,18 @@ k_qn(QnArgs A) {
 #pragma unroll
                         for (int a = 0; a < 3; ++a) sacc[a] += __shfl_xor(sacc[a], m, 64);
                     if (valid && part == 0) {
-                        ContactDyn& D = A.c_dyn[c];
-                        const ContactRec& R = A.c_rec[c];
-                        double vc[3];
-                        contact_velocity(D, k, alpha_prev, vc);
                         if (k > 0) {
 #pragma unroll
                             for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
                         }
                         double u[3];
-                        u[0] = R.t1[0] * sacc[0] + R.t1[1] * sacc[1] + R.t1[2] * sacc[2];
-                        u[1] = R.t2[0] * sacc[0] + R.t2[1] * sacc[1] + R.t2[2] * sacc[2];
-                        u[2] = R.n[0] * sacc[0] + R.n[1] * sacc[1] + R.n[2] * sacc[2];
+                        u[0] = fr[0] * sacc[0] + fr[1] * sacc[1] + fr[2] * sacc[2];
+                        u[1] = fr[3] * sacc[0] + fr[4] * sacc[1] + fr[5] * sacc[2];
+                        u[2] = fr[6] * sacc[0] + fr[7] * sacc[1] + fr[8] * sacc[2];
 #pragma unroll
                         for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
                         double g[3], g00, g01, g11, gnn;
-                        contact_model(params_of(R, A.h), vc, g, &g00, &g01, &g11, &gnn);
+                        contact_model(Pc, vc, g, &g00, &g01, &g11, &gnn);
                         curv[0] += g00 * u[0] * u[0] + 2.0 * g01 * u[0] * u[1] + g11 * u[1] * u[1] + gnn * u[2] * u[2];
                     }
                 }
@@ -990,16 +1013,6 @@ k_qn(QnArgs A) {
             ok = group_sync(bar, G, &gen, &s_ok, cnt);
             if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
             if (!ok) break;
-            double curv0 = curv[0];  // phi''(0) - A
-            if (G > 1u) {
-                for (int i = tid; i < (int)G; i += T) red[i] = partial2[i];
-                __syncthreads();
-                curv0 = 0.0;
-                for (unsigned b = 0; b < G; ++b) curv0 += red[b];
-                __syncthreads();
-            }
-            // first trial step: the Newton step of phi' from alpha = 0
-            const double alpha0 = Aq + curv0 > 0.0 ? -d0 / (Aq + curv0) : alpha_prev;
             // ---- exact line search, redundantly in every block of the group -------
             // Contact ec0 + i is taken by thread i mod T. The closed-form
             // coefficients of the first kLsPer*T contacts stay in registers for
@@ -1019,6 +1032,20 @@ k_qn(QnArgs A) {
                 ls_ovf[tid] = c_lds < ec1 ? ls_coef(params_of(A.c_rec[c_lds], A.h), A.c_dyn[c_lds].vc[src],
                                                     A.c_dyn[c_lds].uc)
                                           : ls_coef_zero();
+            // phi''(0) - A summed over the group (wave 0), then the first trial step:
+            // the Newton step of phi' from alpha = 0
+            double curv0 = curv[0];
+            if (G > 1u) {
+                if (tid < 64) {
+                    double a = 0.0;
+                    for (unsigned b = tid; b < G; b += 64) a += partial2[b];
+                    a = wave_sum(a);
+                    if (tid == 0) tot[0] = a;
+                }
+                __syncthreads();
+                curv0 = tot[0];
+            }
+            const double alpha0 = Aq + curv0 > 0.0 ? -d0 / (Aq + curv0) : alpha_prev;
             auto eval = [&](double alpha, double* d2out) -> double {
                 double acc2[2] = {0.0, 0.0};
 #pragma unroll
