@@ -178,8 +178,9 @@ typedef struct {
     int64_t solver_contact_iters; /* sum over iterations of registered contacts */
     int64_t solver_node_iters;    /* sum over iterations of contact nodes */
     int64_t solver_contact_rounds;/* sum over line-search evaluations of registered contacts */
-    double solver_phase_us[6];    /* solver time of its first block: node-pass gather, node solve and
-                                     sums, barrier, contact pass, barrier, line search */
+    double solver_phase_us[8];    /* solver time of the first block of the longest-solving environment:
+                                     node-pass gather, node solve and sums, barrier, contact pass,
+                                     barrier, line-search set-up, line-search evaluations, update */
 } mpm_profile_data;
 
 typedef struct mpm_handle mpm_handle;

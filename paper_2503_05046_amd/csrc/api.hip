@@ -144,6 +144,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->c_rec = L.take<ContactRec>(C);
     w->c_st = L.take<ContactStencil>(C);
     w->c_dyn = L.take<ContactDyn>(C);
+    w->c_coef = L.take<double>(11 * ((C + 63) / 64) * 64);
     w->pk_a = L.take<unsigned>(27 * C);
     w->pk_b = L.take<unsigned>(27 * C);
     w->pv_a = L.take<unsigned>(27 * C);
@@ -646,7 +647,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
                 h->acc.solver_node_iters += (int64_t)q[e].iterations * q[e].n_slots;
                 h->acc.solver_contact_rounds += (int64_t)q[e].ls_rounds * q[e].n_contacts;
             }
-            for (int ph = 0; ph < 6; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)lead.t_phase[ph] / h->wall_khz;
+            for (int ph = 0; ph < 8; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)lead.t_phase[ph] / h->wall_khz;
         }
     }
     if (h->h_cnt->abort_step && h->h_cnt->abort_substep > 0) {

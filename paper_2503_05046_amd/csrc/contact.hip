@@ -137,6 +137,29 @@ __device__ __forceinline__ LsCoef ls_coef(const ContactParams& P, const double v
     return L;
 }
 
+// Line-search coefficients of every contact, in chunks of 64 contacts: chunk
+// c / 64 holds 11 arrays of 64 values (in the order of LsCoef's members), so a
+// wave reading consecutive contacts reads consecutive words, and the array
+// offsets are constants of the load instructions.
+constexpr int kCoefChunk = 64;
+constexpr int kCoefWords = 11;
+__device__ __forceinline__ long long coef_index(long long c) {
+    return (c / kCoefChunk) * (kCoefChunk * kCoefWords) + (c % kCoefChunk);
+}
+__device__ __forceinline__ void store_coef(double* __restrict__ buf, long long c, const LsCoef& L) {
+    double* p = buf + coef_index(c);
+    const double q[kCoefWords] = {L.q0, L.p0, L.q2, L.mun0, L.a0, L.a1, L.b0, L.b1, L.kn, L.eh, L.ed};
+#pragma unroll
+    for (int j = 0; j < kCoefWords; ++j) p[j * kCoefChunk] = q[j];
+}
+__device__ __forceinline__ LsCoef load_coef(const double* __restrict__ buf, long long c) {
+    const double* p = buf + coef_index(c);
+    LsCoef L;
+    L.q0 = p[0]; L.p0 = p[64]; L.q2 = p[128]; L.mun0 = p[192]; L.a0 = p[256]; L.a1 = p[320];
+    L.b0 = p[384]; L.b1 = p[448]; L.kn = p[512]; L.eh = p[576]; L.ed = p[640];
+    return L;
+}
+
 // Coefficients that contribute exactly zero (padding lanes).
 __device__ __forceinline__ LsCoef ls_coef_zero() {
     LsCoef L;
@@ -471,6 +494,7 @@ struct QnArgs {
     const ContactRec* c_rec;
     const ContactStencil* c_st;
     ContactDyn* c_dyn;
+    double* c_coef;
     const int *s_node, *s_beg;
     const Entry* e_ent;
     SlotRec* s_rec;
@@ -743,7 +767,7 @@ __device__ double exact_line_search(Eval eval, double alpha0, double d0, int max
 
 __device__ __forceinline__ void write_stats(const QnArgs& A, int env, long long nc, long long ns, int k,
                                             int converged, int ls_total, double res, double thr,
-                                            const unsigned long long tph[6], bool aborted, int kind) {
+                                            const unsigned long long tph[8], bool aborted, int kind) {
     SubstepStats st;
     st.n_contacts = (int)nc;
     st.n_slots = (int)ns;
@@ -753,7 +777,7 @@ __device__ __forceinline__ void write_stats(const QnArgs& A, int env, long long 
     st.pad = kind;
     st.residual = res;
     st.threshold = thr;
-    for (int q = 0; q < 6; ++q) st.t_phase[q] = tph[q];
+    for (int q = 0; q < 8; ++q) st.t_phase[q] = tph[q];
     A.stats[(size_t)A.substep * A.n_envs + env] = st;
     if (!converged && !aborted) atomicOr(&A.cnt->flags, kFlagNoconv);
 }
@@ -831,7 +855,7 @@ k_qn(QnArgs A) {
         const unsigned G = A.env_stride > 0 ? 1u : (unsigned)A.env_qn[2 * env + 1];
         const int rank = A.env_stride > 0 ? 0 : me.y;
         const bool timer = rank == 0 && tid == 0;
-        unsigned long long tph[6] = {0, 0, 0, 0, 0, 0};
+        unsigned long long tph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         unsigned long long tmark = 0;
         if (aborted) {
             if (timer) write_stats(A, env, 0, 0, 0, 1, 0, 0.0, 0.0, tph, true, 0);
@@ -1001,6 +1025,7 @@ k_qn(QnArgs A) {
                         u[2] = fr[6] * sacc[0] + fr[7] * sacc[1] + fr[8] * sacc[2];
 #pragma unroll
                         for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
+                        store_coef(A.c_coef, c, ls_coef(Pc, vc, u));
                         double g[3], g00, g01, g11, gnn;
                         contact_model(Pc, vc, g, &g00, &g01, &g11, &gnn);
                         curv[0] += g00 * u[0] * u[0] + 2.0 * g01 * u[0] * u[1] + g11 * u[1] * u[1] + gnn * u[2] * u[2];
@@ -1018,20 +1043,17 @@ k_qn(QnArgs A) {
             // coefficients of the first kLsPer*T contacts stay in registers for
             // all the evaluations, the next T in LDS, and any beyond are formed
             // from memory at each evaluation.
-            const int src = k == 0 ? 0 : (k & 1);
+            // the coefficients the contact pass stored (coalesced loads)
+            auto coef_of = [&](long long c) -> LsCoef { return load_coef(A.c_coef, c); };
             LsCoef lc[kLsPer];
 #pragma unroll
             for (int u = 0; u < kLsPer; ++u) {
                 const long long c = ec0 + tid + (long long)u * T;
-                lc[u] = c < ec1 ? ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc)
-                                : ls_coef_zero();
+                lc[u] = c < ec1 ? coef_of(c) : ls_coef_zero();
             }
             const long long c_lds = ec0 + tid + (long long)kLsPer * T;
             const bool use_lds = (long long)kLsPer * T < nc;
-            if (use_lds)
-                ls_ovf[tid] = c_lds < ec1 ? ls_coef(params_of(A.c_rec[c_lds], A.h), A.c_dyn[c_lds].vc[src],
-                                                    A.c_dyn[c_lds].uc)
-                                          : ls_coef_zero();
+            if (use_lds) ls_ovf[tid] = c_lds < ec1 ? coef_of(c_lds) : ls_coef_zero();
             // phi''(0) - A summed over the group (wave 0), then the first trial step:
             // the Newton step of phi' from alpha = 0
             double curv0 = curv[0];
@@ -1046,6 +1068,7 @@ k_qn(QnArgs A) {
                 curv0 = tot[0];
             }
             const double alpha0 = Aq + curv0 > 0.0 ? -d0 / (Aq + curv0) : alpha_prev;
+            if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
             auto eval = [&](double alpha, double* d2out) -> double {
                 double acc2[2] = {0.0, 0.0};
 #pragma unroll
@@ -1061,8 +1084,7 @@ k_qn(QnArgs A) {
                     acc2[0] += d1;
                     acc2[1] += d2;
                     for (long long c = c_lds + T; c < ec1; c += T) {
-                        ls_eval(ls_coef(params_of(A.c_rec[c], A.h), A.c_dyn[c].vc[src], A.c_dyn[c].uc), alpha,
-                                &d1, &d2);
+                        ls_eval(coef_of(c), alpha, &d1, &d2);
                         acc2[0] += d1;
                         acc2[1] += d2;
                     }
@@ -1072,12 +1094,13 @@ k_qn(QnArgs A) {
                 return fma(Aq, alpha, Bq) + acc2[0];
             };
             const double alpha = exact_line_search(eval, alpha0, d0, A.ls_max_steps, &ls_total);
-            if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
+            if (timer) { const unsigned long long t = wall_clock64(); tph[6] += t - tmark; tmark = t; }
             for (long long s = s0 + tid; s < s1; s += T) {
                 SlotRec& S = A.s_rec[s];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, S.dv[a], S.v[a]);
             }
+            if (timer) { const unsigned long long t = wall_clock64(); tph[7] += t - tmark; tmark = t; }
             alpha_prev = alpha;
             ++k;
         }
@@ -1110,7 +1133,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.vel = w.vel;
     A.cap = w.cap_c;
     A.c_pid = w.c_pid; A.c_rid = w.c_rid;
-    A.c_rec = w.c_rec; A.c_st = w.c_st; A.c_dyn = w.c_dyn;
+    A.c_rec = w.c_rec; A.c_st = w.c_st; A.c_dyn = w.c_dyn; A.c_coef = w.c_coef;
     A.s_node = w.s_node; A.s_beg = w.s_beg;
     A.e_ent = w.e_ent;
     A.s_rec = w.s_rec;

@@ -53,8 +53,8 @@ struct SubstepStats {
     int pad;
     double residual;
     double threshold;
-    unsigned long long t_phase[6];  // solver wall-clock ticks: node gather, node solve, barrier, contact pass,
-                                    // barrier, line search
+    unsigned long long t_phase[8];  // solver wall-clock ticks: node gather, node solve, barrier, contact pass,
+                                    // barrier, line-search set-up, line-search evaluations, update
 };
 
 // Contact solver data as compact records, so that a gather of one contact or
@@ -137,6 +137,7 @@ struct Work {
     ContactRec* c_rec;       // [cap] per-substep contact data
     ContactStencil* c_st;    // [cap] slots and weights of the 27 stencil nodes
     ContactDyn* c_dyn;       // [cap] solver state
+    double* c_coef;          // line-search coefficients of each contact, chunks of 64 contacts x 11 (contact pass)
     // contact-node pairs (capacity 27 cap_c)
     unsigned *pk_a, *pk_b, *pv_a, *pv_b;
     Entry* e_ent;            // [27 cap] (contact, slot, weight) in slot order

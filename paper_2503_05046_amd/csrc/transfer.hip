@@ -673,7 +673,7 @@ __global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, Sub
         SubstepStats z;
         z.n_contacts = z.n_slots = z.iterations = z.converged = z.ls_rounds = z.pad = 0;
         z.residual = z.threshold = 0.0;
-        for (int q = 0; q < 6; ++q) z.t_phase[q] = 0ull;
+        for (int q = 0; q < 8; ++q) z.t_phase[q] = 0ull;
         st[i] = z;
     }
 }

@@ -84,7 +84,7 @@ class ProfileData(ct.Structure):
     _fields_ = [("ms", ct.c_double * 7), ("launches", ct.c_int64 * 7),
                 ("solver_iterations", ct.c_int64), ("solver_ls_rounds", ct.c_int64),
                 ("solver_contact_iters", ct.c_int64), ("solver_node_iters", ct.c_int64),
-                ("solver_contact_rounds", ct.c_int64), ("solver_phase_us", ct.c_double * 6)]
+                ("solver_contact_rounds", ct.c_int64), ("solver_phase_us", ct.c_double * 8)]
 
 
 _lib = None
@@ -241,7 +241,7 @@ def mpm_profile(h, enable: bool) -> dict:
                 solver_contact_iters=p.solver_contact_iters,
                 solver_node_iters=p.solver_node_iters,
                 solver_contact_rounds=p.solver_contact_rounds,
-                solver_phase_us=dict(zip(("node_gather", "node_solve", "barrier1", "contact", "barrier2", "line_search"),
+                solver_phase_us=dict(zip(("node_gather", "node_solve", "barrier1", "contact", "barrier2", "ls_setup", "ls_evals", "update"),
                                          list(p.solver_phase_us))))
 
 
