@@ -381,6 +381,9 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         // and a cap on the solver's blocks (below it, environments share blocks)
         const char* mb = getenv("MPM_SOLVER_MAX_BLOCKS");
         if (mb && atoi(mb) > 0) h->qn_cap = std::min(h->qn_cap, atoi(mb));
+        // MPM_SOLVER_COMPACT=0 sends every solver block through the general node pass
+        const char* cp = getenv("MPM_SOLVER_COMPACT");
+        h->w.qn_compact = (cp && atoi(cp) == 0) ? 0 : 1;
     }
     h->w.n_rigid = 0;
     int tiles = 0;

@@ -513,6 +513,7 @@ struct QnArgs {
     unsigned* env_bar;         // per environment: barrier count and generation
     int n_envs;
     int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
+    int compact;               // 0: no block takes the compact node pass
     DevCounters* cnt;
 };
 
@@ -835,6 +836,11 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, unsigned G, unsigned* 
 
 constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
 constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
+constexpr int kUniqMax = 512;    // distinct contacts of a block's entries the compact node pass holds
+constexpr int kHash = 2048;      // open-addressing table that finds them (power of two)
+static_assert(kHash * sizeof(int) <= 9 * kSlotChunk * sizeof(double), "hash table lives in nacc");
+static_assert(9 * kUniqMax <= 11 * kQnThreads, "contact terms live in the line-search buffer");
+static_assert(kEntBatch * kQnThreads <= kHash / 2, "the hash table is at most half full");
 
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
@@ -842,8 +848,15 @@ k_qn(QnArgs A) {
     __shared__ double tot[kQnSums];
     __shared__ double racc[kMaxRigid * 6];
     __shared__ unsigned s_ok;
-    __shared__ LsCoef ls_ovf[kQnThreads];  // line-search contacts beyond the registers
+    // line-search contacts beyond the registers; in the compact node pass, the
+    // terms of the block's distinct contacts ([9][kUniqMax])
+    __shared__ double ovf_raw[11 * kQnThreads];
+    LsCoef* ls_ovf = reinterpret_cast<LsCoef*>(ovf_raw);
+    double* u_term = ovf_raw;
     __shared__ double nacc[9][kSlotChunk];  // j (3) and R G R^T (6) of a chunk of owned slots
+    __shared__ int2 ent_l[kEntBatch * kQnThreads];  // compact pass: (slot | contact << 16, w) per entry
+    __shared__ int u_list[kUniqMax];                // compact pass: the distinct contacts
+    __shared__ unsigned scan_w[17];
 
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
@@ -882,6 +895,68 @@ k_qn(QnArgs A) {
 
         for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
 
+        // Compact node pass: when the block's contact nodes fit one chunk, its
+        // CSR entries one batch, and the entries name at most kUniqMax distinct
+        // contacts, the entries stay in LDS for the whole solve (slot and
+        // contact as block-local indices) and each distinct contact's terms
+        // are formed once per iteration instead of once per entry.
+        const int E0s = A.s_beg[s0], n_ent = A.s_beg[s1] - E0s;
+        bool compact = A.compact != 0 && s1 - s0 <= kSlotChunk && n_ent <= kEntBatch * T;
+        int n_u = 0;
+        if (compact) {
+            int* htab = reinterpret_cast<int*>(&nacc[0][0]);
+            for (int q = tid; q < kHash; q += T) htab[q] = -1;
+            __syncthreads();
+            int pos[kEntBatch], eslot[kEntBatch];
+            float ew[kEntBatch];
+#pragma unroll
+            for (int u = 0; u < kEntBatch; ++u) {
+                const int e = tid + u * T;
+                pos[u] = -1;
+                if (e < n_ent) {
+                    const Entry en = A.e_ent[E0s + e];
+                    eslot[u] = en.slot - (int)s0;
+                    ew[u] = en.w;
+                    // linear probing; the table is at most half full, so a free
+                    // or matching position is always found
+                    unsigned hsh = (en.c * 2654435761u) >> (32 - 11);
+                    static_assert(kHash == 1 << 11, "hash width");
+                    for (;;) {
+                        const int prev = atomicCAS(&htab[hsh], -1, (int)en.c);
+                        if (prev == -1 || prev == (int)en.c) break;
+                        hsh = (hsh + 1) & (kHash - 1);
+                    }
+                    pos[u] = (int)hsh;
+                }
+            }
+            __syncthreads();
+            // number the occupied positions in table order
+            constexpr int kPer = kHash / kQnThreads;
+            int occ = 0;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) occ += htab[tid * kPer + q] >= 0 ? 1 : 0;
+            unsigned n_occ;
+            int base = (int)block_exclusive_scan_total((unsigned)occ, scan_w, &n_occ);
+            n_u = (int)n_occ;
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) {
+                const int h = tid * kPer + q;
+                const int c = htab[h];
+                if (c >= 0) {
+                    if (base < kUniqMax) u_list[base] = c;
+                    htab[h] = base++;
+                }
+            }
+            __syncthreads();
+            compact = n_u <= kUniqMax;
+            if (compact) {
+#pragma unroll
+                for (int u = 0; u < kEntBatch; ++u)
+                    if (pos[u] >= 0) ent_l[tid + u * T] = make_int2(eslot[u] | (htab[pos[u]] << 16), __float_as_int(ew[u]));
+            }
+            __syncthreads();
+        }
+
         int k = 0, ls_total = 0, converged = 0;
         double alpha_prev = 1.0, res = 0.0, thr = 0.0;
         bool ok = group_sync(bar, G, &gen, &s_ok, cnt);
@@ -891,7 +966,49 @@ k_qn(QnArgs A) {
             double sums[kQnSums];
 #pragma unroll
             for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
-            for (long long sa = s0; sa < s1; sa += kSlotChunk) {
+            if (compact) {
+                const bool own = tid < s1 - s0;
+                const SlotVals sv = slot_vals(A.s_rec[own ? s0 + tid : s0]);
+                for (int t = tid; t < n_u; t += T) {
+                    const unsigned c = (unsigned)u_list[t];
+                    double vc[3], rg[3], rgr[6];
+                    contact_velocity(A.c_dyn[c], k, alpha_prev, vc);
+                    contact_terms(A.c_rec[c], A.h, vc, rg, rgr);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) u_term[a * kUniqMax + t] = rg[a];
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) u_term[(3 + q) * kUniqMax + t] = rgr[q];
+                }
+                if (own) {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) nacc[q][tid] = 0.0;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u = 0; u < kEntBatch; ++u) {
+                    const int e = tid + u * T;
+                    if (e < n_ent) {
+                        const int2 el = ent_l[e];
+                        const int ls = el.x & 0xFFFF, lc = el.x >> 16;
+                        const double w = (double)__int_as_float(el.y);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * u_term[a * kUniqMax + lc]);
+#pragma unroll
+                        for (int q = 3; q < 9; ++q) atomicAdd(&nacc[q][ls], w * w * u_term[q * kUniqMax + lc]);
+                    }
+                }
+                __syncthreads();
+                if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
+                if (own) {
+                    const double j[3] = {nacc[0][tid], nacc[1][tid], nacc[2][tid]};
+                    const double Hc[6] = {nacc[3][tid], nacc[4][tid], nacc[5][tid], nacc[6][tid], nacc[7][tid], nacc[8][tid]};
+                    double dv[3];
+                    node_solve(sv, j, Hc, sums, dv);
+                    SlotRec& S = A.s_rec[s0 + tid];
+                    S.dv[0] = dv[0]; S.dv[1] = dv[1]; S.dv[2] = dv[2];
+                }
+            }
+            for (long long sa = s0; sa < s1 && !compact; sa += kSlotChunk) {
                 const long long sb = std::min<long long>(s1, sa + kSlotChunk);
                 // this thread's contact node of the chunk, loaded before the gather
                 const bool own = tid < sb - sa;
@@ -1134,6 +1251,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.cap = w.cap_c;
     A.c_pid = w.c_pid; A.c_rid = w.c_rid;
     A.c_rec = w.c_rec; A.c_st = w.c_st; A.c_dyn = w.c_dyn; A.c_coef = w.c_coef;
+    A.compact = w.qn_compact;
     A.s_node = w.s_node; A.s_beg = w.s_beg;
     A.e_ent = w.e_ent;
     A.s_rec = w.s_rec;

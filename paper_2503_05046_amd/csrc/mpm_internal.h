@@ -107,8 +107,8 @@ struct DevCounters {
     unsigned pad[7];
 };
 
-constexpr int kBarStride = 16;
-constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps each host step's table)  // unsigned words between the barrier counters of two environments
+constexpr int kBarStride = 16;     // unsigned words between the barrier counters of two environments
+constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps each host step's table)
 
 // Pointers into the caller's workspace.
 struct Work {
@@ -183,6 +183,7 @@ struct Work {
     int n_rigid;
     long long cap_c, cap_s;
     int qn_blocks;           // co-resident solver blocks (capacity of partial and qn_map)
+    int qn_compact;          // 1: blocks that fit take the compact node pass (0 only to test the other)
 };
 
 // One recorded substep of the differentiation tape.

@@ -130,6 +130,23 @@ def test_contact_substep_metric_tolerance(mpm, oracle):
     assert e["x"] < 1e-5 and e["F"] < 1e-5, e
 
 
+def test_contact_substep_general_node_pass(mpm, oracle, monkeypatch):
+    """The solver's general node pass (chunks of contact nodes, entries read
+    from memory each iteration), which blocks too large for the compact pass
+    take: forced for every block, at a tight tolerance."""
+    monkeypatch.setenv("MPM_SOLVER_COMPACT", "0")
+    s = _contact_state(oracle, 22)
+    s.N = 1
+    s.eps_r = 1e-10
+    s.max_iter = 400000
+    _log("plain cube contact substep, general node pass, eps_r = 1e-10")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s)
+    e = field_errors(g, o, s.envs[0].dx)
+    assert max(e.values()) < 1e-5, (e, sg[0], so[0])
+    m_tot = s.envs[0].m_p * s.P
+    assert impulse_error(ig, io, m_tot, s.h) < 1e-4
+
+
 def test_contact_substep_tight(mpm, oracle):
     s = _contact_state(oracle, 22)
     s.N = 1
