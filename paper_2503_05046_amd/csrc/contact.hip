@@ -137,6 +137,20 @@ __device__ __forceinline__ LsCoef ls_coef(const ContactParams& P, const double v
     return L;
 }
 
+// Values the solver's blocks exchange inside the iteration loop (search
+// directions, contact velocities and their projections u_c, line-search
+// coefficients, block partial sums) are stored and loaded as device-scope
+// relaxed atomics, which write through and read past the per-XCD caches. With
+// each thread's stores acknowledged before its block arrives at a barrier,
+// the loop's barriers then need no write-back or invalidation of the caches,
+// and the data that stays fixed during the solve stays cached.
+__device__ __forceinline__ double ld_x(const double* p) {
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_x(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Line-search coefficients of every contact, in chunks of 64 contacts: chunk
 // c / 64 holds 11 arrays of 64 values (in the order of LsCoef's members), so a
 // wave reading consecutive contacts reads consecutive words, and the array
@@ -150,13 +164,14 @@ __device__ __forceinline__ void store_coef(double* __restrict__ buf, long long c
     double* p = buf + coef_index(c);
     const double q[kCoefWords] = {L.q0, L.p0, L.q2, L.mun0, L.a0, L.a1, L.b0, L.b1, L.kn, L.eh, L.ed};
 #pragma unroll
-    for (int j = 0; j < kCoefWords; ++j) p[j * kCoefChunk] = q[j];
+    for (int j = 0; j < kCoefWords; ++j) st_x(p + j * kCoefChunk, q[j]);
 }
 __device__ __forceinline__ LsCoef load_coef(const double* __restrict__ buf, long long c) {
     const double* p = buf + coef_index(c);
     LsCoef L;
-    L.q0 = p[0]; L.p0 = p[64]; L.q2 = p[128]; L.mun0 = p[192]; L.a0 = p[256]; L.a1 = p[320];
-    L.b0 = p[384]; L.b1 = p[448]; L.kn = p[512]; L.eh = p[576]; L.ed = p[640];
+    L.q0 = ld_x(p); L.p0 = ld_x(p + 64); L.q2 = ld_x(p + 128); L.mun0 = ld_x(p + 192); L.a0 = ld_x(p + 256);
+    L.a1 = ld_x(p + 320); L.b0 = ld_x(p + 384); L.b1 = ld_x(p + 448); L.kn = ld_x(p + 512); L.eh = ld_x(p + 576);
+    L.ed = ld_x(p + 640);
     return L;
 }
 
@@ -534,7 +549,7 @@ __device__ __forceinline__ ContactParams params_of(const ContactRec& R, double h
 __device__ __forceinline__ void contact_velocity(const ContactDyn& D, int k, double alpha_prev, double vc[3]) {
     const int src = k == 0 ? 0 : (k - 1) & 1;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) vc[a] = k == 0 ? D.vc[0][a] : fma(alpha_prev, D.uc[a], D.vc[src][a]);
+    for (int a = 0; a < 3; ++a) vc[a] = k == 0 ? ld_x(&D.vc[0][a]) : fma(alpha_prev, ld_x(&D.uc[a]), ld_x(&D.vc[src][a]));
 }
 
 // Sum of x over the 64 lanes of a wave, the same bits in every lane: DPP
@@ -834,6 +849,42 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, unsigned G, unsigned* 
     return *s_ok != 0u;
 }
 
+// Barrier of the iteration loop, for data exchanged through ld_x / st_x: a
+// counter that only grows (bar[2]); the i-th barrier after the start of the
+// solve completes when it reaches its value at the start plus i * G. Each
+// thread waits for its own stores to be acknowledged before the block
+// arrives. Same time limit as group_sync.
+__device__ __forceinline__ bool loop_sync(unsigned* bar, unsigned G, unsigned* target, unsigned* s_ok,
+                                          DevCounters* cnt) {
+    if (G == 1u) {
+        __syncthreads();
+        return true;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    *target += G;
+    if (threadIdx.x == 0) {
+        bool ok = true;
+        __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const long long t0 = clock64();
+        unsigned polls = 0;
+        while ((int)(__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - *target) < 0) {
+            __builtin_amdgcn_s_sleep(1);
+            if ((++polls & 255u) == 0u &&
+                ((__hip_atomic_load(&cnt->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagHang) ||
+                 clock64() - t0 > kBarrierTimeoutCycles)) {
+                atomicOr(&cnt->flags, kFlagHang);
+                ok = false;
+                break;
+            }
+        }
+        *s_ok = ok ? 1u : 0u;
+    }
+    __syncthreads();
+    return *s_ok != 0u;
+}
+
 constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
 constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
 constexpr int kUniqMax = 512;    // distinct contacts of a block's entries the compact node pass holds
@@ -876,6 +927,8 @@ k_qn(QnArgs A) {
         }
         unsigned* bar = A.env_bar + (size_t)env * kBarStride;
         unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // read before the first barrier, which no block passes before all have read it
+        unsigned ltarget = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         const long long ec0 = A.env_range[4 * env], ec1 = A.env_range[4 * env + 1];
         const long long es0 = A.env_range[4 * env + 2], es1 = A.env_range[4 * env + 3];
         const long long nc = ec1 - ec0, ns = es1 - es0;
@@ -1005,7 +1058,7 @@ k_qn(QnArgs A) {
                     double dv[3];
                     node_solve(sv, j, Hc, sums, dv);
                     SlotRec& S = A.s_rec[s0 + tid];
-                    S.dv[0] = dv[0]; S.dv[1] = dv[1]; S.dv[2] = dv[2];
+                    st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
                 }
             }
             for (long long sa = s0; sa < s1 && !compact; sa += kSlotChunk) {
@@ -1056,17 +1109,17 @@ k_qn(QnArgs A) {
                     double dv[3];
                     node_solve(sv, j, Hc, sums, dv);
                     SlotRec& S = A.s_rec[sa + tid];
-                    S.dv[0] = dv[0]; S.dv[1] = dv[1]; S.dv[2] = dv[2];
+                    st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
                 }
                 __syncthreads();
             }
             block_allsum<kQnSums>(sums, rbuf, rpar);
             if (G > 1u && tid == 0) {
 #pragma unroll
-                for (int q = 0; q < kQnSums; ++q) partial[(size_t)rank * kQnSums + q] = sums[q];
+                for (int q = 0; q < kQnSums; ++q) st_x(&partial[(size_t)rank * kQnSums + q], sums[q]);
             }
             if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
-            ok = group_sync(bar, G, &gen, &s_ok, cnt);
+            ok = loop_sync(bar, G, &ltarget, &s_ok, cnt);
             if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
             if (!ok) break;
             if (G > 1u) {
@@ -1074,7 +1127,7 @@ k_qn(QnArgs A) {
                 const int wv = tid >> 6, lane = tid & 63;
                 if (wv < kQnSums) {
                     double a = 0.0;
-                    for (unsigned b = lane; b < G; b += 64) a += partial[(size_t)b * kQnSums + wv];
+                    for (unsigned b = lane; b < G; b += 64) a += ld_x(&partial[(size_t)b * kQnSums + wv]);
                     a = wave_sum(a);
                     if (lane == 0) tot[wv] = a;
                 }
@@ -1120,7 +1173,7 @@ k_qn(QnArgs A) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const SlotRec& S = A.s_rec[sl[j]];
-                        dvs[j][0] = S.dv[0]; dvs[j][1] = S.dv[1]; dvs[j][2] = S.dv[2];
+                        dvs[j][0] = ld_x(&S.dv[0]); dvs[j][1] = ld_x(&S.dv[1]); dvs[j][2] = ld_x(&S.dv[2]);
                     }
                     double sacc[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -1134,14 +1187,14 @@ k_qn(QnArgs A) {
                     if (valid && part == 0) {
                         if (k > 0) {
 #pragma unroll
-                            for (int a = 0; a < 3; ++a) D.vc[k & 1][a] = vc[a];
+                            for (int a = 0; a < 3; ++a) st_x(&D.vc[k & 1][a], vc[a]);
                         }
                         double u[3];
                         u[0] = fr[0] * sacc[0] + fr[1] * sacc[1] + fr[2] * sacc[2];
                         u[1] = fr[3] * sacc[0] + fr[4] * sacc[1] + fr[5] * sacc[2];
                         u[2] = fr[6] * sacc[0] + fr[7] * sacc[1] + fr[8] * sacc[2];
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) D.uc[a] = u[a];
+                        for (int a = 0; a < 3; ++a) st_x(&D.uc[a], u[a]);
                         store_coef(A.c_coef, c, ls_coef(Pc, vc, u));
                         double g[3], g00, g01, g11, gnn;
                         contact_model(Pc, vc, g, &g00, &g01, &g11, &gnn);
@@ -1150,9 +1203,9 @@ k_qn(QnArgs A) {
                 }
             }
             block_allsum<1>(curv, rbuf, rpar);
-            if (G > 1u && tid == 0) partial2[rank] = curv[0];
+            if (G > 1u && tid == 0) st_x(&partial2[rank], curv[0]);
             if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
-            ok = group_sync(bar, G, &gen, &s_ok, cnt);
+            ok = loop_sync(bar, G, &ltarget, &s_ok, cnt);
             if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
             if (!ok) break;
             // ---- exact line search, redundantly in every block of the group -------
@@ -1177,7 +1230,7 @@ k_qn(QnArgs A) {
             if (G > 1u) {
                 if (tid < 64) {
                     double a = 0.0;
-                    for (unsigned b = tid; b < G; b += 64) a += partial2[b];
+                    for (unsigned b = tid; b < G; b += 64) a += ld_x(&partial2[b]);
                     a = wave_sum(a);
                     if (tid == 0) tot[0] = a;
                 }
@@ -1215,7 +1268,7 @@ k_qn(QnArgs A) {
             for (long long s = s0 + tid; s < s1; s += T) {
                 SlotRec& S = A.s_rec[s];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, S.dv[a], S.v[a]);
+                for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, ld_x(&S.dv[a]), S.v[a]);
             }
             if (timer) { const unsigned long long t = wall_clock64(); tph[7] += t - tmark; tmark = t; }
             alpha_prev = alpha;
