@@ -908,6 +908,9 @@ k_qn(QnArgs A) {
     __shared__ int2 ent_l[kEntBatch * kQnThreads];  // compact pass: (slot | contact << 16, w) per entry
     __shared__ int u_list[kUniqMax];                // compact pass: the distinct contacts
     __shared__ unsigned scan_w[17];
+    __shared__ double node_v[3][kSlotChunk];  // compact pass: the iterate of the block's contact nodes
+    __shared__ int cst_slot[4][kQnThreads];   // contact pass of a block with at most T/8 contacts:
+    __shared__ float cst_w[4][kQnThreads];    // each lane's stencil slots and weights
 
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
@@ -1006,8 +1009,26 @@ k_qn(QnArgs A) {
 #pragma unroll
                 for (int u = 0; u < kEntBatch; ++u)
                     if (pos[u] >= 0) ent_l[tid + u * T] = make_int2(eslot[u] | (htab[pos[u]] << 16), __float_as_int(ew[u]));
+                if (tid < s1 - s0) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) node_v[a][tid] = A.s_rec[s0 + tid].v[a];
+                }
             }
             __syncthreads();
+        }
+        // contact pass of a block whose contacts fit one pass (eight lanes each):
+        // the lanes' stencil slots and weights stay in LDS for the whole solve
+        const bool ccache = c1 - c0 <= T / 8;
+        if (ccache) {
+            const long long c = c0 + (tid >> 3);
+            const int part = tid & 7;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = part + 8 * j;
+                const int q = (o < 27 && c < c1) ? A.c_st[c].slot[o] : -1;
+                cst_slot[j][tid] = q < 0 ? 0 : q;
+                cst_w[j][tid] = q < 0 ? 0.f : A.c_st[c].w[o];
+            }
         }
 
         int k = 0, ls_total = 0, converged = 0;
@@ -1021,7 +1042,13 @@ k_qn(QnArgs A) {
             for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
             if (compact) {
                 const bool own = tid < s1 - s0;
-                const SlotVals sv = slot_vals(A.s_rec[own ? s0 + tid : s0]);
+                SlotVals sv;
+                {
+                    const SlotRec& S = A.s_rec[own ? s0 + tid : s0];
+                    sv.m = S.m;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) { sv.vs[a] = S.vstar[a]; sv.v[a] = own ? node_v[a][tid] : 0.0; }
+                }
                 for (int t = tid; t < n_u; t += T) {
                     const unsigned c = (unsigned)u_list[t];
                     double vc[3], rg[3], rgr[6];
@@ -1059,6 +1086,8 @@ k_qn(QnArgs A) {
                     node_solve(sv, j, Hc, sums, dv);
                     SlotRec& S = A.s_rec[s0 + tid];
                     st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) nacc[a][tid] = dv[a];  // kept for the update
                 }
             }
             for (long long sa = s0; sa < s1 && !compact; sa += kSlotChunk) {
@@ -1164,10 +1193,15 @@ k_qn(QnArgs A) {
                     double w[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int o = part + 8 * j;
-                        const int q = (o < 27 && valid) ? st.slot[o] : -1;
-                        sl[j] = q < 0 ? 0 : q;
-                        w[j] = q < 0 ? 0.0 : (double)st.w[o];
+                        if (ccache) {
+                            sl[j] = cst_slot[j][tid];
+                            w[j] = (double)cst_w[j][tid];
+                        } else {
+                            const int o = part + 8 * j;
+                            const int q = (o < 27 && valid) ? st.slot[o] : -1;
+                            sl[j] = q < 0 ? 0 : q;
+                            w[j] = q < 0 ? 0.0 : (double)st.w[o];
+                        }
                     }
                     double dvs[4][3];
 #pragma unroll
@@ -1265,16 +1299,27 @@ k_qn(QnArgs A) {
             };
             const double alpha = exact_line_search(eval, alpha0, d0, A.ls_max_steps, &ls_total);
             if (timer) { const unsigned long long t = wall_clock64(); tph[6] += t - tmark; tmark = t; }
-            for (long long s = s0 + tid; s < s1; s += T) {
-                SlotRec& S = A.s_rec[s];
+            if (compact) {
+                if (tid < s1 - s0) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, ld_x(&S.dv[a]), S.v[a]);
+                    for (int a = 0; a < 3; ++a) node_v[a][tid] = fma(alpha, nacc[a][tid], node_v[a][tid]);
+                }
+            } else {
+                for (long long s = s0 + tid; s < s1; s += T) {
+                    SlotRec& S = A.s_rec[s];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) S.v[a] = fma(alpha, ld_x(&S.dv[a]), S.v[a]);
+                }
             }
             if (timer) { const unsigned long long t = wall_clock64(); tph[7] += t - tmark; tmark = t; }
             alpha_prev = alpha;
             ++k;
         }
         // ---- outputs ----------------------------------------------------------------
+        if (compact && tid < s1 - s0) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) A.s_rec[s0 + tid].v[a] = node_v[a][tid];
+        }
         for (long long s = s0 + tid; s < s1; s += T) {
             const SlotRec& S = A.s_rec[s];
             float4 g = A.vel[A.s_node[s]];
