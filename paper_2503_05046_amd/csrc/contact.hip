@@ -580,12 +580,12 @@ __device__ __forceinline__ double wave_sum(double x) {
     return (r[0] + r[1]) + (r[2] + r[3]);
 }
 
-// Block-wide FP64 sums of NV values per thread, returned in every thread with
-// the same bits in every thread (and in every block that sums the same
-// values): wave sums, one workgroup barrier, then each thread adds the wave
-// sums in wave order. buf holds 2 x 16 x NV doubles used alternately, so a
+// Block-wide FP64 sums of NV values per thread over a block of NW waves,
+// returned in every thread with the same bits in every thread (and in every
+// block that sums the same values): wave sums, one workgroup barrier, then
+// each thread adds the wave sums in wave order. buf holds 2 x 16 x NV doubles used alternately, so a
 // wave that runs ahead cannot overwrite sums another wave is still reading.
-template <int NV>
+template <int NV, int NW = kQnThreads / 64>
 __device__ __forceinline__ void block_allsum(double (&v)[NV], double* buf, unsigned& parity) {
     double* b = buf + (parity & 1u) * 16 * NV;
     parity ^= 1u;
@@ -596,11 +596,12 @@ __device__ __forceinline__ void block_allsum(double (&v)[NV], double* buf, unsig
         if ((threadIdx.x & 63) == 0) b[wave * NV + k] = ws;
     }
     __syncthreads();
-    const int nw = blockDim.x >> 6;
+    // NW is the block's wave count: a constant, so all the reads issue together
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double t = 0.0;
-        for (int w = 0; w < nw; ++w) t += b[w * NV + k];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += b[w * NV + k];
         v[k] = t;
     }
 }
