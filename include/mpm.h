@@ -211,8 +211,11 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
                     mpm_step_stats* st);
 
 /* Profiling: enable (1) or disable (0) event timing of the kernel classes
- * for the following steps. out (may be NULL) receives what was accumulated
- * since the previous call, and the accumulators are reset. Host only. */
+ * for the following steps; 2 also times the solver's phases (solver_phase_us),
+ * whose clock reads sit on the solver's critical path and lengthen it, so
+ * timings taken with 2 are for the breakdown only. out (may be NULL) receives
+ * what was accumulated since the previous call, and the accumulators are
+ * reset. Host only. */
 mpm_status mpm_profile(mpm_handle* h, int32_t enable, mpm_profile_data* out);
 
 /* Current pose and twist of rigid body id (host). */

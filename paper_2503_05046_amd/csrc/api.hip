@@ -247,6 +247,7 @@ struct mpm_handle {
     int* h_env_qn;
     // profiling
     bool prof = false;
+    bool prof_phases = false;  // solver phase timers (they lengthen the solve)
     std::vector<hipEvent_t> events;   // pairs (start, stop)
     std::vector<int> ev_class;        // kernel class of each pair
     mpm_profile_data acc;
@@ -610,7 +611,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         {
             ProfScope ps(h, MPM_K_SOLVE, npair);
             HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
-                              env_stride, s));
+                              env_stride, h->prof_phases ? 1 : 0, s));
         }
         if (rec)
             HIP_TRY(hipMemcpyAsync(tg + W.n_nodes, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
@@ -862,6 +863,7 @@ mpm_status mpm_profile(mpm_handle* h, int32_t enable, mpm_profile_data* out) {
     if (out) *out = h->acc;
     memset(&h->acc, 0, sizeof(h->acc));
     h->prof = enable != 0;
+    h->prof_phases = enable >= 2;
     return MPM_OK;
 }
 

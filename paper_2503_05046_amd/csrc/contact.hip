@@ -529,6 +529,7 @@ struct QnArgs {
     int n_envs;
     int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
     int compact;               // 0: no block takes the compact node pass
+    int timers;                // 1: the first block of each environment times the solver's phases
     DevCounters* cnt;
 };
 
@@ -907,6 +908,7 @@ k_qn(QnArgs A) {
     double* u_term = ovf_raw;
     __shared__ double nacc[9][kSlotChunk];  // j (3) and R G R^T (6) of a chunk of owned slots
     __shared__ int2 ent_l[kEntBatch * kQnThreads];  // compact pass: (slot | contact << 16, w) per entry
+    __shared__ int beg_l[kSlotChunk + 1];           // compact pass: first entry of each contact node
     __shared__ int u_list[kUniqMax];                // compact pass: the distinct contacts
     __shared__ unsigned scan_w[17];
     __shared__ double node_v[3][kSlotChunk];  // compact pass: the iterate of the block's contact nodes
@@ -922,11 +924,12 @@ k_qn(QnArgs A) {
         const int first = A.env_stride > 0 ? (int)blockIdx.x : A.env_qn[2 * env];
         const unsigned G = A.env_stride > 0 ? 1u : (unsigned)A.env_qn[2 * env + 1];
         const int rank = A.env_stride > 0 ? 0 : me.y;
-        const bool timer = rank == 0 && tid == 0;
+        const bool writer = rank == 0 && tid == 0;  // writes the environment's stats
+        const bool timer = writer && A.timers != 0; // and, when asked, times the phases
         unsigned long long tph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         unsigned long long tmark = 0;
         if (aborted) {
-            if (timer) write_stats(A, env, 0, 0, 0, 1, 0, 0.0, 0.0, tph, true, 0);
+            if (writer) write_stats(A, env, 0, 0, 0, 1, 0, 0.0, 0.0, tph, true, 0);
             continue;
         }
         unsigned* bar = A.env_bar + (size_t)env * kBarStride;
@@ -1013,7 +1016,9 @@ k_qn(QnArgs A) {
                 if (tid < s1 - s0) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) node_v[a][tid] = A.s_rec[s0 + tid].v[a];
+                    beg_l[tid] = A.s_beg[s0 + tid] - E0s;
                 }
+                if (tid == 0) beg_l[s1 - s0] = n_ent;
             }
             __syncthreads();
         }
@@ -1060,29 +1065,24 @@ k_qn(QnArgs A) {
 #pragma unroll
                     for (int q = 0; q < 6; ++q) u_term[(3 + q) * kUniqMax + t] = rgr[q];
                 }
-                if (own) {
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) nacc[q][tid] = 0.0;
-                }
                 __syncthreads();
-#pragma unroll
-                for (int u = 0; u < kEntBatch; ++u) {
-                    const int e = tid + u * T;
-                    if (e < n_ent) {
+                // each contact node adds its entries' terms in entry order
+                double j[3] = {0.0, 0.0, 0.0}, Hc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                if (own) {
+                    const int e1 = beg_l[tid + 1];
+                    for (int e = beg_l[tid]; e < e1; ++e) {
                         const int2 el = ent_l[e];
-                        const int ls = el.x & 0xFFFF, lc = el.x >> 16;
+                        const int lc = el.x >> 16;
                         const double w = (double)__int_as_float(el.y);
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) atomicAdd(&nacc[a][ls], w * u_term[a * kUniqMax + lc]);
+                        for (int a = 0; a < 3; ++a) j[a] = fma(w, u_term[a * kUniqMax + lc], j[a]);
+                        const double w2 = w * w;
 #pragma unroll
-                        for (int q = 3; q < 9; ++q) atomicAdd(&nacc[q][ls], w * w * u_term[q * kUniqMax + lc]);
+                        for (int q = 0; q < 6; ++q) Hc[q] = fma(w2, u_term[(3 + q) * kUniqMax + lc], Hc[q]);
                     }
                 }
-                __syncthreads();
                 if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
                 if (own) {
-                    const double j[3] = {nacc[0][tid], nacc[1][tid], nacc[2][tid]};
-                    const double Hc[6] = {nacc[3][tid], nacc[4][tid], nacc[5][tid], nacc[6][tid], nacc[7][tid], nacc[8][tid]};
                     double dv[3];
                     node_solve(sv, j, Hc, sums, dv);
                     SlotRec& S = A.s_rec[s0 + tid];
@@ -1333,7 +1333,7 @@ k_qn(QnArgs A) {
         __syncthreads();
         for (int q = tid; q < A.n_rigid * 6; q += T)
             if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
-        if (timer) write_stats(A, env, nc, ns, k, converged, ls_total, res, thr, tph, false, (int)G);
+        if (writer) write_stats(A, env, nc, ns, k, converged, ls_total, res, thr, tph, false, (int)G);
         __syncthreads();  // racc and the block sums are reused by the next environment
         if (!ok) break;
     }
@@ -1341,7 +1341,7 @@ k_qn(QnArgs A) {
 
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
                      double eps_a, int max_iter, int ls_max_steps, int blocks, int env_stride,
-                     hipStream_t s) {
+                     int timers, hipStream_t s) {
     QnArgs A;
     A.rigids = w.rigids;
     A.x = x;
@@ -1351,6 +1351,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.c_pid = w.c_pid; A.c_rid = w.c_rid;
     A.c_rec = w.c_rec; A.c_st = w.c_st; A.c_dyn = w.c_dyn; A.c_coef = w.c_coef;
     A.compact = w.qn_compact;
+    A.timers = timers;
     A.s_node = w.s_node; A.s_beg = w.s_beg;
     A.e_ent = w.e_ent;
     A.s_rec = w.s_rec;

@@ -231,10 +231,11 @@ def mpm_get_rigid_state(h, rid: int) -> RigidState:
     return s
 
 
-def mpm_profile(h, enable: bool) -> dict:
-    """Switch kernel-class event timing on/off; returns what was accumulated."""
+def mpm_profile(h, enable: int) -> dict:
+    """Kernel-class event timing off (0), on (1), or on with the solver's phase
+    timers (2, which lengthen the solve); returns what was accumulated."""
     p = ProfileData()
-    _check(load().mpm_profile(h, 1 if enable else 0, ct.byref(p)), "mpm_profile")
+    _check(load().mpm_profile(h, int(enable), ct.byref(p)), "mpm_profile")
     return dict(ms={k: p.ms[i] for i, k in enumerate(KERNEL_CLASSES)},
                 launches={k: p.launches[i] for i, k in enumerate(KERNEL_CLASSES)},
                 solver_iterations=p.solver_iterations, solver_ls_rounds=p.solver_ls_rounds,
@@ -349,7 +350,7 @@ class Sim:
         return mpm_step_backward(self.handle, gx.data_ptr(), gv.data_ptr(), gF.data_ptr(), gC.data_ptr(),
                                  len(self.scene.envs), self.n_rigid)
 
-    def profile(self, enable: bool) -> dict:
+    def profile(self, enable: int) -> dict:
         return mpm_profile(self.handle, enable)
 
     def rigid_state(self, i: int) -> RigidState:
