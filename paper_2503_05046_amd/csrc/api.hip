@@ -164,6 +164,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->qn_map = L.take<int2>(kMaxQnBlocks);
     w->env_qn = L.take<int>(2 * (size_t)z.n_envs);
     w->env_bar = L.take<unsigned>((size_t)kBarStride * z.n_envs);
+    w->env_ctr = L.take<unsigned>((size_t)kCtrLanes * kCtrStride * z.n_envs);
     const long long T = z.tape_cap;
     w->tape_p = T ? L.take<float>((size_t)T * 24 * P) : nullptr;
     w->tape_g = T ? L.take<float4>((size_t)T * 2 * z.n_nodes) : nullptr;
@@ -442,6 +443,8 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
     if (e == hipSuccess) e = hipMemsetAsync(W.ptile_of, 0xFF, sizeof(int) * W.n_tiles, s);
     if (e == hipSuccess) e = hipMemsetAsync(W.cnt, 0, sizeof(DevCounters), s);
     if (e == hipSuccess) e = hipMemsetAsync(W.env_bar, 0, sizeof(unsigned) * kBarStride * W.n_envs, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(W.env_ctr, 0, sizeof(unsigned) * kCtrLanes * kCtrStride * W.n_envs, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

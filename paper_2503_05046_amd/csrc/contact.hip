@@ -526,6 +526,7 @@ struct QnArgs {
     const int* env_range;      // per environment: contacts [c0, c1), contact nodes [s0, s1)
     const double* env_pnorm;   // per environment: sum m |v*|^2 over its active nodes
     unsigned* env_bar;         // per environment: barrier count and generation
+    unsigned* env_ctr;         // per environment: loop-barrier arrival counters
     int n_envs;
     int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
     int compact;               // 0: no block takes the compact node pass
@@ -851,12 +852,23 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, unsigned G, unsigned* 
     return *s_ok != 0u;
 }
 
-// Barrier of the iteration loop, for data exchanged through ld_x / st_x: a
-// counter that only grows (bar[2]); the i-th barrier after the start of the
-// solve completes when it reaches its value at the start plus i * G. Each
-// thread waits for its own stores to be acknowledged before the block
-// arrives. Same time limit as group_sync.
-__device__ __forceinline__ bool loop_sync(unsigned* bar, unsigned G, unsigned* target, unsigned* s_ok,
+// Barrier of the iteration loop, for data exchanged through ld_x / st_x.
+// Arrivals are spread over kCtrLanes counters that only grow (a block adds to
+// counter rank mod kCtrLanes, each in its own cache line, so fewer blocks
+// contend for one); the i-th barrier after the start of the solve completes
+// when their sum reaches its value at the start plus i * G. Eight lanes of the
+// first wave poll the counters together. Each thread waits for its own stores
+// to be acknowledged before the block arrives. Same time limit as group_sync.
+__device__ __forceinline__ unsigned ctr_sum(unsigned* ctr) {
+    const int lane = threadIdx.x & 63;
+    int v = lane < kCtrLanes
+                ? (int)__hip_atomic_load(&ctr[lane * kCtrStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                : 0;
+#pragma unroll
+    for (int m = 1; m < kCtrLanes; m <<= 1) v += __shfl_xor(v, m, 64);
+    return (unsigned)__shfl(v, 0, 64);
+}
+__device__ __forceinline__ bool loop_sync(unsigned* ctr, int rank, unsigned G, unsigned* target, unsigned* s_ok,
                                           DevCounters* cnt) {
     if (G == 1u) {
         __syncthreads();
@@ -866,22 +878,24 @@ __device__ __forceinline__ bool loop_sync(unsigned* bar, unsigned G, unsigned* t
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     *target += G;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 64) {
         bool ok = true;
-        __hip_atomic_fetch_add(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&ctr[(rank % kCtrLanes) * kCtrStride], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         const long long t0 = clock64();
         unsigned polls = 0;
-        while ((int)(__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) - *target) < 0) {
+        while ((int)(ctr_sum(ctr) - *target) < 0) {
             __builtin_amdgcn_s_sleep(1);
             if ((++polls & 255u) == 0u &&
                 ((__hip_atomic_load(&cnt->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kFlagHang) ||
                  clock64() - t0 > kBarrierTimeoutCycles)) {
-                atomicOr(&cnt->flags, kFlagHang);
+                if (threadIdx.x == 0) atomicOr(&cnt->flags, kFlagHang);
                 ok = false;
                 break;
             }
         }
-        *s_ok = ok ? 1u : 0u;
+        if (threadIdx.x == 0) *s_ok = ok ? 1u : 0u;
     }
     __syncthreads();
     return *s_ok != 0u;
@@ -935,7 +949,8 @@ k_qn(QnArgs A) {
         unsigned* bar = A.env_bar + (size_t)env * kBarStride;
         unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // read before the first barrier, which no block passes before all have read it
-        unsigned ltarget = __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned* ctr = A.env_ctr + (size_t)env * kCtrLanes * kCtrStride;
+        unsigned ltarget = ctr_sum(ctr);
         const long long ec0 = A.env_range[4 * env], ec1 = A.env_range[4 * env + 1];
         const long long es0 = A.env_range[4 * env + 2], es1 = A.env_range[4 * env + 3];
         const long long nc = ec1 - ec0, ns = es1 - es0;
@@ -1149,7 +1164,7 @@ k_qn(QnArgs A) {
                 for (int q = 0; q < kQnSums; ++q) st_x(&partial[(size_t)rank * kQnSums + q], sums[q]);
             }
             if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
-            ok = loop_sync(bar, G, &ltarget, &s_ok, cnt);
+            ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
             if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
             if (!ok) break;
             if (G > 1u) {
@@ -1240,7 +1255,7 @@ k_qn(QnArgs A) {
             block_allsum<1>(curv, rbuf, rpar);
             if (G > 1u && tid == 0) st_x(&partial2[rank], curv[0]);
             if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
-            ok = loop_sync(bar, G, &ltarget, &s_ok, cnt);
+            ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
             if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
             if (!ok) break;
             // ---- exact line search, redundantly in every block of the group -------
@@ -1368,6 +1383,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.env_range = w.env_range;
     A.env_pnorm = w.env_pnorm;
     A.env_bar = w.env_bar;
+    A.env_ctr = w.env_ctr;
     A.n_envs = w.n_envs;
     A.env_stride = env_stride;
     A.cnt = w.cnt;

@@ -108,6 +108,8 @@ struct DevCounters {
 };
 
 constexpr int kBarStride = 16;     // unsigned words between the barrier counters of two environments
+constexpr int kCtrLanes = 8;       // loop-barrier arrival counters per environment (block rank mod 8)
+constexpr int kCtrStride = 32;     // unsigned words between two of them (separate 128-byte lines)
 constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps each host step's table)
 
 // Pointers into the caller's workspace.
@@ -156,6 +158,7 @@ struct Work {
     int2* qn_map;            // [solver blocks] (env, rank in the env's block group)
     int* env_qn;             // [n_envs][2] first block and block count of the env's group
     unsigned* env_bar;       // [n_envs][kBarStride] barrier arrival count and generation
+    unsigned* env_ctr;       // [n_envs][kCtrLanes][kCtrStride] arrival counters of the solver's loop barriers
     // differentiation tape and reverse-pass buffers (tape_cap substeps; empty when 0)
     float* tape_p;           // [tape_cap][24][P] x, v, F, Q at each substep start
     float4* tape_g;          // [tape_cap][2][n_nodes] grid after the update and after the solve
