@@ -925,7 +925,8 @@ k_qn(QnArgs A) {
     __shared__ int beg_l[kSlotChunk + 1];           // compact pass: first entry of each contact node
     __shared__ int u_list[kUniqMax];                // compact pass: the distinct contacts
     __shared__ unsigned scan_w[17];
-    __shared__ double node_v[3][kSlotChunk];  // compact pass: the iterate of the block's contact nodes
+    __shared__ double node_v[3][kSlotChunk];  // compact pass: the iterate of the block's contact nodes,
+    __shared__ double node_mv[4][kSlotChunk]; // and their mass and free-motion velocity
     __shared__ int cst_slot[4][kQnThreads];   // contact pass of a block with at most T/8 contacts:
     __shared__ float cst_w[4][kQnThreads];    // each lane's stencil slots and weights
 
@@ -1031,12 +1032,20 @@ k_qn(QnArgs A) {
                 if (tid < s1 - s0) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) node_v[a][tid] = A.s_rec[s0 + tid].v[a];
+                    node_mv[0][tid] = A.s_rec[s0 + tid].m;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) node_mv[1 + a][tid] = A.s_rec[s0 + tid].vstar[a];
                     beg_l[tid] = A.s_beg[s0 + tid] - E0s;
                 }
                 if (tid == 0) beg_l[s1 - s0] = n_ent;
             }
             __syncthreads();
         }
+        // compact pass: nl adjacent lanes share a contact node's entries (as many
+        // as the block's threads allow, up to 8)
+        int lg_nl = 0;
+        while (lg_nl < 3 && (s1 - s0) << (lg_nl + 1) <= T) ++lg_nl;
+        const int nl = 1 << lg_nl;
         // contact pass of a block whose contacts fit one pass (eight lanes each):
         // the lanes' stencil slots and weights stay in LDS for the whole solve
         const bool ccache = c1 - c0 <= T / 8;
@@ -1062,13 +1071,15 @@ k_qn(QnArgs A) {
 #pragma unroll
             for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
             if (compact) {
-                const bool own = tid < s1 - s0;
+                const int ls = tid >> lg_nl, sub = tid & (nl - 1);
+                const bool mine = ls < s1 - s0;    // a lane of contact node ls
+                const bool own = mine && sub == 0; // its first lane, which solves it
                 SlotVals sv;
-                {
-                    const SlotRec& S = A.s_rec[own ? s0 + tid : s0];
-                    sv.m = S.m;
+                sv.m = own ? node_mv[0][ls] : 1.0;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) { sv.vs[a] = S.vstar[a]; sv.v[a] = own ? node_v[a][tid] : 0.0; }
+                for (int a = 0; a < 3; ++a) {
+                    sv.vs[a] = own ? node_mv[1 + a][ls] : 0.0;
+                    sv.v[a] = own ? node_v[a][ls] : 0.0;
                 }
                 for (int t = tid; t < n_u; t += T) {
                     const unsigned c = (unsigned)u_list[t];
@@ -1081,11 +1092,12 @@ k_qn(QnArgs A) {
                     for (int q = 0; q < 6; ++q) u_term[(3 + q) * kUniqMax + t] = rgr[q];
                 }
                 __syncthreads();
-                // each contact node adds its entries' terms in entry order
+                // the nl lanes of a contact node add every nl-th of its entries'
+                // terms, then combine their sums by shuffles
                 double j[3] = {0.0, 0.0, 0.0}, Hc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-                if (own) {
-                    const int e1 = beg_l[tid + 1];
-                    for (int e = beg_l[tid]; e < e1; ++e) {
+                if (mine) {
+                    const int e1 = beg_l[ls + 1];
+                    for (int e = beg_l[ls] + sub; e < e1; e += nl) {
                         const int2 el = ent_l[e];
                         const int lc = el.x >> 16;
                         const double w = (double)__int_as_float(el.y);
@@ -1096,14 +1108,20 @@ k_qn(QnArgs A) {
                         for (int q = 0; q < 6; ++q) Hc[q] = fma(w2, u_term[(3 + q) * kUniqMax + lc], Hc[q]);
                     }
                 }
+                for (int m = 1; m < nl; m <<= 1) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) j[a] += __shfl_xor(j[a], m, 64);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) Hc[q] += __shfl_xor(Hc[q], m, 64);
+                }
                 if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
                 if (own) {
                     double dv[3];
                     node_solve(sv, j, Hc, sums, dv);
-                    SlotRec& S = A.s_rec[s0 + tid];
+                    SlotRec& S = A.s_rec[s0 + ls];
                     st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) nacc[a][tid] = dv[a];  // kept for the update
+                    for (int a = 0; a < 3; ++a) nacc[a][ls] = dv[a];  // kept for the update
                 }
             }
             for (long long sa = s0; sa < s1 && !compact; sa += kSlotChunk) {
