@@ -37,6 +37,56 @@ SOLVE_BYTES_PER_NODE_ITER = 88
 SOLVE_BYTES_PER_CONTACT_ROUND = 40  # per line-search reduction round
 
 
+# The solver's HBM traffic per launch, measured with rocprofv3 PMC counters
+# (FETCH_SIZE, WRITE_SIZE) and a plain device copy of known size for scale, is
+# recorded in this summary together with a hash of the solver's sources; it is
+# reported only while the sources still match.
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_solve_granular_pour_1M.md")
+SOLVER_SOURCES = ("contact.hip", "contact_model.h", "mpm_internal.h", "sort_util.h")
+
+
+def solver_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in SOLVER_SOURCES:
+        with open(os.path.join(ROOT, "paper_2503_05046_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """Bytes per solver launch from the PMC summary, or None when there is no
+    summary or the solver's sources changed since it was taken."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    fields = {}
+    with open(PMC_SUMMARY) as f:
+        for line in f:
+            if ":" in line and line.startswith("- "):
+                k, v = line[2:].split(":", 1)
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("solver sources sha256") != solver_source_hash():
+        return None
+    try:
+        return float(fields["HBM bytes per solver launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(n_bytes: int) -> int:
+    """One plain device-to-device copy of n_bytes (the scale for the PMC byte
+    counters)."""
+    import torch
+    n = n_bytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "check": float(dst[-1].item())}), flush=True)
+    return 0
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -205,7 +255,11 @@ def main() -> int:
     ap.add_argument("--max-iter", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device copy of BYTES (scale for the PMC byte counters)")
     args = ap.parse_args()
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
     args.warmup_set = args.warmup is not None
     if args.warmup is None:
         args.warmup = 5
@@ -287,7 +341,7 @@ def main() -> int:
     dom = kernels[dominant]
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": dom.get("algo_GBps"),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom.get("frac_hbm_peak"),
-                "traffic": None}
+                "traffic": measured_traffic() if dominant == "solve" else None}
     iters = [i for st in stats for i in st["iterations"]]
     contacts = [c for st in stats for c in st["contacts"]]
     nodes = [c for st in stats for c in st["contact_nodes"]]
