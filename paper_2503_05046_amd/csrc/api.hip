@@ -314,6 +314,21 @@ int plan_solver(mpm_handle* h, int* env_stride) {
         --g[big];
         --total;
     }
+    // The counts come from an earlier substep; the kernel sizes each group from
+    // the current one and leaves surplus blocks idle. Spare co-resident blocks
+    // go to the groups as headroom, one at a time, smallest group first, so an
+    // environment whose contact grows (or starts) is not held to a stale size.
+    for (bool grew = true; grew && total < cap;) {
+        grew = false;
+        int small = -1;
+        for (int e = 0; e < n_envs; ++e)
+            if (g[e] < kQnMaxGroup && (small < 0 || g[e] < g[small])) small = e;
+        if (small >= 0) {
+            ++g[small];
+            ++total;
+            grew = true;
+        }
+    }
     int b = 0;
     for (int e = 0; e < n_envs; ++e) {
         h->h_env_qn[2 * e] = b;
@@ -614,7 +629,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         {
             ProfScope ps(h, MPM_K_SOLVE, npair);
             HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
-                              env_stride, h->prof_phases ? 1 : 0, s));
+                              env_stride, h->prof_phases ? 1 : 0, h->slots_per_block, s));
         }
         if (rec)
             HIP_TRY(hipMemcpyAsync(tg + W.n_nodes, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));

@@ -531,6 +531,7 @@ struct QnArgs {
     int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
     int compact;               // 0: no block takes the compact node pass
     int timers;                // 1: the first block of each environment times the solver's phases
+    int slots_per_block;       // contact nodes per block that set an environment's group size
     DevCounters* cnt;
 };
 
@@ -937,7 +938,10 @@ k_qn(QnArgs A) {
     unsigned rpar = 0;  // parity of the block-sum buffer
     for (int env = me.x; env < A.n_envs; env += A.env_stride > 0 ? A.env_stride : A.n_envs) {
         const int first = A.env_stride > 0 ? (int)blockIdx.x : A.env_qn[2 * env];
-        const unsigned G = A.env_stride > 0 ? 1u : (unsigned)A.env_qn[2 * env + 1];
+        // blocks launched for this environment; the group uses as many as its
+        // contact nodes in this substep ask for (the launch is planned on the
+        // host from an earlier substep), and the others skip it
+        const unsigned G_launch = A.env_stride > 0 ? 1u : (unsigned)A.env_qn[2 * env + 1];
         const int rank = A.env_stride > 0 ? 0 : me.y;
         const bool writer = rank == 0 && tid == 0;  // writes the environment's stats
         const bool timer = writer && A.timers != 0; // and, when asked, times the phases
@@ -955,6 +959,9 @@ k_qn(QnArgs A) {
         const long long ec0 = A.env_range[4 * env], ec1 = A.env_range[4 * env + 1];
         const long long es0 = A.env_range[4 * env + 2], es1 = A.env_range[4 * env + 3];
         const long long nc = ec1 - ec0, ns = es1 - es0;
+        const unsigned G = (unsigned)std::min<long long>(
+            G_launch, std::max<long long>(1, (ns + A.slots_per_block - 1) / A.slots_per_block));
+        if ((unsigned)rank >= G) continue;
         // contact nodes split so that every block gets about the same number of
         // CSR entries (the node pass's work); contacts split evenly
         long long s0 = es0, s1 = es1;
@@ -1374,7 +1381,7 @@ k_qn(QnArgs A) {
 
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
                      double eps_a, int max_iter, int ls_max_steps, int blocks, int env_stride,
-                     int timers, hipStream_t s) {
+                     int timers, int slots_per_block, hipStream_t s) {
     QnArgs A;
     A.rigids = w.rigids;
     A.x = x;
@@ -1385,6 +1392,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.c_rec = w.c_rec; A.c_st = w.c_st; A.c_dyn = w.c_dyn; A.c_coef = w.c_coef;
     A.compact = w.qn_compact;
     A.timers = timers;
+    A.slots_per_block = std::max(1, slots_per_block);
     A.s_node = w.s_node; A.s_beg = w.s_beg;
     A.e_ent = w.e_ent;
     A.s_rec = w.s_rec;

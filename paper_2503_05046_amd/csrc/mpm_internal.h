@@ -215,7 +215,7 @@ hipError_t launch_registration(const Work& w, const float* x, const float* v, do
 hipError_t launch_contact_setup(const Work& w, hipStream_t s);
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
                      double eps_a, int max_iter, int ls_max_steps, int blocks, int env_stride,
-                     int timers, hipStream_t s);
+                     int timers, int slots_per_block, hipStream_t s);
 int qn_max_blocks();
 constexpr int kQnMaxGroup = 128;  // blocks of one environment's group (partials staged in LDS)
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
