@@ -210,6 +210,27 @@ mpm_status mpm_add_rigid_sdf(mpm_handle* h, int32_t env, const mpm_rigid_desc* r
 mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse* out,
                     mpm_step_stats* st);
 
+/* Advance n_steps host steps as one replay of a HIP graph that holds all of
+ * them (for the batched form, where many small environments make each solve
+ * short and the ~16 launches per substep a visible cost): the sort and N
+ * substeps of every host step, n_steps times, become one graph launch. Rigid
+ * bodies follow the library's own state, as with in = NULL in mpm_step:
+ * static bodies stay put, kinematic bodies advance with their twist after
+ * every host step (on the device inside the graph; the host state then takes
+ * the device's values). The graph is recorded on the first call and again
+ * when n_steps, the number of rigid bodies or the solver's block plan
+ * changes; the solver's groups are planned per replay from the latest host
+ * step (the kernel sizes each group from the current substep). It runs on a
+ * stream of the handle's own, after the work already queued on desc->stream,
+ * and the call returns when the replay is done. out (may be NULL): impulses
+ * on the rigid bodies summed over the n_steps host steps. st (may be NULL):
+ * statistics of the last host step. A host step that stops (capacity
+ * overflow, non-finite state, a particle outside the grid) leaves the host
+ * steps after it in the replay without effect, and its error is returned as
+ * in mpm_step. MPM_EINVAL while the differentiation tape records or event
+ * timing is on, or for n_steps < 1. */
+mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out, mpm_step_stats* st);
+
 /* Profiling: enable (1) or disable (0) event timing of the kernel classes
  * for the following steps; 2 also times the solver's phases (solver_phase_us),
  * whose clock reads sit on the solver's critical path and lengthen it, so

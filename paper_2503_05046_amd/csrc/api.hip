@@ -198,7 +198,7 @@ struct HostRigid {
     int env;
 };
 
-void rodrigues_advance(double R[9], const double w[3], double dt) {
+__host__ __device__ void rodrigues_advance(double R[9], const double w[3], double dt) {
     const double wn = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
     const double th = wn * dt;
     if (th == 0.0) return;
@@ -218,7 +218,23 @@ void rodrigues_advance(double R[9], const double w[3], double dt) {
             for (int q = 0; q < 3; ++q) s += Rot[r * 3 + q] * R[q * 3 + c];
             Rn[r * 3 + c] = s;
         }
-    memcpy(R, Rn, sizeof(Rn));
+    for (int i = 0; i < 9; ++i) R[i] = Rn[i];
+}
+
+// The kinematic advance of the rigid table on the device (graph path): the
+// same rule as the host's; static bodies carry a zero twist.
+__global__ void k_advance_kinematic(DevRigid* r, int n, double dt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    DevRigid& q = r[i];
+    for (int a = 0; a < 3; ++a) q.t[a] += dt * q.V[a];
+    rodrigues_advance(q.R, q.w, dt);
+}
+
+hipError_t launch_advance_kinematic(DevRigid* r, int n, double dt, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_advance_kinematic, dim3((n + 63) / 64), dim3(64), 0, s, r, n, dt);
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -252,6 +268,13 @@ struct mpm_handle {
     std::vector<hipEvent_t> events;   // pairs (start, stop)
     std::vector<int> ev_class;        // kernel class of each pair
     mpm_profile_data acc;
+    // graph path: a stream of its own (capture needs one that is not the null
+    // stream), ordered after the handle's stream by an event
+    hipStream_t gstream = nullptr;
+    hipEvent_t gevent = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_steps = 0, graph_qn_blocks = 0, graph_stride = 0, graph_nr = -1;
 };
 
 namespace {
@@ -338,6 +361,221 @@ int plan_solver(mpm_handle* h, int* env_stride) {
     *env_stride = 0;
     return total;
 }
+
+// Device-order rigid table (h_rigids) and each environment's rigid range from
+// the host state, grouped by environment (stable) so that each environment
+// owns a range; order[k] is the user id of device entry k.
+void build_rigid_table(mpm_handle* h, std::vector<int>& order) {
+    const int nr = (int)h->rigids.size();
+    order.resize(nr);
+    for (int i = 0; i < nr; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->rigids[a].env < h->rigids[b].env; });
+    for (DevEnv& D : h->denv) D.rigid_begin = D.rigid_end = 0;
+    for (int k = 0; k < nr; ++k) {
+        const HostRigid& q = h->rigids[order[k]];
+        DevRigid& R = h->h_rigids[k];
+        R.shape = q.desc.shape;
+        R.env = q.env;
+        memcpy(R.normal, q.desc.normal, sizeof(R.normal));
+        R.offset = q.desc.offset;
+        memcpy(R.half, q.desc.half, sizeof(R.half));
+        R.mu = q.desc.mu;
+        memcpy(R.R, q.desc.R, sizeof(R.R));
+        memcpy(R.t, q.desc.t, sizeof(R.t));
+        if (q.desc.motion == MPM_STATIC) {
+            memset(R.V, 0, sizeof(R.V));
+            memset(R.w, 0, sizeof(R.w));
+        } else {
+            memcpy(R.V, q.desc.V, sizeof(R.V));
+            memcpy(R.w, q.desc.w, sizeof(R.w));
+        }
+        DevEnv& D = h->denv[q.env];
+        if (D.rigid_end == D.rigid_begin) D.rigid_begin = D.rigid_end = k;
+        D.rigid_end = k + 1;
+    }
+    h->w.n_rigid = nr;
+}
+
+// Device work of one host step on the handle's stream (the tables are already
+// uploaded). Inside a graph the step clears only its statistics (the replay
+// clears flags and impulse sums once), records neither tape nor events, and
+// ends by advancing the kinematic bodies on the device.
+mpm_status enqueue_host_step(mpm_handle* h, int qn_blocks, int env_stride, bool graph, int& npair, hipStream_t s) {
+    Work& W = h->w;
+    const mpm_desc& d = h->d;
+    const int N = d.N;
+    const int ls_steps = d.ls_max_steps > 0 ? d.ls_max_steps : 100;
+    const int n_envs = (int)h->envs.size();
+    const int nr = W.n_rigid;
+    const bool rec = !graph && h->tape_on;
+    HIP_TRY(launch_clear_step(W, N, graph, s));
+    {
+        // once per host step: cell keys, stable sort, gather, tile list (Sec. V-A)
+        ProfScope ps(h, MPM_K_SORT, npair);
+        HIP_TRY(launch_keys(W, d.x, s));
+        unsigned *keys_sorted, *idx_sorted;
+        HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
+        HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
+        if (rec) {
+            const size_t j = (size_t)(h->tape_len / N);
+            HIP_TRY(hipMemcpyAsync(W.tape_idx + j * W.P, idx_sorted, sizeof(unsigned) * W.P,
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(W.tape_rig + j * kMaxRigidTape, W.rigids, sizeof(DevRigid) * std::max(nr, 1),
+                                   hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(W.tape_env + j * n_envs, W.envs, sizeof(DevEnv) * n_envs,
+                                   hipMemcpyDeviceToDevice, s));
+        }
+        HIP_TRY(launch_tile_maps(W, s, true));   // forget the previous step's tiles
+        HIP_TRY(launch_tile_list(W, keys_sorted, s));
+        HIP_TRY(launch_tile_maps(W, s, false));
+        W.keys_sorted = keys_sorted;
+    }
+    for (int k = 0; k < N; ++k) {
+        const bool first = k == 0, last = k == N - 1;
+        const float* x_in = first ? W.xs : d.x;
+        const float* v_in = first ? W.vs : d.v;
+        const float* F_in = first ? W.Fs : d.F;
+        HIP_TRY(launch_clear_substep(W, s));
+        float* tp = rec ? W.tape_p + (size_t)(h->tape_len + k) * 24 * W.P : nullptr;
+        float4* tg = rec ? W.tape_g + (size_t)(h->tape_len + k) * 2 * W.n_nodes : nullptr;
+        if (rec) {
+            const size_t P = W.P;
+            HIP_TRY(hipMemcpyAsync(tp, x_in, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(tp + 3 * P, v_in, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(tp + 6 * P, F_in, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+            HIP_TRY(hipMemcpyAsync(tp + 15 * P, W.Q, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_P2G, npair);
+            HIP_TRY(launch_p2g(W, x_in, v_in, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_GRID, npair);
+            HIP_TRY(launch_grid_update(W, d.h, s));
+        }
+        if (rec) HIP_TRY(hipMemcpyAsync(tg, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
+        {
+            ProfScope ps(h, MPM_K_REGISTER, npair);
+            HIP_TRY(launch_registration(W, x_in, v_in, d.h, k, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_SETUP, npair);
+            HIP_TRY(launch_contact_setup(W, s));
+        }
+        {
+            ProfScope ps(h, MPM_K_SOLVE, npair);
+            HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
+                              env_stride, h->prof_phases ? 1 : 0, h->slots_per_block, s));
+        }
+        if (rec)
+            HIP_TRY(hipMemcpyAsync(tg + W.n_nodes, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
+        {
+            ProfScope ps(h, MPM_K_G2P, npair);
+            HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
+                               (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h, s));
+        }
+    }
+    if (graph) HIP_TRY(launch_advance_kinematic(W.rigids, nr, N * d.h, s));
+    return MPM_OK;
+}
+
+// After the stream has synchronised (counters, statistics and impulses copied
+// to the host): tape bookkeeping, profile sums, outputs in user order, the
+// statistics, the next step's solver plan, and the status of the host step(s).
+mpm_status finish_host_steps(mpm_handle* h, const std::vector<int>& order, int npair, bool rec,
+                             mpm_rigid_impulse* out, mpm_step_stats* st) {
+    Work& W = h->w;
+    hipStream_t s = h->stream;
+    const mpm_desc& d = h->d;
+    const int N = d.N;
+    const int n_envs = (int)h->envs.size();
+    const int nr = W.n_rigid;
+    const unsigned flags = h->h_cnt->flags;
+    if (rec) {
+        h->tape_len += N;
+        for (int k = 0; k < N; ++k) {
+            int nc = 0;
+            for (int e = 0; e < n_envs; ++e) nc += h->h_stats[(size_t)k * n_envs + e].n_contacts;
+            h->tape_ncon.push_back(nc);
+        }
+    }
+    if (h->prof) {
+        for (int q = 0; q < npair; ++q) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * q], h->events[2 * q + 1]));
+            h->acc.ms[h->ev_class[q]] += ms;
+            h->acc.launches[h->ev_class[q]] += 1;
+        }
+        for (int k = 0; k < N; ++k) {
+            const SubstepStats* q = h->h_stats + (size_t)k * n_envs;
+            const SubstepStats& lead = q[longest_solve(q, n_envs)];
+            h->acc.solver_iterations += lead.iterations;
+            h->acc.solver_ls_rounds += lead.ls_rounds;
+            for (int e = 0; e < n_envs; ++e) {
+                h->acc.solver_contact_iters += (int64_t)q[e].iterations * q[e].n_contacts;
+                h->acc.solver_node_iters += (int64_t)q[e].iterations * q[e].n_slots;
+                h->acc.solver_contact_rounds += (int64_t)q[e].ls_rounds * q[e].n_contacts;
+            }
+            for (int ph = 0; ph < 8; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)lead.t_phase[ph] / h->wall_khz;
+        }
+    }
+    if (h->h_cnt->abort_step && h->h_cnt->abort_substep > 0) {
+        // the step stopped early: the caller's C lags the state; rebuild it from Q
+        HIP_TRY(launch_recover_C(W, d.F, d.C, d.h, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    // outputs in user order
+    if (out) {
+        for (int k = 0; k < nr; ++k) {
+            mpm_rigid_impulse& o = out[order[k]];
+            for (int a = 0; a < 3; ++a) {
+                o.impulse[a] = h->h_racc[6 * k + a];
+                o.torque[a] = h->h_racc[6 * k + 3 + a];
+            }
+        }
+    }
+    if (st) {
+        st->flags = (int32_t)(flags & 0xF);
+        st->max_iterations = 0;
+        st->total_iterations = 0;
+        st->max_contacts = 0;
+        for (int k = 0; k < N; ++k) {
+            // over the environments: the longest solve, all contacts, the worst residual
+            const SubstepStats* q = h->h_stats + (size_t)k * n_envs;
+            const SubstepStats& lead = q[longest_solve(q, n_envs)];
+            int contacts = 0, nodes = 0, worst = 0;
+            for (int e = 0; e < n_envs; ++e) {
+                contacts += q[e].n_contacts;
+                nodes += q[e].n_slots;
+                if (q[e].threshold > 0.0 &&
+                    (q[worst].threshold <= 0.0 || q[e].residual * q[worst].threshold > q[worst].residual * q[e].threshold))
+                    worst = e;
+            }
+            st->max_iterations = std::max(st->max_iterations, lead.iterations);
+            st->total_iterations += lead.iterations;
+            st->max_contacts = std::max(st->max_contacts, contacts);
+            if (st->iterations) st->iterations[k] = lead.iterations;
+            if (st->contacts) st->contacts[k] = contacts;
+            if (st->contact_nodes) st->contact_nodes[k] = nodes;
+            if (st->residual) st->residual[k] = q[worst].residual;
+            if (st->threshold) st->threshold[k] = q[worst].threshold;
+        }
+    }
+    // size the next step's solver groups from this step's problems
+    for (int e = 0; e < n_envs; ++e) {
+        int most = 0;
+        for (int k = 0; k < N; ++k) most = std::max(most, h->h_stats[(size_t)k * n_envs + e].n_slots);
+        h->env_slots[e] = most;
+    }
+    if (flags & 16u) return fail(MPM_EDEVICE, "contact solver barrier timed out");
+    if (flags & MPM_FLAG_CAPACITY)
+        return fail(MPM_ENOMEM, "contact capacity %lld exceeded (%u contacts)", (long long)W.cap_c, h->h_cnt->n_contacts);
+    if (flags & MPM_FLAG_NAN) return fail(MPM_ENAN, "non-finite particle state");
+    if (flags & MPM_FLAG_DOMAIN) return fail(MPM_EDOMAIN, "a particle stencil left the grid");
+    if (flags & MPM_FLAG_NOCONV) return fail(MPM_ENOCONV, "contact solve hit max_iter");
+    return MPM_OK;
+}
+
 
 }  // namespace
 
@@ -531,39 +769,11 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
             memcpy(d.w, in[i].w, sizeof(d.w));
         }
     }
-    // device order: grouped by environment (stable), so each env owns a range
-    std::vector<int> order(nr);
-    for (int i = 0; i < nr; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return h->rigids[a].env < h->rigids[b].env; });
-    for (DevEnv& D : h->denv) D.rigid_begin = D.rigid_end = 0;
-    for (int k = 0; k < nr; ++k) {
-        const HostRigid& q = h->rigids[order[k]];
-        DevRigid& R = h->h_rigids[k];
-        R.shape = q.desc.shape;
-        R.env = q.env;
-        memcpy(R.normal, q.desc.normal, sizeof(R.normal));
-        R.offset = q.desc.offset;
-        memcpy(R.half, q.desc.half, sizeof(R.half));
-        R.mu = q.desc.mu;
-        memcpy(R.R, q.desc.R, sizeof(R.R));
-        memcpy(R.t, q.desc.t, sizeof(R.t));
-        if (q.desc.motion == MPM_STATIC) {
-            memset(R.V, 0, sizeof(R.V));
-            memset(R.w, 0, sizeof(R.w));
-        } else {
-            memcpy(R.V, q.desc.V, sizeof(R.V));
-            memcpy(R.w, q.desc.w, sizeof(R.w));
-        }
-        DevEnv& D = h->denv[q.env];
-        if (D.rigid_end == D.rigid_begin) D.rigid_begin = D.rigid_end = k;
-        D.rigid_end = k + 1;
-    }
+    std::vector<int> order;
+    build_rigid_table(h, order);
     Work& W = h->w;
-    W.n_rigid = nr;
     hipStream_t s = h->stream;
-    const mpm_desc& d = h->d;
-    const int N = d.N;
-    const int ls_steps = d.ls_max_steps > 0 ? d.ls_max_steps : 100;
+    const int N = h->d.N;
     const int n_envs = (int)h->envs.size();
     int env_stride = 0;
     const int qn_blocks = plan_solver(h, &env_stride);
@@ -571,155 +781,14 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     HIP_TRY(hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(W.qn_map, h->h_qn_map, sizeof(int2) * qn_blocks, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(W.env_qn, h->h_env_qn, sizeof(int) * 2 * n_envs, hipMemcpyHostToDevice, s));
-    HIP_TRY(launch_clear_step(W, N, s));
     int npair = 0;
-    {
-        // once per host step: cell keys, stable sort, gather, tile list (Sec. V-A)
-        ProfScope ps(h, MPM_K_SORT, npair);
-        HIP_TRY(launch_keys(W, d.x, s));
-        unsigned *keys_sorted, *idx_sorted;
-        HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
-        HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
-        if (rec) {
-            const size_t j = (size_t)(h->tape_len / N);
-            HIP_TRY(hipMemcpyAsync(W.tape_idx + j * W.P, idx_sorted, sizeof(unsigned) * W.P,
-                                   hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(W.tape_rig + j * kMaxRigidTape, W.rigids, sizeof(DevRigid) * std::max(nr, 1),
-                                   hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(W.tape_env + j * n_envs, W.envs, sizeof(DevEnv) * n_envs,
-                                   hipMemcpyDeviceToDevice, s));
-        }
-        HIP_TRY(launch_tile_maps(W, s, true));   // forget the previous step's tiles
-        HIP_TRY(launch_tile_list(W, keys_sorted, s));
-        HIP_TRY(launch_tile_maps(W, s, false));
-        W.keys_sorted = keys_sorted;
-    }
-    for (int k = 0; k < N; ++k) {
-        const bool first = k == 0, last = k == N - 1;
-        const float* x_in = first ? W.xs : d.x;
-        const float* v_in = first ? W.vs : d.v;
-        const float* F_in = first ? W.Fs : d.F;
-        HIP_TRY(launch_clear_substep(W, s));
-        float* tp = rec ? W.tape_p + (size_t)(h->tape_len + k) * 24 * W.P : nullptr;
-        float4* tg = rec ? W.tape_g + (size_t)(h->tape_len + k) * 2 * W.n_nodes : nullptr;
-        if (rec) {
-            const size_t P = W.P;
-            HIP_TRY(hipMemcpyAsync(tp, x_in, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(tp + 3 * P, v_in, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(tp + 6 * P, F_in, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
-            HIP_TRY(hipMemcpyAsync(tp + 15 * P, W.Q, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
-        }
-        {
-            ProfScope ps(h, MPM_K_P2G, npair);
-            HIP_TRY(launch_p2g(W, x_in, v_in, s));
-        }
-        {
-            ProfScope ps(h, MPM_K_GRID, npair);
-            HIP_TRY(launch_grid_update(W, d.h, s));
-        }
-        if (rec) HIP_TRY(hipMemcpyAsync(tg, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
-        {
-            ProfScope ps(h, MPM_K_REGISTER, npair);
-            HIP_TRY(launch_registration(W, x_in, v_in, d.h, k, s));
-        }
-        {
-            ProfScope ps(h, MPM_K_SETUP, npair);
-            HIP_TRY(launch_contact_setup(W, s));
-        }
-        {
-            ProfScope ps(h, MPM_K_SOLVE, npair);
-            HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
-                              env_stride, h->prof_phases ? 1 : 0, h->slots_per_block, s));
-        }
-        if (rec)
-            HIP_TRY(hipMemcpyAsync(tg + W.n_nodes, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
-        {
-            ProfScope ps(h, MPM_K_G2P, npair);
-            HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
-                               (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h, s));
-        }
-    }
+    const mpm_status es = enqueue_host_step(h, qn_blocks, env_stride, false, npair, s);
+    if (es != MPM_OK) return es;
     HIP_TRY(hipMemcpyAsync(h->h_cnt, W.cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N * n_envs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    const unsigned flags = h->h_cnt->flags;
-    if (rec) {
-        h->tape_len += N;
-        for (int k = 0; k < N; ++k) {
-            int nc = 0;
-            for (int e = 0; e < n_envs; ++e) nc += h->h_stats[(size_t)k * n_envs + e].n_contacts;
-            h->tape_ncon.push_back(nc);
-        }
-    }
-    if (h->prof) {
-        for (int q = 0; q < npair; ++q) {
-            float ms = 0.f;
-            HIP_TRY(hipEventElapsedTime(&ms, h->events[2 * q], h->events[2 * q + 1]));
-            h->acc.ms[h->ev_class[q]] += ms;
-            h->acc.launches[h->ev_class[q]] += 1;
-        }
-        for (int k = 0; k < N; ++k) {
-            const SubstepStats* q = h->h_stats + (size_t)k * n_envs;
-            const SubstepStats& lead = q[longest_solve(q, n_envs)];
-            h->acc.solver_iterations += lead.iterations;
-            h->acc.solver_ls_rounds += lead.ls_rounds;
-            for (int e = 0; e < n_envs; ++e) {
-                h->acc.solver_contact_iters += (int64_t)q[e].iterations * q[e].n_contacts;
-                h->acc.solver_node_iters += (int64_t)q[e].iterations * q[e].n_slots;
-                h->acc.solver_contact_rounds += (int64_t)q[e].ls_rounds * q[e].n_contacts;
-            }
-            for (int ph = 0; ph < 8; ++ph) h->acc.solver_phase_us[ph] += 1e3 * (double)lead.t_phase[ph] / h->wall_khz;
-        }
-    }
-    if (h->h_cnt->abort_step && h->h_cnt->abort_substep > 0) {
-        // the step stopped early: the caller's C lags the state; rebuild it from Q
-        HIP_TRY(launch_recover_C(W, d.F, d.C, d.h, s));
-        HIP_TRY(hipStreamSynchronize(s));
-    }
-    // outputs in user order
-    if (out) {
-        for (int k = 0; k < nr; ++k) {
-            mpm_rigid_impulse& o = out[order[k]];
-            for (int a = 0; a < 3; ++a) {
-                o.impulse[a] = h->h_racc[6 * k + a];
-                o.torque[a] = h->h_racc[6 * k + 3 + a];
-            }
-        }
-    }
-    if (st) {
-        st->flags = (int32_t)(flags & 0xF);
-        st->max_iterations = 0;
-        st->total_iterations = 0;
-        st->max_contacts = 0;
-        for (int k = 0; k < N; ++k) {
-            // over the environments: the longest solve, all contacts, the worst residual
-            const SubstepStats* q = h->h_stats + (size_t)k * n_envs;
-            const SubstepStats& lead = q[longest_solve(q, n_envs)];
-            int contacts = 0, nodes = 0, worst = 0;
-            for (int e = 0; e < n_envs; ++e) {
-                contacts += q[e].n_contacts;
-                nodes += q[e].n_slots;
-                if (q[e].threshold > 0.0 &&
-                    (q[worst].threshold <= 0.0 || q[e].residual * q[worst].threshold > q[worst].residual * q[e].threshold))
-                    worst = e;
-            }
-            st->max_iterations = std::max(st->max_iterations, lead.iterations);
-            st->total_iterations += lead.iterations;
-            st->max_contacts = std::max(st->max_contacts, contacts);
-            if (st->iterations) st->iterations[k] = lead.iterations;
-            if (st->contacts) st->contacts[k] = contacts;
-            if (st->contact_nodes) st->contact_nodes[k] = nodes;
-            if (st->residual) st->residual[k] = q[worst].residual;
-            if (st->threshold) st->threshold[k] = q[worst].threshold;
-        }
-    }
-    // size the next step's solver groups from this step's problems
-    for (int e = 0; e < n_envs; ++e) {
-        int most = 0;
-        for (int k = 0; k < N; ++k) most = std::max(most, h->h_stats[(size_t)k * n_envs + e].n_slots);
-        h->env_slots[e] = most;
-    }
+    const mpm_desc& d = h->d;
     // host side of the split: advance kinematic bodies with their twist
     for (HostRigid& q : h->rigids) {
         if (q.desc.motion != MPM_KINEMATIC) continue;
@@ -727,13 +796,81 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         for (int a = 0; a < 3; ++a) q.desc.t[a] += dt * q.desc.V[a];
         rodrigues_advance(q.desc.R, q.desc.w, dt);
     }
-    if (flags & 16u) return fail(MPM_EDEVICE, "contact solver barrier timed out");
-    if (flags & MPM_FLAG_CAPACITY)
-        return fail(MPM_ENOMEM, "contact capacity %lld exceeded (%u contacts)", (long long)W.cap_c, h->h_cnt->n_contacts);
-    if (flags & MPM_FLAG_NAN) return fail(MPM_ENAN, "non-finite particle state");
-    if (flags & MPM_FLAG_DOMAIN) return fail(MPM_EDOMAIN, "a particle stencil left the grid");
-    if (flags & MPM_FLAG_NOCONV) return fail(MPM_ENOCONV, "contact solve hit max_iter");
-    return MPM_OK;
+    return finish_host_steps(h, order, npair, rec, out, st);
+}
+
+mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out, mpm_step_stats* st) {
+    if (!h) return fail(MPM_EINVAL, "handle is NULL");
+    if (n_steps < 1) return fail(MPM_EINVAL, "n_steps must be at least 1 (got %d)", (int)n_steps);
+    if (h->tape_on) return fail(MPM_EINVAL, "the graph path does not record the differentiation tape");
+    if (h->prof) return fail(MPM_EINVAL, "the graph path does not run while mpm_profile timing is on");
+    if (!h->gstream) {
+        HIP_TRY(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&h->gevent, hipEventDisableTiming));
+    }
+    std::vector<int> order;
+    build_rigid_table(h, order);
+    Work& W = h->w;
+    hipStream_t s = h->gstream;
+    const int N = h->d.N;
+    const int n_envs = (int)h->envs.size();
+    const int nr = W.n_rigid;
+    int env_stride = 0;
+    const int qn_blocks = plan_solver(h, &env_stride);
+    if (h->graph_exec && (h->graph_steps != n_steps || h->graph_qn_blocks != qn_blocks ||
+                          h->graph_stride != env_stride || h->graph_nr != nr)) {
+        HIP_TRY(hipGraphExecDestroy(h->graph_exec));
+        HIP_TRY(hipGraphDestroy(h->graph));
+        h->graph_exec = nullptr;
+        h->graph = nullptr;
+    }
+    // after everything already queued on the handle's stream
+    HIP_TRY(hipEventRecord(h->gevent, h->stream));
+    HIP_TRY(hipStreamWaitEvent(s, h->gevent, 0));
+    HIP_TRY(hipMemcpyAsync(W.rigids, h->h_rigids, sizeof(DevRigid) * std::max(nr, 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.qn_map, h->h_qn_map, sizeof(int2) * qn_blocks, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.env_qn, h->h_env_qn, sizeof(int) * 2 * n_envs, hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_clear_step(W, N, false, s));  // once per replay: flags, abort state, impulse sums
+    if (!h->graph_exec) {
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        mpm_status cs = MPM_OK;
+        int npair = 0;
+        for (int j = 0; j < n_steps && cs == MPM_OK; ++j) cs = enqueue_host_step(h, qn_blocks, env_stride, true, npair, s);
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(s, &g);
+        if (cs != MPM_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return cs;
+        }
+        if (ee != hipSuccess) return fail(MPM_EDEVICE, "graph capture failed: %s", hipGetErrorString(ee));
+        hipGraphExec_t ge = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return fail(MPM_EDEVICE, "graph instantiation failed: %s", hipGetErrorString(ie));
+        }
+        h->graph = g;
+        h->graph_exec = ge;
+        h->graph_steps = n_steps;
+        h->graph_qn_blocks = qn_blocks;
+        h->graph_stride = env_stride;
+        h->graph_nr = nr;
+    }
+    HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+    HIP_TRY(hipMemcpyAsync(h->h_cnt, W.cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N * n_envs, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->h_rigids, W.rigids, sizeof(DevRigid) * std::max(nr, 1), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // the host's rigid state takes the device's kinematic advance
+    for (int k = 0; k < nr; ++k) {
+        HostRigid& q = h->rigids[order[k]];
+        if (q.desc.motion != MPM_KINEMATIC) continue;
+        memcpy(q.desc.R, h->h_rigids[k].R, sizeof(q.desc.R));
+        memcpy(q.desc.t, h->h_rigids[k].t, sizeof(q.desc.t));
+    }
+    return finish_host_steps(h, order, 0, false, out, st);
 }
 
 mpm_status mpm_tape_reset(mpm_handle* h, int32_t record) {
@@ -773,7 +910,7 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
     HIP_TRY(hipMemcpyAsync(A + 15 * P, gC, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemsetAsync(W.lame, 0, sizeof(double) * 2 * n_envs, s));
     HIP_TRY(hipMemsetAsync(W.rgrad, 0, sizeof(double) * 6 * kMaxRigidTape * n_host, s));
-    HIP_TRY(launch_clear_step(W, N, s));
+    HIP_TRY(launch_clear_step(W, N, false, s));
     W.n_rigid = nr;
     int cur = 0;
     for (int j = n_host - 1; j >= 0; --j) {
@@ -887,6 +1024,10 @@ mpm_status mpm_profile(mpm_handle* h, int32_t enable, mpm_profile_data* out) {
 
 void mpm_destroy(mpm_handle* h) {
     if (!h) return;
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->gevent) (void)hipEventDestroy(h->gevent);
+    if (h->gstream) (void)hipStreamDestroy(h->gstream);
     for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
     if (h->h_rigids) (void)hipHostFree(h->h_rigids);
     if (h->h_racc) (void)hipHostFree(h->h_racc);

@@ -221,7 +221,7 @@ constexpr int kQnMaxGroup = 128;  // blocks of one environment's group (partials
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
                       float* v_out, float* F_out, float* C_out, const int* pid_in,
                       int* pid_out, double h, hipStream_t s);
-hipError_t launch_clear_step(const Work& w, int N, hipStream_t s);
+hipError_t launch_clear_step(const Work& w, int N, bool stats_only, hipStream_t s);
 // reverse mode (adjoint.hip)
 hipError_t launch_g2p_adj(const Work& w, const TapeStep& t, float h, float* ax, const float* av, float* aF,
                           const float* aQ, const float* aC, float4* gbar, double* lame, hipStream_t s);

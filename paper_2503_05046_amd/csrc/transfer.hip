@@ -661,14 +661,21 @@ hipError_t launch_recover_C(const Work& w, const float* F, float* C, double h, h
 }
 
 // Start of a host step: flags, impulse accumulators and per-substep stats.
-__global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, SubstepStats* st, int n_st) {
+// Start of a host step: flags, the abort state and the impulse sums (all but
+// stats_only), and the substep statistics. A graph of several host steps
+// clears everything once and only the statistics per host step, so flags and
+// impulses accumulate and a stopped step stops the ones after it.
+__global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, SubstepStats* st, int n_st,
+                             int stats_only) {
     const int t = threadIdx.x;
-    if (t == 0) {
-        cnt->flags = 0u;
-        cnt->abort_step = 0u;
-        cnt->abort_substep = 0u;
+    if (!stats_only) {
+        if (t == 0) {
+            cnt->flags = 0u;
+            cnt->abort_step = 0u;
+            cnt->abort_substep = 0u;
+        }
+        for (int i = t; i < n_acc; i += blockDim.x) rigid_acc[i] = 0.0;
     }
-    for (int i = t; i < n_acc; i += blockDim.x) rigid_acc[i] = 0.0;
     for (int i = t; i < n_st; i += blockDim.x) {
         SubstepStats z;
         z.n_contacts = z.n_slots = z.iterations = z.converged = z.ls_rounds = z.pad = 0;
@@ -690,9 +697,9 @@ __global__ void k_clear_substep(DevCounters* cnt, double* env_pnorm, int n_envs)
     for (int e = threadIdx.x; e < n_envs; e += blockDim.x) env_pnorm[e] = 0.0;
 }
 
-hipError_t launch_clear_step(const Work& w, int N, hipStream_t s) {
+hipError_t launch_clear_step(const Work& w, int N, bool stats_only, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_step, dim3(1), dim3(256), 0, s, w.cnt, w.rigid_acc, 6 * 256,
-                       w.sstats, N * w.n_envs);
+                       w.sstats, N * w.n_envs, stats_only ? 1 : 0);
     return hipGetLastError();
 }
 

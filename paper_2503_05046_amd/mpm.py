@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "MPM_OK", 1: "MPM_ENOCONV", 2: "MPM_EDOMAIN", 3: "MPM_ENAN", 
                 5: "MPM_ENOMEM", 6: "MPM_EDEVICE"}
 FLAG_NOCONV, FLAG_DOMAIN, FLAG_NAN, FLAG_CAPACITY = 1, 2, 4, 8
 
-EXPORTED = ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
+EXPORTED = ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step", "mpm_step_graph",
             "mpm_get_rigid_state", "mpm_profile", "mpm_destroy", "mpm_tape_reset",
             "mpm_step_backward", "mpm_last_error")
 KERNEL_CLASSES = ("sort", "p2g", "grid", "register", "setup", "solve", "g2p")
@@ -104,6 +104,7 @@ def load():
                                         ct.POINTER(ct.c_int32)]
         L.mpm_step.argtypes = [ct.c_void_p, ct.POINTER(RigidState), ct.POINTER(RigidImpulse),
                                ct.POINTER(StepStats)]
+        L.mpm_step_graph.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidImpulse), ct.POINTER(StepStats)]
         L.mpm_get_rigid_state.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidState)]
         L.mpm_profile.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ProfileData)]
         L.mpm_tape_reset.argtypes = [ct.c_void_p, ct.c_int32]
@@ -199,6 +200,35 @@ def mpm_add_rigid_sdf(h, env: int, r: RigidDesc) -> int:
     rid = ct.c_int32(-1)
     _check(load().mpm_add_rigid_sdf(h, env, ct.byref(r), ct.byref(rid)), "mpm_add_rigid_sdf")
     return rid.value
+
+
+def _stats_buffers(N: int):
+    its, ncs, nns = (ct.c_int32 * N)(), (ct.c_int32 * N)(), (ct.c_int32 * N)()
+    res, thr = (ct.c_double * N)(), (ct.c_double * N)()
+    st = StepStats()
+    st.iterations, st.contacts, st.contact_nodes = its, ncs, nns
+    st.residual, st.threshold = res, thr
+    return st, (its, ncs, nns, res, thr)
+
+
+def _stats_dict(st, bufs) -> dict:
+    its, ncs, nns, res, thr = bufs
+    return dict(flags=st.flags, max_iterations=st.max_iterations,
+                total_iterations=st.total_iterations, max_contacts=st.max_contacts,
+                iterations=list(its), contacts=list(ncs), contact_nodes=list(nns),
+                residual=list(res), threshold=list(thr))
+
+
+def mpm_step_graph(h, n_rigid: int, N: int, n_steps: int):
+    """n_steps host steps as one graph replay (the library's own rigid state).
+    Returns (status, impulses [n_rigid, 6] summed over the steps, stats of the
+    last host step)."""
+    imp = (RigidImpulse * max(1, n_rigid))()
+    st, bufs = _stats_buffers(N)
+    status = load().mpm_step_graph(h, int(n_steps), imp, ct.byref(st))
+    _check(status, "mpm_step_graph", allow=(MPM_OK, MPM_ENOCONV))
+    out = np.array([[*imp[i].impulse, *imp[i].torque] for i in range(n_rigid)]).reshape(n_rigid, 6)
+    return status, out, _stats_dict(st, bufs)
 
 
 def mpm_step(h, n_rigid: int, N: int, states: Optional[Sequence[RigidState]] = None):
@@ -307,6 +337,10 @@ class Sim:
 
     def step(self, states=None):
         return mpm_step(self.handle, self.n_rigid, self.N, states)
+
+    def step_graph(self, n_steps: int):
+        """n_steps host steps in one HIP graph replay (see mpm_step_graph)."""
+        return mpm_step_graph(self.handle, self.n_rigid, self.N, n_steps)
 
     def state(self, original_order: bool = True) -> dict:
         """Particle state as float32 numpy arrays (in the caller's original
