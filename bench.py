@@ -145,6 +145,18 @@ def run_batched(args) -> int:
     t_b = time.perf_counter() - t0
     prof = sim.profile(False)
     sim.close()
+    # the same host steps as one HIP graph replay (mpm_step_graph), on a second
+    # handle warmed up the same way; the recording is inside the timed region
+    gsim = M.Sim(scene)
+    for i in range(warm):
+        gsim.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, gst = gsim.step_graph(args.steps)
+    torch.cuda.synchronize()
+    t_g = time.perf_counter() - t0
+    log(f"graph: {args.steps} host steps in one replay, {t_g:.2f} s, last step contacts {gst['contacts']}")
+    gsim.close()
     sub = list(range(0, n_envs, 8))
     sims = [M.Sim(I.single_env(scene, e)) for e in sub]
     for s in sims:
@@ -177,6 +189,9 @@ def run_batched(args) -> int:
                  "method": "single-environment handles stepped in turn; time of the timed "
                            "environments scaled by 64 / 8"},
         "batched_over_loop": value_b / value_l,
+        "graph": {"value": P * N * args.steps / t_g, "ms_per_step": 1e3 * t_g / args.steps,
+                  "method": f"the {args.steps} timed host steps ({N * args.steps} substeps) as one "
+                            f"HIP graph (mpm_step_graph), recording included"},
         "solve_share": prof["ms"]["solve"] / max(1e-9, sum(prof["ms"].values())),
         "longest_solve_iterations_mean": float(np.mean(iters)),
     }
