@@ -1,0 +1,110 @@
+"""The HIP path at the benchmark's full size (granular pour: 1M Drucker-Prager
+particles, 128^3 grid, four boxes), in the launch configuration bench.py
+times, checked where the FP64 oracle can follow it.
+
+* Free motion, sampled: one substep of the full scene before contact; the
+  oracle runs that substep on a column of the same particles padded by four
+  cells (a particle's result depends only on nodes within 1.5 cells, whose
+  values depend only on particles within 1.5 cells of them), and the column's
+  interior is compared particle by particle at the parity bar.
+* Contact, a property that holds at any size: with the transfers conserving
+  linear momentum (quadratic B-spline weights have zero first moment, and
+  G2P returns sum_i m_i v_i), the change of sum_p m_p v_p over a host step is
+  M g N h plus the impulse on the material, which the library returns with
+  the opposite sign as the impulse on the boxes. The solve stops with
+  |grad~| <= thr, so each substep's mismatch is at most sqrt(M) |grad~|
+  (Cauchy-Schwarz over the contact nodes); float32 storage of v adds about
+  1e-7 of sum m |v|. The sand stays clear of the grid's boundary band over
+  the steps checked.
+
+Run on an MI355X: python -m pytest tests -m gpu
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2503_05046_amd import inputs as I
+from tests.parity import field_errors
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mpm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2503_05046_amd import mpm as M
+    M.load()
+    return M
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_full_size_free_motion_column(mpm, oracle):
+    scene = I.granular_pour(n_particles=1_000_000)
+    scene.N = 1
+    dx = scene.envs[0].dx
+    x0 = scene.x.copy()
+    sim = mpm.Sim(scene)
+    status, imp, st = sim.step()
+    assert status == 0 and st["max_contacts"] == 0
+    out = sim.state()
+    sim.close()
+    a, b, pad = 0.45, 0.55, 4 * dx
+    inner = (x0[0] > a) & (x0[0] < b) & (x0[1] > a) & (x0[1] < b)
+    padded = (x0[0] > a - pad) & (x0[0] < b + pad) & (x0[1] > a - pad) & (x0[1] < b + pad)
+    sel = np.nonzero(padded)[0]
+    sub = scene.copy()
+    sub.x, sub.v, sub.F, sub.C = (np.ascontiguousarray(getattr(scene, k)[:, sel]) for k in ("x", "v", "F", "C"))
+    sub.envs[0].p_begin, sub.envs[0].p_end = 0, len(sel)
+    _log(f"full size: oracle on a {len(sel)}-particle column, {int(inner.sum())} compared")
+    ora = oracle.OracleSim(sub)
+    rc, _, _ = ora.host_step()
+    assert rc == 0
+    keep = inner[sel]
+    g = {k: out[k][:, sel][:, keep] for k in ("x", "v", "F", "C")}
+
+    class _Ref:
+        pass
+
+    ref = _Ref()
+    ref.x, ref.v, ref.F, ref.C = (getattr(ora, k)[:, keep] for k in ("x", "v", "F", "C"))
+    err = field_errors(g, ref, dx)
+    _log(f"full size, free motion, column interior: {err}")
+    assert max(err.values()) < 1e-5, err
+
+
+def test_full_size_momentum_balance_in_contact(mpm):
+    scene = I.granular_pour(n_particles=1_000_000)
+    scene.max_iter = 200_000  # as bench.py
+    env = scene.envs[0]
+    m_p = env.m_p
+    M = m_p * scene.P
+    g = np.array(env.gravity, np.float64)
+    sim = mpm.Sim(scene)
+    for _ in range(4):  # contact begins in the fourth host step
+        sim.step()
+    checked = 0
+    for step in range(2):
+        v0 = sim.state()["v"].astype(np.float64)
+        status, imp, st = sim.step()
+        assert status == 0
+        v1 = sim.state()["v"].astype(np.float64)
+        assert max(st["contacts"]) > 0
+        assert all(r < t for r, t in zip(st["residual"], st["threshold"]) if t > 0)
+        dP = m_p * (v1.sum(axis=1) - v0.sum(axis=1))
+        expected = M * g * scene.N * scene.h - imp[:, :3].sum(axis=0)
+        tol = (np.sqrt(M) * sum(st["residual"]) +
+               2e-7 * m_p * (np.abs(v0).sum() + np.abs(v1).sum()))
+        mis = float(np.abs(dP - expected).max())
+        _log(f"full size, host step {step}: dP {dP}, M g N h - sum impulses {expected}, "
+             f"mismatch {mis:.3e}, bound {tol:.3e}, contacts {max(st['contacts'])}")
+        assert mis <= tol, (dP, expected, tol)
+        checked += 1
+    sim.close()
+    assert checked == 2
