@@ -552,7 +552,8 @@ __device__ __forceinline__ ContactParams params_of(const ContactRec& R, double h
 __device__ __forceinline__ void contact_velocity(const ContactDyn& D, int k, double alpha_prev, double vc[3]) {
     const int src = k == 0 ? 0 : (k - 1) & 1;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) vc[a] = k == 0 ? ld_x(&D.vc[0][a]) : fma(alpha_prev, ld_x(&D.uc[a]), ld_x(&D.vc[src][a]));
+    for (int a = 0; a < 3; ++a)
+        vc[a] = k == 0 ? ld_x(&D.vc[0][a]) : fma(alpha_prev, ld_x(&D.uc[src][a]), ld_x(&D.vc[src][a]));
 }
 
 // Sum of x over the 64 lanes of a wave, the same bits in every lane: DPP
@@ -1192,25 +1193,15 @@ k_qn(QnArgs A) {
             ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
             if (timer) { const unsigned long long t = wall_clock64(); tph[2] += t - tmark; tmark = t; }
             if (!ok) break;
-            if (G > 1u) {
-                // wave q adds sum q of the group's blocks (the same bits in every block)
-                const int wv = tid >> 6, lane = tid & 63;
-                if (wv < kQnSums) {
-                    double a = 0.0;
-                    for (unsigned b = lane; b < G; b += 64) a += ld_x(&partial[(size_t)b * kQnSums + wv]);
-                    a = wave_sum(a);
-                    if (lane == 0) tot[wv] = a;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int q = 0; q < kQnSums; ++q) sums[q] = tot[q];
+            // group sums: wave q adds sum q of the group's blocks (the same bits in
+            // every block); the loads are issued here and used after the contact
+            // pass, which runs before the stopping test (its stores go to
+            // parity buffers and the coefficients, which the exit does not read)
+            const int wv = tid >> 6, lane = tid & 63;
+            double ga = 0.0;
+            if (G > 1u && wv < kQnSums) {
+                for (unsigned b = lane; b < G; b += 64) ga += ld_x(&partial[(size_t)b * kQnSums + wv]);
             }
-            const double p2 = fmax(pnorm_env - sums[3] + sums[2], 0.0);
-            res = sqrt(sums[0]);
-            thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(sums[1]));
-            const double Aq = sums[4], Bq = sums[5], d0 = sums[6];
-            if (res < thr) { converged = 1; break; }
-            if (k >= A.max_iter || !(d0 < 0.0)) break;
             // ---- contact pass: store v_c^k, u_c = R_c^T J dv, and u_c^T G(v_c^k) u_c
             // (this block's share of phi''(0)). Eight lanes gather one contact's
             // 27 stencil nodes and combine their sums by shuffles.
@@ -1269,7 +1260,7 @@ k_qn(QnArgs A) {
                         u[1] = fr[3] * sacc[0] + fr[4] * sacc[1] + fr[5] * sacc[2];
                         u[2] = fr[6] * sacc[0] + fr[7] * sacc[1] + fr[8] * sacc[2];
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) st_x(&D.uc[a], u[a]);
+                        for (int a = 0; a < 3; ++a) st_x(&D.uc[k & 1][a], u[a]);
                         store_coef(A.c_coef, c, ls_coef(Pc, vc, u));
                         double g[3], g00, g01, g11, gnn;
                         contact_model(Pc, vc, g, &g00, &g01, &g11, &gnn);
@@ -1277,7 +1268,21 @@ k_qn(QnArgs A) {
                     }
                 }
             }
-            block_allsum<1>(curv, rbuf, rpar);
+            if (G > 1u && wv < kQnSums) {
+                const double a = wave_sum(ga);
+                if (lane == 0) tot[wv] = a;
+            }
+            block_allsum<1>(curv, rbuf, rpar);  // its workgroup barrier also publishes tot
+            if (G > 1u) {
+#pragma unroll
+                for (int q = 0; q < kQnSums; ++q) sums[q] = tot[q];
+            }
+            const double p2 = fmax(pnorm_env - sums[3] + sums[2], 0.0);
+            res = sqrt(sums[0]);
+            thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(sums[1]));
+            const double Aq = sums[4], Bq = sums[5], d0 = sums[6];
+            if (res < thr) { converged = 1; break; }
+            if (k >= A.max_iter || !(d0 < 0.0)) break;
             if (G > 1u && tid == 0) st_x(&partial2[rank], curv[0]);
             if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
             ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);

@@ -74,7 +74,7 @@ struct alignas(16) ContactStencil {
 
 struct alignas(128) ContactDyn {
     double vc[2][3];  // contact velocity, double-buffered by iteration parity
-    double uc[3];     // R_c^T J dv of the current iteration
+    double uc[2][3];  // R_c^T J dv, double-buffered by iteration parity
     double gam[3];    // impulse on MPM at exit (contact frame)
     double b[3];      // bias velocity -R_c^T v_rigid(x_p)
 };
