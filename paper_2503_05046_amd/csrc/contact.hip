@@ -559,7 +559,8 @@ __device__ __forceinline__ void contact_velocity(const ContactDyn& D, int k, dou
 // Sum of x over the 64 lanes of a wave, the same bits in every lane: DPP
 // exchanges inside each row of 16 lanes (pairs, quads, half rows, rows; each
 // step adds two equal partial sums in either order, so the lanes stay equal),
-// then the four row sums read back and added in row order. Every lane of the
+// then the rows pairwise and the halves by the permlane swaps of gfx950: the
+// total is (row 0 + row 1) + (row 2 + row 3) in every lane. Every lane of the
 // wave must be active.
 template <int kCtrl>
 __device__ __forceinline__ double dpp_move(double x) {
@@ -568,20 +569,28 @@ __device__ __forceinline__ double dpp_move(double x) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
     return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
 }
+// x plus its value in the partner row (kHalf = false: rows 0-1 and 2-3) or
+// half (true); both swap results together hold the lane's own value and the
+// partner's, in an order that is the same in every lane of a pair.
+template <bool kHalf>
+__device__ __forceinline__ double swap_add(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    const auto l = kHalf ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                         : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = kHalf ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                         : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const double a = __builtin_bit_cast(double, ((long long)h[0] << 32) | (long long)l[0]);
+    const double c = __builtin_bit_cast(double, ((long long)h[1] << 32) | (long long)l[1]);
+    return a + c;
+}
 __device__ __forceinline__ double wave_sum(double x) {
     x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
     x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
     x += dpp_move<0x141>(x);  // row_half_mirror
     x += dpp_move<0x140>(x);  // row_mirror
-    const long long b = __builtin_bit_cast(long long, x);
-    double r[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int lo = __builtin_amdgcn_readlane((int)b, 16 * q);
-        const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 16 * q);
-        r[q] = __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned)lo);
-    }
-    return (r[0] + r[1]) + (r[2] + r[3]);
+    x = swap_add<false>(x);   // rows 0 + 1, rows 2 + 3
+    return swap_add<true>(x); // the two halves
 }
 
 // Block-wide FP64 sums of NV values per thread over a block of NW waves,
