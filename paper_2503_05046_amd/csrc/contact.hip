@@ -915,10 +915,14 @@ __device__ __forceinline__ bool loop_sync(unsigned* ctr, int rank, unsigned G, u
 constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
 constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
 constexpr int kUniqMax = 512;    // distinct contacts of a block's entries the compact node pass holds
-constexpr int kHash = 2048;      // open-addressing table that finds them (power of two)
+constexpr int kEntMax = 2048;    // CSR entries of a block the compact node pass holds
+constexpr int kHashBits = 12;
+constexpr int kHash = 1 << kHashBits;  // open-addressing table that finds the distinct contacts
 static_assert(kHash * sizeof(int) <= 9 * kSlotChunk * sizeof(double), "hash table lives in nacc");
 static_assert(9 * kUniqMax <= 11 * kQnThreads, "contact terms live in the line-search buffer");
-static_assert(kEntBatch * kQnThreads <= kHash / 2, "the hash table is at most half full");
+static_assert(kEntMax <= kHash / 2, "the hash table is at most half full");
+static_assert(kUniqMax <= 65536, "block-local contact indices are 16-bit");
+constexpr int kEntPer = kEntMax / kQnThreads;  // entries per thread in the compact set-up
 
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
@@ -932,7 +936,8 @@ k_qn(QnArgs A) {
     LsCoef* ls_ovf = reinterpret_cast<LsCoef*>(ovf_raw);
     double* u_term = ovf_raw;
     __shared__ double nacc[9][kSlotChunk];  // j (3) and R G R^T (6) of a chunk of owned slots
-    __shared__ int2 ent_l[kEntBatch * kQnThreads];  // compact pass: (slot | contact << 16, w) per entry
+    __shared__ unsigned short ent_c[kEntMax];  // compact pass: block-local contact of each entry
+    __shared__ float ent_w[kEntMax];           // and its stencil weight
     __shared__ int beg_l[kSlotChunk + 1];           // compact pass: first entry of each contact node
     __shared__ int u_list[kUniqMax];                // compact pass: the distinct contacts
     __shared__ unsigned scan_w[17];
@@ -989,31 +994,29 @@ k_qn(QnArgs A) {
         for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
 
         // Compact node pass: when the block's contact nodes fit one chunk, its
-        // CSR entries one batch, and the entries name at most kUniqMax distinct
-        // contacts, the entries stay in LDS for the whole solve (slot and
-        // contact as block-local indices) and each distinct contact's terms
+        // CSR entries number at most kEntMax, and they name at most kUniqMax distinct
+        // contacts, the entries stay in LDS for the whole solve (the contact as
+        // a block-local index, and the weight) and each distinct contact's terms
         // are formed once per iteration instead of once per entry.
         const int E0s = A.s_beg[s0], n_ent = A.s_beg[s1] - E0s;
-        bool compact = A.compact != 0 && s1 - s0 <= kSlotChunk && n_ent <= kEntBatch * T;
+        bool compact = A.compact != 0 && s1 - s0 <= kSlotChunk && n_ent <= kEntMax;
         int n_u = 0;
         if (compact) {
             int* htab = reinterpret_cast<int*>(&nacc[0][0]);
             for (int q = tid; q < kHash; q += T) htab[q] = -1;
             __syncthreads();
-            int pos[kEntBatch], eslot[kEntBatch];
-            float ew[kEntBatch];
+            int pos[kEntPer];
+            float ew[kEntPer];
 #pragma unroll
-            for (int u = 0; u < kEntBatch; ++u) {
+            for (int u = 0; u < kEntPer; ++u) {
                 const int e = tid + u * T;
                 pos[u] = -1;
                 if (e < n_ent) {
                     const Entry en = A.e_ent[E0s + e];
-                    eslot[u] = en.slot - (int)s0;
                     ew[u] = en.w;
                     // linear probing; the table is at most half full, so a free
                     // or matching position is always found
-                    unsigned hsh = (en.c * 2654435761u) >> (32 - 11);
-                    static_assert(kHash == 1 << 11, "hash width");
+                    unsigned hsh = (en.c * 2654435761u) >> (32 - kHashBits);
                     for (;;) {
                         const int prev = atomicCAS(&htab[hsh], -1, (int)en.c);
                         if (prev == -1 || prev == (int)en.c) break;
@@ -1044,8 +1047,11 @@ k_qn(QnArgs A) {
             compact = n_u <= kUniqMax;
             if (compact) {
 #pragma unroll
-                for (int u = 0; u < kEntBatch; ++u)
-                    if (pos[u] >= 0) ent_l[tid + u * T] = make_int2(eslot[u] | (htab[pos[u]] << 16), __float_as_int(ew[u]));
+                for (int u = 0; u < kEntPer; ++u)
+                    if (pos[u] >= 0) {
+                        ent_c[tid + u * T] = (unsigned short)htab[pos[u]];
+                        ent_w[tid + u * T] = ew[u];
+                    }
                 if (tid < s1 - s0) {
 #pragma unroll
                     for (int a = 0; a < 3; ++a) node_v[a][tid] = A.s_rec[s0 + tid].v[a];
@@ -1115,9 +1121,8 @@ k_qn(QnArgs A) {
                 if (mine) {
                     const int e1 = beg_l[ls + 1];
                     for (int e = beg_l[ls] + sub; e < e1; e += nl) {
-                        const int2 el = ent_l[e];
-                        const int lc = el.x >> 16;
-                        const double w = (double)__int_as_float(el.y);
+                        const int lc = ent_c[e];
+                        const double w = (double)ent_w[e];
 #pragma unroll
                         for (int a = 0; a < 3; ++a) j[a] = fma(w, u_term[a * kUniqMax + lc], j[a]);
                         const double w2 = w * w;
