@@ -92,8 +92,10 @@ def log(msg: str) -> None:
 
 
 def cpu_baseline(state: dict, scene, budget_s: float) -> dict:
-    """The FP64 oracle, as it stands, on one substep of a column of the same
-    state (particles with x, y in [0.36, 0.44], all heights, over one box)."""
+    """The FP64 oracle, as it stands, on substeps of a column of the same state
+    (particles with x, y in [0.36, 0.44], all heights, over one box): as many
+    substeps of one host step as fit in about budget_s / 3 seconds (at least
+    one)."""
     import numpy as np
     from oracle import oracle as O
     O.build(force=not os.path.exists(O.LIB))
@@ -103,13 +105,20 @@ def cpu_baseline(state: dict, scene, budget_s: float) -> dict:
     sub.x, sub.v, sub.F, sub.C = (np.ascontiguousarray(state[k][:, sel]) for k in ("x", "v", "F", "C"))
     sub.envs[0].p_begin, sub.envs[0].p_end = 0, len(sel)
     ora = O.OracleSim(sub)
+    n_sub, contacts, iters, rc = 0, [], [], 0
     t0 = time.perf_counter()
-    rc, st, _ = ora.substep()
+    while n_sub < scene.N and (n_sub == 0 or time.perf_counter() - t0 < budget_s / 3):
+        rc, st, _ = ora.substep()
+        n_sub += 1
+        contacts.append(st.n_contacts)
+        iters.append(st.iterations)
+        if rc >= 2:  # an error (1 is the iteration-cap warning)
+            break
     dt = time.perf_counter() - t0
-    return {"value": len(sel) / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"1 substep of a {len(sel)}-particle column (x, y in [0.36, 0.44]) of the "
-                       f"benchmark state after the timed steps: {st.n_contacts} contacts, "
-                       f"{st.iterations} solver iterations, {dt:.1f} s single-threaded FP64"),
+    return {"value": len(sel) * n_sub / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"{n_sub} substeps of a {len(sel)}-particle column (x, y in [0.36, 0.44]) of the "
+                       f"benchmark state after the timed steps: {max(contacts)} contacts at most, "
+                       f"{sum(iters)} solver iterations in all, {dt:.1f} s single-threaded FP64"),
             "status": rc}
 
 
