@@ -139,7 +139,13 @@ def run_batched(args) -> int:
     P, N, n_envs = scene.P, scene.N, len(scene.envs)
     warm = args.warmup if args.warmup_set else 9  # contact starts near the 8th host step
     log(f"batched: {n_envs} environments, P={P}, warmup {warm}, steps {args.steps}")
-    sim = M.Sim(scene)
+    spb, tuning = 0, None
+    if args.autotune:
+        from paper_2503_05046_amd import autotune
+        spb, tuning = autotune.tune(scene, candidates=(64, 96, 128, 192, 256), warmup_steps=warm,
+                                    trial_steps=2, log=log)
+        log(f"autotune: {spb} contact nodes per solver block")
+    sim = M.Sim(scene, solver_slots_per_block=spb)
     for i in range(warm):
         sim.step()
     sim.profile(True)
@@ -156,7 +162,7 @@ def run_batched(args) -> int:
     sim.close()
     # the same host steps as one HIP graph replay (mpm_step_graph), on a second
     # handle warmed up the same way; the recording is inside the timed region
-    gsim = M.Sim(scene)
+    gsim = M.Sim(scene, solver_slots_per_block=spb)
     for i in range(warm):
         gsim.step()
     torch.cuda.synchronize()
@@ -198,6 +204,9 @@ def run_batched(args) -> int:
                  "method": "single-environment handles stepped in turn; time of the timed "
                            "environments scaled by 64 / 8"},
         "batched_over_loop": value_b / value_l,
+        "solver_slots_per_block": spb or 128,
+        "autotune": ({"chosen": spb, "ms_per_step": {k: round(1e3 * t, 1) for k, t in tuning.items()}}
+                     if tuning else None),
         "graph": {"value": P * N * args.steps / t_g, "ms_per_step": 1e3 * t_g / args.steps,
                   "method": f"the {args.steps} timed host steps ({N * args.steps} substeps) as one "
                             f"HIP graph (mpm_step_graph), recording included"},
@@ -279,6 +288,8 @@ def main() -> int:
     ap.add_argument("--max-iter", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched workload: pick the solver's contact nodes per block with the autotuner first")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run one device copy of BYTES (scale for the PMC byte counters)")
     args = ap.parse_args()

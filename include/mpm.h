@@ -110,6 +110,9 @@ typedef struct {
     int32_t tape_substeps;     /* substeps the differentiation tape can hold (0 = no tape); a
                                   multiple of N. The workspace grows by about
                                   tape_substeps x (96 P + 32 grid nodes) bytes. */
+    int32_t solver_slots_per_block; /* contact nodes per block of the contact solver, which
+                                  sets each environment's group of blocks (0 = 128; the
+                                  autotuner of the Python package picks it per scene) */
 } mpm_desc;
 
 /* Rigid primitive (body frame) with its initial pose and twist. */

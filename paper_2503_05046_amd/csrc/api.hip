@@ -70,6 +70,7 @@ mpm_status validate(const mpm_desc* d, Sizes* sz) {
     if (!(d->eps_r >= 0.0) || !(d->eps_a >= 0.0)) return fail(MPM_EINVAL, "tolerances must be >= 0");
     if (d->max_iter < 1) return fail(MPM_EINVAL, "max_iter must be >= 1");
     if (d->ls_max_steps < 0) return fail(MPM_EINVAL, "ls_max_steps must be >= 0");
+    if (d->solver_slots_per_block < 0) return fail(MPM_EINVAL, "solver_slots_per_block must be >= 0");
     if (d->n_particles < 1 || d->n_particles > (1ll << 31) - 1)
         return fail(MPM_EINVAL, "n_particles out of range");
     long long expect = 0, nodes = 0;
@@ -630,9 +631,11 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         h->wall_khz = khz;
     }
     {
-        // tuning override of the contact nodes per solver block
+        // contact nodes per solver block: the description's, else the default;
+        // MPM_SOLVER_SLOTS_PER_BLOCK overrides both (for sweeps)
         const char* spb = getenv("MPM_SOLVER_SLOTS_PER_BLOCK");
-        h->slots_per_block = spb ? std::max(1, atoi(spb)) : kQnItemsPerBlock;
+        h->slots_per_block = spb ? std::max(1, atoi(spb))
+                                 : (desc->solver_slots_per_block > 0 ? desc->solver_slots_per_block : kQnItemsPerBlock);
         // and a cap on the solver's blocks (below it, environments share blocks)
         const char* mb = getenv("MPM_SOLVER_MAX_BLOCKS");
         if (mb && atoi(mb) > 0) h->qn_cap = std::min(h->qn_cap, atoi(mb));

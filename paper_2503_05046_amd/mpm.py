@@ -45,7 +45,7 @@ class Desc(ct.Structure):
                 ("x", ct.c_void_p), ("v", ct.c_void_p), ("F", ct.c_void_p), ("C", ct.c_void_p),
                 ("pid", ct.c_void_p), ("max_contacts", ct.c_int64), ("workspace", ct.c_void_p),
                 ("workspace_bytes", ct.c_size_t), ("stream", ct.c_void_p),
-                ("tape_substeps", ct.c_int32)]
+                ("tape_substeps", ct.c_int32), ("solver_slots_per_block", ct.c_int32)]
 
 
 class EnvGrad(ct.Structure):
@@ -154,7 +154,7 @@ def env_descs(scene) -> ct.Array:
 
 
 def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 0,
-              tape_substeps: int = 0) -> Desc:
+              tape_substeps: int = 0, solver_slots_per_block: int = 0) -> Desc:
     d = Desc()
     d.struct_size = ct.sizeof(Desc)
     d.n_envs = len(scene.envs)
@@ -166,6 +166,7 @@ def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 
     d.n_particles = scene.P
     d.max_contacts = max_contacts
     d.tape_substeps = tape_substeps
+    d.solver_slots_per_block = solver_slots_per_block
     return d
 
 
@@ -302,7 +303,8 @@ class Sim:
     workspace, the library steps them in place."""
 
     def __init__(self, scene, device: str = "cuda:0", max_contacts: int = 0,
-                 ls_max_steps: int = 0, track_ids: bool = True, tape_substeps: int = 0):
+                 ls_max_steps: int = 0, track_ids: bool = True, tape_substeps: int = 0,
+                 solver_slots_per_block: int = 0):
         import torch
         load()
         self.torch = torch
@@ -317,7 +319,8 @@ class Sim:
         self.C = torch.from_numpy(np.ascontiguousarray(scene.C, np.float32)).to(dev)
         self.pid = torch.arange(self.P, dtype=torch.int32, device=dev) if track_ids else None
         self._envs = env_descs(scene)
-        self.desc = make_desc(scene, self._envs, max_contacts, ls_max_steps, tape_substeps)
+        self.desc = make_desc(scene, self._envs, max_contacts, ls_max_steps, tape_substeps,
+                              solver_slots_per_block)
         self.ws_bytes = mpm_workspace_size(self.desc)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
