@@ -261,9 +261,11 @@ void mpm_destroy(mpm_handle* h);
  * grid update, the contact solve (implicit differentiation at its optimum:
  * the full Hessian system by preconditioned conjugate gradients), contact
  * registration (penetration, lagged normal impulse and bias of every
- * contact) and G2P with the fixed-corotated stress. Environments of
- * Drucker-Prager material are refused with MPM_EINVAL (the return map has no
- * reverse mode here). The set of registered contacts is held fixed. */
+ * contact) and G2P with either material: the fixed-corotated stress, or the
+ * Drucker-Prager return map of the trial Hencky strain (tip, cone and
+ * elastic branches, Sec. II-A) with the Hencky stress. At a branch boundary
+ * the branch the forward took is differentiated. The set of registered
+ * contacts is held fixed. */
 
 /* Adjoints of one environment's material parameters. */
 typedef struct {

@@ -168,6 +168,143 @@ __device__ __forceinline__ void tau_adjoint(const Material& m, const float F[9],
     *lab = (J - 1.0f) * J * trT;
 }
 
+// Adjoint of the Hencky update of the Drucker-Prager material. From the trial
+// F_t = U diag(sig) V^T the forward forms s, the return map in Hencky strain
+// (eps = ln sig projected onto the cone; at its tip when tr eps >= 0) when
+// plastic, else s = sig, and writes F_out = U diag(s) V^T and
+// tau = U diag(t) U^T with t = 2 mu ln s + la tr(ln s). Given Fob = dL/dF_out
+// and Tb = dL/dtau, adds dL/dF_t to Ftb and returns dL/dmu and dL/dla. Both
+// outputs are isotropic functions of F_t: a perturbation dP = U^T dF_t V
+// changes their diagonals (in the frames U, V and U, U) through the Jacobians
+// of s and t with respect to sig, and their off-diagonal entries through
+// divided differences of s and t times the symmetric and skew parts of dP;
+// where two singular values coincide the divided differences take their
+// limits from the Jacobians. Evaluated in FP64 from the forward's own FP32 SVD.
+__device__ void hencky_dp_adjoint(const Material& m, bool plastic, const float Ft[9], const float Fob[9],
+                                  const float Tb[9], float Ftb[9], float* mub, float* lab) {
+    float Uf[9], sf[3], Vf[9];
+    svd3(Ft, Uf, sf, Vf);
+    double U[9], V[9], sig[3], e[3];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        U[k] = Uf[k];
+        V[k] = Vf[k];
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        sig[i] = fmax((double)sf[i], 1e-6);
+        e[i] = log(sig[i]);
+    }
+    const double mu = m.mu, la = m.la, tr = e[0] + e[1] + e[2];
+    // eps_p(eps), its Jacobian Jp (row i, column k: d eps_p,i / d eps_k), and
+    // d eps_p / d kappa, kappa = (3 la + 2 mu) alpha / (2 mu) (the cone)
+    double ep[3] = {e[0], e[1], e[2]}, Jp[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1}, dkap[3] = {0, 0, 0};
+    if (plastic) {
+        if (tr >= 0.0) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) ep[i] = 0.0;
+#pragma unroll
+            for (int k = 0; k < 9; ++k) Jp[k] = 0.0;
+        } else {
+            const double dv[3] = {e[0] - tr / 3.0, e[1] - tr / 3.0, e[2] - tr / 3.0};
+            const double nd = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+            const double kap = (3.0 * la + 2.0 * mu) / (2.0 * mu) * (double)m.alpha;
+            if (nd > 0.0 && nd + kap * tr > 0.0) {
+                // eps_p = (tr/3) 1 - kappa tr n, n = dev(eps) / |dev(eps)|
+                const double n[3] = {dv[0] / nd, dv[1] / nd, dv[2] / nd};
+                const double g = kap * tr / nd;
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    ep[i] = tr / 3.0 - kap * tr * n[i];
+                    dkap[i] = -tr * n[i];
+#pragma unroll
+                    for (int k = 0; k < 3; ++k)
+                        Jp[i * 3 + k] = 1.0 / 3.0 - kap * n[i] - g * ((i == k ? 1.0 : 0.0) - n[i] * n[k] - 1.0 / 3.0);
+                }
+            }
+        }
+    }
+    const double trp = ep[0] + ep[1] + ep[2];
+    double sv[3], tv[3], Js[9], Jt[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        sv[i] = exp(ep[i]);
+        tv[i] = 2.0 * mu * ep[i] + la * trp;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double colsum = Jp[0 * 3 + k] + Jp[1 * 3 + k] + Jp[2 * 3 + k];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            Js[i * 3 + k] = sv[i] * Jp[i * 3 + k] / sig[k];
+            Jt[i * 3 + k] = (2.0 * mu * Jp[i * 3 + k] + la * colsum) / sig[k];
+        }
+    }
+    // the adjoints in the frames: Ab = U^T Fob V, Bb = U^T sym(Tb) U
+    double Ab[9], Bb[9];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            double a = 0.0, b = 0.0;
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    a += U[r * 3 + i] * (double)Fob[r * 3 + c] * V[c * 3 + j];
+                    b += U[r * 3 + i] * 0.5 * ((double)Tb[r * 3 + c] + (double)Tb[c * 3 + r]) * U[c * 3 + j];
+                }
+            Ab[i * 3 + j] = a;
+            Bb[i * 3 + j] = b;
+        }
+    double Pb[9];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) acc += Ab[i * 4] * Js[i * 3 + k] + Bb[i * 4] * Jt[i * 3 + k];
+        Pb[k * 4] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = i + 1; j < 3; ++j) {
+            const double gap = sig[j] - sig[i], sum = sig[i] + sig[j];
+            const bool close = fabs(gap) <= 1e-6 * sum;
+            const double a = close ? Js[i * 3 + i] - Js[i * 3 + j] : (sv[j] - sv[i]) / gap;
+            const double b = (sv[i] + sv[j]) / sum;
+            const double c = close ? Jt[i * 3 + i] - Jt[i * 3 + j] : (tv[j] - tv[i]) / gap;
+            const double d = (tv[j] - tv[i]) / sum;
+            const double symA = 0.5 * (Ab[i * 3 + j] + Ab[j * 3 + i]), skwA = 0.5 * (Ab[i * 3 + j] - Ab[j * 3 + i]);
+            const double bs = Bb[i * 3 + j] + Bb[j * 3 + i];
+            Pb[i * 3 + j] = a * symA + b * skwA + 0.5 * bs * (c + d);
+            Pb[j * 3 + i] = a * symA - b * skwA + 0.5 * bs * (c - d);
+        }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) acc += U[r * 3 + i] * Pb[i * 3 + j] * V[c * 3 + j];
+            Ftb[r * 3 + c] += (float)acc;
+        }
+    // the Lame parameters: directly in t, and through kappa on the cone
+    const double dkap_dmu = -3.0 * la * (double)m.alpha / (2.0 * mu * mu);
+    const double dkap_dla = 3.0 * (double)m.alpha / (2.0 * mu);
+    double mb = 0.0, lb = 0.0;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double dep_mu = dkap[i] * dkap_dmu, dep_la = dkap[i] * dkap_dla;
+        mb += Ab[i * 4] * sv[i] * dep_mu + Bb[i * 4] * (2.0 * ep[i] + 2.0 * mu * dep_mu);
+        lb += Ab[i * 4] * sv[i] * dep_la + Bb[i * 4] * (trp + 2.0 * mu * dep_la);
+    }
+    *mub = (float)mb;
+    *lab = (float)lb;
+}
+
 // Per-environment FP64 sums of two values: a wave whose lanes share one
 // environment adds them with shuffles first.
 __device__ __forceinline__ void add_env_pair(double* acc, int env, double a, double b) {
@@ -254,16 +391,24 @@ k_g2p_adj(long long P, const DevEnv* __restrict__ envs, int n_envs, float h, con
         Cb[k] = aC ? aC[k * P + q] : 0.f;
     }
     float mub = 0.f, lab = 0.f;
+    float Tb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (aQ) {
         // Q' = m_p C' - h V0 D tau(F')
-        float Qb[9], Tb[9];
         const float c = h * E.V0 * E.D;
 #pragma unroll
         for (int k = 0; k < 9; ++k) {
-            Qb[k] = aQ[k * P + q];
-            Cb[k] += E.m_p * Qb[k];
-            Tb[k] = -c * Qb[k];
+            const float Qb = aQ[k * P + q];
+            Cb[k] += E.m_p * Qb;
+            Tb[k] = -c * Qb;
         }
+    }
+    if (E.mat.type == 1) {
+        // sand: F' and tau both come from the return map of the trial F
+        float Ftb[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        hencky_dp_adjoint(E.mat, true, Fn, Fnb, Tb, Ftb, &mub, &lab);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Fnb[k] = Ftb[k];
+    } else if (aQ) {
         tau_adjoint(E.mat, Fn, Tb, Fnb, &mub, &lab);
     }
     // F' = (I + h C') F
@@ -443,7 +588,13 @@ k_permute_adj(long long P, const DevEnv* __restrict__ envs, int n_envs, float h,
         Tb[k] = -c * Qb[k];
     }
     float mub, lab;
-    tau_adjoint(E.mat, Fp, Tb, Fb, &mub, &lab);
+    if (E.mat.type == 1) {
+        // the Hencky stress of the stored (already projected) F
+        const float zero[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        hencky_dp_adjoint(E.mat, false, Fp, zero, Tb, Fb, &mub, &lab);
+    } else {
+        tau_adjoint(E.mat, Fp, Tb, Fb, &mub, &lab);
+    }
     if (live) {
         const long long s = idx[i];
 #pragma unroll

@@ -890,9 +890,6 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
     if (!h) return fail(MPM_EINVAL, "handle is NULL");
     if (!gx || !gv || !gF || !gC) return fail(MPM_EINVAL, "adjoint arrays must be non-NULL");
     if (h->tape_len <= 0) return fail(MPM_EINVAL, "nothing recorded: call mpm_tape_reset, then mpm_step");
-    for (const mpm_env_desc& E : h->envs)
-        if (E.material != MPM_FIXED_COROTATED)
-            return fail(MPM_EINVAL, "the reverse pass covers the fixed-corotated material only");
     Work& W = h->w;
     hipStream_t s = h->stream;
     const int N = h->d.N, n_envs = (int)h->envs.size(), nr = (int)h->rigids.size();

@@ -1,10 +1,12 @@
 """Reverse pass of the HIP library against central finite differences of the
 FP64 oracle.
 
-Two scenes: one without contact (P2G, the grid update, G2P with the
-fixed-corotated stress and the host step's sort in reverse), and one in
-contact with a half-space and a rotating, moving box (adding the contact
-solve, differentiated at its optimum, and contact registration). Loss functionals
+Three scenes: one without contact (P2G, the grid update, G2P with the
+fixed-corotated stress and the host step's sort in reverse), one in contact
+with a half-space and a rotating, moving box (adding the contact solve,
+differentiated at its optimum, and contact registration), and sand without
+contact (the Drucker-Prager return map of the trial strain in all three of
+its branches, and the Hencky stress of the projected and of the gathered F). Loss functionals
 L_a = <W_a, a_final> (a in x, v, F, C, random weights W_a) after two host steps
 of two substeps; for every pair (loss a, input field b) the directional
 derivative of L_a along a random direction in b from mpm_step_backward is
@@ -52,9 +54,10 @@ def _free_scene(seed):
     return s
 
 
-def _oracle_final(oracle, scene, shift=None, eps=0.0, dE=0.0):
+def _oracle_final(oracle, scene, shift=None, eps=0.0, dE=0.0, dnu=0.0):
     s = scene.copy()
     s.envs[0].E += dE
+    s.envs[0].nu += dnu
     ora = oracle.OracleSim(s)
     if shift is not None:
         b, d = shift
@@ -213,3 +216,118 @@ def test_box_velocity_gradient(oracle, reverse_contact, a):
     _log(f"contact: dL_{a}/dV: gpu {gpu} fd {fd}")
     assert np.abs(gpu - fd).max() <= 1e-3 * np.abs(fd).max() + 1e-9, (gpu, fd)
     assert np.all(out[a][2]["dV"][0] == 0.0)  # the half-space is static
+
+
+def _sand_scene():
+    """Random sand state (Drucker-Prager, friction angle 30 degrees), no rigid
+    bodies: 100 particles with velocities N(0, 0.9) m/s and random
+    deformations, so that particles sit at the cone's tip, on its surface and
+    inside it (elastic) in every substep."""
+    s = I.tiny_random(P=100, seed=45, n=16, material=I.DRUCKER_PRAGER, with_box=False)
+    s.rigids = []
+    s.N = 2
+    s.h = 2e-4
+    s.v *= np.float32(3.0)
+    return s
+
+
+def _branch_margins(oracle, scene):
+    """Per substep, the smallest distance of a particle's trial Hencky strain
+    from the return map's branch boundaries (tr eps = 0 and the cone
+    |dev eps| + kappa tr eps = 0), on the oracle's trajectory, and the count of
+    particles in each branch."""
+    env = scene.envs[0]
+    mu = env.E / (2 * (1 + env.nu))
+    la = env.E * env.nu / ((1 + env.nu) * (1 - 2 * env.nu))
+    sphi = np.sin(np.radians(env.friction_angle))
+    kappa = (3 * la + 2 * mu) / (2 * mu) * np.sqrt(2.0 / 3.0) * 2 * sphi / (3 - sphi)
+    ora = oracle.OracleSim(scene)
+    out = []
+    for _ in range(scene.N * HOST_STEPS):
+        F0 = ora.F.T.reshape(-1, 3, 3).copy()
+        rc, _, _ = ora.substep()
+        assert rc == 0
+        Ft = (np.eye(3) + scene.h * ora.C.T.reshape(-1, 3, 3)) @ F0
+        e = np.log(np.linalg.svd(Ft, compute_uv=False))
+        tr = e.sum(axis=1)
+        dg = np.linalg.norm(e - tr[:, None] / 3, axis=1) + kappa * tr
+        counts = (int((tr >= 0).sum()), int(((tr < 0) & (dg > 0)).sum()), int(((tr < 0) & (dg <= 0)).sum()))
+        out.append((float(np.minimum(np.abs(tr), np.abs(dg)).min()), counts))
+    return out
+
+
+@pytest.fixture(scope="module")
+def reverse_sand(mpm, oracle):
+    import torch
+    scene = _sand_scene()
+    margins = _branch_margins(oracle, scene)
+    _log(f"sand: per substep (smallest branch margin, (tip, cone, elastic)): {margins}")
+    # float32 forward and the oracle's finite differences take the same branch
+    # for every particle when no trial strain lies near a boundary
+    assert min(m for m, _ in margins) > 1e-5, margins
+    assert all(min(c) > 0 for _, c in margins), margins
+    rng = np.random.default_rng(9)
+    W = {a: rng.normal(size=(n, scene.P)) for a, n in FIELDS}
+    sim = mpm.Sim(scene, tape_substeps=scene.N * HOST_STEPS)
+    sim.tape_reset(True)
+    for _ in range(HOST_STEPS):
+        status, _, st = sim.step()
+        assert status == 0 and st["max_contacts"] == 0
+    pid = sim.pid.cpu().numpy()
+    out = {}
+    for a, _ in FIELDS:
+        g = {b: torch.zeros((n, scene.P), dtype=torch.float32, device=sim.device) for b, n in FIELDS}
+        g[a].copy_(torch.from_numpy(W[a][:, pid].astype(np.float32)))
+        env_grads, _ = sim.backward(g["x"], g["v"], g["F"], g["C"])
+        out[a] = ({b: g[b].cpu().numpy().astype(np.float64) for b, _ in FIELDS}, env_grads[0])
+    sim.close()
+    return scene, W, out
+
+
+@pytest.mark.parametrize("a", [f for f, _ in FIELDS])
+@pytest.mark.parametrize("b", [f for f, _ in FIELDS])
+def test_sand_state_gradient_matches_finite_differences(oracle, reverse_sand, a, b):
+    scene, W, out = reverse_sand
+    grad = out[a][0][b]
+    names = [f for f, _ in FIELDS]
+    rng = np.random.default_rng(300 + 10 * names.index(a) + names.index(b))
+    d = rng.normal(size=grad.shape)
+    # small steps keep every perturbed trajectory on the same branches
+    eps = 1e-7 * (scene.envs[0].dx if b == "x" else 1.0)
+    lp = (W[a] * _oracle_final(oracle, scene, (b, d), eps)[a]).sum()
+    lm = (W[a] * _oracle_final(oracle, scene, (b, d), -eps)[a]).sum()
+    fd = (lp - lm) / (2 * eps)
+    gpu = float((grad * d).sum())
+    if a == b and a in ("x", "F"):
+        ident = float((W[a] * d).sum())
+        fd, gpu = fd - ident, gpu - ident
+    _log(f"sand: L_{a} along d{b}: gpu {gpu:.6e} fd {fd:.6e}")
+    assert abs(gpu - fd) <= 1e-3 * abs(fd) + 1e-7 * np.sqrt((W[a] ** 2).sum() * (d ** 2).sum()), (gpu, fd)
+
+
+@pytest.mark.parametrize("a", [f for f, _ in FIELDS])
+def test_sand_youngs_modulus_gradient(oracle, reverse_sand, a):
+    scene, W, out = reverse_sand
+    E = scene.envs[0].E
+    eps = 1e-7 * E
+    lp = (W[a] * _oracle_final(oracle, scene, dE=eps)[a]).sum()
+    lm = (W[a] * _oracle_final(oracle, scene, dE=-eps)[a]).sum()
+    fd = (lp - lm) / (2 * eps)
+    gpu = out[a][1][0]
+    _log(f"sand: dL_{a}/dE: gpu {gpu:.6e} fd {fd:.6e}")
+    assert abs(gpu - fd) <= 1e-3 * abs(fd) + 1e-12, (gpu, fd)
+
+
+@pytest.mark.parametrize("a", [f for f, _ in FIELDS])
+def test_sand_poisson_ratio_gradient(oracle, reverse_sand, a):
+    """nu moves the cone's slope (3 la + 2 mu) alpha / (2 mu), which E leaves
+    unchanged: this checks the return map's dependence on the Lame
+    parameters through the cone."""
+    scene, W, out = reverse_sand
+    eps = 1e-7
+    lp = (W[a] * _oracle_final(oracle, scene, dnu=eps)[a]).sum()
+    lm = (W[a] * _oracle_final(oracle, scene, dnu=-eps)[a]).sum()
+    fd = (lp - lm) / (2 * eps)
+    gpu = out[a][1][1]
+    _log(f"sand: dL_{a}/dnu: gpu {gpu:.6e} fd {fd:.6e}")
+    assert abs(gpu - fd) <= 1e-3 * abs(fd) + 1e-9, (gpu, fd)
