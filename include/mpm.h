@@ -257,7 +257,7 @@ void mpm_destroy(mpm_handle* h);
  * adjoint of the state after the recorded steps to the adjoint of the state
  * before them, and returns the adjoints of the Lame parameters as adjoints of
  * each environment's E and nu (with k, V0 and rho held fixed) and of each
- * rigid body's linear velocity. It covers the substep of Eq. (5)-(8): P2G,
+ * rigid body's twist (V, w) and pose. It covers the substep of Eq. (5)-(8): P2G,
  * grid update, the contact solve (implicit differentiation at its optimum:
  * the full Hessian system by preconditioned conjugate gradients), contact
  * registration (penetration, lagged normal impulse and bias of every
@@ -280,6 +280,14 @@ typedef struct {
     double dV_kinematic[3];  /* dV plus the library's own kinematic update of t (t advances
                                 by N h V after each host step), i.e. the full derivative when
                                 mpm_step was called with in = NULL */
+    double dw[3];            /* through the angular velocity w in the velocity field
+                                V + w x (x - t) of every recorded host step */
+    double dR[3];            /* through a small rotation (world rotation vector, about t) of
+                                the first recorded pose, later poses following it by the
+                                kinematic advance (R turns by N h w after each host step) */
+    double dw_kinematic[3];  /* dw plus the kinematic advance's dependence of the poses on w,
+                                i.e. the full derivative when mpm_step was called with
+                                in = NULL */
 } mpm_rigid_grad;
 
 /* Empty the tape; with record = 1 the following mpm_step calls record, with

@@ -630,6 +630,11 @@ __device__ __forceinline__ void from_frame(const ContactRec& R, const double c[3
 #pragma unroll
     for (int a = 0; a < 3; ++a) w[a] = R.t1[a] * c[0] + R.t2[a] * c[1] + R.n[a] * c[2];
 }
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
 __device__ __forceinline__ void apply_G(double g00, double g01, double g11, double gnn, const double u[3], double o[3]) {
     o[0] = g00 * u[0] + g01 * u[1];
     o[1] = g01 * u[0] + g11 * u[1];
@@ -823,7 +828,9 @@ __global__ void k_cg_next(double* sc) {
 
 // Per contact: the adjoints of the contact's parameters, chained through
 // registration to the particle (x, v at the substep start: into cx, cv) and
-// to the rigid body (twist V and position t: into rg, 6 doubles per body).
+// to the rigid body (into rg, 12 doubles per body: V, t, w through the
+// velocity V + w x (x - t), and a small rotation th of the pose about t,
+// R -> (I + [th]x) R).
 __global__ void __launch_bounds__(256)
 k_cadj_params(const DevCounters* cnt, long long cap, long long P, double h, const DevEnv* __restrict__ envs,
               const DevRigid* __restrict__ rigids, const ContactRec* __restrict__ rec,
@@ -893,10 +900,11 @@ k_cadj_params(const DevCounters* cnt, long long cap, long long P, double h, cons
             from_frame(R, bb, rbb);  // b = -R^T v_r
             vrb[0] = -rbb[0]; vrb[1] = -rbb[1]; vrb[2] = -rbb[2];
         }
+        double vn0b = 0.0;
         if (a0 > 0.0 && b0 > 0.0) {
             const double n0b = B.mu * mun0b;
             phib += n0b * h * Pm.k * b0;
-            const double vn0b = n0b * h * Pm.k * (-h * b0 - Pm.d * a0);
+            vn0b = n0b * h * Pm.k * (-h * b0 - Pm.d * a0);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
                 vb[q] += vn0b * R.n[q];
@@ -909,13 +917,40 @@ k_cadj_params(const DevCounters* cnt, long long cap, long long P, double h, cons
                               vrb[0] * B.w[1] - vrb[1] * B.w[0]};  // vrb x w
 #pragma unroll
         for (int q = 0; q < 3; ++q) xb[q] += -phib * R.n[q] + wx[q];
+        // w: d(w x rel) = dw x rel, so dL/dw = rel x vrb
+        double wb[3];
+        cross3(rel, vrb, wb);
+        // a rotation th of the pose about t: phi0 changes by th . (rel x n);
+        // the normal turns with the body (dn = th x n), and so does the
+        // contact frame (the model is isotropic about n, so any completion of
+        // the turned normal gives the same impulse); in the solve's optimality
+        // condition the term J^T R grad l(R^T (J v - v_r)) then changes by
+        // J^T (-th x R gamma - R G R^T (th x u)), u = R v_c, and -lam^T of
+        // that is th . (R gamma x J lam + u x R G y)
+        double thb[3], tq[3], u[3];
+        cross3(rel, R.n, thb);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) thb[q] *= phib;
+        const double dvp[3] = {vp[0] - vr[0], vp[1] - vr[1], vp[2] - vr[2]};
+        cross3(R.n, dvp, tq);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) thb[q] += vn0b * tq[q];
+        cross3(Rg, ly, tq);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) thb[q] += tq[q];
+        from_frame(R, vcf, u);
+        cross3(u, RGy, tq);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) thb[q] += tq[q];
         const int rid = c_rid[c];
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
             atomicAdd(&cx[q * P + p], (float)xb[q]);
             atomicAdd(&cv[q * P + p], (float)vb[q]);
-            atomicAdd(&rg[6 * rid + q], vrb[q]);
-            atomicAdd(&rg[6 * rid + 3 + q], phib * R.n[q] - wx[q]);
+            atomicAdd(&rg[kRigidGradStride * rid + q], vrb[q]);
+            atomicAdd(&rg[kRigidGradStride * rid + 3 + q], phib * R.n[q] - wx[q]);
+            atomicAdd(&rg[kRigidGradStride * rid + 6 + q], wb[q]);
+            atomicAdd(&rg[kRigidGradStride * rid + 9 + q], thb[q]);
         }
     }
 }

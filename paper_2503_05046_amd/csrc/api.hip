@@ -180,7 +180,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->cg_q = T ? L.take<double>((size_t)3 * z.cap_c) : nullptr;
     w->cg_sc = T ? L.take<double>(8) : nullptr;
     w->cxv = T ? L.take<float>((size_t)6 * P) : nullptr;
-    w->rgrad = T ? L.take<double>((size_t)(T / z.N) * kMaxRigidTape * 6) : nullptr;
+    w->rgrad = T ? L.take<double>((size_t)(T / z.N) * kMaxRigidTape * kRigidGradStride) : nullptr;
     w->tape_cap = (int)T;
     w->cnt = L.take<DevCounters>(1);
     w->envs = L.take<DevEnv>(z.n_envs);
@@ -220,6 +220,31 @@ __host__ __device__ void rodrigues_advance(double R[9], const double w[3], doubl
             Rn[r * 3 + c] = s;
         }
     for (int i = 0; i < 9; ++i) R[i] = Rn[i];
+}
+
+// For the rotation vector phi (angle |phi| about phi / |phi|): o = Rot(phi)^T v,
+// and o = J(phi)^T v with J(phi) = I + (1 - cos t)/t^2 [phi]x + (t - sin t)/t^3
+// [phi]x^2, t = |phi|, the left Jacobian of the rotation map (series below
+// t = 1e-4).
+void rotate_transposed(const double phi[3], const double v[3], double o[3]) {
+    const double t = sqrt(phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2]);
+    if (t == 0.0) {
+        for (int a = 0; a < 3; ++a) o[a] = v[a];
+        return;
+    }
+    const double k[3] = {phi[0] / t, phi[1] / t, phi[2] / t};
+    const double kv[3] = {k[1] * v[2] - k[2] * v[1], k[2] * v[0] - k[0] * v[2], k[0] * v[1] - k[1] * v[0]};
+    const double kkv[3] = {k[1] * kv[2] - k[2] * kv[1], k[2] * kv[0] - k[0] * kv[2], k[0] * kv[1] - k[1] * kv[0]};
+    for (int a = 0; a < 3; ++a) o[a] = v[a] - sin(t) * kv[a] + (1.0 - cos(t)) * kkv[a];
+}
+void left_jacobian_transposed(const double phi[3], const double v[3], double o[3]) {
+    const double t2 = phi[0] * phi[0] + phi[1] * phi[1] + phi[2] * phi[2], t = sqrt(t2);
+    const double a = t < 1e-4 ? 0.5 - t2 / 24.0 : (1.0 - cos(t)) / t2;
+    const double b = t < 1e-4 ? 1.0 / 6.0 - t2 / 120.0 : (t - sin(t)) / (t2 * t);
+    const double pv[3] = {phi[1] * v[2] - phi[2] * v[1], phi[2] * v[0] - phi[0] * v[2], phi[0] * v[1] - phi[1] * v[0]};
+    const double ppv[3] = {phi[1] * pv[2] - phi[2] * pv[1], phi[2] * pv[0] - phi[0] * pv[2],
+                           phi[0] * pv[1] - phi[1] * pv[0]};
+    for (int q = 0; q < 3; ++q) o[q] = v[q] - a * pv[q] + b * ppv[q];
 }
 
 // The kinematic advance of the rigid table on the device (graph path): the
@@ -909,7 +934,7 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
     HIP_TRY(hipMemcpyAsync(A + 6 * P, gF, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(A + 15 * P, gC, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemsetAsync(W.lame, 0, sizeof(double) * 2 * n_envs, s));
-    HIP_TRY(hipMemsetAsync(W.rgrad, 0, sizeof(double) * 6 * kMaxRigidTape * n_host, s));
+    HIP_TRY(hipMemsetAsync(W.rgrad, 0, sizeof(double) * kRigidGradStride * kMaxRigidTape * n_host, s));
     HIP_TRY(launch_clear_step(W, N, false, s));
     W.n_rigid = nr;
     int cur = 0;
@@ -957,7 +982,7 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
                 cx = W.cxv;
                 cv = W.cxv + 3 * P;
                 HIP_TRY(hipMemsetAsync(W.cxv, 0, sizeof(float) * 6 * P, s));
-                HIP_TRY(launch_cadj_finish(W, hd, t, t.vel, cx, cv, W.rgrad + (size_t)j * kMaxRigidTape * 6, s));
+                HIP_TRY(launch_cadj_finish(W, hd, t, t.vel, cx, cv, W.rgrad + (size_t)j * kMaxRigidTape * kRigidGradStride, s));
             }
             HIP_TRY(launch_grid_adj(W, t, hf, W.gbar, s));
             HIP_TRY(launch_p2g_adj(W, t, W.gbar, cx, cv, ax, av, aCQ, s));
@@ -975,9 +1000,15 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
     HIP_TRY(hipMemcpyAsync(gv, A + 3 * P, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(gF, A + 6 * P, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
     HIP_TRY(hipMemcpyAsync(gC, A + 15 * P, sizeof(float) * 9 * P, hipMemcpyDeviceToDevice, s));
-    std::vector<double> lame(2 * n_envs), rg((size_t)6 * kMaxRigidTape * n_host);
+    std::vector<double> lame(2 * n_envs), rg((size_t)kRigidGradStride * kMaxRigidTape * n_host);
+    const int nr1 = std::max(nr, 1);
+    std::vector<DevRigid> trig((size_t)n_host * nr1);
     HIP_TRY(hipMemcpyAsync(lame.data(), W.lame, sizeof(double) * 2 * n_envs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(rg.data(), W.rgrad, sizeof(double) * rg.size(), hipMemcpyDeviceToHost, s));
+    if (rigid_grads)
+        for (int j = 0; j < n_host; ++j)
+            HIP_TRY(hipMemcpyAsync(trig.data() + (size_t)j * nr1, W.tape_rig + (size_t)j * kMaxRigidTape,
+                                   sizeof(DevRigid) * nr1, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (env_grads) {
         for (int e = 0; e < n_envs; ++e) {
@@ -1000,11 +1031,22 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
             memset(&g, 0, sizeof(g));
             if (h->rigids[order[k]].desc.motion == MPM_STATIC) continue;
             for (int j = 0; j < n_host; ++j) {
-                const double* q = rg.data() + ((size_t)j * kMaxRigidTape + k) * 6;
+                const double* q = rg.data() + ((size_t)j * kMaxRigidTape + k) * kRigidGradStride;
+                // pose j of the window is Rot(j dT w) applied to the first; a
+                // rotation d of the first turns pose j by Rot(j dT w) d, and
+                // dw turns it by j dT J(j dT w) dw (J: the left Jacobian of
+                // the rotation map)
+                double phi[3], rt[3], jt[3];
+                for (int a = 0; a < 3; ++a) phi[a] = j * dT * trig[(size_t)j * nr1 + k].w[a];
+                rotate_transposed(phi, q + 9, rt);
+                left_jacobian_transposed(phi, q + 9, jt);
                 for (int a = 0; a < 3; ++a) {
                     g.dV[a] += q[a];
                     g.dt[a] += q[3 + a];
                     g.dV_kinematic[a] += q[a] + j * dT * q[3 + a];
+                    g.dw[a] += q[6 + a];
+                    g.dR[a] += rt[a];
+                    g.dw_kinematic[a] += q[6 + a] + j * dT * jt[a];
                 }
             }
         }

@@ -111,6 +111,9 @@ constexpr int kBarStride = 16;     // unsigned words between the barrier counter
 constexpr int kCtrLanes = 8;       // loop-barrier arrival counters per environment (block rank mod 8)
 constexpr int kCtrStride = 32;     // unsigned words between two of them (separate 128-byte lines)
 constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps each host step's table)
+// adjoints per rigid body and recorded host step: V, t, w (through the
+// velocity field), a small rotation of the pose about t
+constexpr int kRigidGradStride = 12;
 
 // Pointers into the caller's workspace.
 struct Work {
@@ -173,7 +176,7 @@ struct Work {
     double* cg_q;            // [cap_c][3]
     double* cg_sc;           // [8] scalars
     float* cxv;              // [6][P] particle adjoints from the contact solve (x, v)
-    double* rgrad;           // [tape_cap / N][n_rigid][6] rigid adjoints (V, t) per host step
+    double* rgrad;           // [tape_cap / N][n_rigid][kRigidGradStride] rigid adjoints per host step
     int tape_cap;
     DevCounters* cnt;
     DevEnv* envs;

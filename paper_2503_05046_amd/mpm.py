@@ -53,7 +53,8 @@ class EnvGrad(ct.Structure):
 
 
 class RigidGrad(ct.Structure):
-    _fields_ = [("dV", ct.c_double * 3), ("dt", ct.c_double * 3), ("dV_kinematic", ct.c_double * 3)]
+    _fields_ = [("dV", ct.c_double * 3), ("dt", ct.c_double * 3), ("dV_kinematic", ct.c_double * 3),
+                ("dw", ct.c_double * 3), ("dR", ct.c_double * 3), ("dw_kinematic", ct.c_double * 3)]
 
 
 class RigidDesc(ct.Structure):
@@ -283,13 +284,13 @@ def mpm_tape_reset(h, record: bool = True) -> None:
 
 def mpm_step_backward(h, gx: int, gv: int, gF: int, gC: int, n_envs: int, n_rigid: int):
     """Device pointers of the four adjoint arrays (updated in place); returns
-    ([(dL/dE, dL/dnu)] per environment, {"dV", "dt", "dV_kinematic"} arrays of
-    shape [n_rigid, 3])."""
+    ([(dL/dE, dL/dnu)] per environment, {"dV", "dt", "dV_kinematic", "dw", "dR",
+    "dw_kinematic"} arrays of shape [n_rigid, 3])."""
     g = (EnvGrad * n_envs)()
     r = (RigidGrad * max(1, n_rigid))()
     _check(load().mpm_step_backward(h, gx, gv, gF, gC, g, r), "mpm_step_backward")
     rig = {k: np.array([list(getattr(q, k)) for q in r[:n_rigid]]).reshape(n_rigid, 3)
-           for k in ("dV", "dt", "dV_kinematic")}
+           for k in ("dV", "dt", "dV_kinematic", "dw", "dR", "dw_kinematic")}
     return [(e.dE, e.dnu) for e in g], rig
 
 

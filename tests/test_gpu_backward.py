@@ -136,11 +136,29 @@ def _contact_scene():
     return s
 
 
-def _oracle_final_rigid(oracle, scene, dV):
+def _oracle_final_rigid(oracle, scene, dV=None, dw=None, dth=None):
+    """The box's velocity or angular velocity shifted, or its initial pose
+    turned by the rotation vector dth about its centre."""
     s = scene.copy()
     r = s.rigids[1]
-    s.rigids[1] = type(r)(**{**r.__dict__, "V": tuple(np.array(r.V) + dV)})
+    kw = dict(r.__dict__)
+    if dV is not None:
+        kw["V"] = tuple(np.array(r.V) + dV)
+    if dw is not None:
+        kw["w"] = tuple(np.array(r.w) + dw)
+    if dth is not None:
+        kw["R"] = tuple((_rotation(dth) @ np.array(r.R).reshape(3, 3)).reshape(-1))
+    s.rigids[1] = type(r)(**kw)
     return _oracle_final(oracle, s)
+
+
+def _rotation(phi):
+    t = float(np.linalg.norm(phi))
+    if t == 0.0:
+        return np.eye(3)
+    k = np.asarray(phi, np.float64) / t
+    K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
+    return np.eye(3) + np.sin(t) * K + (1.0 - np.cos(t)) * (K @ K)
 
 
 @pytest.fixture(scope="module")
@@ -210,12 +228,35 @@ def test_box_velocity_gradient(oracle, reverse_contact, a):
     for k in range(3):
         dv = np.zeros(3)
         dv[k] = 1e-6
-        lp = (W[a] * _oracle_final_rigid(oracle, scene, dv)[a]).sum()
-        lm = (W[a] * _oracle_final_rigid(oracle, scene, -dv)[a]).sum()
+        lp = (W[a] * _oracle_final_rigid(oracle, scene, dV=dv)[a]).sum()
+        lm = (W[a] * _oracle_final_rigid(oracle, scene, dV=-dv)[a]).sum()
         fd[k] = (lp - lm) / 2e-6
     _log(f"contact: dL_{a}/dV: gpu {gpu} fd {fd}")
     assert np.abs(gpu - fd).max() <= 1e-3 * np.abs(fd).max() + 1e-9, (gpu, fd)
     assert np.all(out[a][2]["dV"][0] == 0.0)  # the half-space is static
+
+
+@pytest.mark.parametrize("a", [f for f, _ in FIELDS])
+@pytest.mark.parametrize("kind", ["w", "R"])
+def test_box_rotation_gradient(oracle, reverse_contact, a, kind):
+    """d L / d w of the kinematic box (through its velocity field in both host
+    steps and through its turn before the second), and d L / d th for a
+    rotation th of its initial pose about its centre (the normals, frames and
+    penetrations of its contacts turn with it)."""
+    scene, W, out = reverse_contact
+    gpu = out[a][2]["dw_kinematic" if kind == "w" else "dR"][1]
+    fd = np.zeros(3)
+    for k in range(3):
+        d = np.zeros(3)
+        d[k] = 1e-6
+        arg = "dw" if kind == "w" else "dth"
+        lp = (W[a] * _oracle_final_rigid(oracle, scene, **{arg: d})[a]).sum()
+        lm = (W[a] * _oracle_final_rigid(oracle, scene, **{arg: -d})[a]).sum()
+        fd[k] = (lp - lm) / 2e-6
+    _log(f"contact: dL_{a}/d{kind}: gpu {gpu} fd {fd}")
+    assert np.abs(gpu - fd).max() <= 1e-3 * np.abs(fd).max() + 1e-9, (gpu, fd)
+    for key in ("dw", "dR", "dw_kinematic"):
+        assert np.all(out[a][2][key][0] == 0.0)  # the half-space is static
 
 
 def _sand_scene():
