@@ -146,6 +146,9 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->c_st = L.take<ContactStencil>(C);
     w->c_dyn = L.take<ContactDyn>(C);
     w->c_coef = L.take<double>(11 * ((C + 63) / 64) * 64);
+    w->qn_uacc = L.take<double>((size_t)9 * C);
+    w->qn_vcblk = L.take<double>((size_t)kMaxQnBlocks * 6 * kQnScatterMax);
+    w->qn_pend = L.take<int>(z.n_envs);
     w->pk_a = L.take<unsigned>(27 * C);
     w->pk_b = L.take<unsigned>(27 * C);
     w->pv_a = L.take<unsigned>(27 * C);
@@ -157,6 +160,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->s_rec = L.take<SlotRec>(S);
     w->blk = L.take<unsigned>(256 * kSortBlocks + 2 * kSortBlocks);
     w->partial = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
+    w->partial_odd = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
     w->partial2 = L.take<double>(kMaxQnBlocks);
     w->rigid_acc = L.take<double>(6 * kMaxRigidTotal);
     w->sstats = L.take<SubstepStats>((size_t)z.N * z.n_envs);
@@ -667,6 +671,9 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         // MPM_SOLVER_COMPACT=0 sends every solver block through the general node pass
         const char* cp = getenv("MPM_SOLVER_COMPACT");
         h->w.qn_compact = (cp && atoi(cp) == 0) ? 0 : 1;
+        // MPM_SOLVER_SCATTER=0 keeps every environment on the two-barrier form
+        const char* sc = getenv("MPM_SOLVER_SCATTER");
+        h->w.qn_scatter = (sc && atoi(sc) == 0) ? 0 : 1;
     }
     h->w.n_rigid = 0;
     int tiles = 0;

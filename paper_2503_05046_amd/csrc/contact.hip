@@ -30,6 +30,19 @@
 //               block obtains the same step length.
 // Contact velocities are carried as v_c + alpha u_c (the contact velocity is
 // linear in the grid velocity), double-buffered by iteration parity.
+// One-barrier form (k_qn<true>, launched first: it solves the environments
+// whose blocks all hold their contact nodes in the compact form and that have
+// at most kScatterMax contacts, and marks the others for k_qn<false>): the
+// node pass also forms u_c = R_c^T sum w dv over its entries (a block sum in
+// LDS, projected, then one device-scope FP64 atomic add per distinct contact
+// and component, into one of three buffers by iteration), so after the
+// barrier every block forms the line-search coefficients and phi''(0) of all
+// the environment's contacts itself, and the contact pass and the second
+// barrier go away. Each block carries the contact velocities it
+// needs (its distinct contacts in LDS, the line search's in a scratch array of
+// its own), updated with the same arithmetic from the same values, so they
+// agree in every block. The order of the atomic adds varies from run to run,
+// so this form is reproducible to rounding, not bit for bit.
 #include "contact_model.h"
 #include "mpm_internal.h"
 #include "sort_util.h"
@@ -514,6 +527,7 @@ struct QnArgs {
     const Entry* e_ent;
     SlotRec* s_rec;
     double* partial;        // per block: the node pass's sums
+    double* partial_odd;    // the same for odd iterations of the one-barrier form
     double* partial2;       // per block: the contact pass's share of phi''(0)
     double* rigid_acc;
     int n_rigid;
@@ -530,6 +544,9 @@ struct QnArgs {
     int n_envs;
     int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
     int compact;               // 0: no block takes the compact node pass
+    int* env_pend;             // per environment: 1 when k_qn<true> left it to k_qn<false>
+    double* u_acc;             // [3 buffers][3][cap] per-contact sums U_c of the one-barrier form
+    double* vc_blk;            // per block: [6][kScatterMax] v_c, u_c of the line search's contacts
     int timers;                // 1: the first block of each environment times the solver's phases
     int slots_per_block;       // contact nodes per block that set an environment's group size
     DevCounters* cnt;
@@ -554,6 +571,13 @@ __device__ __forceinline__ void contact_velocity(const ContactDyn& D, int k, dou
 #pragma unroll
     for (int a = 0; a < 3; ++a)
         vc[a] = k == 0 ? ld_x(&D.vc[0][a]) : fma(alpha_prev, ld_x(&D.uc[src][a]), ld_x(&D.vc[src][a]));
+}
+
+// u = R_c^T U in the contact frame, with the same rounding wherever it is formed.
+__device__ __forceinline__ void frame_project(const ContactRec& R, const double U[3], double u[3]) {
+    u[0] = fma(R.t1[0], U[0], fma(R.t1[1], U[1], R.t1[2] * U[2]));
+    u[1] = fma(R.t2[0], U[0], fma(R.t2[1], U[1], R.t2[2] * U[2]));
+    u[2] = fma(R.n[0], U[0], fma(R.n[1], U[1], R.n[2] * U[2]));
 }
 
 // Sum of x over the 64 lanes of a wave, the same bits in every lane: DPP
@@ -658,9 +682,10 @@ __device__ __forceinline__ void initial_contact_velocity(const QnArgs& A, long l
     stencil_sum<kSlotV>(A, c, sacc);
     const ContactRec& rec = A.c_rec[c];
     ContactDyn& D = A.c_dyn[c];
-    D.vc[0][0] = rec.t1[0] * sacc[0] + rec.t1[1] * sacc[1] + rec.t1[2] * sacc[2] + D.b[0];
-    D.vc[0][1] = rec.t2[0] * sacc[0] + rec.t2[1] * sacc[1] + rec.t2[2] * sacc[2] + D.b[1];
-    D.vc[0][2] = rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2] + D.b[2];
+    // device-scope stores: other blocks read v_c^0 after the solve's first barrier
+    st_x(&D.vc[0][0], rec.t1[0] * sacc[0] + rec.t1[1] * sacc[1] + rec.t1[2] * sacc[2] + D.b[0]);
+    st_x(&D.vc[0][1], rec.t2[0] * sacc[0] + rec.t2[1] * sacc[1] + rec.t2[2] * sacc[2] + D.b[1]);
+    st_x(&D.vc[0][2], rec.n[0] * sacc[0] + rec.n[1] * sacc[1] + rec.n[2] * sacc[2] + D.b[2]);
 }
 
 // g, H -> dv by 3x3 Cholesky, and this node's share of the iteration sums.
@@ -732,11 +757,9 @@ __device__ __forceinline__ void contact_terms(const ContactRec& rec, double h, c
 
 // Impulse on the rigid bodies at the final iterate (minus the impulse on MPM),
 // reduced per body in LDS (racc: 6 doubles per body, zeroed by the caller).
-__device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, int k, double alpha_prev,
-                                                double* racc) {
+__device__ __forceinline__ void contact_impulse_at(const QnArgs& A, long long c, const double vc[3],
+                                                   double* racc) {
     ContactDyn& D = A.c_dyn[c];
-    double vc[3];
-    contact_velocity(D, k, alpha_prev, vc);
     const ContactRec& rec = A.c_rec[c];
     double g[3], g00, g01, g11, gnn;
     contact_model(params_of(rec, A.h), vc, g, &g00, &g01, &g11, &gnn);
@@ -758,6 +781,12 @@ __device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, in
         atomicAdd(&racc[r * 6 + a], -rg[a]);
         atomicAdd(&racc[r * 6 + 3 + a], -tq[a]);
     }
+}
+__device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, int k, double alpha_prev,
+                                                double* racc) {
+    double vc[3];
+    contact_velocity(A.c_dyn[c], k, alpha_prev, vc);
+    contact_impulse_at(A, c, vc, racc);
 }
 
 // Exact line search: the root of phi'(alpha) for alpha > 0 (phi is convex
@@ -923,7 +952,14 @@ static_assert(9 * kUniqMax <= 11 * kQnThreads, "contact terms live in the line-s
 static_assert(kEntMax <= kHash / 2, "the hash table is at most half full");
 static_assert(kUniqMax <= 65536, "block-local contact indices are 16-bit");
 constexpr int kEntPer = kEntMax / kQnThreads;  // entries per thread in the compact set-up
+// contacts of an environment the one-barrier form takes: each thread keeps
+// kLsPer in registers and one in LDS during the line search
+constexpr int kScatterMax = (kLsPer + 1) * kQnThreads;
+static_assert(kScatterMax == kQnScatterMax, "scratch of the one-barrier form");
+static_assert(3 * kUniqMax <= 4 * kQnThreads, "contact velocities live in the stencil cache");
+static_assert(9 * kUniqMax <= 9 * kSlotChunk, "per-contact sums live in nacc");
 
+template <bool kOne>
 __global__ void __launch_bounds__(kQnThreads)
 k_qn(QnArgs A) {
     __shared__ double rbuf[2 * 16 * kQnSums];
@@ -943,8 +979,13 @@ k_qn(QnArgs A) {
     __shared__ unsigned scan_w[17];
     __shared__ double node_v[3][kSlotChunk];  // compact pass: the iterate of the block's contact nodes,
     __shared__ double node_mv[4][kSlotChunk]; // and their mass and free-motion velocity
-    __shared__ int cst_slot[4][kQnThreads];   // contact pass of a block with at most T/8 contacts:
-    __shared__ float cst_w[4][kQnThreads];    // each lane's stencil slots and weights
+    // contact pass of a block with at most T/8 contacts: each lane's stencil
+    // slots and weights; in the one-barrier form, the contact velocities of
+    // the block's distinct contacts ([3][kUniqMax])
+    __shared__ double cst_raw[4 * kQnThreads];
+    int(*cst_slot)[kQnThreads] = reinterpret_cast<int(*)[kQnThreads]>(cst_raw);
+    float(*cst_w)[kQnThreads] = reinterpret_cast<float(*)[kQnThreads]>(cst_raw + 2 * kQnThreads);
+    double* vcl = cst_raw;
 
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
@@ -962,6 +1003,9 @@ k_qn(QnArgs A) {
         const bool timer = writer && A.timers != 0; // and, when asked, times the phases
         unsigned long long tph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         unsigned long long tmark = 0;
+        // after the one-barrier kernel, only the environments it left
+        if (!kOne && A.env_pend != nullptr && A.env_pend[env] == 0) continue;
+        if (kOne && writer) A.env_pend[env] = aborted ? 0 : 1;
         if (aborted) {
             if (writer) write_stats(A, env, 0, 0, 0, 1, 0, 0.0, 0.0, tph, true, 0);
             continue;
@@ -977,6 +1021,7 @@ k_qn(QnArgs A) {
         const unsigned G = (unsigned)std::min<long long>(
             G_launch, std::max<long long>(1, (ns + A.slots_per_block - 1) / A.slots_per_block));
         if ((unsigned)rank >= G) continue;
+        if (kOne && nc > kScatterMax) continue;
         // contact nodes split so that every block gets about the same number of
         // CSR entries (the node pass's work); contacts split evenly
         long long s0 = es0, s1 = es1;
@@ -990,6 +1035,11 @@ k_qn(QnArgs A) {
         const double pnorm_env = A.env_pnorm[env];
         double* partial = A.partial + (size_t)first * kQnSums;
         double* partial2 = A.partial2 + first;
+        // the one-barrier form alternates two buffers of block sums by iteration
+        // parity: a block may post iteration k + 1's sums before another has read
+        // iteration k's, but not iteration k + 2's (that needs the other's arrival
+        // at the next barrier)
+        double* partial_odd = A.partial_odd + (size_t)first * kQnSums;
 
         for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
 
@@ -1084,16 +1134,54 @@ k_qn(QnArgs A) {
             }
         }
 
+        // the one-barrier form needs every block of the group in the compact
+        // form: each block posts its flag before the first barrier and reads
+        // the others' after it; the first two iterations' sums start at zero
+        if (kOne) {
+            if (G > 1u && tid == 0) st_x(&partial2[rank], compact ? 1.0 : 0.0);
+            for (long long c = c0 + tid; c < c1; c += T)
+#pragma unroll
+                for (int q = 0; q < 6; ++q) st_x(&A.u_acc[(size_t)q * A.cap + c], 0.0);
+        }
+
         int k = 0, ls_total = 0, converged = 0;
         double alpha_prev = 1.0, res = 0.0, thr = 0.0;
+        // every thread's stores above (v_c^0, cleared sums, flags) acknowledged
+        // before its block arrives
+        __builtin_amdgcn_s_waitcnt(0);
         bool ok = group_sync(bar, G, &gen, &s_ok, cnt);
+        bool all_compact = compact;
+        if (kOne && ok && G > 1u) {
+            if (tid < 64) {
+                double a = 0.0;
+                for (unsigned b = tid; b < G; b += 64) a += ld_x(&partial2[b]);
+                a = wave_sum(a);
+                if (tid == 0) tot[0] = a;
+            }
+            __syncthreads();
+            all_compact = tot[0] == (double)G;
+            __syncthreads();
+        }
+        if (kOne && !all_compact) continue;  // left to k_qn<false>
+        constexpr bool scatter = kOne;
+        const bool cmp = kOne || compact;  // the compact node pass
+        double* vblk = A.vc_blk + (size_t)blockIdx.x * 6 * kScatterMax;  // [6][kScatterMax]: v_c, u_c
+        if (scatter) {
+            for (int t = tid; t < n_u; t += T) {
+                const int c = u_list[t];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vcl[a * kUniqMax + t] = ld_x(&A.c_dyn[c].vc[0][a]);
+            }
+            __syncthreads();
+        }
+        int buf = 0;  // the iteration's buffer of the per-contact sums (k mod 3)
         while (ok) {
             if (timer) tmark = wall_clock64();
             // ---- node pass: CSR entries spread over the threads, FP64 LDS sums ----
             double sums[kQnSums];
 #pragma unroll
             for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
-            if (compact) {
+            if (cmp) {
                 const int ls = tid >> lg_nl, sub = tid & (nl - 1);
                 const bool mine = ls < s1 - s0;    // a lane of contact node ls
                 const bool own = mine && sub == 0; // its first lane, which solves it
@@ -1107,7 +1195,15 @@ k_qn(QnArgs A) {
                 for (int t = tid; t < n_u; t += T) {
                     const unsigned c = (unsigned)u_list[t];
                     double vc[3], rg[3], rgr[6];
-                    contact_velocity(A.c_dyn[c], k, alpha_prev, vc);
+                    if (scatter) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            vc[a] = vcl[a * kUniqMax + t];
+                            nacc[3 + a][t] = 0.0;
+                        }
+                    } else {
+                        contact_velocity(A.c_dyn[c], k, alpha_prev, vc);
+                    }
                     contact_terms(A.c_rec[c], A.h, vc, rg, rgr);
 #pragma unroll
                     for (int a = 0; a < 3; ++a) u_term[a * kUniqMax + t] = rg[a];
@@ -1137,16 +1233,54 @@ k_qn(QnArgs A) {
                     for (int q = 0; q < 6; ++q) Hc[q] += __shfl_xor(Hc[q], m, 64);
                 }
                 if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
+                double dv[3] = {0.0, 0.0, 0.0};
                 if (own) {
-                    double dv[3];
                     node_solve(sv, j, Hc, sums, dv);
-                    SlotRec& S = A.s_rec[s0 + ls];
-                    st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
+                    if (!scatter) {
+                        SlotRec& S = A.s_rec[s0 + ls];
+                        st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
+                    }
 #pragma unroll
                     for (int a = 0; a < 3; ++a) nacc[a][ls] = dv[a];  // kept for the update
                 }
+                if (scatter) {
+                    // U_c += w dv over the node's entries: the node's lanes take
+                    // its dv from its first lane and add their entries into the
+                    // block's per-contact sums, which then go to the buffer of
+                    // this iteration; the next iteration's buffer is cleared for
+                    // the block's contacts
+                    const int src = (tid & 63) & ~(nl - 1);
+                    double d[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) d[a] = __shfl(dv[a], src, 64);
+                    if (mine) {
+                        const int e1 = beg_l[ls + 1];
+                        for (int e = beg_l[ls] + sub; e < e1; e += nl) {
+                            const int lc = ent_c[e];
+                            const double w = (double)ent_w[e];
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) atomicAdd(&nacc[3 + a][lc], w * d[a]);
+                        }
+                    }
+                    __syncthreads();
+                    double* U = A.u_acc + (size_t)buf * 3 * A.cap;
+                    for (int t = tid; t < n_u; t += T) {
+                        const long long c = u_list[t];
+                        const double Uw[3] = {nacc[3][t], nacc[4][t], nacc[5][t]};
+                        double uu[3];
+                        frame_project(A.c_rec[c], Uw, uu);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            __hip_atomic_fetch_add(&U[(size_t)a * A.cap + c], uu[a], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    double* Un = A.u_acc + (size_t)(buf == 2 ? 0 : buf + 1) * 3 * A.cap;
+                    for (long long c = c0 + tid; c < c1; c += T)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) st_x(&Un[(size_t)a * A.cap + c], 0.0);
+                }
             }
-            for (long long sa = s0; sa < s1 && !compact; sa += kSlotChunk) {
+            for (long long sa = s0; sa < s1 && !cmp; sa += kSlotChunk) {
                 const long long sb = std::min<long long>(s1, sa + kSlotChunk);
                 // this thread's contact node of the chunk, loaded before the gather
                 const bool own = tid < sb - sa;
@@ -1198,10 +1332,11 @@ k_qn(QnArgs A) {
                 }
                 __syncthreads();
             }
+            double* part = (kOne && (k & 1)) ? partial_odd : partial;
             block_allsum<kQnSums>(sums, rbuf, rpar);
             if (G > 1u && tid == 0) {
 #pragma unroll
-                for (int q = 0; q < kQnSums; ++q) st_x(&partial[(size_t)rank * kQnSums + q], sums[q]);
+                for (int q = 0; q < kQnSums; ++q) st_x(&part[(size_t)rank * kQnSums + q], sums[q]);
             }
             if (timer) { const unsigned long long t = wall_clock64(); tph[1] += t - tmark; tmark = t; }
             ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
@@ -1214,13 +1349,54 @@ k_qn(QnArgs A) {
             const int wv = tid >> 6, lane = tid & 63;
             double ga = 0.0;
             if (G > 1u && wv < kQnSums) {
-                for (unsigned b = lane; b < G; b += 64) ga += ld_x(&partial[(size_t)b * kQnSums + wv]);
+                for (unsigned b = lane; b < G; b += 64) ga += ld_x(&part[(size_t)b * kQnSums + wv]);
             }
+            double curv[1] = {0.0};
+            LsCoef lc[kLsPer];
+            const long long c_lds = ec0 + tid + (long long)kLsPer * T;
+            const bool use_lds = (long long)kLsPer * T < nc;
+            if (scatter) {
+                // ---- line-search set-up in every block, over all the environment's
+                // contacts (contact ec0 + i taken by thread i mod T): v_c^k from the
+                // thread's own v_c^{k-1}, u_c^{k-1} (or the initial gather), u_c^k
+                // from the sums, the closed-form coefficients, and phi''(0)
+                const double* U = A.u_acc + (size_t)buf * 3 * A.cap;
+#pragma unroll
+                for (int u = 0; u <= kLsPer; ++u) {
+                    const long long c = ec0 + tid + (long long)u * T;
+                    LsCoef L = ls_coef_zero();
+                    if (c < ec1) {
+                        double* vb = vblk + (c - ec0);
+                        double vc[3], uu[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) uu[a] = ld_x(&U[(size_t)a * A.cap + c]);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            vc[a] = k == 0 ? ld_x(&A.c_dyn[c].vc[0][a])
+                                           : fma(alpha_prev, vb[(3 + a) * kScatterMax], vb[a * kScatterMax]);
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            vb[a * kScatterMax] = vc[a];
+                            vb[(3 + a) * kScatterMax] = uu[a];
+                        }
+                        L = ls_coef(params_of(A.c_rec[c], A.h), vc, uu);
+                        double d1, d2;
+                        ls_eval(L, 0.0, &d1, &d2);
+                        curv[0] += d2;
+                    }
+                    if (u < kLsPer) lc[u] = L;
+                    else if (use_lds) ls_ovf[tid] = L;
+                }
+                // u_c^k of the block's distinct contacts, for their velocities' update
+                for (int t = tid; t < n_u; t += T) {
+                    const long long c = u_list[t];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) nacc[6 + a][t] = ld_x(&U[(size_t)a * A.cap + c]);
+                }
+            } else {
             // ---- contact pass: store v_c^k, u_c = R_c^T J dv, and u_c^T G(v_c^k) u_c
             // (this block's share of phi''(0)). Eight lanes gather one contact's
             // 27 stencil nodes and combine their sums by shuffles.
-            double curv[1] = {0.0};
-            {
                 const int part = tid & 7;
                 for (long long cb = c0; cb < c1; cb += T / 8) {
                     const long long c = cb + (tid >> 3);
@@ -1297,31 +1473,31 @@ k_qn(QnArgs A) {
             const double Aq = sums[4], Bq = sums[5], d0 = sums[6];
             if (res < thr) { converged = 1; break; }
             if (k >= A.max_iter || !(d0 < 0.0)) break;
-            if (G > 1u && tid == 0) st_x(&partial2[rank], curv[0]);
             if (timer) { const unsigned long long t = wall_clock64(); tph[3] += t - tmark; tmark = t; }
-            ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
-            if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
-            if (!ok) break;
             // ---- exact line search, redundantly in every block of the group -------
             // Contact ec0 + i is taken by thread i mod T. The closed-form
             // coefficients of the first kLsPer*T contacts stay in registers for
             // all the evaluations, the next T in LDS, and any beyond are formed
             // from memory at each evaluation.
-            // the coefficients the contact pass stored (coalesced loads)
             auto coef_of = [&](long long c) -> LsCoef { return load_coef(A.c_coef, c); };
-            LsCoef lc[kLsPer];
+            if (!scatter) {
+                if (G > 1u && tid == 0) st_x(&partial2[rank], curv[0]);
+                ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
+                if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
+                if (!ok) break;
+                // the coefficients the contact pass stored (coalesced loads)
 #pragma unroll
-            for (int u = 0; u < kLsPer; ++u) {
-                const long long c = ec0 + tid + (long long)u * T;
-                lc[u] = c < ec1 ? coef_of(c) : ls_coef_zero();
+                for (int u = 0; u < kLsPer; ++u) {
+                    const long long c = ec0 + tid + (long long)u * T;
+                    lc[u] = c < ec1 ? coef_of(c) : ls_coef_zero();
+                }
+                if (use_lds) ls_ovf[tid] = c_lds < ec1 ? coef_of(c_lds) : ls_coef_zero();
             }
-            const long long c_lds = ec0 + tid + (long long)kLsPer * T;
-            const bool use_lds = (long long)kLsPer * T < nc;
-            if (use_lds) ls_ovf[tid] = c_lds < ec1 ? coef_of(c_lds) : ls_coef_zero();
-            // phi''(0) - A summed over the group (wave 0), then the first trial step:
-            // the Newton step of phi' from alpha = 0
+            // phi''(0) - A summed over the group (wave 0; the one-barrier form
+            // summed every contact in the block already), then the first trial
+            // step: the Newton step of phi' from alpha = 0
             double curv0 = curv[0];
-            if (G > 1u) {
+            if (G > 1u && !scatter) {
                 if (tid < 64) {
                     double a = 0.0;
                     for (unsigned b = tid; b < G; b += 64) a += ld_x(&partial2[b]);
@@ -1359,10 +1535,19 @@ k_qn(QnArgs A) {
             };
             const double alpha = exact_line_search(eval, alpha0, d0, A.ls_max_steps, &ls_total);
             if (timer) { const unsigned long long t = wall_clock64(); tph[6] += t - tmark; tmark = t; }
-            if (compact) {
-                if (tid < s1 - s0) {
+            if (cmp) {
+                // by the node's first lane, which formed its dv and reads its
+                // iterate at the start of the next node pass (no barrier between)
+                const int ls = tid >> lg_nl;
+                if ((tid & (nl - 1)) == 0 && ls < s1 - s0) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) node_v[a][tid] = fma(alpha, nacc[a][tid], node_v[a][tid]);
+                    for (int a = 0; a < 3; ++a) node_v[a][ls] = fma(alpha, nacc[a][ls], node_v[a][ls]);
+                }
+                if (scatter) {
+                    for (int t = tid; t < n_u; t += T)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            vcl[a * kUniqMax + t] = fma(alpha, nacc[6 + a][t], vcl[a * kUniqMax + t]);
                 }
             } else {
                 for (long long s = s0 + tid; s < s1; s += T) {
@@ -1374,9 +1559,10 @@ k_qn(QnArgs A) {
             if (timer) { const unsigned long long t = wall_clock64(); tph[7] += t - tmark; tmark = t; }
             alpha_prev = alpha;
             ++k;
+            buf = buf == 2 ? 0 : buf + 1;
         }
         // ---- outputs ----------------------------------------------------------------
-        if (compact && tid < s1 - s0) {
+        if (cmp && tid < s1 - s0) {
 #pragma unroll
             for (int a = 0; a < 3; ++a) A.s_rec[s0 + tid].v[a] = node_v[a][tid];
         }
@@ -1388,11 +1574,24 @@ k_qn(QnArgs A) {
         }
         for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
         __syncthreads();
-        for (long long c = c0 + tid; c < c1; c += T) contact_impulse(A, c, k, alpha_prev, racc);
+        if (scatter) {
+            // v_c at the final iterate: the set-up of the last iteration stored it
+            // for the thread's line-search contacts; each block takes its own
+            for (int u = 0; u <= kLsPer; ++u) {
+                const long long c = ec0 + tid + (long long)u * T;
+                if (c < c0 || c >= c1) continue;
+                const double* vb = vblk + (c - ec0);
+                const double vc[3] = {vb[0], vb[kScatterMax], vb[2 * kScatterMax]};
+                contact_impulse_at(A, c, vc, racc);
+            }
+        } else {
+            for (long long c = c0 + tid; c < c1; c += T) contact_impulse(A, c, k, alpha_prev, racc);
+        }
         __syncthreads();
         for (int q = tid; q < A.n_rigid * 6; q += T)
             if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
         if (writer) write_stats(A, env, nc, ns, k, converged, ls_total, res, thr, tph, false, (int)G);
+        if (kOne && writer) A.env_pend[env] = 0;
         __syncthreads();  // racc and the block sums are reused by the next environment
         if (!ok) break;
     }
@@ -1410,12 +1609,15 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.c_pid = w.c_pid; A.c_rid = w.c_rid;
     A.c_rec = w.c_rec; A.c_st = w.c_st; A.c_dyn = w.c_dyn; A.c_coef = w.c_coef;
     A.compact = w.qn_compact;
+    A.u_acc = w.qn_uacc;
+    A.vc_blk = w.qn_vcblk;
     A.timers = timers;
     A.slots_per_block = std::max(1, slots_per_block);
     A.s_node = w.s_node; A.s_beg = w.s_beg;
     A.e_ent = w.e_ent;
     A.s_rec = w.s_rec;
     A.partial = w.partial;
+    A.partial_odd = w.partial_odd;
     A.partial2 = w.partial2;
     A.rigid_acc = w.rigid_acc;
     A.n_rigid = w.n_rigid;
@@ -1433,14 +1635,26 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.env_stride = env_stride;
     A.cnt = w.cnt;
     void* args[] = {&A};
-    return hipLaunchCooperativeKernel((const void*)k_qn, dim3(blocks), dim3(kQnThreads), args, 0, s);
+    if (w.qn_scatter) {
+        // the one-barrier kernel, then the two-barrier kernel for what it left
+        A.env_pend = w.qn_pend;
+        const hipError_t e =
+            hipLaunchCooperativeKernel((const void*)k_qn<true>, dim3(blocks), dim3(kQnThreads), args, 0, s);
+        if (e != hipSuccess) return e;
+    } else {
+        A.env_pend = nullptr;
+    }
+    return hipLaunchCooperativeKernel((const void*)k_qn<false>, dim3(blocks), dim3(kQnThreads), args, 0, s);
 }
 
 // Blocks of k_qn that can be resident at once (the cooperative launch limit).
 int qn_max_blocks() {
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_qn, kQnThreads, 0) != hipSuccess)
+    int per_cu1 = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_qn<false>, kQnThreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, (const void*)k_qn<true>, kQnThreads, 0) != hipSuccess)
         return 0;
+    per_cu = std::min(per_cu, per_cu1);
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;

@@ -114,6 +114,8 @@ constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps e
 // adjoints per rigid body and recorded host step: V, t, w (through the
 // velocity field), a small rotation of the pose about t
 constexpr int kRigidGradStride = 12;
+// contacts of one environment the solver's one-barrier form takes
+constexpr int kQnScatterMax = 2048;
 
 // Pointers into the caller's workspace.
 struct Work {
@@ -152,6 +154,7 @@ struct Work {
     // scratch
     unsigned* blk;           // [kSortBlocks * 256 + 2 * kSortBlocks] histograms / block sums
     double* partial;         // [solver blocks][kQnSums]
+    double* partial_odd;     // [solver blocks][kQnSums] odd iterations of the one-barrier form
     double* partial2;        // [solver blocks]
     double* rigid_acc;       // [n_rigid][6] FP64 impulse accumulators
     SubstepStats* sstats;    // [N][n_envs]
@@ -190,6 +193,10 @@ struct Work {
     long long cap_c, cap_s;
     int qn_blocks;           // co-resident solver blocks (capacity of partial and qn_map)
     int qn_compact;          // 1: blocks that fit take the compact node pass (0 only to test the other)
+    int qn_scatter;          // 1: environments that fit take the solver's one-barrier form
+    double* qn_uacc;         // [3][3][cap_c] per-contact sums of the one-barrier form
+    double* qn_vcblk;        // [kMaxQnBlocks][6][kQnScatterMax] per-block contact velocities
+    int* qn_pend;            // [n_envs] environments the one-barrier solver kernel left to the other
 };
 
 // One recorded substep of the differentiation tape.
