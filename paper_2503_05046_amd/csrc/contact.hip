@@ -30,9 +30,10 @@
 //               block obtains the same step length.
 // Contact velocities are carried as v_c + alpha u_c (the contact velocity is
 // linear in the grid velocity), double-buffered by iteration parity.
-// One-barrier form (k_qn<true>, launched first: it solves the environments
-// whose blocks all hold their contact nodes in the compact form and that have
-// at most kScatterMax contacts, and marks the others for k_qn<false>): the
+// One-barrier form (k_qn<true>, for a handle of one environment, launched
+// first: it solves the environment when its blocks all hold their contact
+// nodes in the compact form and it has at most kScatterMax contacts, and
+// otherwise leaves it to k_qn<false>): the
 // node pass also forms u_c = R_c^T sum w dv over its entries (a block sum in
 // LDS, projected, then one device-scope FP64 atomic add per distinct contact
 // and component, into one of three buffers by iteration), so after the
@@ -1635,8 +1636,11 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.env_stride = env_stride;
     A.cnt = w.cnt;
     void* args[] = {&A};
-    if (w.qn_scatter) {
-        // the one-barrier kernel, then the two-barrier kernel for what it left
+    if (w.qn_scatter && w.n_envs == 1) {
+        // the one-barrier kernel, then the two-barrier kernel for what it left.
+        // With several environments the second launch would start only after
+        // the first kernel's slowest environment, so the batched form keeps the
+        // two-barrier kernel for all of them.
         A.env_pend = w.qn_pend;
         const hipError_t e =
             hipLaunchCooperativeKernel((const void*)k_qn<true>, dim3(blocks), dim3(kQnThreads), args, 0, s);

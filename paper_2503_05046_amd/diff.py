@@ -84,7 +84,7 @@ def _left_jacobian(phi) -> np.ndarray:
     return np.eye(3) + a * P + b * (P @ P)
 
 
-def _run(sim, path, n_steps, step0, x, v, F, C, V, W, record: bool) -> None:
+def _run(sim, path, n_steps, step0, x, v, F, C, V, W=None, record: bool = False) -> None:
     sim.load_state(x, v, F, C)
     sim.tape_reset(record)
     Vn = V.detach().cpu().numpy().astype(np.float64).reshape(-1, 3)
@@ -105,7 +105,7 @@ def _make_function():
             ctx.sim, ctx.path, ctx.n_steps, ctx.step0 = sim, path, n_steps, step0
             ctx.has_w = W is not None
             ctx.save_for_backward(x, v, F, C, E, V, W if W is not None else V)
-            _run(sim, path, n_steps, step0, x, v, F, C, V, W, record=False)
+            _run(sim, path, n_steps, step0, x, v, F, C, V, W=W, record=False)
             return sim.state_tensors()
 
         @staticmethod
@@ -114,7 +114,7 @@ def _make_function():
             if not ctx.has_w:
                 W = None
             sim = ctx.sim
-            _run(sim, ctx.path, ctx.n_steps, ctx.step0, x, v, F, C, V, W, record=True)
+            _run(sim, ctx.path, ctx.n_steps, ctx.step0, x, v, F, C, V, W=W, record=True)
             pid = sim.pid.long()
             g = []
             for gt, ref in ((gx, x), (gv, v), (gF, F), (gC, C)):

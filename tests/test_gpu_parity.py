@@ -29,10 +29,10 @@ def _log(msg):
     sys.stdout.flush()
 
 
-def _run_both(mpm, oracle, scene, host_steps=1, basis=0):
+def _run_both(mpm, oracle, scene, host_steps=1, basis=0, **sim_kw):
     """Step the scene on the GPU and in the oracle; returns (gpu state, oracle
     sim, gpu impulses, oracle impulses, gpu stats, oracle stats)."""
-    sim = mpm.Sim(scene)
+    sim = mpm.Sim(scene, **sim_kw)
     ora = oracle.OracleSim(scene, basis=basis)
     imp_g = np.zeros((len(scene.rigids), 6))
     imp_o = np.zeros((len(scene.rigids), 6))
@@ -141,6 +141,25 @@ def test_contact_substep_general_node_pass(mpm, oracle, monkeypatch):
     s.max_iter = 400000
     _log("plain cube contact substep, general node pass, eps_r = 1e-10")
     g, o, ig, io, sg, so = _run_both(mpm, oracle, s)
+    e = field_errors(g, o, s.envs[0].dx)
+    assert max(e.values()) < 1e-5, (e, sg[0], so[0])
+    m_tot = s.envs[0].m_p * s.P
+    assert impulse_error(ig, io, m_tot, s.h) < 1e-4
+
+
+@pytest.mark.parametrize("spb", [16, 128])
+def test_contact_substep_two_barrier_form(mpm, oracle, monkeypatch, spb):
+    """The solver's two-barrier form (a contact pass gathers u_c between two
+    group barriers), which environments with more contacts than the
+    one-barrier form holds take: forced for every environment, with small and
+    default block groups, at a tight tolerance."""
+    monkeypatch.setenv("MPM_SOLVER_SCATTER", "0")
+    s = _contact_state(oracle, 22)
+    s.N = 1
+    s.eps_r = 1e-10
+    s.max_iter = 400000
+    _log(f"plain cube contact substep, two-barrier form, {spb} contact nodes per block, eps_r = 1e-10")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s, solver_slots_per_block=spb)
     e = field_errors(g, o, s.envs[0].dx)
     assert max(e.values()) < 1e-5, (e, sg[0], so[0])
     m_tot = s.envs[0].m_p * s.P
