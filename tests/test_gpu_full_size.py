@@ -1,6 +1,7 @@
-"""The HIP path at the benchmark's full size (granular pour: 1M Drucker-Prager
-particles, 128^3 grid, four boxes), in the launch configuration bench.py
-times, checked where the FP64 oracle can follow it.
+"""The HIP path at full size, checked where the FP64 oracle can follow it:
+the benchmark (granular pour: 1M Drucker-Prager particles, 128^3 grid, four
+boxes) in the launch configuration bench.py times, and the gripper (250k
+elastic particles, 96^3 grid, two closing jaws).
 
 * Free motion, sampled: one substep of the full scene before contact; the
   oracle runs that substep on a column of the same particles padded by four
@@ -108,3 +109,82 @@ def test_full_size_momentum_balance_in_contact(mpm):
         checked += 1
     sim.close()
     assert checked == 2
+
+
+def _gripper_in_contact():
+    """The gripper (250k elastic particles in an ellipsoid, 96^3 grid, two
+    kinematic jaws closing at 0.05 m/s) with the jaws started 4 mm inside the
+    ellipsoid's tips, so that the squeeze has contacts from the first substep
+    (the jaws would otherwise need thousands of host steps to reach it)."""
+    scene = I.gripper()
+    scene.max_iter = 200_000
+    for i, r in enumerate(scene.rigids):
+        t = np.array(r.t)
+        t[0] -= np.sign(t[0] - 0.5) * 0.004
+        scene.rigids[i] = type(r)(**{**r.__dict__, "t": tuple(t)})
+    return scene
+
+
+def test_gripper_full_size_slab(mpm, oracle):
+    """One substep of the full gripper in contact; a slab x in [0.45, 0.55],
+    far from the jaws (contact nodes lie near x = 0.25 and 0.75), against the
+    oracle run on the slab padded by four cells."""
+    scene = _gripper_in_contact()
+    scene.N = 1
+    dx = scene.envs[0].dx
+    x0 = scene.x.copy()
+    sim = mpm.Sim(scene)
+    status, imp, st = sim.step()
+    assert status == 0 and st["max_contacts"] > 0
+    out = sim.state()
+    sim.close()
+    a, b, pad = 0.45, 0.55, 4 * dx
+    inner = (x0[0] > a) & (x0[0] < b)
+    sel = np.nonzero((x0[0] > a - pad) & (x0[0] < b + pad))[0]
+    sub = scene.copy()
+    sub.x, sub.v, sub.F, sub.C = (np.ascontiguousarray(getattr(scene, k)[:, sel]) for k in ("x", "v", "F", "C"))
+    sub.envs[0].p_begin, sub.envs[0].p_end = 0, len(sel)
+    sub.rigids = []
+    _log(f"gripper: {st['max_contacts']} contacts; oracle on a {len(sel)}-particle slab, {int(inner.sum())} compared")
+    ora = oracle.OracleSim(sub)
+    rc, _, _ = ora.host_step()
+    assert rc == 0
+    keep = inner[sel]
+    g = {k: out[k][:, sel][:, keep] for k in ("x", "v", "F", "C")}
+
+    class _Ref:
+        pass
+
+    ref = _Ref()
+    ref.x, ref.v, ref.F, ref.C = (getattr(ora, k)[:, keep] for k in ("x", "v", "F", "C"))
+    err = field_errors(g, ref, dx)
+    _log(f"gripper, slab interior: {err}")
+    assert max(err.values()) < 1e-5, err
+
+
+def test_gripper_full_size_momentum_balance(mpm):
+    """Two host steps of the full gripper in contact: the change of
+    sum_p m_p v_p is M g N h minus the impulses on the jaws, within the
+    stopping test's bound (as for the granular pour)."""
+    scene = _gripper_in_contact()
+    env = scene.envs[0]
+    m_p = env.m_p
+    M = m_p * scene.P
+    g = np.array(env.gravity, np.float64)
+    sim = mpm.Sim(scene)
+    for step in range(2):
+        v0 = sim.state()["v"].astype(np.float64)
+        status, imp, st = sim.step()
+        assert status == 0
+        v1 = sim.state()["v"].astype(np.float64)
+        assert max(st["contacts"]) > 0
+        assert all(r < t for r, t in zip(st["residual"], st["threshold"]) if t > 0)
+        dP = m_p * (v1.sum(axis=1) - v0.sum(axis=1))
+        expected = M * g * scene.N * scene.h - imp[:, :3].sum(axis=0)
+        tol = (np.sqrt(M) * sum(st["residual"]) +
+               2e-7 * m_p * (np.abs(v0).sum() + np.abs(v1).sum()))
+        mis = float(np.abs(dP - expected).max())
+        _log(f"gripper, host step {step}: dP {dP}, M g N h - sum impulses {expected}, "
+             f"mismatch {mis:.3e}, bound {tol:.3e}, contacts {max(st['contacts'])}")
+        assert mis <= tol, (dP, expected, tol)
+    sim.close()
