@@ -54,7 +54,7 @@ typedef enum {
 
 enum { MPM_FIXED_COROTATED = 0, MPM_DRUCKER_PRAGER = 1 };
 enum { MPM_HALF_SPACE = 0, MPM_BOX = 1 };
-enum { MPM_STATIC = 0, MPM_KINEMATIC = 1 };
+enum { MPM_STATIC = 0, MPM_KINEMATIC = 1, MPM_DYNAMIC = 2 };
 
 /* Step flags (mpm_step_stats.flags) */
 enum {
@@ -122,11 +122,24 @@ typedef struct {
     double offset;             /* half-space: sdf(p) = normal . p - offset */
     double half[3];            /* box: half extents, each > 0 */
     double mu;                 /* Coulomb friction coefficient, >= 0 */
-    int32_t motion;            /* MPM_STATIC or MPM_KINEMATIC */
+    int32_t motion;            /* MPM_STATIC, MPM_KINEMATIC or MPM_DYNAMIC */
     double R[9];               /* body-to-world rotation, row-major */
     double t[3];               /* body origin in world */
     double V[3];               /* linear velocity of the body origin */
     double w[3];               /* angular velocity (world) */
+    /* MPM_DYNAMIC (boxes only; the body origin is the centre of mass). After
+     * each host step (the pose frozen during it, Sec. V-B) the library
+     * integrates the free body on the host, in FP64, from the impulse and
+     * moment the MPM side exerted on it over the step (Eq. (3) with the body's
+     * mass matrix and Coriolis term, semi-implicit):
+     *   m (V' - V) = I_lin + N h (m g + force),
+     *   I_w (w' - w) = I_ang + N h (torque - w x I_w w),  I_w = R diag(inertia) R^T,
+     * then t' = t + N h V' and R' = Rot(N h w') R. g is the environment's
+     * gravity. Ignored for other motions. */
+    double mass;               /* > 0 */
+    double inertia[3];         /* principal moments about the body axes, each > 0 */
+    double force[3];           /* constant external force (world), besides gravity */
+    double torque[3];          /* constant external torque about the body origin (world) */
 } mpm_rigid_desc;
 
 /* Pose and twist of one rigid body, frozen for a host step. */
@@ -204,8 +217,9 @@ mpm_status mpm_add_rigid_sdf(mpm_handle* h, int32_t env, const mpm_rigid_desc* r
 
 /* Advance one host step of N substeps in place. in: host array of the frozen
  * pose and twist of every rigid body for this step, or NULL to use the
- * library's own state (kinematic bodies advanced with their twist after each
- * step). out: host array, one entry per rigid body (may be NULL). st may be
+ * library's own state (after each step, kinematic bodies advance with their
+ * twist, and dynamic bodies are integrated from the step's impulses, see
+ * mpm_rigid_desc; with in given, dynamic bodies start from it). out: host array, one entry per rigid body (may be NULL). st may be
  * NULL. Synchronises the handle's stream once, to read impulses and stats.
  * Returns MPM_OK, a warning (MPM_ENOCONV), or an error (MPM_EDOMAIN, MPM_ENAN,
  * MPM_ENOMEM when the contact capacity overflowed: the step stops at that

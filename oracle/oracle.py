@@ -45,7 +45,8 @@ class Rigid(ct.Structure):
     _fields_ = [("shape", ct.c_int), ("normal", ct.c_double * 3), ("offset", ct.c_double),
                 ("half", ct.c_double * 3), ("mu", ct.c_double), ("motion", ct.c_int),
                 ("R", ct.c_double * 9), ("t", ct.c_double * 3), ("V", ct.c_double * 3),
-                ("w", ct.c_double * 3)]
+                ("w", ct.c_double * 3), ("mass", ct.c_double), ("inertia", ct.c_double * 3),
+                ("force", ct.c_double * 3), ("torque", ct.c_double * 3)]
 
 
 class Stats(ct.Structure):
@@ -143,6 +144,10 @@ def make_rigids(scene, e: int = 0):
         a.t[:] = list(r.t)
         a.V[:] = list(r.V)
         a.w[:] = list(r.w)
+        a.mass = getattr(r, "mass", 0.0)
+        a.inertia[:] = list(getattr(r, "inertia", (0.0, 0.0, 0.0)))
+        a.force[:] = list(getattr(r, "force", (0.0, 0.0, 0.0)))
+        a.torque[:] = list(getattr(r, "torque", (0.0, 0.0, 0.0)))
     return arr, len(rs)
 
 

@@ -912,17 +912,51 @@ int oracle_substep(const oracle_env* env, const oracle_rigid* rigid, int n_rigid
     return qs;
 }
 
+void oracle_integrate_dynamic(oracle_rigid* r, const double imp[6], const double g[3], double dt) {
+    for (int a = 0; a < 3; ++a) r->V[a] += imp[a] / r->mass + dt * (g[a] + r->force[a] / r->mass);
+    /* world inertia I_w = R diag(I) R^T and its inverse R diag(1/I) R^T */
+    double Iw[9], Iinv[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double s1 = 0.0, s2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                s1 += r->R[i * 3 + k] * r->inertia[k] * r->R[j * 3 + k];
+                s2 += r->R[i * 3 + k] / r->inertia[k] * r->R[j * 3 + k];
+            }
+            Iw[i * 3 + j] = s1;
+            Iinv[i * 3 + j] = s2;
+        }
+    double Lw[3], rhs[3];
+    for (int i = 0; i < 3; ++i) Lw[i] = Iw[i * 3 + 0] * r->w[0] + Iw[i * 3 + 1] * r->w[1] + Iw[i * 3 + 2] * r->w[2];
+    const double gyro[3] = {r->w[1] * Lw[2] - r->w[2] * Lw[1], r->w[2] * Lw[0] - r->w[0] * Lw[2],
+                            r->w[0] * Lw[1] - r->w[1] * Lw[0]};
+    for (int a = 0; a < 3; ++a) rhs[a] = imp[3 + a] + dt * (r->torque[a] - gyro[a]);
+    for (int i = 0; i < 3; ++i)
+        r->w[i] += Iinv[i * 3 + 0] * rhs[0] + Iinv[i * 3 + 1] * rhs[1] + Iinv[i * 3 + 2] * rhs[2];
+    oracle_advance_pose(r, dt);
+}
+
 int oracle_host_step(const oracle_env* env, oracle_rigid* rigid, int n_rigid, int P, double* x,
                      double* v, double* F, double* C, double* impulse, oracle_substep_stats* st) {
-    if (impulse) memset(impulse, 0, sizeof(double) * 6 * (size_t)n_rigid);
+    double* imp = impulse ? impulse : (double*)calloc(6 * (size_t)(n_rigid > 0 ? n_rigid : 1), sizeof(double));
+    if (!imp) return OR_EINVAL;
+    memset(imp, 0, sizeof(double) * 6 * (size_t)n_rigid);
     int worst = OR_OK;
     for (int k = 0; k < env->N; ++k) {
-        int rc = oracle_substep(env, rigid, n_rigid, P, x, v, F, C, impulse, st ? &st[k] : NULL, NULL);
+        int rc = oracle_substep(env, rigid, n_rigid, P, x, v, F, C, imp, st ? &st[k] : NULL, NULL);
         if (rc == OR_NOCONV) worst = OR_NOCONV;
-        else if (rc != OR_OK) return rc;
+        else if (rc != OR_OK) {
+            if (!impulse) free(imp);
+            return rc;
+        }
     }
-    for (int r = 0; r < n_rigid; ++r)
+    /* the rigid side of the split, with the pose frozen until here */
+    for (int r = 0; r < n_rigid; ++r) {
         if (rigid[r].motion == OR_KINEMATIC) oracle_advance_pose(&rigid[r], env->N * env->h);
+        else if (rigid[r].motion == OR_DYNAMIC)
+            oracle_integrate_dynamic(&rigid[r], imp + 6 * r, env->gravity, env->N * env->h);
+    }
+    if (!impulse) free(imp);
     return worst;
 }
 

@@ -36,7 +36,7 @@ extern "C" {
 enum { OR_OK = 0, OR_NOCONV = 1, OR_DOMAIN = 2, OR_NAN = 3, OR_EINVAL = 4 };
 enum { OR_FIXED_COROTATED = 0, OR_DRUCKER_PRAGER = 1 };
 enum { OR_HALF_SPACE = 0, OR_BOX = 1 };
-enum { OR_STATIC = 0, OR_KINEMATIC = 1 };
+enum { OR_STATIC = 0, OR_KINEMATIC = 1, OR_DYNAMIC = 2 };
 
 typedef struct {
     int nx, ny, nz;            /* grid nodes per axis */
@@ -63,11 +63,16 @@ typedef struct {
     double offset;             /* half-space: sdf = n.(p) - offset, p in body frame */
     double half[3];            /* box: half extents, body frame */
     double mu;                 /* Coulomb friction coefficient */
-    int motion;                /* OR_STATIC or OR_KINEMATIC */
+    int motion;                /* OR_STATIC, OR_KINEMATIC or OR_DYNAMIC */
     double R[9];               /* body-to-world rotation, row-major */
     double t[3];               /* body origin in world */
     double V[3];               /* linear velocity of the body origin */
     double w[3];               /* angular velocity */
+    /* OR_DYNAMIC (a box whose body origin is its centre of mass): */
+    double mass;               /* > 0 */
+    double inertia[3];         /* principal moments about the body axes, > 0 */
+    double force[3];           /* constant external force (world), besides gravity */
+    double torque[3];          /* constant external torque about the origin (world) */
 } oracle_rigid;
 
 typedef struct {
@@ -166,6 +171,15 @@ int oracle_contact_problem(const oracle_env* env, const oracle_rigid* rigid, int
 
 /* Advance a kinematic pose by dt with the frozen twist (Rodrigues). */
 void oracle_advance_pose(oracle_rigid* r, double dt);
+
+/* The rigid side of the split for a free body (Eq. (3) with the body's mass
+ * matrix and Coriolis term), one host step of length dt, semi-implicit:
+ *   m (V' - V) = I_lin + dt (m g + f),
+ *   I_w (w' - w) = I_ang + dt (tau - w x I_w w),   I_w = R diag(inertia) R^T,
+ * with (I_lin, I_ang) = imp, the impulse and its moment about the origin that
+ * the MPM side exerted on the body over the step; then the pose advances with
+ * the new twist (oracle_advance_pose). */
+void oracle_integrate_dynamic(oracle_rigid* r, const double imp[6], const double g[3], double dt);
 
 #ifdef __cplusplus
 }

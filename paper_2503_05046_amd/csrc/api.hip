@@ -251,6 +251,36 @@ void left_jacobian_transposed(const double phi[3], const double v[3], double o[3
     for (int q = 0; q < 3; ++q) o[q] = v[q] - a * pv[q] + b * ppv[q];
 }
 
+// A free body over one host step of length dt (the rigid side of the split,
+// Eq. (3) with the body's mass matrix and Coriolis term, semi-implicit): the
+// impulse imp[0..2] and its moment imp[3..5] about the body origin, which the
+// MPM side exerted on the body during the step, plus gravity and the constant
+// external wrench over dt, give the new twist,
+//   V' = V + imp/m + dt (g + f/m),   w' = w + I_w^-1 (imp_ang + dt (tau - w x I_w w)),
+// with I_w = R diag(I) R^T; the pose then advances with it (in the caller).
+void integrate_free_body(mpm_rigid_desc& d, const double imp[6], const float g[3], double dt) {
+    for (int a = 0; a < 3; ++a) d.V[a] = d.V[a] + imp[a] / d.mass + dt * ((double)g[a] + d.force[a] / d.mass);
+    double Iw[9], Ii[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            double a = 0.0, b = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                a += d.R[i * 3 + k] * d.inertia[k] * d.R[j * 3 + k];
+                b += d.R[i * 3 + k] * d.R[j * 3 + k] / d.inertia[k];
+            }
+            Iw[i * 3 + j] = a;
+            Ii[i * 3 + j] = b;
+        }
+    double L[3];
+    for (int i = 0; i < 3; ++i) L[i] = Iw[i * 3] * d.w[0] + Iw[i * 3 + 1] * d.w[1] + Iw[i * 3 + 2] * d.w[2];
+    const double wxL[3] = {d.w[1] * L[2] - d.w[2] * L[1], d.w[2] * L[0] - d.w[0] * L[2], d.w[0] * L[1] - d.w[1] * L[0]};
+    double m[3];
+    for (int a = 0; a < 3; ++a) m[a] = imp[3 + a] + dt * (d.torque[a] - wxL[a]);
+    double dw[3];
+    for (int i = 0; i < 3; ++i) dw[i] = Ii[i * 3] * m[0] + Ii[i * 3 + 1] * m[1] + Ii[i * 3 + 2] * m[2];
+    for (int a = 0; a < 3; ++a) d.w[a] += dw[a];
+}
+
 // The kinematic advance of the rigid table on the device (graph path): the
 // same rule as the host's; static bodies carry a zero twist.
 __global__ void k_advance_kinematic(DevRigid* r, int n, double dt) {
@@ -752,7 +782,18 @@ mpm_status mpm_add_rigid_sdf(mpm_handle* h, int32_t env, const mpm_rigid_desc* r
     for (const HostRigid& q : h->rigids) in_env += q.env == env;
     if (in_env >= kMaxRigidPerEnv) return fail(MPM_EINVAL, "at most %d rigid bodies per environment", kMaxRigidPerEnv);
     if (r->shape != MPM_HALF_SPACE && r->shape != MPM_BOX) return fail(MPM_EINVAL, "unknown shape");
-    if (r->motion != MPM_STATIC && r->motion != MPM_KINEMATIC) return fail(MPM_EINVAL, "unknown motion");
+    if (r->motion != MPM_STATIC && r->motion != MPM_KINEMATIC && r->motion != MPM_DYNAMIC)
+        return fail(MPM_EINVAL, "unknown motion");
+    if (r->motion == MPM_DYNAMIC) {
+        if (r->shape != MPM_BOX) return fail(MPM_EINVAL, "dynamic bodies are boxes");
+        if (!(r->mass > 0.0) || !isfinite(r->mass)) return fail(MPM_EINVAL, "a dynamic body needs mass > 0");
+        for (int a = 0; a < 3; ++a) {
+            if (!(r->inertia[a] > 0.0) || !isfinite(r->inertia[a]))
+                return fail(MPM_EINVAL, "a dynamic body needs principal moments > 0");
+            if (!isfinite(r->force[a]) || !isfinite(r->torque[a]))
+                return fail(MPM_EINVAL, "external force and torque must be finite");
+        }
+    }
     if (!(r->mu >= 0.0) || !isfinite(r->mu)) return fail(MPM_EINVAL, "mu must be >= 0");
     if (r->shape == MPM_BOX && !(r->half[0] > 0 && r->half[1] > 0 && r->half[2] > 0))
         return fail(MPM_EINVAL, "degenerate box");
@@ -824,10 +865,13 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const mpm_desc& d = h->d;
-    // host side of the split: advance kinematic bodies with their twist
-    for (HostRigid& q : h->rigids) {
-        if (q.desc.motion != MPM_KINEMATIC) continue;
+    // host side of the split: advance kinematic bodies with their twist, and
+    // integrate dynamic bodies from this step's impulses (device order k)
+    for (int k = 0; k < nr; ++k) {
+        HostRigid& q = h->rigids[order[k]];
         const double dt = N * d.h;
+        if (q.desc.motion == MPM_DYNAMIC) integrate_free_body(q.desc, h->h_racc + 6 * k, h->envs[q.env].gravity, dt);
+        if (q.desc.motion == MPM_STATIC) continue;
         for (int a = 0; a < 3; ++a) q.desc.t[a] += dt * q.desc.V[a];
         rodrigues_advance(q.desc.R, q.desc.w, dt);
     }
@@ -839,6 +883,10 @@ mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out
     if (n_steps < 1) return fail(MPM_EINVAL, "n_steps must be at least 1 (got %d)", (int)n_steps);
     if (h->tape_on) return fail(MPM_EINVAL, "the graph path does not record the differentiation tape");
     if (h->prof) return fail(MPM_EINVAL, "the graph path does not run while mpm_profile timing is on");
+    for (const HostRigid& q : h->rigids)
+        if (q.desc.motion == MPM_DYNAMIC)
+            return fail(MPM_EINVAL, "the graph path advances kinematic bodies only (a dynamic body needs each "
+                                    "step's impulses on the host)");
     if (!h->gstream) {
         HIP_TRY(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&h->gevent, hipEventDisableTiming));
@@ -922,6 +970,9 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
     if (!h) return fail(MPM_EINVAL, "handle is NULL");
     if (!gx || !gv || !gF || !gC) return fail(MPM_EINVAL, "adjoint arrays must be non-NULL");
     if (h->tape_len <= 0) return fail(MPM_EINVAL, "nothing recorded: call mpm_tape_reset, then mpm_step");
+    for (const HostRigid& q : h->rigids)
+        if (q.desc.motion == MPM_DYNAMIC)
+            return fail(MPM_EINVAL, "the reverse pass covers static and kinematic bodies only");
     Work& W = h->w;
     hipStream_t s = h->stream;
     const int N = h->d.N, n_envs = (int)h->envs.size(), nr = (int)h->rigids.size();

@@ -49,6 +49,7 @@ HALF_SPACE = 0
 BOX = 1
 STATIC = 0
 KINEMATIC = 1
+DYNAMIC = 2
 
 KAPPA = 10.0
 EPS_S = 1e-4
@@ -91,6 +92,11 @@ class RigidSpec:
     t: Sequence[float] = (0.0, 0.0, 0.0)
     V: Sequence[float] = (0.0, 0.0, 0.0)
     w: Sequence[float] = (0.0, 0.0, 0.0)
+    # DYNAMIC boxes (body origin at the centre of mass)
+    mass: float = 0.0
+    inertia: Sequence[float] = (0.0, 0.0, 0.0)
+    force: Sequence[float] = (0.0, 0.0, 0.0)
+    torque: Sequence[float] = (0.0, 0.0, 0.0)
 
 
 @dataclasses.dataclass

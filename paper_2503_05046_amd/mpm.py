@@ -61,7 +61,8 @@ class RigidDesc(ct.Structure):
     _fields_ = [("shape", ct.c_int32), ("normal", ct.c_double * 3), ("offset", ct.c_double),
                 ("half", ct.c_double * 3), ("mu", ct.c_double), ("motion", ct.c_int32),
                 ("R", ct.c_double * 9), ("t", ct.c_double * 3), ("V", ct.c_double * 3),
-                ("w", ct.c_double * 3)]
+                ("w", ct.c_double * 3), ("mass", ct.c_double), ("inertia", ct.c_double * 3),
+                ("force", ct.c_double * 3), ("torque", ct.c_double * 3)]
 
 
 class RigidState(ct.Structure):
@@ -195,6 +196,10 @@ def rigid_desc(r) -> RigidDesc:
     q.t[:] = list(r.t)
     q.V[:] = list(r.V)
     q.w[:] = list(r.w)
+    q.mass = getattr(r, "mass", 0.0)
+    q.inertia[:] = list(getattr(r, "inertia", (0.0, 0.0, 0.0)))
+    q.force[:] = list(getattr(r, "force", (0.0, 0.0, 0.0)))
+    q.torque[:] = list(getattr(r, "torque", (0.0, 0.0, 0.0)))
     return q
 
 
