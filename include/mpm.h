@@ -245,7 +245,8 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
  * overflow, non-finite state, a particle outside the grid) leaves the host
  * steps after it in the replay without effect, and its error is returned as
  * in mpm_step. MPM_EINVAL while the differentiation tape records or event
- * timing is on, or for n_steps < 1. */
+ * timing is on, for n_steps < 1, or when the handle has a dynamic body (its
+ * integration needs each host step's impulses on the host). */
 mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out, mpm_step_stats* st);
 
 /* Profiling: enable (1) or disable (0) event timing of the kernel classes
@@ -279,7 +280,8 @@ void mpm_destroy(mpm_handle* h);
  * Drucker-Prager return map of the trial Hencky strain (tip, cone and
  * elastic branches, Sec. II-A) with the Hencky stress. At a branch boundary
  * the branch the forward took is differentiated. The set of registered
- * contacts is held fixed. */
+ * contacts is held fixed. MPM_EINVAL for a handle with a dynamic body, whose
+ * dynamics the reverse pass does not differentiate. */
 
 /* Adjoints of one environment's material parameters. */
 typedef struct {
