@@ -70,3 +70,37 @@ def test_null_arguments(mpm):
     assert lib.mpm_workspace_size(None, ct.byref(n)) == mpm.MPM_EINVAL
     assert lib.mpm_step(None, None, None, None) == mpm.MPM_EINVAL
     lib.mpm_destroy(None)
+
+
+def test_struct_layouts_match_the_header(mpm, tmp_path):
+    """Every ctypes mirror of a struct in include/mpm.h has the header's size
+    and field offsets (compiled with the host C compiler; no GPU)."""
+    import ctypes as ct
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    pairs = {"EnvDesc": "mpm_env_desc", "Desc": "mpm_desc", "EnvGrad": "mpm_env_grad",
+             "RigidGrad": "mpm_rigid_grad", "RigidDesc": "mpm_rigid_desc", "RigidState": "mpm_rigid_state",
+             "RigidImpulse": "mpm_rigid_impulse", "StepStats": "mpm_step_stats",
+             "ProfileData": "mpm_profile_data"}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mpm.h"', "int main(void) {"]
+    expect = []
+    for py, c in pairs.items():
+        cls = getattr(mpm, py)
+        lines.append(f'    printf("%zu\\n", sizeof({c}));')
+        expect.append((f"sizeof {c}", ct.sizeof(cls)))
+        for name, _ in cls._fields_:
+            lines.append(f'    printf("%zu\\n", offsetof({c}, {name}));')
+            expect.append((f"{c}.{name}", getattr(cls, name).offset))
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    include = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.check_call([cc, "-std=c99", "-I", include, str(src), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    assert len(got) == len(expect)
+    bad = [(what, want, g) for (what, want), g in zip(expect, got) if want != g]
+    assert not bad, bad
