@@ -38,7 +38,7 @@ class Env(ct.Structure):
                 ("k", ct.c_double), ("d", ct.c_double), ("eps_s", ct.c_double),
                 ("h", ct.c_double), ("N", ct.c_int), ("eps_r", ct.c_double),
                 ("eps_a", ct.c_double), ("max_iter", ct.c_int), ("ls_max_iter", ct.c_int),
-                ("basis", ct.c_int)]
+                ("basis", ct.c_int), ("solve_all_nodes", ct.c_int)]
 
 
 class Rigid(ct.Structure):

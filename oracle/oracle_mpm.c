@@ -532,10 +532,15 @@ static void chol3_solve(const double H[9], const double rhs[3], double x[3]) {
     x[0] = (y0 - l10 * x[1] - l20 * x[2]) / l00;
 }
 
-int oracle_qn_solve(const oracle_env* env, int n, const double* m, const double* vstar, int nc,
-                    const int* nodes, const double* w, const double* Rc, const double* b,
-                    const double* phi0, const double* n0, const double* mu, double* v,
-                    double* gamma_out, oracle_substep_stats* st, double* lp_hist) {
+/* Algorithm 1 over n nodes; p2_rest is the part of |p~|^2 = sum m |v|^2 that
+ * comes from active nodes outside the problem (nodes no contact stencil
+ * touches, whose iterate stays at v* exactly: their gradient is zero at v*,
+ * so their Newton direction is zero; reading R3). */
+static int qn_solve_core(const oracle_env* env, int n, const double* m, const double* vstar, int nc,
+                         const int* nodes, const double* w, const double* Rc, const double* b,
+                         const double* phi0, const double* n0, const double* mu, double* v,
+                         double* gamma_out, oracle_substep_stats* st, double* lp_hist,
+                         double p2_rest) {
     double* vc = (double*)malloc(sizeof(double) * 3 * (size_t)(nc > 0 ? nc : 1));
     double* uc = (double*)malloc(sizeof(double) * 3 * (size_t)(nc > 0 ? nc : 1));
     double* gam = (double*)malloc(sizeof(double) * 3 * (size_t)(nc > 0 ? nc : 1));
@@ -579,7 +584,7 @@ int oracle_qn_solve(const oracle_env* env, int n, const double* m, const double*
                 for (int a = 0; a < 3; ++a) ji[a] += w[27 * c + o] * rg[a];
             }
         }
-        double grad2 = 0.0, p2 = 0.0, j2 = 0.0;
+        double grad2 = 0.0, p2 = p2_rest, j2 = 0.0;
         for (int i = 0; i < n; ++i)
             for (int a = 0; a < 3; ++a) {
                 double gi = m[i] * (v[3 * i + a] - vstar[3 * i + a]) - j[3 * i + a];
@@ -658,6 +663,13 @@ int oracle_qn_solve(const oracle_env* env, int n, const double* m, const double*
     }
     free(vc); free(uc); free(gam); free(Gc); free(j); free(g); free(H); free(dv);
     return status;
+}
+
+int oracle_qn_solve(const oracle_env* env, int n, const double* m, const double* vstar, int nc,
+                    const int* nodes, const double* w, const double* Rc, const double* b,
+                    const double* phi0, const double* n0, const double* mu, double* v,
+                    double* gamma_out, oracle_substep_stats* st, double* lp_hist) {
+    return qn_solve_core(env, n, m, vstar, nc, nodes, w, Rc, b, phi0, n0, mu, v, gamma_out, st, lp_hist, 0.0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -823,24 +835,59 @@ int oracle_substep(const oracle_env* env, const oracle_rigid* rigid, int n_rigid
         return rc;
     }
     const double D = 4.0 / (env->dx * env->dx);
-    /* compact node arrays for Algorithm 1 */
-    int n = fr.n_act;
+    /* Algorithm 1 (READING R3: it starts from v = v*). An active node that no
+     * contact stencil touches (weight > 0) has j = 0 and g = m (v - v*) = 0 at
+     * v*, so its Newton direction is zero and it keeps v = v* exactly: unless
+     * env->solve_all_nodes is set, the iteration runs over the touched nodes
+     * only and the others' share of |p~|^2 = sum m |v*|^2 enters as a constant
+     * (the same norms and iterates; only the order of that sum differs). */
+    const int n_act = fr.n_act;
+    int* sub_of = (int*)malloc(sizeof(int) * (size_t)(n_act > 0 ? n_act : 1));
+    int n = 0;
+    for (int i = 0; i < n_act; ++i) sub_of[i] = env->solve_all_nodes ? i : -1;
+    if (env->solve_all_nodes) {
+        n = n_act;
+    } else {
+        for (int c = 0; c < fr.nc; ++c)
+            for (int o = 0; o < 27; ++o)
+                if (fr.cw[27 * c + o] > 0.0) sub_of[fr.cnodes[27 * c + o]] = -2;  /* touched */
+        for (int i = 0; i < n_act; ++i)  /* numbered in node order */
+            if (sub_of[i] == -2) sub_of[i] = n++;
+    }
+    int* act_node = (int*)malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));  /* problem node -> active node */
+    double p2_rest = 0.0;
+    for (int i = 0; i < n_act; ++i) {
+        if (sub_of[i] >= 0) {
+            act_node[sub_of[i]] = i;
+        } else {
+            for (int a = 0; a < 3; ++a) p2_rest += fr.m[fr.act[i]] * fr.vgrid[3 * fr.act[i] + a] * fr.vgrid[3 * fr.act[i] + a];
+        }
+    }
+    int* cnodes = (int*)malloc(sizeof(int) * 27 * (size_t)(fr.nc > 0 ? fr.nc : 1));
+    for (int c = 0; c < fr.nc; ++c)
+        for (int o = 0; o < 27; ++o) {
+            /* a zero-weight stencil entry may name a node outside the problem:
+             * point it at problem node 0 (its weight is exactly 0) */
+            const int q = sub_of[fr.cnodes[27 * c + o]];
+            cnodes[27 * c + o] = (fr.cw[27 * c + o] > 0.0 || q >= 0) ? q : 0;
+        }
     double* m = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
     double* vs = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     double* vv = (double*)malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
     for (int i = 0; i < n; ++i) {
-        m[i] = fr.m[fr.act[i]];
-        for (int a = 0; a < 3; ++a) vs[3 * i + a] = vv[3 * i + a] = fr.vgrid[3 * fr.act[i] + a];
+        const long node = fr.act[act_node[i]];
+        m[i] = fr.m[node];
+        for (int a = 0; a < 3; ++a) vs[3 * i + a] = vv[3 * i + a] = fr.vgrid[3 * node + a];
     }
     double* gam = (double*)malloc(sizeof(double) * 3 * (size_t)(fr.nc > 0 ? fr.nc : 1));
     oracle_substep_stats local;
     memset(&local, 0, sizeof(local));
-    int qs = oracle_qn_solve(env, n, m, vs, fr.nc, fr.cnodes, fr.cw, fr.cR, fr.cb, fr.cphi,
-                             fr.cn0, fr.cmu, vv, gam, &local, lp_hist);
+    int qs = qn_solve_core(env, n, m, vs, fr.nc, cnodes, fr.cw, fr.cR, fr.cb, fr.cphi,
+                           fr.cn0, fr.cmu, vv, gam, &local, lp_hist, p2_rest);
     local.n_contacts = fr.nc;
-    local.n_active_nodes = n;
+    local.n_active_nodes = n_act;
     {
-        char* touched = (char*)calloc((size_t)(n > 0 ? n : 1), 1);
+        char* touched = (char*)calloc((size_t)(n_act > 0 ? n_act : 1), 1);
         int cnt = 0;
         for (int c = 0; c < fr.nc; ++c)
             for (int o = 0; o < 27; ++o)
@@ -852,7 +899,10 @@ int oracle_substep(const oracle_env* env, const oracle_rigid* rigid, int n_rigid
         free(touched);
     }
     for (int i = 0; i < n; ++i)
-        for (int a = 0; a < 3; ++a) fr.vgrid[3 * fr.act[i] + a] = vv[3 * i + a];
+        for (int a = 0; a < 3; ++a) fr.vgrid[3 * fr.act[act_node[i]] + a] = vv[3 * i + a];
+    free(sub_of);
+    free(act_node);
+    free(cnodes);
     /* impulses on the rigid bodies: minus the impulse on MPM, Eq. (3) */
     if (impulse) {
         for (int c = 0; c < fr.nc; ++c) {

@@ -55,6 +55,8 @@ typedef struct {
     int max_iter;              /* Algorithm 1 iteration cap */
     int ls_max_iter;           /* line-search step cap */
     int basis;                 /* tangent completion: 0 Duff et al. 2017, 1 axis-based */
+    int solve_all_nodes;       /* 1: Algorithm 1 iterates over every active node; 0: over the
+                                  nodes a contact stencil touches (the others keep v = v*) */
 } oracle_env;
 
 typedef struct {

@@ -312,6 +312,38 @@ def test_single_contact_normal_closed_form(oracle):
         assert np.abs(vc - (vc @ nrm) * nrm).max() < 1e-10
 
 
+@pytest.mark.parametrize("d", [10.0, 100.0])
+def test_single_contact_dissipative_normal_closed_form(oracle, d):
+    """Hunt-Crossley normal impulse (d > 0), frictionless single contact: the
+    effective mass is m_p (Sum w = 1), so the optimal normal velocity is the
+    root of m_p (v - v*) = h k (phi0 - h v)(1 - d v) below vbar = min(phi0/h,
+    1/d), found here by bracketing (scipy brentq), independent of Algorithm 1."""
+    env = _env(oracle, eps_r=1e-13, eps_a=1e-300, max_iter=100000)
+    env.d = d
+    m_p, k, h = env.m_p, env.k, env.h
+    n_in = 0
+    for _ in range(20):
+        xp = RNG.uniform(0.4, 0.6, 3)
+        nrm = RNG.normal(size=3)
+        nrm /= np.linalg.norm(nrm)
+        phi0 = RNG.uniform(1e-5, 1e-3)
+        vbar = min(phi0 / h, 1.0 / d)
+        vn_star = RNG.uniform(-1.0, 1.2 * vbar)
+        prob = _single_contact_problem(oracle, env, xp, nrm, vn_star * nrm, phi0, 0.0, 0.0)
+        rc, v, gam, st, _ = oracle.qn_solve(env, prob)
+        assert rc == oracle.OK
+        if vn_star < vbar:
+            f = lambda s: m_p * (s - vn_star) - h * k * (phi0 - h * s) * (1.0 - d * s)
+            vn = scipy.optimize.brentq(f, vn_star, vbar, xtol=1e-300, rtol=1e-15)
+            n_in += 1
+        else:  # released: no impulse at the optimum
+            vn = vn_star
+        vc = prob["w"][0] @ v
+        assert vc @ nrm == pytest.approx(vn, rel=1e-10, abs=1e-13)
+        assert np.abs(vc - (vc @ nrm) * nrm).max() < 1e-10
+    assert n_in >= 10
+
+
 def test_single_contact_friction_closed_form(oracle):
     env = _env(oracle, eps_r=1e-12, eps_a=1e-300, max_iter=2000)
     m_p, eps_s = env.m_p, env.eps_s
@@ -437,6 +469,30 @@ def test_noncontact_nodes_keep_free_motion(oracle):
     assert np.array_equal(v[~touched], prob["vstar"][~touched])
 
 
+@pytest.mark.parametrize("material", [I.FIXED_COROTATED, I.DRUCKER_PRAGER])
+def test_contact_node_solve_equals_all_node_solve(oracle, material):
+    """Algorithm 1 over the nodes a contact stencil touches (the oracle's
+    default) and over every active node give the same substep: the other
+    nodes keep v = v* exactly, and only the summation order of |p~| differs."""
+    scene = I.tiny_random(P=400, seed=12, material=material)
+    out = []
+    for all_nodes in (0, 1):
+        sim = oracle.OracleSim(scene)
+        sim.env.solve_all_nodes = all_nodes
+        sim.env.eps_s = 1e-2
+        sim.env.eps_r = 1e-10
+        sim.env.max_iter = 100000
+        rc, imp, st = sim.host_step()
+        assert rc == oracle.OK
+        out.append((sim.v.copy(), sim.x.copy(), imp.copy(), st))
+    (v0, x0, i0, s0), (v1, x1, i1, s1) = out
+    assert s0[0]["n_contacts"] > 0 and s0[0]["n_contact_nodes"] < s0[0]["n_active_nodes"]
+    sv = max(np.abs(v1).max(), 1e-3)
+    assert np.abs(v0 - v1).max() < 1e-9 * sv
+    assert np.abs(x0 - x1).max() < 1e-12
+    assert np.abs(i0 - i1).max() < 1e-8 * np.abs(i1).max()
+
+
 def test_tangent_basis_invariance(oracle):
     scene = I.tiny_random(P=300, seed=8)
     out = []
@@ -526,6 +582,37 @@ def test_free_fall_closed_form(oracle):
 # --------------------------------------------------------------------------
 # Physics pins of the coupled step: resting block, Coulomb sliding
 # --------------------------------------------------------------------------
+def test_resting_block_carries_its_weight(oracle):
+    """A slab resting on a plane (Hunt-Crossley dissipation d = 100 s/m damps
+    its bounce): once settled, the contact force averaged over a window is
+    m g and the centre of mass is at rest; and over the window the impulse the
+    plane receives equals m g T plus the change of MPM momentum (Eq. (3)-(5):
+    contact impulses are the only other force)."""
+    s = I.slab_on_plane(6, 3, (0.0, 0.0, 0.0), 0.5, seed=31)
+    s.envs[0].d = 100.0
+    sim = oracle.OracleSim(s)
+    m_tot = sim.env.m_p * sim.P
+    for _ in range(4000):  # settle
+        rc, st, _ = sim.substep()
+        assert rc == oracle.OK
+    P0 = sim.env.m_p * sim.v.sum(1)
+    tot = np.zeros(6)
+    K = 1000
+    bound = 0.0
+    vz = []
+    for _ in range(K):
+        rc, st, _ = sim.substep(impulse=tot)
+        assert rc == oracle.OK
+        bound += math.sqrt(m_tot) * st.residual
+        vz.append(sim.v[2].mean())
+    P1 = sim.env.m_p * sim.v.sum(1)
+    T = K * s.h
+    force = -tot[2] / T  # impulse on MPM per unit time (on the plane: -)
+    assert force == pytest.approx(9.81 * m_tot, rel=1e-3)
+    assert np.abs(vz).max() < 2e-5  # settled: g h is 1e-3 m/s per substep
+    assert abs(-tot[2] - (P1[2] - P0[2] + 9.81 * m_tot * T)) <= bound + 1e-15
+
+
 def test_resting_block_momentum_balance(oracle):
     """Impulse the plane receives over a window equals m g T + change of MPM
     momentum (Eq. (3)-(5): contact impulses are the only other force)."""
