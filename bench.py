@@ -1,19 +1,35 @@
 #!/usr/bin/env python
-"""Throughput of the coupled MPM-rigid host step on one MI355X.
+"""Throughput of the coupled MPM-rigid substep on one MI355X.
 
-Workload: granular pour, 1,000,000 Drucker-Prager sand particles on a 128^3
-grid (dx = 1/128) falling onto four static rigid boxes (mu = 0.4), substep
-h = 1e-4 s, N = 10 substeps per host step, contact residual eps_r = 1e-6,
-eps_a = FP64 machine epsilon. One benchmark step is one host step: the
-once-per-step cell sort plus ten full substeps (P2G, grid update, contact
-registration, the contact-node table, Algorithm 1 to convergence, G2P with the
-return map). Inputs are seeded and synthetic and resident in HBM before the
-timed region starts.
+One invocation measures the three forms of the metric (particle-substeps/s at
+contact residual eps_r = 1e-6, eps_a = FP64 machine epsilon), each on its
+configuration, all inputs seeded, synthetic and resident in HBM before the
+timed regions start:
 
-Prints one JSON line with the metric (particle-substeps/s), a roofline entry
-for the kernel that takes most of the time, per-kernel figures measured with
-HIP events inside the timed region, and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+* plain (the line's `value`): the granular pour, 1,000,000 Drucker-Prager
+  sand particles on a 128^3 grid falling at 1 m/s onto four static boxes,
+  h = 1e-4 s, N = 10 substeps per host step, 200 substeps = 20 host steps.
+  One step = one host step (the once-per-step cell sort and ten substeps of
+  P2G, grid update, registration, contact-node table, Algorithm 1 to
+  convergence, G2P with the return map). The timed window is the K host
+  steps after W warmup host steps of that 20-host-step run; a window that
+  reaches past host step 19 continues on a fresh copy of the initial state
+  (so K = 20 times every host step of the run exactly once);
+* batched: 64 independent environments (log-uniform 5k-100k particles, 64^3
+  grids, elastic or sand, 1-3 boxes each), the configuration's 100 substeps
+  (10 host steps) in one handle, as a HIP graph replay, and looping
+  single-environment handles over all 64 environments;
+* forward + backward: a 200k-particle elastic cube pushed by a box, 50
+  substeps with a checkpoint every 10, the loss x of the final centre of
+  mass differentiated with respect to the initial velocity, E and the box
+  velocity; cost relative to the plain forward, and the 3 x 7 Jacobian.
+
+Also: the gripper in dense contact (250k particles, about 2e4 contacts), P2G
+and G2P at 4M particles (past the 256 MB last-level cache), per-kernel
+figures from HIP events recorded on the library's stream inside the timed
+region, a roofline entry for the kernel that takes most of the time, and the
+FP64 CPU oracle timed beside the GPU on one substep of the granular pour in
+contact.
 """
 import argparse
 import json
@@ -27,6 +43,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+RUN_HOST_STEPS = 20    # the granular pour's 200 substeps
+BATCH_HOST_STEPS = 10  # the batched configuration's 100 substeps
+DIFF_HOST_STEPS = 5    # the differentiable configuration's 50 substeps
 
 # Algorithmic bytes (minimal float32 structure-of-arrays traffic).
 P2G_BYTES_PER_PARTICLE = 60        # reads x, v, Q
@@ -35,7 +54,6 @@ SORT_BYTES_PER_PARTICLE = 210      # keys + stable sort passes + gather, once pe
 SOLVE_BYTES_PER_CONTACT_ITER = 52  # per Algorithm 1 iteration
 SOLVE_BYTES_PER_NODE_ITER = 88
 SOLVE_BYTES_PER_CONTACT_ROUND = 40  # per line-search reduction round
-
 
 # The solver's HBM traffic per launch, measured with rocprofv3 PMC counters
 # (FETCH_SIZE, WRITE_SIZE) and a plain device copy of known size for scale, is
@@ -91,266 +109,26 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(state: dict, scene, budget_s: float) -> dict:
-    """The FP64 oracle, as it stands, on substeps of a column of the same state
-    (particles with x, y in [0.36, 0.44], all heights, over one box): as many
-    substeps of one host step as fit in about budget_s / 3 seconds (at least
-    one)."""
-    import numpy as np
-    from oracle import oracle as O
-    O.build(force=not os.path.exists(O.LIB))
-    x = state["x"]
-    sel = np.nonzero((x[0] > 0.36) & (x[0] < 0.44) & (x[1] > 0.36) & (x[1] < 0.44))[0]
-    sub = scene.copy()
-    sub.x, sub.v, sub.F, sub.C = (np.ascontiguousarray(state[k][:, sel]) for k in ("x", "v", "F", "C"))
-    sub.envs[0].p_begin, sub.envs[0].p_end = 0, len(sel)
-    ora = O.OracleSim(sub)
-    n_sub, contacts, iters, rc = 0, [], [], 0
-    t0 = time.perf_counter()
-    while n_sub < scene.N and (n_sub == 0 or time.perf_counter() - t0 < budget_s / 3):
-        rc, st, _ = ora.substep()
-        n_sub += 1
-        contacts.append(st.n_contacts)
-        iters.append(st.iterations)
-        if rc >= 2:  # an error (1 is the iteration-cap warning)
-            break
-    dt = time.perf_counter() - t0
-    return {"value": len(sel) * n_sub / dt, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"{n_sub} substeps of a {len(sel)}-particle column (x, y in [0.36, 0.44]) of the "
-                       f"benchmark state after the timed steps: {max(contacts)} contacts at most, "
-                       f"{sum(iters)} solver iterations in all, {dt:.1f} s single-threaded FP64"),
-            "status": rc}
+def host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
 
 
-def run_batched(args) -> int:
-    """The batched form: 64 independent environments (log-uniform 5k-100k
-    particles, 64^3 grids, elastic or sand, 1-3 boxes each) in one handle,
-    against looping single-environment handles over the same environments.
-    Looping all 64 at the contact tolerance takes minutes per host step, so
-    the loop is timed on every 8th environment and scaled by the environment
-    count (the per-environment solve is latency-bound, not size-bound)."""
-    import numpy as np
-    import torch
-    from paper_2503_05046_amd import inputs as I
+def kernel_table(prof: dict, P: int) -> dict:
+    """Per kernel class: event time, launches, and for the streaming kernels
+    and the solver their algorithmic bytes over the time as a fraction of HBM
+    peak."""
     from paper_2503_05046_amd import mpm as M
-
-    scene = I.batched()
-    scene.max_iter = args.max_iter
-    P, N, n_envs = scene.P, scene.N, len(scene.envs)
-    warm = args.warmup if args.warmup_set else 9  # contact starts near the 8th host step
-    log(f"batched: {n_envs} environments, P={P}, warmup {warm}, steps {args.steps}")
-    spb, tuning = 0, None
-    if args.autotune:
-        from paper_2503_05046_amd import autotune
-        spb, tuning = autotune.tune(scene, candidates=(64, 96, 128, 192, 256), warmup_steps=warm,
-                                    trial_steps=2, log=log)
-        log(f"autotune: {spb} contact nodes per solver block")
-    sim = M.Sim(scene, solver_slots_per_block=spb)
-    for i in range(warm):
-        sim.step()
-    sim.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = []
-    for i in range(args.steps):
-        _, _, st = sim.step()
-        iters += st["iterations"]
-        log(f"batched step {i}: contacts {st['contacts']}, longest solve {max(st['iterations'])} iterations")
-    torch.cuda.synchronize()
-    t_b = time.perf_counter() - t0
-    prof = sim.profile(False)
-    sim.close()
-    # the same host steps as one HIP graph replay (mpm_step_graph), on a second
-    # handle warmed up the same way; the recording is inside the timed region
-    gsim = M.Sim(scene, solver_slots_per_block=spb)
-    for i in range(warm):
-        gsim.step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, gst = gsim.step_graph(args.steps)
-    torch.cuda.synchronize()
-    t_g = time.perf_counter() - t0
-    log(f"graph: {args.steps} host steps in one replay, {t_g:.2f} s, last step contacts {gst['contacts']}")
-    gsim.close()
-    sub = list(range(0, n_envs, 8))
-    sims = [M.Sim(I.single_env(scene, e)) for e in sub]
-    for s in sims:
-        for i in range(warm):
-            s.step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        for s in sims:
-            s.step()
-        log(f"loop step {i} done")
-    torch.cuda.synchronize()
-    t_sub = time.perf_counter() - t0
-    for s in sims:
-        s.close()
-    t_loop = t_sub * n_envs / len(sub)
-    value_b = P * N * args.steps / t_b
-    value_l = P * N * args.steps / t_loop
-    out = {
-        "metric": "particle-substeps/s (batched, 64 environments, contact residual 1e-6)",
-        "value": value_b, "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": warm, "ms_per_step": 1e3 * t_b / args.steps, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": (f"batched: {n_envs} independent environments, {P} particles "
-                                f"(log-uniform 5k-100k each), 64^3 grids, elastic/sand, 1-3 boxes, "
-                                f"h=1e-4 s, {N} substeps per host step, eps_r=1e-6"),
-                   "particles": P, "environments": n_envs},
-        "loop": {"value": value_l, "ms_per_step": 1e3 * t_loop / args.steps,
-                 "timed_environments": sub,
-                 "method": "single-environment handles stepped in turn; time of the timed "
-                           "environments scaled by 64 / 8"},
-        "batched_over_loop": value_b / value_l,
-        "solver_slots_per_block": spb or 128,
-        "autotune": ({"chosen": spb, "ms_per_step": {k: round(1e3 * t, 1) for k, t in tuning.items()}}
-                     if tuning else None),
-        "graph": {"value": P * N * args.steps / t_g, "ms_per_step": 1e3 * t_g / args.steps,
-                  "method": f"the {args.steps} timed host steps ({N * args.steps} substeps) as one "
-                            f"HIP graph (mpm_step_graph), recording included"},
-        "solve_share": prof["ms"]["solve"] / max(1e-9, sum(prof["ms"].values())),
-        "longest_solve_iterations_mean": float(np.mean(iters)),
-    }
-    print(json.dumps(out), flush=True)
-    return 0
-
-
-def run_differentiable(args) -> int:
-    """The backward form: 200k-particle elastic cube pushed by a box (C5), 50
-    substeps (5 host steps) with a checkpoint every host step; the loss is the
-    x coordinate of the final centre of mass, differentiated with respect to a
-    uniform offset of the initial velocity, Young's modulus and the box
-    velocity. Reports the forward-plus-backward rate and its cost relative to
-    the plain forward."""
-    import numpy as np
-    import torch
-    from paper_2503_05046_amd import diff
-    from paper_2503_05046_amd import inputs as I
-    from paper_2503_05046_amd import mpm as M
-
-    scene = I.differentiable()
-    scene.max_iter = args.max_iter
-    P, N, steps = scene.P, scene.N, 5
-    log(f"differentiable: P={P}, {steps} host steps of {N} substeps, checkpoint every host step")
-    sim = M.Sim(scene, tape_substeps=N)
-    path = diff.RigidPath(scene)
-    dev = sim.device
-    x0, v0, F0, C0 = (torch.from_numpy(a).to(dev) for a in (scene.x, scene.v, scene.F, scene.C))
-    V0 = torch.tensor([list(r.V) for r in scene.rigids], dtype=torch.float64)
-    E0 = torch.tensor([scene.envs[0].E], dtype=torch.float64)
-    # plain forward (no tape, no autograd)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    diff._run(sim, path, steps, 0, x0, v0, F0, C0, V0, record=False)
-    torch.cuda.synchronize()
-    t_fwd = time.perf_counter() - t0
-    log(f"forward: {t_fwd:.2f} s")
-    # forward + backward through the checkpointed segments
-    u = torch.zeros(3, dtype=torch.float32, device=dev, requires_grad=True)
-    E = E0.clone().requires_grad_(True)
-    V = V0.clone().requires_grad_(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    x, v, F, C = diff.simulate(sim, path, steps, 1, x0, v0 + u[:, None], F0, C0, E, V)
-    loss = x[0].mean()
-    loss.backward()
-    torch.cuda.synchronize()
-    t_fb = time.perf_counter() - t0
-    log(f"forward + backward: {t_fb:.2f} s")
-    sim.close()
-    out = {
-        "metric": "particle-substeps/s (forward + backward, contact residual 1e-6)",
-        "value": P * N * steps / t_fb, "unit": "particle-substeps/s", "n_gpus": 1, "steps": 1,
-        "warmup": 0, "ms_per_step": 1e3 * t_fb, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
-        "config": {"workload": (f"differentiable: {P}-particle elastic cube, 96^3 grid, pushed by a box at "
-                                f"0.5 m/s, {N * steps} substeps, checkpoint every {N} substeps, "
-                                f"eps_r=1e-6; one step = the whole forward-plus-backward run"),
-                   "particles": P, "substeps": N * steps},
-        "forward_s": t_fwd, "forward_backward_s": t_fb, "fwd_bwd_over_fwd": t_fb / t_fwd,
-        "gradient": {"d_com_x/d_v0": u.grad.cpu().tolist(), "d_com_x/d_E": float(E.grad[0]),
-                     "d_com_x/d_V_box": V.grad[0].tolist()},
-    }
-    print(json.dumps(out), flush=True)
-    return 0
-
-
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", choices=("granular_pour", "batched", "differentiable"),
-                    default="granular_pour")
-    ap.add_argument("--particles", type=int, default=1_000_000)
-    ap.add_argument("--max-iter", type=int, default=200_000)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--autotune", action="store_true",
-                    help="batched workload: pick the solver's contact nodes per block with the autotuner first")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
-                    help="only run one device copy of BYTES (scale for the PMC byte counters)")
-    args = ap.parse_args()
-    if args.copy_calibration > 0:
-        return copy_calibration(args.copy_calibration)
-    args.warmup_set = args.warmup is not None
-    if args.warmup is None:
-        args.warmup = 5
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (a single scene "
-              "would shard into slabs, one per GPU, and the "
-              "environments of the batched form would be assigned to GPUs whole). Run with --gpus 1.",
-              file=sys.stderr)
-        return 2
-    if args.workload == "batched":
-        return run_batched(args)
-    if args.workload == "differentiable":
-        return run_differentiable(args)
-
-    import numpy as np
-    import torch
-    from paper_2503_05046_amd import inputs as I
-    from paper_2503_05046_amd import mpm as M
-
-    scene = I.granular_pour(n_particles=args.particles)
-    scene.max_iter = args.max_iter
-    log(f"scene {scene.name}: P={scene.P}, grid {tuple(scene.envs[0].dims)}, N={scene.N}, "
-        f"h={scene.h}, eps_r={scene.eps_r}")
-    sim = M.Sim(scene, device="cuda:0")
-    P, N = scene.P, scene.N
-
-    def run(k_steps, tag):
-        per = []
-        for i in range(k_steps):
-            t = time.perf_counter()
-            status, imp, st = sim.step()
-            per.append(st)
-            log(f"{tag} step {i}: {1e3 * (time.perf_counter() - t):.1f} ms, contacts max "
-                f"{st['max_contacts']}, iterations/substep {st['iterations']}, flags {st['flags']}")
-        return per
-
-    run(args.warmup, "warmup")
-    sim.profile(True)  # reset and start event timing
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = run(args.steps, "timed")
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = sim.profile(0)
-    elapsed = t1 - t0
-    value = P * N * args.steps / elapsed
-    # one more host step, untimed, with the solver's phase timers on (their
-    # clock reads lengthen the solve, so they stay out of the timed steps)
-    sim.profile(2)
-    run(1, "phase-timer")
-    phase_prof = sim.profile(0)
-
-    # per-kernel figures from the live events
     ms, launches = prof["ms"], prof["launches"]
     total_ms = sum(ms.values())
-    sub_launches = max(1, launches["p2g"])
     solve_bytes = (SOLVE_BYTES_PER_CONTACT_ITER * prof["solver_contact_iters"] +
                    SOLVE_BYTES_PER_NODE_ITER * prof["solver_node_iters"] +
                    SOLVE_BYTES_PER_CONTACT_ROUND * prof["solver_contact_rounds"])
@@ -372,52 +150,402 @@ def main() -> int:
             e["algo_GBps"] = round(gbs, 1)
             e["frac_hbm_peak"] = round(gbs / HBM_PEAK_GBS, 4)
         kernels[k] = e
-    dominant = max(kernels, key=lambda k: kernels[k]["ms_total"])
-    dom = kernels[dominant]
-    roofline = {"kernel": dominant, "bound": "hbm", "achieved": dom.get("algo_GBps"),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom.get("frac_hbm_peak"),
-                "traffic": measured_traffic() if dominant == "solve" else None}
-    iters = [i for st in stats for i in st["iterations"]]
+    return kernels
+
+
+def add_profiles(a: dict, b: dict) -> dict:
+    out = {}
+    for k, v in a.items():
+        if isinstance(v, dict):
+            out[k] = {q: v[q] + b[k][q] for q in v}
+        else:
+            out[k] = v + b[k]
+    return out
+
+
+def solver_summary(stats: list, prof: dict, phase_prof: dict) -> dict:
+    import numpy as np
+    from paper_2503_05046_amd import mpm as M
+    iters = [i for st in stats for i in st["iterations"] if i > 0]
     contacts = [c for st in stats for c in st["contacts"]]
     nodes = [c for st in stats for c in st["contact_nodes"]]
-    noconv = sum(1 for st in stats if st["flags"] & M.FLAG_NOCONV)
-    solver = {
-        "iterations_per_substep_mean": round(float(np.mean(iters)), 1),
-        "iterations_per_substep_max": int(max(iters)),
+    return {
+        "iterations_per_contact_substep_mean": round(float(np.mean(iters)), 1) if iters else 0,
+        "iterations_per_substep_max": int(max(iters)) if iters else 0,
         "contacts_mean": round(float(np.mean(contacts)), 1), "contacts_max": int(max(contacts)),
         "contact_nodes_mean": round(float(np.mean(nodes)), 1),
-        "us_per_iteration": (round(1e3 * ms["solve"] / prof["solver_iterations"], 2)
+        "us_per_iteration": (round(1e3 * prof["ms"]["solve"] / prof["solver_iterations"], 2)
                              if prof["solver_iterations"] else None),
         "ls_rounds_per_iteration": (round(prof["solver_ls_rounds"] / prof["solver_iterations"], 2)
                                     if prof["solver_iterations"] else None),
         "phase_us_per_iteration": ({k: round(v / phase_prof["solver_iterations"], 2)
                                     for k, v in phase_prof["solver_phase_us"].items()}
-                                   if phase_prof["solver_iterations"] else None),
-        "phase_us_note": "one extra untimed host step with the phase timers on",
-        "host_steps_not_converged": noconv,
+                                   if phase_prof and phase_prof["solver_iterations"] else None),
+        "host_steps_not_converged": sum(1 for st in stats if st["flags"] & M.FLAG_NOCONV),
         "residual_over_threshold_max": max(
-            (r / t for st in stats for r, t in zip(st["residual"], st["threshold"]) if t > 0),
-            default=None),
+            (r / t for st in stats for r, t in zip(st["residual"], st["threshold"]) if t > 0), default=None),
     }
-    out = {
-        "metric": "particle-substeps/s (plain substep at contact residual 1e-6)",
-        "value": value, "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": (f"granular pour: {P} Drucker-Prager sand particles, 128^3 grid, "
-                                f"4 static boxes, h=1e-4 s, {N} substeps per host step, "
-                                f"eps_r=1e-6; one step = one host step"),
-                   "particles": P, "substeps_per_step": N, "parallelism": "single GPU"},
-        "roofline": roofline,
-        "kernels": kernels,
-        "solver": solver,
+
+
+# ---------------------------------------------------------------------------
+# plain form: the granular pour
+# ---------------------------------------------------------------------------
+def run_plain(args) -> dict:
+    import torch
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+
+    scene = I.granular_pour(n_particles=args.particles)
+    scene.max_iter = args.max_iter
+    P, N = scene.P, scene.N
+    W, K = args.warmup, args.steps
+    n_runs = (W + K + RUN_HOST_STEPS - 1) // RUN_HOST_STEPS
+    log(f"plain: granular pour P={P}, grid {tuple(scene.envs[0].dims)}, N={N}, h={scene.h}, "
+        f"eps_r={scene.eps_r}; warmup {W}, timed {K} host steps over {n_runs} copies of the run")
+    sims = [M.Sim(scene, device="cuda:0") for _ in range(n_runs)]  # each from the initial state
+    torch.cuda.synchronize()
+
+    step_ms = []
+
+    def step_at(j, tag):
+        sim = sims[j // RUN_HOST_STEPS]
+        t = time.perf_counter()
+        status, imp, st = sim.step()
+        ms = 1e3 * (time.perf_counter() - t)
+        if tag == "timed":
+            step_ms.append(ms)
+        log(f"{tag} host step {j % RUN_HOST_STEPS} of run {j // RUN_HOST_STEPS}: "
+            f"{ms:.1f} ms, contacts max {st['max_contacts']}, "
+            f"iterations/substep {st['iterations']}, flags {st['flags']}")
+        return st
+
+    for j in range(W):
+        step_at(j, "warmup")
+    for s in sims:
+        s.profile(True)  # reset and start event timing
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [step_at(j, "timed") for j in range(W, W + K)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = None
+    for s in sims:
+        p = s.profile(0)
+        prof = p if prof is None else add_profiles(prof, p)
+    # one more host step, untimed, with the solver's phase timers on (their
+    # clock reads lengthen the solve); on the first copy, in contact
+    sims[0].profile(2)
+    sims[0].step()
+    phase_prof = sims[0].profile(0)
+    for s in sims:
+        s.close()
+    kernels = kernel_table(prof, P)
+    solver = solver_summary(stats, prof, phase_prof)
+    dominant = max(kernels, key=lambda k: kernels[k]["ms_total"])
+    dom = kernels[dominant]
+    roofline = {"kernel": dominant,
+                "bound": "latency" if dominant == "solve" else "hbm",
+                "achieved": dom.get("algo_GBps"), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dom.get("frac_hbm_peak"),
+                "traffic": measured_traffic() if dominant == "solve" else None}
+    if dominant == "solve":
+        roofline["us_per_iteration"] = solver["us_per_iteration"]
+        roofline["note"] = ("Algorithm 1 is a chain of dependent steps per iteration (group barrier, "
+                            "memory round trips, block reductions): latency-bound; frac is its "
+                            "algorithmic bytes per launch over HBM peak, us_per_iteration its cost")
+    return {
+        "value": P * N * K / elapsed, "elapsed_s": elapsed, "ms_per_step": 1e3 * elapsed / K,
+        "window": (f"host steps {W % RUN_HOST_STEPS}.. of the {RUN_HOST_STEPS}-host-step "
+                   f"({RUN_HOST_STEPS * N}-substep) run after {W} warmup host steps, {K} timed; "
+                   f"past host step {RUN_HOST_STEPS - 1} the window continues on a fresh copy of "
+                   f"the initial state"),
+        "host_step_ms": [round(t, 1) for t in step_ms],
+        "roofline": roofline, "kernels": kernels, "solver": solver, "scene": scene,
     }
-    state = sim.state()
+
+
+def run_streaming_4m(args) -> dict:
+    """P2G and G2P at 4M particles (the granular pour at 4x the density on the
+    same 128^3 grid, before contact): the state (384 MB) exceeds the 256 MB
+    last-level cache, so the kernels stream from HBM."""
+    import torch
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+    scene = I.granular_pour(n_particles=4_000_000)
+    sim = M.Sim(scene, device="cuda:0")
+    sim.step()  # warm
+    sim.profile(True)
+    torch.cuda.synchronize()
+    sim.step()
+    torch.cuda.synchronize()
+    prof = sim.profile(0)
     sim.close()
-    if not args.no_cpu_baseline:
-        log("cpu baseline: FP64 oracle on a column sample")
-        out["cpu_baseline"] = cpu_baseline(state, scene, args.cpu_budget)
+    k = kernel_table(prof, scene.P)
+    return {"particles": scene.P, "p2g": k.get("p2g"), "g2p": k.get("g2p"), "sort": k.get("sort"),
+            "grid": k.get("grid")}
+
+
+def run_gripper_dense(args) -> dict:
+    """Ten substeps (one host step) of the gripper started in dense contact
+    (both jaws 0.065 m inside the ellipsoid's tips: about 2e4 contacts)."""
+    import torch
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+    scene = I.gripper(overlap=0.065)
+    scene.max_iter = args.max_iter
+    sim = M.Sim(scene, device="cuda:0")
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, imp, st = sim.step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    prof = sim.profile(0)
+    sim.close()
+    log(f"gripper dense: {dt * 1e3:.1f} ms, contacts {st['contacts']}, iterations {st['iterations']}")
+    return {"value": scene.P * scene.N / dt, "unit": "particle-substeps/s", "ms_per_host_step": 1e3 * dt,
+            "contacts_mean": sum(st["contacts"]) / scene.N, "contact_nodes_mean": sum(st["contact_nodes"]) / scene.N,
+            "iterations_per_substep": st["iterations"],
+            "us_per_iteration": (round(1e3 * prof["ms"]["solve"] / prof["solver_iterations"], 2)
+                                 if prof["solver_iterations"] else None),
+            "config": "gripper: 250000 elastic particles, 96^3 grid, two jaws closing at 0.05 m/s started "
+                      "0.065 m inside the tips, mu=0.8, h=1e-4 s, 10 substeps, eps_r=1e-6"}
+
+
+def cpu_baseline(args) -> dict:
+    """The FP64 oracle, as it stands, single-threaded, and the GPU library on
+    the same input: one substep of the granular pour (1M particles) started
+    with its bottom layer 0.7 mm inside the box tops at 1 m/s (the
+    benchmark's contact density)."""
+    import torch
+    from oracle import oracle as O
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+    O.build(force=not os.path.exists(O.LIB))
+    scene = I.granular_pour(n_particles=args.particles, sink=0.5 / 128 + 7e-4)
+    scene.N = 1
+    scene.max_iter = args.max_iter
+    sim = M.Sim(scene, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    status, _, st_g = sim.step()
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    sim.close()
+    log(f"cpu baseline: GPU {t_gpu:.3f} s, {st_g['iterations'][0]} iterations; now the oracle")
+    ora = O.OracleSim(scene)
+    t0 = time.perf_counter()
+    rc, _, st_o = ora.host_step()
+    t_cpu = time.perf_counter() - t0
+    st_o = st_o[0]
+    return {"value": scene.P / t_cpu, "unit": "particle-substeps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one substep of the {scene.P}-particle granular pour started 0.7 mm inside the box "
+                       f"tops at 1 m/s: {st_o['n_contacts']} contacts, {st_o['n_contact_nodes']} contact "
+                       f"nodes, {st_o['iterations']} Algorithm 1 iterations, {t_cpu:.1f} s single-threaded "
+                       f"FP64"),
+            "status": rc, "oracle_iterations": st_o["iterations"],
+            "gpu_same_sample": {"value": scene.P / t_gpu, "seconds": t_gpu,
+                                "iterations": st_g["iterations"][0], "contacts": st_g["contacts"][0]},
+            "host": host_info()}
+
+
+# ---------------------------------------------------------------------------
+# batched form
+# ---------------------------------------------------------------------------
+def run_batched(args) -> dict:
+    import numpy as np
+    import torch
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+
+    scene = I.batched()
+    scene.max_iter = args.max_iter
+    P, N, n_envs = scene.P, scene.N, len(scene.envs)
+    K = BATCH_HOST_STEPS
+    log(f"batched: {n_envs} environments, P={P}, the {K} host steps of the run")
+    spb, tuning = 0, None
+    if args.autotune:
+        from paper_2503_05046_amd import autotune
+        spb, tuning = autotune.tune(scene, candidates=(64, 96, 128, 192, 256), warmup_steps=8,
+                                    trial_steps=2, log=log)
+        log(f"autotune: {spb} contact nodes per solver block")
+    # warm the kernels at these sizes (a throwaway handle, one host step)
+    w = M.Sim(scene, solver_slots_per_block=spb)
+    w.step()
+    w.close()
+    sim = M.Sim(scene, solver_slots_per_block=spb)
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    longest = []
+    for i in range(K):
+        _, _, st = sim.step()
+        longest += st["iterations"]
+        log(f"batched host step {i}: contacts {st['contacts']}, longest solve {max(st['iterations'])} iterations")
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    prof = sim.profile(False)
+    sim.close()
+    # the same run as one HIP graph replay (recording included)
+    gsim = M.Sim(scene, solver_slots_per_block=spb)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gsim.step_graph(K)
+    torch.cuda.synchronize()
+    t_g = time.perf_counter() - t0
+    gsim.close()
+    log(f"graph: {K} host steps in one replay, {t_g:.2f} s")
+    # looping single-environment handles over every environment
+    sims = [M.Sim(I.single_env(scene, e)) for e in range(n_envs)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(K):
+        for s in sims:
+            s.step()
+        log(f"loop host step {i} done ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+    for s in sims:
+        s.close()
+    value_b = P * N * K / t_b
+    value_l = P * N * K / t_loop
+    return {
+        "metric": "particle-substeps/s (batched, 64 environments, contact residual 1e-6)",
+        "value": value_b, "unit": "particle-substeps/s", "ms_per_host_step": 1e3 * t_b / K,
+        "config": (f"batched: {n_envs} independent environments, {P} particles (log-uniform 5k-100k each), "
+                   f"64^3 grids, elastic/sand, 1-3 boxes, h=1e-4 s, {K * N} substeps ({K} host steps), "
+                   f"eps_r=1e-6"),
+        "loop": {"value": value_l, "ms_per_host_step": 1e3 * t_loop / K,
+                 "method": f"all {n_envs} single-environment handles stepped in turn, every host step"},
+        "batched_over_loop": value_b / value_l,
+        "graph": {"value": P * N * K / t_g, "ms_per_host_step": 1e3 * t_g / K,
+                  "method": f"the {K} host steps as one HIP graph (mpm_step_graph), recording included"},
+        "solver_slots_per_block": spb or 128,
+        "autotune": ({"chosen": spb, "ms_per_step": {k: round(1e3 * t, 1) for k, t in tuning.items()}}
+                     if tuning else None),
+        "solve_share": prof["ms"]["solve"] / max(1e-9, sum(prof["ms"].values())),
+        "longest_solve_iterations_mean": float(np.mean(longest)),
+    }
+
+
+# ---------------------------------------------------------------------------
+# forward + backward form
+# ---------------------------------------------------------------------------
+def run_fwd_bwd(args) -> dict:
+    import torch
+    from paper_2503_05046_amd import diff
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+
+    scene = I.differentiable()
+    scene.max_iter = args.max_iter
+    P, N, steps = scene.P, scene.N, DIFF_HOST_STEPS
+    log(f"forward + backward: P={P}, {steps} host steps of {N} substeps, checkpoint every host step")
+    sim = M.Sim(scene, tape_substeps=N)
+    path = diff.RigidPath(scene)
+    dev = sim.device
+    x0, v0, F0, C0 = (torch.from_numpy(a).to(dev) for a in (scene.x, scene.v, scene.F, scene.C))
+    V0 = torch.tensor([list(r.V) for r in scene.rigids], dtype=torch.float64)
+    E0 = torch.tensor([scene.envs[0].E], dtype=torch.float64)
+    # one untimed host step first (first launches at these sizes)
+    diff._run(sim, path, 1, 0, x0, v0, F0, C0, V0, record=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    diff._run(sim, path, steps, 0, x0, v0, F0, C0, V0, record=False)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    log(f"forward: {t_fwd:.2f} s")
+    u = torch.zeros(3, dtype=torch.float32, device=dev, requires_grad=True)
+    E = E0.clone().requires_grad_(True)
+    V = V0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, v, F, C = diff.simulate(sim, path, steps, 1, x0, v0 + u[:, None], F0, C0, E, V)
+    com = x.mean(dim=1)
+    com[0].backward(retain_graph=True)
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    log(f"forward + backward (row x): {t_fb:.2f} s")
+    rows = [[*u.grad.cpu().tolist(), float(E.grad[0]), *V.grad[0].tolist()]]
+    t0 = time.perf_counter()
+    for a in (1, 2):  # the Jacobian's other rows: one more reverse pass each
+        gu, gE, gV = torch.autograd.grad(com[a], (u, E, V), retain_graph=a < 2)
+        rows.append([*gu.cpu().tolist(), float(gE[0]), *gV[0].tolist()])
+    torch.cuda.synchronize()
+    t_rows = time.perf_counter() - t0
+    sim.close()
+    return {
+        "metric": "particle-substeps/s (forward + backward, contact residual 1e-6)",
+        "value": P * N * steps / t_fb, "unit": "particle-substeps/s", "seconds": t_fb,
+        "config": (f"differentiable: {P}-particle elastic cube, 96^3 grid, pushed by a box at 0.5 m/s, "
+                   f"{N * steps} substeps, checkpoint every {N} substeps, eps_r=1e-6; loss x of the final "
+                   f"centre of mass"),
+        "forward_s": t_fwd, "forward_backward_s": t_fb, "fwd_bwd_over_fwd": t_fb / t_fwd,
+        "forward_note": "both timed after one untimed host step on the same handle",
+        "jacobian": {"rows": "d(mean x, mean y, mean z of the final particles)",
+                     "columns": "d(initial velocity offset x, y, z), dE, d(box velocity x, y, z)",
+                     "values": rows, "extra_rows_s": t_rows},
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gripper,4m",
+                    help="comma-separated subset of plain, batched, fwd_bwd, gripper, 4m")
+    ap.add_argument("--particles", type=int, default=1_000_000)
+    ap.add_argument("--max-iter", type=int, default=200_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batched form: pick the solver's contact nodes per block with the autotuner first")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run one device copy of BYTES (scale for the PMC byte counters)")
+    args = ap.parse_args()
+    if args.copy_calibration > 0:
+        return copy_calibration(args.copy_calibration)
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (a single scene "
+              "would shard into slabs, one per GPU, and the "
+              "environments of the batched form would be assigned to GPUs whole). Run with --gpus 1.",
+              file=sys.stderr)
+        return 2
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        return 2
+    forms = set(f.strip() for f in args.forms.split(",") if f.strip())
+
+    out = {"metric": "particle-substeps/s (plain substep at contact residual 1e-6)"}
+    if "plain" in forms:
+        r = run_plain(args)
+        scene = r.pop("scene")
+        out.update({
+            "value": r["value"], "unit": "particle-substeps/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+            "config": {"workload": (f"granular pour: {scene.P} Drucker-Prager sand particles, 128^3 grid, "
+                                    f"4 static boxes, h=1e-4 s, {scene.N} substeps per host step, "
+                                    f"{RUN_HOST_STEPS * scene.N} substeps, eps_r=1e-6; one step = one "
+                                    f"host step"),
+                       "particles": scene.P, "substeps_per_step": scene.N, "parallelism": "single GPU",
+                       "window": r["window"]},
+            "roofline": r["roofline"], "kernels": r["kernels"], "solver": r["solver"],
+            "host_step_ms": r["host_step_ms"],
+        })
+    extra = {}
+    if "4m" in forms:
+        extra["streaming_4M"] = run_streaming_4m(args)
+    if "gripper" in forms:
+        extra["gripper_dense"] = run_gripper_dense(args)
+    if "batched" in forms:
+        extra["batched"] = run_batched(args)
+    if "fwd_bwd" in forms:
+        extra["fwd_bwd"] = run_fwd_bwd(args)
+    if extra:
+        out["forms"] = extra
+    if "plain" in forms and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
     return 0
 

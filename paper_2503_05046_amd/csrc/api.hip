@@ -705,6 +705,10 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         // MPM_SOLVER_SCATTER=0 keeps every environment on the two-barrier form
         const char* sc = getenv("MPM_SOLVER_SCATTER");
         h->w.qn_scatter = (sc && atoi(sc) == 0) ? 0 : 1;
+        // MPM_SOLVER_LAUNCH=plain launches the solver without the cooperative
+        // API (profiler runs); the grid never exceeds the co-resident blocks
+        const char* ln = getenv("MPM_SOLVER_LAUNCH");
+        h->w.qn_plain_launch = (ln && strcmp(ln, "plain") == 0) ? 1 : 0;
     }
     h->w.n_rigid = 0;
     int tiles = 0;

@@ -1636,19 +1636,26 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.env_stride = env_stride;
     A.cnt = w.cnt;
     void* args[] = {&A};
+    auto launch = [&](const void* fn) -> hipError_t {
+        if (w.qn_plain_launch) {
+            // blocks <= the co-resident count (qn_max_blocks), so all are resident
+            // on an otherwise idle device; every barrier wait is bounded regardless
+            return hipLaunchKernel(fn, dim3(blocks), dim3(kQnThreads), args, 0, s);
+        }
+        return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kQnThreads), args, 0, s);
+    };
     if (w.qn_scatter && w.n_envs == 1) {
         // the one-barrier kernel, then the two-barrier kernel for what it left.
         // With several environments the second launch would start only after
         // the first kernel's slowest environment, so the batched form keeps the
         // two-barrier kernel for all of them.
         A.env_pend = w.qn_pend;
-        const hipError_t e =
-            hipLaunchCooperativeKernel((const void*)k_qn<true>, dim3(blocks), dim3(kQnThreads), args, 0, s);
+        const hipError_t e = launch((const void*)k_qn<true>);
         if (e != hipSuccess) return e;
     } else {
         A.env_pend = nullptr;
     }
-    return hipLaunchCooperativeKernel((const void*)k_qn<false>, dim3(blocks), dim3(kQnThreads), args, 0, s);
+    return launch((const void*)k_qn<false>);
 }
 
 // Blocks of k_qn that can be resident at once (the cooperative launch limit).

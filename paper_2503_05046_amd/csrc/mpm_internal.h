@@ -194,6 +194,8 @@ struct Work {
     int qn_blocks;           // co-resident solver blocks (capacity of partial and qn_map)
     int qn_compact;          // 1: blocks that fit take the compact node pass (0 only to test the other)
     int qn_scatter;          // 1: environments that fit take the solver's one-barrier form
+    int qn_plain_launch;     // 1: launch the solver with hipLaunchKernel instead of the cooperative API
+                             //    (the grid is still sized to the co-resident block count)
     double* qn_uacc;         // [3][3][cap_c] per-contact sums of the one-barrier form
     double* qn_vcblk;        // [kMaxQnBlocks][6][kQnScatterMax] per-block contact velocities
     int* qn_pend;            // [n_envs] environments the one-barrier solver kernel left to the other

@@ -91,6 +91,11 @@ def _run(sim, path, n_steps, step0, x, v, F, C, V, W=None, record: bool = False)
     Wn = None if W is None else W.detach().cpu().numpy().astype(np.float64).reshape(-1, 3)
     for j in range(n_steps):
         status, _, _ = sim.step(path.states(step0 + j, Vn, Wn))
+        if status != M.MPM_OK:
+            # a contact solve that stopped at its iteration cap: the implicit
+            # differentiation of the recorded solve assumes its optimum
+            raise M.MPMError(status, f"host step {step0 + j} of a differentiated segment"
+                                     f"{' (recording)' if record else ''}")
 
 
 def _make_function():

@@ -180,11 +180,13 @@ def plain_cube(contact: bool = False, seed: int = 0, n_side: int = 20) -> Scene:
                  x, v, F, C)
 
 
-def granular_pour(n_particles: int = 1_000_000, seed: int = 1, n: int = 128) -> Scene:
-    """Sand block falling at 1 m/s onto four static boxes (dx = 1/128)."""
+def granular_pour(n_particles: int = 1_000_000, seed: int = 1, n: int = 128, sink: float = 0.0) -> Scene:
+    """Sand block falling at 1 m/s onto four static boxes (dx = 1/128). With
+    sink > 0 the block starts sink metres lower; past dx/2 its bottom layer
+    starts inside the box tops (z = 0.15), so the first substep has contacts."""
     rng = np.random.default_rng(seed)
     dx = 1.0 / n
-    z_s = 0.15 + 0.5 * dx
+    z_s = 0.15 + 0.5 * dx - sink
     lo = np.array([0.3, 0.3, z_s])
     pos = lo + rng.uniform(0.0, 0.4, (n_particles, 3))
     V0 = 0.4 ** 3 / n_particles
@@ -197,8 +199,10 @@ def granular_pour(n_particles: int = 1_000_000, seed: int = 1, n: int = 128) -> 
     return Scene("granular_pour", 1e-4, 10, [env], boxes, x, v, F, C)
 
 
-def gripper(n_particles: int = 250_000, seed: int = 2, n: int = 96) -> Scene:
-    """Elastic ellipsoid between two kinematic jaws closing at 0.05 m/s."""
+def gripper(n_particles: int = 250_000, seed: int = 2, n: int = 96, overlap: float = 0.0) -> Scene:
+    """Elastic ellipsoid between two kinematic jaws closing at 0.05 m/s. With
+    overlap > 0 each jaw starts that many metres inside the ellipsoid's tip
+    (a dense-contact state: about 2e4 particles inside the jaws at 0.065 m)."""
     rng = np.random.default_rng(seed)
     dx = 1.0 / n
     semi = np.array([0.25, 0.185, 0.185])
@@ -212,7 +216,7 @@ def gripper(n_particles: int = 250_000, seed: int = 2, n: int = 96) -> Scene:
     env = EnvSpec(dims=(n, n, n), dx=dx, E=5e4, nu=0.4, rho=1000.0, V0=V0,
                   k=_stiffness(5e4, V0), p_begin=0, p_end=n_particles)
     jaws = [RigidSpec(env=0, shape=BOX, mu=0.8, motion=KINEMATIC, half=(0.02, 0.25, 0.25),
-                      t=(0.5 + s * (0.25 + 0.02), 0.5, 0.5), V=(-s * 0.05, 0.0, 0.0))
+                      t=(0.5 + s * (0.25 + 0.02 - overlap), 0.5, 0.5), V=(-s * 0.05, 0.0, 0.0))
             for s in (-1.0, 1.0)]
     x, v, F, C = _state(pos, (0.0, 0.0, 0.0))
     return Scene("gripper", 1e-4, 10, [env], jaws, x, v, F, C)

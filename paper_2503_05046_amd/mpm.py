@@ -90,6 +90,17 @@ class ProfileData(ct.Structure):
 
 
 _lib = None
+_live = None  # handles not yet closed (weak references), closed at interpreter exit
+
+
+def _close_live() -> None:
+    """atexit: release every handle still open while the HIP runtime and
+    torch are intact (not from finalizers during interpreter teardown)."""
+    for sim in list(_live or ()):
+        try:
+            sim.close()
+        except Exception:
+            pass
 
 
 def load():
@@ -338,6 +349,13 @@ class Sim:
         self.stream = torch.cuda.current_stream(dev)
         d.stream = self.stream.cuda_stream
         self.handle = mpm_create(d)
+        global _live
+        if _live is None:
+            import atexit
+            import weakref
+            _live = weakref.WeakSet()
+            atexit.register(_close_live)
+        _live.add(self)
         self.rigid_ids = [mpm_add_rigid_sdf(self.handle, r.env, rigid_desc(r)) for r in scene.rigids]
 
     @property
@@ -406,6 +424,9 @@ class Sim:
             self.handle = None
 
     def __del__(self):
+        import sys
+        if sys.is_finalizing():
+            return  # the atexit hook has released it; no HIP calls during teardown
         try:
             self.close()
         except Exception:

@@ -188,3 +188,81 @@ def test_gripper_full_size_momentum_balance(mpm):
              f"mismatch {mis:.3e}, bound {tol:.3e}, contacts {max(st['contacts'])}")
         assert mis <= tol, (dP, expected, tol)
     sim.close()
+
+
+def test_full_size_contact_substep_elementwise(mpm, oracle):
+    """One substep of the full benchmark scene in contact, every particle
+    against the oracle at the benchmark tolerance eps_r = 1e-6: the sand
+    block (1M particles, 128^3 grid, four boxes) started with its bottom
+    layer 0.7 mm inside the box tops at 1 m/s (about 1,400 contacts and 7,500
+    contact nodes, the benchmark's contact density, solved by the one-barrier
+    form with a group of tens of blocks). Both solves stop at
+    |grad~| < thr, so the particle velocities agree within thr_gpu + thr_oracle
+    in the mass norm (the Hessian dominates M, and G2P is an average); x and F
+    are compared at the per-substep bar."""
+    scene = I.granular_pour(n_particles=1_000_000, sink=0.5 / 128 + 7e-4)
+    scene.N = 1
+    scene.max_iter = 200_000
+    env = scene.envs[0]
+    sim = mpm.Sim(scene)
+    status, imp_g, st_g = sim.step()
+    assert status == 0
+    out = sim.state()
+    sim.close()
+    _log(f"full size in contact: GPU {st_g['contacts'][0]} contacts, {st_g['contact_nodes'][0]} contact nodes, "
+         f"{st_g['iterations'][0]} iterations; oracle on all {scene.P} particles")
+    ora = oracle.OracleSim(scene)
+    rc, imp_o, st_o = ora.host_step()
+    assert rc == oracle.OK
+    st_o = st_o[0]
+    _log(f"  oracle: {st_o['n_contacts']} contacts, {st_o['iterations']} iterations")
+    assert st_g["contacts"][0] == st_o["n_contacts"] > 1000
+    assert st_g["residual"][0] < st_g["threshold"][0]
+    from tests.parity import m_norm
+    bound = st_g["threshold"][0] + st_o["threshold"] + 1e-6 * np.sqrt(env.m_p * scene.P)
+    dv = m_norm(out["v"] - ora.v, env.m_p)
+    err = field_errors(out, ora, env.dx)
+    _log(f"  |v_gpu - v_oracle|_M {dv:.3e} (bound {bound:.3e}); field errors {err}")
+    assert dv <= bound
+    assert err["x"] < 1e-5 and err["F"] < 1e-5, err
+    # the impulses on the boxes: their difference is the mass-weighted sum of
+    # the velocity differences, bounded by sqrt(M) times the M-norm bound
+    m_tot = env.m_p * scene.P
+    assert float(np.abs(imp_g[:, :3] - imp_o[:, :3]).max()) <= np.sqrt(m_tot) * bound
+
+
+def test_gripper_dense_contact(mpm):
+    """One substep of the full gripper in dense contact (both jaws started
+    0.065 m inside the ellipsoid's tips: about 2e4 contacts, more than the
+    one-barrier form holds) at eps_r = 1e-6, against the oracle's result
+    stored by tests/golden/make_gripper_dense.py: the contact count, the
+    velocity of every particle within three cells of the jaws (mass-norm
+    bound as above, with the oracle's stored threshold) and the impulses."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "gripper_dense_contact.npz")
+    ref = np.load(path)
+    overlap = 0.065
+    scene = I.gripper(overlap=overlap)
+    scene.N = 1
+    scene.max_iter = 200_000
+    env = scene.envs[0]
+    sel = np.abs(scene.x[0].astype(np.float64) - 0.5) > 0.25 - overlap - 3.0 * env.dx
+    assert int(sel.sum()) == int(ref["n_selected"])
+    sim = mpm.Sim(scene)
+    status, imp_g, st_g = sim.step()
+    assert status == 0
+    out = sim.state()
+    sim.close()
+    _log(f"gripper dense: GPU {st_g['contacts'][0]} contacts, {st_g['contact_nodes'][0]} contact nodes, "
+         f"{st_g['iterations'][0]} iterations; oracle {int(ref['n_contacts'])} contacts, "
+         f"{int(ref['iterations'])} iterations")
+    assert st_g["contacts"][0] == int(ref["n_contacts"]) > 15000
+    assert st_g["contact_nodes"][0] == int(ref["n_contact_nodes"])
+    assert st_g["residual"][0] < st_g["threshold"][0]
+    from tests.parity import m_norm
+    bound = st_g["threshold"][0] + float(ref["threshold"]) + 1e-6 * np.sqrt(env.m_p * scene.P)
+    dv = m_norm(out["v"][:, sel] - ref["v"].astype(np.float64), env.m_p)
+    _log(f"  near the jaws: |v_gpu - v_oracle|_M {dv:.3e} (bound {bound:.3e})")
+    assert dv <= bound
+    m_tot = env.m_p * scene.P
+    assert float(np.abs(imp_g[:, :3] - ref["impulse"][:, :3]).max()) <= np.sqrt(m_tot) * bound
