@@ -148,7 +148,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->c_coef = L.take<double>(11 * ((C + 63) / 64) * 64);
     // the solver's one-barrier form runs for handles of one environment only
     w->qn_uacc = z.n_envs == 1 ? L.take<double>((size_t)9 * C) : nullptr;
-    w->qn_vcblk = z.n_envs == 1 ? L.take<double>((size_t)kMaxQnBlocks * 6 * kQnScatterMax) : nullptr;
+    w->qn_vcblk = z.n_envs == 1 ? L.take<double>((size_t)kQnMaxGroup * 6 * kQnScatterMax) : nullptr;
     w->qn_pend = L.take<int>(z.n_envs);
     w->pk_a = L.take<unsigned>(27 * C);
     w->pk_b = L.take<unsigned>(27 * C);

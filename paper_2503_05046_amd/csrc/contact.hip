@@ -547,7 +547,7 @@ struct QnArgs {
     int compact;               // 0: no block takes the compact node pass
     int* env_pend;             // per environment: 1 when k_qn<true> left it to k_qn<false>
     double* u_acc;             // [3 buffers][3][cap] per-contact sums U_c of the one-barrier form
-    double* vc_blk;            // per block: [6][kScatterMax] v_c, u_c of the line search's contacts
+    double* vc_blk;            // per group rank: [6][kScatterMax] v_c, u_c of the line search's contacts
     int timers;                // 1: the first block of each environment times the solver's phases
     int slots_per_block;       // contact nodes per block that set an environment's group size
     DevCounters* cnt;
@@ -1166,7 +1166,7 @@ k_qn(QnArgs A) {
         if (kOne && !all_compact) continue;  // left to k_qn<false>
         constexpr bool scatter = kOne;
         const bool cmp = kOne || compact;  // the compact node pass
-        double* vblk = A.vc_blk + (size_t)blockIdx.x * 6 * kScatterMax;  // [6][kScatterMax]: v_c, u_c
+        double* vblk = A.vc_blk + (size_t)rank * 6 * kScatterMax;  // [6][kScatterMax]: v_c, u_c (rank < G <= kQnMaxGroup)
         if (scatter) {
             for (int t = tid; t < n_u; t += T) {
                 const int c = u_list[t];

@@ -197,7 +197,7 @@ struct Work {
     int qn_plain_launch;     // 1: launch the solver with hipLaunchKernel instead of the cooperative API
                              //    (the grid is still sized to the co-resident block count)
     double* qn_uacc;         // [3][3][cap_c] per-contact sums of the one-barrier form
-    double* qn_vcblk;        // [kMaxQnBlocks][6][kQnScatterMax] per-block contact velocities
+    double* qn_vcblk;        // [kQnMaxGroup][6][kQnScatterMax] contact velocities per rank of the group
     int* qn_pend;            // [n_envs] environments the one-barrier solver kernel left to the other
 };
 
