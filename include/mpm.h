@@ -113,7 +113,16 @@ typedef struct {
     int32_t solver_slots_per_block; /* contact nodes per block of the contact solver, which
                                   sets each environment's group of blocks (0 = 128; the
                                   autotuner of the Python package picks it per scene) */
+    int32_t solver;            /* MPM_SOLVER_QN (0): Algorithm 1, the block-diagonal quasi-Newton
+                                  iteration of Sec. IV-C. MPM_SOLVER_NEWTON (1): a study variant of
+                                  the same solve (same objective, stopping test and exact line
+                                  search) whose search direction solves the full Hessian system by
+                                  conjugate gradients preconditioned with the node blocks
+                                  Algorithm 1 inverts; for comparison only. The workspace grows by
+                                  224 bytes per contact node and 128 per contact. */
 } mpm_desc;
+
+enum { MPM_SOLVER_QN = 0, MPM_SOLVER_NEWTON = 1 };
 
 /* Rigid primitive (body frame) with its initial pose and twist. */
 typedef struct {
@@ -170,6 +179,8 @@ typedef struct {
     int32_t* contact_nodes;    /* [N] grid nodes touched by a contact stencil */
     double* residual;          /* [N] final |grad~| */
     double* threshold;         /* [N] eps_a + eps_r max(|p~|, |j~|) at exit */
+    int64_t total_inner_iterations; /* MPM_SOLVER_NEWTON: conjugate-gradient iterations of the
+                                  longest solve of each substep, summed (0 for MPM_SOLVER_QN) */
 } mpm_step_stats;
 
 /* Kernel classes timed by mpm_profile. */
@@ -260,6 +271,16 @@ mpm_status mpm_profile(mpm_handle* h, int32_t enable, mpm_profile_data* out);
 /* Current pose and twist of rigid body id (host). */
 mpm_status mpm_get_rigid_state(const mpm_handle* h, int32_t id, mpm_rigid_state* s);
 
+/* Set the pose and twist of rigid body id to s advanced by host_steps >= 0
+ * host steps of the library's kinematic rule (per host step t += N h V and
+ * R <- Rot(N h w) R, as after each mpm_step with in = NULL; only kinematic
+ * bodies advance). s is the body's reference state: the reverse pass reports
+ * dV_kinematic and dw_kinematic with respect to its twist, through the host
+ * steps between it and the recording as well (see mpm_rigid_grad). A pose
+ * passed to mpm_step as `in` becomes the reference instead. Host only;
+ * MPM_EINVAL for a bad id, host_steps < 0 or an invalid pose. */
+mpm_status mpm_set_rigid_state(mpm_handle* h, int32_t id, const mpm_rigid_state* s, int32_t host_steps);
+
 /* Release the handle (not the borrowed memory). Safe on NULL. */
 void mpm_destroy(mpm_handle* h);
 
@@ -294,16 +315,17 @@ typedef struct {
     double dV[3];            /* through the velocity V used in every recorded host step */
     double dt[3];            /* through the position t, as a common shift of every recorded pose */
     double dV_kinematic[3];  /* dV plus the library's own kinematic update of t (t advances
-                                by N h V after each host step), i.e. the full derivative when
-                                mpm_step was called with in = NULL */
+                                by N h V after each host step), i.e. the full derivative with
+                                respect to the velocity of the body's reference state (the last
+                                mpm_set_rigid_state, else the first recorded pose) when the
+                                host steps since it ran with in = NULL */
     double dw[3];            /* through the angular velocity w in the velocity field
                                 V + w x (x - t) of every recorded host step */
     double dR[3];            /* through a small rotation (world rotation vector, about t) of
                                 the first recorded pose, later poses following it by the
                                 kinematic advance (R turns by N h w after each host step) */
     double dw_kinematic[3];  /* dw plus the kinematic advance's dependence of the poses on w,
-                                i.e. the full derivative when mpm_step was called with
-                                in = NULL */
+                                from the reference state as for dV_kinematic */
 } mpm_rigid_grad;
 
 /* Empty the tape; with record = 1 the following mpm_step calls record, with

@@ -17,6 +17,8 @@
 
 using namespace mpm;
 
+static_assert(kSolverNewton == MPM_SOLVER_NEWTON, "solver ids of the ABI and the kernels");
+
 namespace {
 
 thread_local std::string g_err;
@@ -41,6 +43,7 @@ mpm_status fail(mpm_status st, const char* fmt, ...) {
 constexpr int kMaxRigidTotal = 256;
 constexpr int kMaxQnBlocks = 1024;
 constexpr int kQnItemsPerBlock = 128;  // contact nodes per solver block
+constexpr int kTransferBlocks = 4096;  // default blocks of the tiled P2G and G2P launches
 constexpr size_t kAlign = 256;
 
 struct Layout {
@@ -57,7 +60,7 @@ struct Layout {
 
 struct Sizes {
     long long P = 0, n_nodes = 0, cap_c = 0, cap_s = 0;
-    int n_tiles = 0, n_envs = 0, N = 1, tape_cap = 0;
+    int n_tiles = 0, n_envs = 0, N = 1, tape_cap = 0, solver = 0;
 };
 
 mpm_status validate(const mpm_desc* d, Sizes* sz) {
@@ -71,6 +74,7 @@ mpm_status validate(const mpm_desc* d, Sizes* sz) {
     if (d->max_iter < 1) return fail(MPM_EINVAL, "max_iter must be >= 1");
     if (d->ls_max_steps < 0) return fail(MPM_EINVAL, "ls_max_steps must be >= 0");
     if (d->solver_slots_per_block < 0) return fail(MPM_EINVAL, "solver_slots_per_block must be >= 0");
+    if (d->solver != MPM_SOLVER_QN && d->solver != MPM_SOLVER_NEWTON) return fail(MPM_EINVAL, "unknown solver %d", d->solver);
     if (d->n_particles < 1 || d->n_particles > (1ll << 31) - 1)
         return fail(MPM_EINVAL, "n_particles out of range");
     long long expect = 0, nodes = 0;
@@ -109,6 +113,7 @@ mpm_status validate(const mpm_desc* d, Sizes* sz) {
     sz->cap_c = d->max_contacts > 0 ? d->max_contacts : d->n_particles;
     sz->cap_s = std::min<long long>(27 * sz->cap_c, nodes);
     sz->tape_cap = d->tape_substeps;
+    sz->solver = d->solver;
     return MPM_OK;
 }
 
@@ -150,6 +155,10 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->qn_uacc = z.n_envs == 1 ? L.take<double>((size_t)9 * C) : nullptr;
     w->qn_vcblk = z.n_envs == 1 ? L.take<double>((size_t)kQnMaxGroup * 6 * kQnScatterMax) : nullptr;
     w->qn_pend = L.take<int>(z.n_envs);
+    // the exact-Newton variant's vectors, only when it is asked for
+    w->nt_slot = z.solver == MPM_SOLVER_NEWTON ? L.take<double>((size_t)kNtSlot * z.cap_s) : nullptr;
+    w->nt_con = z.solver == MPM_SOLVER_NEWTON ? L.take<double>((size_t)kNtCon * z.cap_c) : nullptr;
+    w->solver = z.solver;
     w->pk_a = L.take<unsigned>(27 * C);
     w->pk_b = L.take<unsigned>(27 * C);
     w->pv_a = L.take<unsigned>(27 * C);
@@ -199,9 +208,135 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     return L.off + kAlign;
 }
 
+// What a workspace must hold before its first host step: empty grid
+// accumulators and tile maps, zero counters and solver barriers, and the
+// environment table (queued on s).
+hipError_t init_workspace(const Work& W, const DevEnv* denv, hipStream_t s) {
+    hipError_t e = hipMemsetAsync(W.acc, 0, sizeof(float4) * W.n_nodes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.vel, 0, sizeof(float4) * W.n_nodes, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.tile_flag, 0, sizeof(unsigned) * W.n_tiles, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.ntile_mark, 0, sizeof(unsigned) * W.n_tiles, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.ptile_of, 0xFF, sizeof(int) * W.n_tiles, s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.cnt, 0, sizeof(DevCounters), s);
+    if (e == hipSuccess) e = hipMemsetAsync(W.env_bar, 0, sizeof(unsigned) * kBarStride * W.n_envs, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(W.env_ctr, 0, sizeof(unsigned) * kCtrLanes * kCtrStride * W.n_envs, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(W.envs, denv, sizeof(DevEnv) * W.n_envs, hipMemcpyHostToDevice, s);
+    return e;
+}
+
+// Solver options of a handle: contact nodes per block (the description's, else
+// the default), and the environment overrides used by sweeps and tests:
+// MPM_SOLVER_SLOTS_PER_BLOCK overrides the block size, MPM_SOLVER_MAX_BLOCKS
+// caps the blocks (below it, environments share blocks), MPM_SOLVER_COMPACT=0
+// sends every block through the general node pass, MPM_SOLVER_SCATTER=0 keeps
+// every environment on the two-barrier form, MPM_SOLVER_LAUNCH=plain launches
+// the solver without the cooperative API (profiler runs; the grid never
+// exceeds the co-resident blocks); MPM_SORT_POLICY=truncated (keys cut to
+// their top kTruncBits bits) or none (no reordering) selects an arm of the
+// sort ablation, with the plain scatter and gather.
+void solver_options(const mpm_desc* desc, Work* w, int* slots_per_block, int* qn_cap) {
+    const char* spb = getenv("MPM_SOLVER_SLOTS_PER_BLOCK");
+    *slots_per_block = spb ? std::max(1, atoi(spb))
+                           : (desc->solver_slots_per_block > 0 ? desc->solver_slots_per_block : kQnItemsPerBlock);
+    const char* mb = getenv("MPM_SOLVER_MAX_BLOCKS");
+    if (mb && atoi(mb) > 0) *qn_cap = std::min(*qn_cap, atoi(mb));
+    const char* cp = getenv("MPM_SOLVER_COMPACT");
+    w->qn_compact = (cp && atoi(cp) == 0) ? 0 : 1;
+    const char* sc = getenv("MPM_SOLVER_SCATTER");
+    w->qn_scatter = (sc && atoi(sc) == 0) ? 0 : 1;
+    const char* ln = getenv("MPM_SOLVER_LAUNCH");
+    w->qn_plain_launch = (ln && strcmp(ln, "plain") == 0) ? 1 : 0;
+    // MPM_TRANSFER_BLOCKS: blocks of the tiled P2G and G2P launches
+    const char* tb = getenv("MPM_TRANSFER_BLOCKS");
+    w->transfer_blocks = (tb && atoi(tb) > 0) ? atoi(tb) : kTransferBlocks;
+    // MPM_SORT_POLICY=truncated or none selects an arm of the sort ablation
+    const char* sp = getenv("MPM_SORT_POLICY");
+    w->sort_policy = !sp ? kSortTiles
+                         : strcmp(sp, "truncated") == 0 ? kSortTruncated : strcmp(sp, "none") == 0 ? kSortNone : kSortTiles;
+}
+
+// Device table of the environments (tile and node bases in order, Lame
+// parameters, the Drucker-Prager slope); returns the sort key width in bits.
+int make_dev_envs(const mpm_env_desc* envs, int n_envs, DevEnv* out) {
+    int tiles = 0;
+    long long nodes = 0;
+    for (int e = 0; e < n_envs; ++e) {
+        const mpm_env_desc& E = envs[e];
+        DevEnv& D = out[e];
+        memset(&D, 0, sizeof(D));
+        for (int a = 0; a < 3; ++a) {
+            D.dims[a] = E.dims[a];
+            D.ntile[a] = (E.dims[a] + 3) / 4;
+            D.origin[a] = E.origin[a];
+            D.gravity[a] = E.gravity[a];
+        }
+        D.tile_base = tiles;
+        D.node_base = nodes;
+        tiles += D.ntile[0] * D.ntile[1] * D.ntile[2];
+        nodes += (long long)E.dims[0] * E.dims[1] * E.dims[2];
+        D.p_begin = E.p_begin;
+        D.p_end = E.p_end;
+        D.dx = E.dx;
+        D.inv_dx = 1.0f / E.dx;
+        D.D = 4.0f / (E.dx * E.dx);
+        D.mat.type = E.material;
+        D.mat.mu = (float)(E.E / (2.0 * (1.0 + E.nu)));
+        D.mat.la = (float)(E.E * E.nu / ((1.0 + E.nu) * (1.0 - 2.0 * E.nu)));
+        const double sphi = sin(E.friction_angle * M_PI / 180.0);
+        D.mat.alpha = (float)(sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi));
+        D.m_p = E.m_p;
+        D.V0 = E.V0;
+        D.k = E.k;
+        D.d = E.d;
+        D.eps_s = E.eps_s;
+        D.rigid_begin = D.rigid_end = 0;
+    }
+    int bits = 1;
+    while ((1ll << bits) < (long long)tiles) ++bits;
+    return bits + 6;
+}
+
+// Shape, motion, friction and pose of a rigid descriptor.
+mpm_status check_rigid(const mpm_rigid_desc* r) {
+    if (r->shape != MPM_HALF_SPACE && r->shape != MPM_BOX) return fail(MPM_EINVAL, "unknown shape");
+    if (r->motion != MPM_STATIC && r->motion != MPM_KINEMATIC && r->motion != MPM_DYNAMIC)
+        return fail(MPM_EINVAL, "unknown motion");
+    if (r->motion == MPM_DYNAMIC) {
+        if (r->shape != MPM_BOX) return fail(MPM_EINVAL, "dynamic bodies are boxes");
+        if (!(r->mass > 0.0) || !isfinite(r->mass)) return fail(MPM_EINVAL, "a dynamic body needs mass > 0");
+        for (int a = 0; a < 3; ++a) {
+            if (!(r->inertia[a] > 0.0) || !isfinite(r->inertia[a]))
+                return fail(MPM_EINVAL, "a dynamic body needs principal moments > 0");
+            if (!isfinite(r->force[a]) || !isfinite(r->torque[a]))
+                return fail(MPM_EINVAL, "external force and torque must be finite");
+        }
+    }
+    if (!(r->mu >= 0.0) || !isfinite(r->mu)) return fail(MPM_EINVAL, "mu must be >= 0");
+    if (r->shape == MPM_BOX && !(r->half[0] > 0 && r->half[1] > 0 && r->half[2] > 0))
+        return fail(MPM_EINVAL, "degenerate box");
+    if (r->shape == MPM_HALF_SPACE) {
+        const double nn = r->normal[0] * r->normal[0] + r->normal[1] * r->normal[1] + r->normal[2] * r->normal[2];
+        if (!(fabs(nn - 1.0) < 1e-9)) return fail(MPM_EINVAL, "half-space normal must be unit");
+    }
+    double RtR[9];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            double s = 0;
+            for (int q = 0; q < 3; ++q) s += r->R[q * 3 + a] * r->R[q * 3 + b];
+            RtR[a * 3 + b] = s;
+        }
+    for (int i = 0; i < 9; ++i)
+        if (fabs(RtR[i] - (i % 4 == 0 ? 1.0 : 0.0)) > 1e-9) return fail(MPM_EINVAL, "R must be a rotation");
+    return MPM_OK;
+}
+
 struct HostRigid {
     mpm_rigid_desc desc;  // shape, pose and twist (pose/twist updated as the step advances)
     int env;
+    int kin_steps = 0;    // kinematic host steps the pose has advanced from its reference state
+                          // (the last mpm_set_rigid_state, or a pose given to mpm_step)
+    int rec_steps = 0;    // the same at the start of the recording
 };
 
 __host__ __device__ void rodrigues_advance(double R[9], const double w[3], double dt) {
@@ -344,7 +479,7 @@ struct ProfScope {
     mpm_handle* h;
     int pair;
     ProfScope(mpm_handle* hh, int cls, int& next) : h(hh), pair(-1) {
-        if (!h->prof) return;
+        if (!h || !h->prof) return;
         pair = next++;
         if ((int)h->ev_class.size() <= pair) {
             hipEvent_t a, b;
@@ -371,24 +506,23 @@ int longest_solve(const SubstepStats* q, int n_envs) {
 // Solver plan for one host step: a group of blocks per environment, sized by
 // the environment's contact nodes in the previous step (at least one block,
 // at most kQnMaxGroup, all groups co-resident). With more environments than
-// co-resident blocks every block takes environments in turn. Fills the pinned
-// staging tables; returns the number of blocks.
-int plan_solver(mpm_handle* h, int* env_stride) {
-    const int n_envs = (int)h->envs.size();
-    const int cap = h->qn_cap;
+// co-resident blocks every block takes environments in turn. Fills the
+// staging tables qn_map and env_qn (g: scratch of n_envs entries); returns the
+// number of blocks.
+int plan_groups(int n_envs, const int* env_slots, int slots_per_block, int cap, int* g, int2* qn_map,
+                int* env_qn, int* env_stride) {
     if (n_envs > cap) {
-        for (int b = 0; b < cap; ++b) h->h_qn_map[b] = make_int2(b, 0);
+        for (int b = 0; b < cap; ++b) qn_map[b] = make_int2(b, 0);
         for (int e = 0; e < n_envs; ++e) {
-            h->h_env_qn[2 * e] = e % cap;
-            h->h_env_qn[2 * e + 1] = 1;
+            env_qn[2 * e] = e % cap;
+            env_qn[2 * e + 1] = 1;
         }
         *env_stride = cap;
         return cap;
     }
-    std::vector<int> g(n_envs);
     int total = 0;
     for (int e = 0; e < n_envs; ++e) {
-        g[e] = std::max(1, std::min(kQnMaxGroup, (h->env_slots[e] + h->slots_per_block - 1) / h->slots_per_block));
+        g[e] = std::max(1, std::min(kQnMaxGroup, (env_slots[e] + slots_per_block - 1) / slots_per_block));
         total += g[e];
     }
     while (total > cap) {  // shrink the largest groups until all fit
@@ -415,12 +549,43 @@ int plan_solver(mpm_handle* h, int* env_stride) {
     }
     int b = 0;
     for (int e = 0; e < n_envs; ++e) {
-        h->h_env_qn[2 * e] = b;
-        h->h_env_qn[2 * e + 1] = g[e];
-        for (int r = 0; r < g[e]; ++r) h->h_qn_map[b++] = make_int2(e, r);
+        env_qn[2 * e] = b;
+        env_qn[2 * e + 1] = g[e];
+        for (int r = 0; r < g[e]; ++r) qn_map[b++] = make_int2(e, r);
     }
     *env_stride = 0;
     return total;
+}
+
+int plan_solver(mpm_handle* h, int* env_stride) {
+    const int n_envs = (int)h->envs.size();
+    std::vector<int> g(n_envs);
+    return plan_groups(n_envs, h->env_slots.data(), h->slots_per_block, h->qn_cap, g.data(), h->h_qn_map,
+                       h->h_env_qn, env_stride);
+}
+
+// Device entry k of the rigid table from a descriptor in environment env
+// (static bodies carry a zero twist); extends the environment's range, so the
+// entries of one environment must be placed consecutively.
+void place_dev_rigid(const mpm_rigid_desc& d, int env, int k, DevRigid* R, DevEnv* denv) {
+    R->shape = d.shape;
+    R->env = env;
+    memcpy(R->normal, d.normal, sizeof(R->normal));
+    R->offset = d.offset;
+    memcpy(R->half, d.half, sizeof(R->half));
+    R->mu = d.mu;
+    memcpy(R->R, d.R, sizeof(R->R));
+    memcpy(R->t, d.t, sizeof(R->t));
+    if (d.motion == MPM_STATIC) {
+        memset(R->V, 0, sizeof(R->V));
+        memset(R->w, 0, sizeof(R->w));
+    } else {
+        memcpy(R->V, d.V, sizeof(R->V));
+        memcpy(R->w, d.w, sizeof(R->w));
+    }
+    DevEnv& D = denv[env];
+    if (D.rigid_end == D.rigid_begin) D.rigid_begin = D.rigid_end = k;
+    D.rigid_end = k + 1;
 }
 
 // Device-order rigid table (h_rigids) and each environment's rigid range from
@@ -434,51 +599,67 @@ void build_rigid_table(mpm_handle* h, std::vector<int>& order) {
     for (DevEnv& D : h->denv) D.rigid_begin = D.rigid_end = 0;
     for (int k = 0; k < nr; ++k) {
         const HostRigid& q = h->rigids[order[k]];
-        DevRigid& R = h->h_rigids[k];
-        R.shape = q.desc.shape;
-        R.env = q.env;
-        memcpy(R.normal, q.desc.normal, sizeof(R.normal));
-        R.offset = q.desc.offset;
-        memcpy(R.half, q.desc.half, sizeof(R.half));
-        R.mu = q.desc.mu;
-        memcpy(R.R, q.desc.R, sizeof(R.R));
-        memcpy(R.t, q.desc.t, sizeof(R.t));
-        if (q.desc.motion == MPM_STATIC) {
-            memset(R.V, 0, sizeof(R.V));
-            memset(R.w, 0, sizeof(R.w));
-        } else {
-            memcpy(R.V, q.desc.V, sizeof(R.V));
-            memcpy(R.w, q.desc.w, sizeof(R.w));
-        }
-        DevEnv& D = h->denv[q.env];
-        if (D.rigid_end == D.rigid_begin) D.rigid_begin = D.rigid_end = k;
-        D.rigid_end = k + 1;
+        place_dev_rigid(q.desc, q.env, k, h->h_rigids + k, h->denv.data());
     }
     h->w.n_rigid = nr;
+}
+
+// What one host step's device work needs besides the workspace: the
+// description, the sort key width, the solver's group sizing, the tape
+// position when recording, and the handle whose event timing is on (NULL for
+// none).
+struct StepCtx {
+    Work* w;
+    const mpm_desc* d;
+    int key_bits;
+    int slots_per_block;
+    bool rec;
+    int tape_len;
+    mpm_handle* prof;
+    bool phases;
+};
+
+StepCtx step_ctx(mpm_handle* h) {
+    StepCtx c;
+    c.w = &h->w;
+    c.d = &h->d;
+    c.key_bits = h->key_bits;
+    c.slots_per_block = h->slots_per_block;
+    c.rec = h->tape_on;
+    c.tape_len = h->tape_len;
+    c.prof = h;
+    c.phases = h->prof_phases;
+    return c;
 }
 
 // Device work of one host step on the handle's stream (the tables are already
 // uploaded). Inside a graph the step clears only its statistics (the replay
 // clears flags and impulse sums once), records neither tape nor events, and
 // ends by advancing the kinematic bodies on the device.
-mpm_status enqueue_host_step(mpm_handle* h, int qn_blocks, int env_stride, bool graph, int& npair, hipStream_t s) {
-    Work& W = h->w;
-    const mpm_desc& d = h->d;
+mpm_status enqueue_host_step(const StepCtx& c, int qn_blocks, int env_stride, bool graph, int& npair,
+                             hipStream_t s) {
+    Work& W = *c.w;
+    const mpm_desc& d = *c.d;
     const int N = d.N;
     const int ls_steps = d.ls_max_steps > 0 ? d.ls_max_steps : 100;
-    const int n_envs = (int)h->envs.size();
+    const int n_envs = W.n_envs;
     const int nr = W.n_rigid;
-    const bool rec = !graph && h->tape_on;
+    const bool rec = !graph && c.rec;
+    mpm_handle* h = c.prof;
     HIP_TRY(launch_clear_step(W, N, graph, s));
     {
         // once per host step: cell keys, stable sort, gather, tile list (Sec. V-A)
         ProfScope ps(h, MPM_K_SORT, npair);
-        HIP_TRY(launch_keys(W, d.x, s));
-        unsigned *keys_sorted, *idx_sorted;
-        HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, h->key_bits, s, &keys_sorted, &idx_sorted));
+        const bool trunc = W.sort_policy == kSortTruncated;
+        const int shift = trunc ? std::max(0, c.key_bits - kTruncBits) : 0;
+        HIP_TRY(launch_keys(W, d.x, shift, s));
+        unsigned *keys_sorted = W.key_a, *idx_sorted = W.idx_a;  // unsorted: the identity order
+        if (W.sort_policy != kSortNone)
+            HIP_TRY(radix_sort(W, W.key_a, W.idx_a, W.key_b, W.idx_b, nullptr, W.P, c.key_bits - shift, s,
+                               &keys_sorted, &idx_sorted));
         HIP_TRY(launch_permute(W, idx_sorted, d.x, d.v, d.F, d.C, d.pid, d.h, s));
         if (rec) {
-            const size_t j = (size_t)(h->tape_len / N);
+            const size_t j = (size_t)(c.tape_len / N);
             HIP_TRY(hipMemcpyAsync(W.tape_idx + j * W.P, idx_sorted, sizeof(unsigned) * W.P,
                                    hipMemcpyDeviceToDevice, s));
             HIP_TRY(hipMemcpyAsync(W.tape_rig + j * kMaxRigidTape, W.rigids, sizeof(DevRigid) * std::max(nr, 1),
@@ -486,9 +667,13 @@ mpm_status enqueue_host_step(mpm_handle* h, int qn_blocks, int env_stride, bool 
             HIP_TRY(hipMemcpyAsync(W.tape_env + j * n_envs, W.envs, sizeof(DevEnv) * n_envs,
                                    hipMemcpyDeviceToDevice, s));
         }
-        HIP_TRY(launch_tile_maps(W, s, true));   // forget the previous step's tiles
-        HIP_TRY(launch_tile_list(W, keys_sorted, s));
-        HIP_TRY(launch_tile_maps(W, s, false));
+        if (W.sort_policy == kSortTiles) {
+            HIP_TRY(launch_tile_maps(W, s, true));   // forget the previous step's tiles
+            HIP_TRY(launch_tile_list(W, keys_sorted, s));
+            HIP_TRY(launch_tile_maps(W, s, false));
+        } else {
+            HIP_TRY(launch_no_tiles(W, s));
+        }
         W.keys_sorted = keys_sorted;
     }
     for (int k = 0; k < N; ++k) {
@@ -497,8 +682,8 @@ mpm_status enqueue_host_step(mpm_handle* h, int qn_blocks, int env_stride, bool 
         const float* v_in = first ? W.vs : d.v;
         const float* F_in = first ? W.Fs : d.F;
         HIP_TRY(launch_clear_substep(W, s));
-        float* tp = rec ? W.tape_p + (size_t)(h->tape_len + k) * 24 * W.P : nullptr;
-        float4* tg = rec ? W.tape_g + (size_t)(h->tape_len + k) * 2 * W.n_nodes : nullptr;
+        float* tp = rec ? W.tape_p + (size_t)(c.tape_len + k) * 24 * W.P : nullptr;
+        float4* tg = rec ? W.tape_g + (size_t)(c.tape_len + k) * 2 * W.n_nodes : nullptr;
         if (rec) {
             const size_t P = W.P;
             HIP_TRY(hipMemcpyAsync(tp, x_in, sizeof(float) * 3 * P, hipMemcpyDeviceToDevice, s));
@@ -508,7 +693,10 @@ mpm_status enqueue_host_step(mpm_handle* h, int qn_blocks, int env_stride, bool 
         }
         {
             ProfScope ps(h, MPM_K_P2G, npair);
-            HIP_TRY(launch_p2g(W, x_in, v_in, s));
+            if (W.sort_policy == kSortTiles)
+                HIP_TRY(launch_p2g(W, x_in, v_in, s));
+            else
+                HIP_TRY(launch_p2g_plain(W, x_in, v_in, s));
         }
         {
             ProfScope ps(h, MPM_K_GRID, npair);
@@ -526,17 +714,66 @@ mpm_status enqueue_host_step(mpm_handle* h, int qn_blocks, int env_stride, bool 
         {
             ProfScope ps(h, MPM_K_SOLVE, npair);
             HIP_TRY(launch_qn(W, x_in, k, d.h, d.eps_r, d.eps_a, d.max_iter, ls_steps, qn_blocks,
-                              env_stride, h->prof_phases ? 1 : 0, h->slots_per_block, s));
+                              env_stride, c.phases ? 1 : 0, c.slots_per_block, s));
         }
         if (rec)
             HIP_TRY(hipMemcpyAsync(tg + W.n_nodes, W.vel, sizeof(float4) * W.n_nodes, hipMemcpyDeviceToDevice, s));
         {
             ProfScope ps(h, MPM_K_G2P, npair);
-            HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
-                               (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h, s));
+            if (W.sort_policy == kSortTiles)
+                HIP_TRY(launch_g2p(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
+                                   (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h, s));
+            else
+                HIP_TRY(launch_g2p_plain(W, x_in, F_in, d.x, d.v, d.F, last ? d.C : nullptr,
+                                         (first && d.pid) ? W.pids : nullptr, (first && d.pid) ? d.pid : nullptr, d.h,
+                                         s));
         }
     }
     if (graph) HIP_TRY(launch_advance_kinematic(W.rigids, nr, N * d.h, s));
+    return MPM_OK;
+}
+
+// The caller's statistics of a host step from the per-substep, per-environment
+// records (over the environments: the longest solve, all contacts, the worst
+// residual relative to its threshold).
+void fill_step_stats(const SubstepStats* stats, int N, int n_envs, unsigned flags, mpm_step_stats* st) {
+    if (!st) return;
+    st->flags = (int32_t)(flags & 0xF);
+    st->max_iterations = 0;
+    st->total_iterations = 0;
+    st->max_contacts = 0;
+    st->total_inner_iterations = 0;
+    for (int k = 0; k < N; ++k) {
+        const SubstepStats* q = stats + (size_t)k * n_envs;
+        const SubstepStats& lead = q[longest_solve(q, n_envs)];
+        int contacts = 0, nodes = 0, worst = 0;
+        for (int e = 0; e < n_envs; ++e) {
+            contacts += q[e].n_contacts;
+            nodes += q[e].n_slots;
+            if (q[e].threshold > 0.0 &&
+                (q[worst].threshold <= 0.0 || q[e].residual * q[worst].threshold > q[worst].residual * q[e].threshold))
+                worst = e;
+        }
+        st->max_iterations = std::max(st->max_iterations, lead.iterations);
+        st->total_iterations += lead.iterations;
+        st->total_inner_iterations += lead.inner_iterations;
+        st->max_contacts = std::max(st->max_contacts, contacts);
+        if (st->iterations) st->iterations[k] = lead.iterations;
+        if (st->contacts) st->contacts[k] = contacts;
+        if (st->contact_nodes) st->contact_nodes[k] = nodes;
+        if (st->residual) st->residual[k] = q[worst].residual;
+        if (st->threshold) st->threshold[k] = q[worst].threshold;
+    }
+}
+
+// Status of a host step from its device flags.
+mpm_status step_status(unsigned flags, long long cap_c, unsigned n_contacts) {
+    if (flags & 16u) return fail(MPM_EDEVICE, "contact solver barrier timed out");
+    if (flags & MPM_FLAG_CAPACITY)
+        return fail(MPM_ENOMEM, "contact capacity %lld exceeded (%u contacts)", cap_c, n_contacts);
+    if (flags & MPM_FLAG_NAN) return fail(MPM_ENAN, "non-finite particle state");
+    if (flags & MPM_FLAG_DOMAIN) return fail(MPM_EDOMAIN, "a particle stencil left the grid");
+    if (flags & MPM_FLAG_NOCONV) return fail(MPM_ENOCONV, "contact solve hit max_iter");
     return MPM_OK;
 }
 
@@ -595,46 +832,14 @@ mpm_status finish_host_steps(mpm_handle* h, const std::vector<int>& order, int n
             }
         }
     }
-    if (st) {
-        st->flags = (int32_t)(flags & 0xF);
-        st->max_iterations = 0;
-        st->total_iterations = 0;
-        st->max_contacts = 0;
-        for (int k = 0; k < N; ++k) {
-            // over the environments: the longest solve, all contacts, the worst residual
-            const SubstepStats* q = h->h_stats + (size_t)k * n_envs;
-            const SubstepStats& lead = q[longest_solve(q, n_envs)];
-            int contacts = 0, nodes = 0, worst = 0;
-            for (int e = 0; e < n_envs; ++e) {
-                contacts += q[e].n_contacts;
-                nodes += q[e].n_slots;
-                if (q[e].threshold > 0.0 &&
-                    (q[worst].threshold <= 0.0 || q[e].residual * q[worst].threshold > q[worst].residual * q[e].threshold))
-                    worst = e;
-            }
-            st->max_iterations = std::max(st->max_iterations, lead.iterations);
-            st->total_iterations += lead.iterations;
-            st->max_contacts = std::max(st->max_contacts, contacts);
-            if (st->iterations) st->iterations[k] = lead.iterations;
-            if (st->contacts) st->contacts[k] = contacts;
-            if (st->contact_nodes) st->contact_nodes[k] = nodes;
-            if (st->residual) st->residual[k] = q[worst].residual;
-            if (st->threshold) st->threshold[k] = q[worst].threshold;
-        }
-    }
+    fill_step_stats(h->h_stats, N, n_envs, flags, st);
     // size the next step's solver groups from this step's problems
     for (int e = 0; e < n_envs; ++e) {
         int most = 0;
         for (int k = 0; k < N; ++k) most = std::max(most, h->h_stats[(size_t)k * n_envs + e].n_slots);
         h->env_slots[e] = most;
     }
-    if (flags & 16u) return fail(MPM_EDEVICE, "contact solver barrier timed out");
-    if (flags & MPM_FLAG_CAPACITY)
-        return fail(MPM_ENOMEM, "contact capacity %lld exceeded (%u contacts)", (long long)W.cap_c, h->h_cnt->n_contacts);
-    if (flags & MPM_FLAG_NAN) return fail(MPM_ENAN, "non-finite particle state");
-    if (flags & MPM_FLAG_DOMAIN) return fail(MPM_EDOMAIN, "a particle stencil left the grid");
-    if (flags & MPM_FLAG_NOCONV) return fail(MPM_ENOCONV, "contact solve hit max_iter");
-    return MPM_OK;
+    return step_status(flags, W.cap_c, h->h_cnt->n_contacts);
 }
 
 
@@ -690,64 +895,14 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
         if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
         h->wall_khz = khz;
     }
-    {
-        // contact nodes per solver block: the description's, else the default;
-        // MPM_SOLVER_SLOTS_PER_BLOCK overrides both (for sweeps)
-        const char* spb = getenv("MPM_SOLVER_SLOTS_PER_BLOCK");
-        h->slots_per_block = spb ? std::max(1, atoi(spb))
-                                 : (desc->solver_slots_per_block > 0 ? desc->solver_slots_per_block : kQnItemsPerBlock);
-        // and a cap on the solver's blocks (below it, environments share blocks)
-        const char* mb = getenv("MPM_SOLVER_MAX_BLOCKS");
-        if (mb && atoi(mb) > 0) h->qn_cap = std::min(h->qn_cap, atoi(mb));
-        // MPM_SOLVER_COMPACT=0 sends every solver block through the general node pass
-        const char* cp = getenv("MPM_SOLVER_COMPACT");
-        h->w.qn_compact = (cp && atoi(cp) == 0) ? 0 : 1;
-        // MPM_SOLVER_SCATTER=0 keeps every environment on the two-barrier form
-        const char* sc = getenv("MPM_SOLVER_SCATTER");
-        h->w.qn_scatter = (sc && atoi(sc) == 0) ? 0 : 1;
-        // MPM_SOLVER_LAUNCH=plain launches the solver without the cooperative
-        // API (profiler runs); the grid never exceeds the co-resident blocks
-        const char* ln = getenv("MPM_SOLVER_LAUNCH");
-        h->w.qn_plain_launch = (ln && strcmp(ln, "plain") == 0) ? 1 : 0;
+    solver_options(desc, &h->w, &h->slots_per_block, &h->qn_cap);
+    if (h->w.sort_policy != kSortTiles && desc->tape_substeps > 0) {
+        delete h;
+        return fail(MPM_EINVAL, "the sort-policy arms run without the differentiation tape");
     }
     h->w.n_rigid = 0;
-    int tiles = 0;
-    long long nodes = 0;
-    for (int e = 0; e < desc->n_envs; ++e) {
-        const mpm_env_desc& E = h->envs[e];
-        DevEnv D;
-        memset(&D, 0, sizeof(D));
-        for (int a = 0; a < 3; ++a) {
-            D.dims[a] = E.dims[a];
-            D.ntile[a] = (E.dims[a] + 3) / 4;
-            D.origin[a] = E.origin[a];
-            D.gravity[a] = E.gravity[a];
-        }
-        D.tile_base = tiles;
-        D.node_base = nodes;
-        tiles += D.ntile[0] * D.ntile[1] * D.ntile[2];
-        nodes += (long long)E.dims[0] * E.dims[1] * E.dims[2];
-        D.p_begin = E.p_begin;
-        D.p_end = E.p_end;
-        D.dx = E.dx;
-        D.inv_dx = 1.0f / E.dx;
-        D.D = 4.0f / (E.dx * E.dx);
-        D.mat.type = E.material;
-        D.mat.mu = (float)(E.E / (2.0 * (1.0 + E.nu)));
-        D.mat.la = (float)(E.E * E.nu / ((1.0 + E.nu) * (1.0 - 2.0 * E.nu)));
-        const double sphi = sin(E.friction_angle * M_PI / 180.0);
-        D.mat.alpha = (float)(sqrt(2.0 / 3.0) * 2.0 * sphi / (3.0 - sphi));
-        D.m_p = E.m_p;
-        D.V0 = E.V0;
-        D.k = E.k;
-        D.d = E.d;
-        D.eps_s = E.eps_s;
-        D.rigid_begin = D.rigid_end = 0;
-        h->denv.push_back(D);
-    }
-    int bits = 1;
-    while ((1ll << bits) < (long long)tiles) ++bits;
-    h->key_bits = bits + 6;
+    h->denv.resize(desc->n_envs);
+    h->key_bits = make_dev_envs(desc->envs, desc->n_envs, h->denv.data());
     if (hipHostMalloc((void**)&h->h_rigids, sizeof(DevRigid) * kMaxRigidTotal) != hipSuccess ||
         hipHostMalloc((void**)&h->h_racc, sizeof(double) * 6 * kMaxRigidTotal) != hipSuccess ||
         hipHostMalloc((void**)&h->h_stats, sizeof(SubstepStats) * desc->N * desc->n_envs) != hipSuccess ||
@@ -759,17 +914,7 @@ mpm_status mpm_create(const mpm_desc* desc, mpm_handle** out) {
     }
     hipStream_t s = h->stream;
     const Work& W = h->w;
-    hipError_t e = hipMemsetAsync(W.acc, 0, sizeof(float4) * W.n_nodes, s);
-    if (e == hipSuccess) e = hipMemsetAsync(W.vel, 0, sizeof(float4) * W.n_nodes, s);
-    if (e == hipSuccess) e = hipMemsetAsync(W.tile_flag, 0, sizeof(unsigned) * W.n_tiles, s);
-    if (e == hipSuccess) e = hipMemsetAsync(W.ntile_mark, 0, sizeof(unsigned) * W.n_tiles, s);
-    if (e == hipSuccess) e = hipMemsetAsync(W.ptile_of, 0xFF, sizeof(int) * W.n_tiles, s);
-    if (e == hipSuccess) e = hipMemsetAsync(W.cnt, 0, sizeof(DevCounters), s);
-    if (e == hipSuccess) e = hipMemsetAsync(W.env_bar, 0, sizeof(unsigned) * kBarStride * W.n_envs, s);
-    if (e == hipSuccess)
-        e = hipMemsetAsync(W.env_ctr, 0, sizeof(unsigned) * kCtrLanes * kCtrStride * W.n_envs, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(W.envs, h->denv.data(), sizeof(DevEnv) * h->denv.size(), hipMemcpyHostToDevice, s);
+    hipError_t e = init_workspace(W, h->denv.data(), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         mpm_destroy(h);
@@ -786,40 +931,38 @@ mpm_status mpm_add_rigid_sdf(mpm_handle* h, int32_t env, const mpm_rigid_desc* r
     int in_env = 0;
     for (const HostRigid& q : h->rigids) in_env += q.env == env;
     if (in_env >= kMaxRigidPerEnv) return fail(MPM_EINVAL, "at most %d rigid bodies per environment", kMaxRigidPerEnv);
-    if (r->shape != MPM_HALF_SPACE && r->shape != MPM_BOX) return fail(MPM_EINVAL, "unknown shape");
-    if (r->motion != MPM_STATIC && r->motion != MPM_KINEMATIC && r->motion != MPM_DYNAMIC)
-        return fail(MPM_EINVAL, "unknown motion");
-    if (r->motion == MPM_DYNAMIC) {
-        if (r->shape != MPM_BOX) return fail(MPM_EINVAL, "dynamic bodies are boxes");
-        if (!(r->mass > 0.0) || !isfinite(r->mass)) return fail(MPM_EINVAL, "a dynamic body needs mass > 0");
-        for (int a = 0; a < 3; ++a) {
-            if (!(r->inertia[a] > 0.0) || !isfinite(r->inertia[a]))
-                return fail(MPM_EINVAL, "a dynamic body needs principal moments > 0");
-            if (!isfinite(r->force[a]) || !isfinite(r->torque[a]))
-                return fail(MPM_EINVAL, "external force and torque must be finite");
-        }
-    }
-    if (!(r->mu >= 0.0) || !isfinite(r->mu)) return fail(MPM_EINVAL, "mu must be >= 0");
-    if (r->shape == MPM_BOX && !(r->half[0] > 0 && r->half[1] > 0 && r->half[2] > 0))
-        return fail(MPM_EINVAL, "degenerate box");
-    if (r->shape == MPM_HALF_SPACE) {
-        const double nn = r->normal[0] * r->normal[0] + r->normal[1] * r->normal[1] + r->normal[2] * r->normal[2];
-        if (!(fabs(nn - 1.0) < 1e-9)) return fail(MPM_EINVAL, "half-space normal must be unit");
-    }
-    double RtR[9];
-    for (int a = 0; a < 3; ++a)
-        for (int b = 0; b < 3; ++b) {
-            double s = 0;
-            for (int q = 0; q < 3; ++q) s += r->R[q * 3 + a] * r->R[q * 3 + b];
-            RtR[a * 3 + b] = s;
-        }
-    for (int i = 0; i < 9; ++i)
-        if (fabs(RtR[i] - (i % 4 == 0 ? 1.0 : 0.0)) > 1e-9) return fail(MPM_EINVAL, "R must be a rotation");
+    const mpm_status rs = check_rigid(r);
+    if (rs != MPM_OK) return rs;
     HostRigid q;
     q.desc = *r;
     q.env = env;
     h->rigids.push_back(q);
     if (id) *id = (int32_t)h->rigids.size() - 1;
+    return MPM_OK;
+}
+
+mpm_status mpm_set_rigid_state(mpm_handle* h, int32_t id, const mpm_rigid_state* s, int32_t host_steps) {
+    if (!h || !s) return fail(MPM_EINVAL, "handle or state is NULL");
+    if (id < 0 || id >= (int)h->rigids.size()) return fail(MPM_EINVAL, "rigid id %d out of range", id);
+    if (host_steps < 0) return fail(MPM_EINVAL, "host_steps must be >= 0");
+    HostRigid& q = h->rigids[id];
+    mpm_rigid_desc d = q.desc;
+    memcpy(d.R, s->R, sizeof(d.R));
+    memcpy(d.t, s->t, sizeof(d.t));
+    memcpy(d.V, s->V, sizeof(d.V));
+    memcpy(d.w, s->w, sizeof(d.w));
+    const mpm_status rs = check_rigid(&d);
+    if (rs != MPM_OK) return rs;
+    if (host_steps > 0 && d.motion == MPM_KINEMATIC) {
+        // the library's kinematic rule, host step by host step
+        const double dT = h->d.N * h->d.h;
+        for (int j = 0; j < host_steps; ++j) {
+            for (int a = 0; a < 3; ++a) d.t[a] += dT * d.V[a];
+            rodrigues_advance(d.R, d.w, dT);
+        }
+    }
+    q.desc = d;
+    q.kin_steps = d.motion == MPM_KINEMATIC ? host_steps : 0;
     return MPM_OK;
 }
 
@@ -848,8 +991,12 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
             memcpy(d.t, in[i].t, sizeof(d.t));
             memcpy(d.V, in[i].V, sizeof(d.V));
             memcpy(d.w, in[i].w, sizeof(d.w));
+            h->rigids[i].kin_steps = 0;
         }
     }
+    // the first host step of a recording: where the poses stand on their path
+    if (rec && h->tape_len == 0)
+        for (HostRigid& q : h->rigids) q.rec_steps = q.kin_steps;
     std::vector<int> order;
     build_rigid_table(h, order);
     Work& W = h->w;
@@ -863,7 +1010,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     HIP_TRY(hipMemcpyAsync(W.qn_map, h->h_qn_map, sizeof(int2) * qn_blocks, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(W.env_qn, h->h_env_qn, sizeof(int) * 2 * n_envs, hipMemcpyHostToDevice, s));
     int npair = 0;
-    const mpm_status es = enqueue_host_step(h, qn_blocks, env_stride, false, npair, s);
+    const mpm_status es = enqueue_host_step(step_ctx(h), qn_blocks, env_stride, false, npair, s);
     if (es != MPM_OK) return es;
     HIP_TRY(hipMemcpyAsync(h->h_cnt, W.cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N * n_envs, hipMemcpyDeviceToHost, s));
@@ -879,6 +1026,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
         if (q.desc.motion == MPM_STATIC) continue;
         for (int a = 0; a < 3; ++a) q.desc.t[a] += dt * q.desc.V[a];
         rodrigues_advance(q.desc.R, q.desc.w, dt);
+        ++q.kin_steps;
     }
     return finish_host_steps(h, order, npair, rec, out, st);
 }
@@ -924,7 +1072,8 @@ mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         mpm_status cs = MPM_OK;
         int npair = 0;
-        for (int j = 0; j < n_steps && cs == MPM_OK; ++j) cs = enqueue_host_step(h, qn_blocks, env_stride, true, npair, s);
+        const StepCtx ctx = step_ctx(h);
+        for (int j = 0; j < n_steps && cs == MPM_OK; ++j) cs = enqueue_host_step(ctx, qn_blocks, env_stride, true, npair, s);
         hipGraph_t g = nullptr;
         const hipError_t ee = hipStreamEndCapture(s, &g);
         if (cs != MPM_OK) {
@@ -957,6 +1106,7 @@ mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out
         if (q.desc.motion != MPM_KINEMATIC) continue;
         memcpy(q.desc.R, h->h_rigids[k].R, sizeof(q.desc.R));
         memcpy(q.desc.t, h->h_rigids[k].t, sizeof(q.desc.t));
+        q.kin_steps += n_steps;
     }
     return finish_host_steps(h, order, 0, false, out, st);
 }
@@ -1093,6 +1243,7 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
             mpm_rigid_grad& g = rigid_grads[order[k]];
             memset(&g, 0, sizeof(g));
             if (h->rigids[order[k]].desc.motion == MPM_STATIC) continue;
+            const int j0 = h->rigids[order[k]].rec_steps;
             for (int j = 0; j < n_host; ++j) {
                 const double* q = rg.data() + ((size_t)j * kMaxRigidTape + k) * kRigidGradStride;
                 // pose j of the window is Rot(j dT w) applied to the first; a
@@ -1110,6 +1261,20 @@ mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, flo
                     g.dw[a] += q[6 + a];
                     g.dR[a] += rt[a];
                     g.dw_kinematic[a] += q[6 + a] + j * dT * jt[a];
+                }
+            }
+            if (j0 > 0) {
+                // the first recorded pose is the reference state advanced by j0
+                // kinematic host steps: t = t_ref + j0 dT V and R = Rot(j0 dT w) R_ref,
+                // so V also moves every recorded position by j0 dT, and a change dw
+                // turns the first pose by b J(b w) dw, b = j0 dT
+                const double b = j0 * dT;
+                double phi[3], jt[3];
+                for (int a = 0; a < 3; ++a) phi[a] = b * trig[k].w[a];
+                left_jacobian_transposed(phi, g.dR, jt);
+                for (int a = 0; a < 3; ++a) {
+                    g.dV_kinematic[a] += b * g.dt[a];
+                    g.dw_kinematic[a] += b * jt[a];
                 }
             }
         }

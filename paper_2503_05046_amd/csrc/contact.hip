@@ -550,6 +550,8 @@ struct QnArgs {
     double* vc_blk;            // per group rank: [6][kScatterMax] v_c, u_c of the line search's contacts
     int timers;                // 1: the first block of each environment times the solver's phases
     int slots_per_block;       // contact nodes per block that set an environment's group size
+    double* nt_slot;           // exact-Newton variant: per contact-node vectors
+    double* nt_con;            // exact-Newton variant: per-contact terms
     DevCounters* cnt;
 };
 
@@ -1598,6 +1600,387 @@ k_qn(QnArgs A) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Exact-Newton variant of the contact solve (MPM_SOLVER_NEWTON), a study of the
+// block-diagonal choice of Sec. IV-C: the same objective, stopping test and
+// exact line search as Algorithm 1, with the search direction taken from the
+// full Hessian H^ = M + sum_c J_c^T R_c G_c R_c^T J_c (nodes coupled through
+// every contact's stencil) instead of its 3x3 node blocks. H^ d = -g is solved
+// by conjugate gradients preconditioned with those node blocks (the matrix
+// Algorithm 1 inverts), inexactly: until the residual's preconditioned norm
+// falls to eta times its start, eta = min(1/2, sqrt(|grad~| / |grad~| at the
+// first iteration)) (a forcing term that tightens as the gradient falls).
+// Each group of blocks splits the environment's contact nodes and contacts as
+// in k_qn; values other blocks read go through ld_x / st_x and a loop barrier
+// separates their writes from the reads (three per conjugate-gradient
+// iteration: after the contact pass, after p.H^p, after r.z).
+// Per contact node (kNtSlot doubles): the inverse of its block [0, 6) (upper
+// triangle 00 01 02 11 12 22), the gradient g [6, 9), the conjugate-gradient
+// solution x [9, 12) (the Newton direction), residual r [12, 15), z = P r
+// [15, 18), direction p in two buffers by iteration parity [18, 21) and
+// [21, 24), q = H^ p [24, 27).
+// Per contact (kNtCon doubles): R gamma [0, 3) and R G R^T [3, 9) (world), G in
+// the contact frame [9, 13) (g00 g01 g11 gnn), and [13, 16): R G u for the
+// products, then u = R^T J x for the line search.
+// ---------------------------------------------------------------------------
+constexpr int kNtPi = 0, kNtG = 6, kNtX = 9, kNtR = 12, kNtZ = 15, kNtP = 18, kNtQ = 24;
+constexpr int kNtRg = 0, kNtRgr = 3, kNtGc = 9, kNtW = 13;
+constexpr int kNtCgMax = 5000;  // conjugate-gradient iterations per Newton step
+
+__global__ void __launch_bounds__(kQnThreads)
+k_newton(QnArgs A) {
+    __shared__ double rbuf[2 * 16 * kQnSums];
+    __shared__ double tot[kQnSums];
+    __shared__ double racc[kMaxRigid * 6];
+    __shared__ unsigned s_ok;
+    __shared__ double ovf_raw[11 * kQnThreads];
+    LsCoef* ls_ovf = reinterpret_cast<LsCoef*>(ovf_raw);
+    DevCounters* cnt = A.cnt;
+    const bool aborted = cnt->abort_step != 0u;
+    const int tid = threadIdx.x, T = blockDim.x;
+    const int2 me = A.qn_map[blockIdx.x];
+    unsigned rpar = 0;
+    for (int env = me.x; env < A.n_envs; env += A.env_stride > 0 ? A.env_stride : A.n_envs) {
+        const int first = A.env_stride > 0 ? (int)blockIdx.x : A.env_qn[2 * env];
+        const unsigned G_launch = A.env_stride > 0 ? 1u : (unsigned)A.env_qn[2 * env + 1];
+        const int rank = A.env_stride > 0 ? 0 : me.y;
+        const bool writer = rank == 0 && tid == 0;
+        const unsigned long long tph[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (aborted) {
+            if (writer) write_stats(A, env, 0, 0, 0, 1, 0, 0.0, 0.0, tph, true, 0);
+            continue;
+        }
+        unsigned* bar = A.env_bar + (size_t)env * kBarStride;
+        unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // read before the first group barrier, which no block passes before all
+        // have read it (the loop barriers' counters only grow)
+        unsigned* ctr = A.env_ctr + (size_t)env * kCtrLanes * kCtrStride;
+        unsigned ltarget = ctr_sum(ctr);
+        const long long ec0 = A.env_range[4 * env], ec1 = A.env_range[4 * env + 1];
+        const long long es0 = A.env_range[4 * env + 2], es1 = A.env_range[4 * env + 3];
+        const long long nc = ec1 - ec0, ns = es1 - es0;
+        const unsigned G = (unsigned)std::min<long long>(
+            G_launch, std::max<long long>(1, (ns + A.slots_per_block - 1) / A.slots_per_block));
+        if ((unsigned)rank >= G) continue;
+        long long s0 = es0, s1 = es1;
+        if (G > 1u) {
+            const long long e_lo = A.s_beg[es0], e_n = (long long)A.s_beg[es1] - e_lo;
+            s0 = rank == 0 ? es0 : es0 + lower_bound_i(A.s_beg + es0, ns, e_lo + (e_n * rank + G - 1) / G);
+            s1 = rank + 1 == (int)G ? es1 : es0 + lower_bound_i(A.s_beg + es0, ns, e_lo + (e_n * (rank + 1) + G - 1) / G);
+        }
+        const long long cper = (nc + G - 1) / G;
+        const long long c0 = ec0 + std::min<long long>(nc, cper * rank), c1 = std::min<long long>(ec1, c0 + cper);
+        const double pnorm_env = A.env_pnorm[env];
+        double* const pbuf[2] = {A.partial + (size_t)first * kQnSums, A.partial_odd + (size_t)first * kQnSums};
+        int ph = 0;
+        // Block sums of v[0, nv), then (groups of several blocks) the group's
+        // sums in every block, the same bits everywhere; the loop barrier in
+        // between also orders every st_x before it against every ld_x after it.
+        auto group_sum = [&](double (&v)[kQnSums], int nv) -> bool {
+            block_allsum<kQnSums>(v, rbuf, rpar);
+            double* pb = pbuf[ph];
+            ph ^= 1;
+            if (G > 1u && tid == 0)
+                for (int q = 0; q < nv; ++q) st_x(&pb[(size_t)rank * kQnSums + q], v[q]);
+            if (!loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt)) return false;
+            if (G > 1u) {
+                const int wv = tid >> 6, lane = tid & 63;
+                if (wv < nv) {
+                    double a = 0.0;
+                    for (unsigned b = lane; b < G; b += 64) a += ld_x(&pb[(size_t)b * kQnSums + wv]);
+                    a = wave_sum(a);
+                    if (lane == 0) tot[wv] = a;
+                }
+                __syncthreads();
+                for (int q = 0; q < nv; ++q) v[q] = tot[q];
+                __syncthreads();
+            }
+            return true;
+        };
+        double* const ns_base = A.nt_slot;
+        double* const nc_base = A.nt_con;
+        auto S = [&](long long s, int off) -> double* { return ns_base + (size_t)s * kNtSlot + off; };
+        auto Cw = [&](long long c, int off) -> double* { return nc_base + (size_t)c * kNtCon + off; };
+
+        for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
+
+        int k = 0, cg_total = 0, ls_total = 0, converged = 0;
+        double res = 0.0, thr = 0.0, res0 = -1.0;
+        __builtin_amdgcn_s_waitcnt(0);
+        bool ok = group_sync(bar, G, &gen, &s_ok, cnt);
+        while (ok) {
+            // (1) contact terms at v_c for the block's contacts
+            for (long long c = c0 + tid; c < c1; c += T) {
+                const ContactRec& R = A.c_rec[c];
+                const double* vc = A.c_dyn[c].vc[0];
+                double g[3], g00, g01, g11, gnn;
+                contact_model(params_of(R, A.h), vc, g, &g00, &g01, &g11, &gnn);
+                double rg[3], rgr[6];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) rg[a] = R.t1[a] * g[0] + R.t2[a] * g[1] + R.n[a] * g[2];
+                int q = 0;
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int cc = r; cc < 3; ++cc)
+                        rgr[q++] = g00 * R.t1[r] * R.t1[cc] + g01 * (R.t1[r] * R.t2[cc] + R.t2[r] * R.t1[cc]) +
+                                   g11 * R.t2[r] * R.t2[cc] + gnn * R.n[r] * R.n[cc];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) st_x(Cw(c, kNtRg + a), rg[a]);
+#pragma unroll
+                for (int a = 0; a < 6; ++a) st_x(Cw(c, kNtRgr + a), rgr[a]);
+                double* gc = Cw(c, kNtGc);
+                gc[0] = g00; gc[1] = g01; gc[2] = g11; gc[3] = gnn;
+            }
+            double sums[kQnSums];
+#pragma unroll
+            for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
+            if (!(ok = group_sum(sums, 0))) break;
+            // (2) node pass: gradient, node blocks and their inverses, the
+            // conjugate-gradient start x = 0, r = -g, z = P r
+            for (long long s = s0 + tid; s < s1; s += T) {
+                const SlotRec& Sr = A.s_rec[s];
+                const double m = Sr.m;
+                double j[3] = {0.0, 0.0, 0.0}, Hc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                for (int e = A.s_beg[s]; e < A.s_beg[s + 1]; ++e) {
+                    const Entry en = A.e_ent[e];
+                    const double w = en.w;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) j[a] = fma(w, ld_x(Cw(en.c, kNtRg + a)), j[a]);
+#pragma unroll
+                    for (int a = 0; a < 6; ++a) Hc[a] = fma(w * w, ld_x(Cw(en.c, kNtRgr + a)), Hc[a]);
+                }
+                const double H[6] = {m + Hc[0], Hc[1], Hc[2], m + Hc[3], Hc[4], m + Hc[5]};
+                const double c00 = H[3] * H[5] - H[4] * H[4], c01 = H[2] * H[4] - H[1] * H[5];
+                const double c02 = H[1] * H[4] - H[2] * H[3], c11 = H[0] * H[5] - H[2] * H[2];
+                const double c12 = H[1] * H[2] - H[0] * H[4], c22 = H[0] * H[3] - H[1] * H[1];
+                const double id = 1.0 / (H[0] * c00 + H[1] * c01 + H[2] * c02);
+                const double Pi[6] = {c00 * id, c01 * id, c02 * id, c11 * id, c12 * id, c22 * id};
+                double g[3], r[3], z[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    g[a] = m * (Sr.v[a] - Sr.vstar[a]) - j[a];
+                    r[a] = -g[a];
+                }
+                z[0] = Pi[0] * r[0] + Pi[1] * r[1] + Pi[2] * r[2];
+                z[1] = Pi[1] * r[0] + Pi[3] * r[1] + Pi[4] * r[2];
+                z[2] = Pi[2] * r[0] + Pi[4] * r[1] + Pi[5] * r[2];
+#pragma unroll
+                for (int a = 0; a < 6; ++a) S(s, kNtPi)[a] = Pi[a];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    S(s, kNtG)[a] = g[a];
+                    S(s, kNtR)[a] = r[a];
+                    st_x(S(s, kNtX + a), 0.0);
+                    st_x(S(s, kNtZ + a), z[a]);
+                    st_x(S(s, kNtP + a), 0.0);  // p of "iteration -1": the first direction is z
+                    sums[0] += g[a] * g[a] / m;
+                    sums[1] += j[a] * j[a] / m;
+                    sums[2] += m * Sr.v[a] * Sr.v[a];
+                    sums[3] += m * Sr.vstar[a] * Sr.vstar[a];
+                    sums[4] += r[a] * z[a];
+                }
+            }
+            if (!(ok = group_sum(sums, 5))) break;
+            const double p2 = fmax(pnorm_env - sums[3] + sums[2], 0.0);
+            res = sqrt(sums[0]);
+            thr = A.eps_a + A.eps_r * fmax(sqrt(p2), sqrt(sums[1]));
+            if (res < thr) { converged = 1; break; }
+            if (k >= A.max_iter) break;
+            if (res0 < 0.0) res0 = res;
+            const double eta = fmin(0.5, sqrt(res / res0));
+            const double rz0 = sums[4];
+            double rz = rz0, beta = 0.0;
+            // (3) preconditioned conjugate gradients on H^ x = -g
+            int pb = 0;  // buffer of the previous direction
+            for (int it = 0; it < kNtCgMax && rz > 0.0; ++it) {
+                // contacts: R G u with u = R^T J p, p = z + beta p_prev
+                for (long long c = c0 + tid; c < c1; c += T) {
+                    const ContactRec& R = A.c_rec[c];
+                    const ContactStencil& st = A.c_st[c];
+                    double acc[3] = {0.0, 0.0, 0.0};
+                    for (int o = 0; o < 27; ++o) {
+                        const int sl = st.slot[o];
+                        if (sl < 0) continue;
+                        const double w = st.w[o];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a)
+                            acc[a] = fma(w, fma(beta, ld_x(S(sl, kNtP + 3 * pb + a)), ld_x(S(sl, kNtZ + a))), acc[a]);
+                    }
+                    double u[3];
+                    frame_project(R, acc, u);
+                    const double* gc = Cw(c, kNtGc);
+                    const double y[3] = {gc[0] * u[0] + gc[1] * u[1], gc[1] * u[0] + gc[2] * u[1], gc[3] * u[2]};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) st_x(Cw(c, kNtW + a), R.t1[a] * y[0] + R.t2[a] * y[1] + R.n[a] * y[2]);
+                }
+                // the block's nodes: p = z + beta p_prev into the other buffer
+                for (long long s = s0 + tid; s < s1; s += T)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a)
+                        st_x(S(s, kNtP + 3 * (pb ^ 1) + a), fma(beta, ld_x(S(s, kNtP + 3 * pb + a)), ld_x(S(s, kNtZ + a))));
+#pragma unroll
+                for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
+                if (!(ok = group_sum(sums, 0))) break;
+                pb ^= 1;
+                // q = H^ p on the block's nodes, and p.q
+                for (long long s = s0 + tid; s < s1; s += T) {
+                    const double m = A.s_rec[s].m;
+                    double pv[3], qv[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        pv[a] = ld_x(S(s, kNtP + 3 * pb + a));
+                        qv[a] = m * pv[a];
+                    }
+                    for (int e = A.s_beg[s]; e < A.s_beg[s + 1]; ++e) {
+                        const Entry en = A.e_ent[e];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) qv[a] = fma((double)en.w, ld_x(Cw(en.c, kNtW + a)), qv[a]);
+                    }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        S(s, kNtQ)[a] = qv[a];
+                        sums[0] += pv[a] * qv[a];
+                    }
+                }
+                if (!(ok = group_sum(sums, 1))) break;
+                const double alpha_cg = sums[0] > 0.0 ? rz / sums[0] : 0.0;
+                sums[0] = 0.0;
+                // x += alpha p, r -= alpha q, z = P r, and r.z
+                for (long long s = s0 + tid; s < s1; s += T) {
+                    const double* Pi = S(s, kNtPi);
+                    double r[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        st_x(S(s, kNtX + a), fma(alpha_cg, ld_x(S(s, kNtP + 3 * pb + a)), ld_x(S(s, kNtX + a))));
+                        r[a] = fma(-alpha_cg, S(s, kNtQ)[a], S(s, kNtR)[a]);
+                        S(s, kNtR)[a] = r[a];
+                    }
+                    const double z[3] = {Pi[0] * r[0] + Pi[1] * r[1] + Pi[2] * r[2],
+                                         Pi[1] * r[0] + Pi[3] * r[1] + Pi[4] * r[2],
+                                         Pi[2] * r[0] + Pi[4] * r[1] + Pi[5] * r[2]};
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        st_x(S(s, kNtZ + a), z[a]);
+                        sums[0] += r[a] * z[a];
+                    }
+                }
+                if (!(ok = group_sum(sums, 1))) break;
+                ++cg_total;
+                beta = rz > 0.0 ? sums[0] / rz : 0.0;
+                rz = sums[0];
+                if (rz <= eta * eta * rz0) break;
+            }
+            if (!ok) break;
+            // (4) exact line search along x: u_c = R^T J x, the coefficients, and
+            // phi''(0); node sums A = |x|_M^2, B = x.M (v - v*), d0 = g.x
+#pragma unroll
+            for (int q = 0; q < kQnSums; ++q) sums[q] = 0.0;
+            for (long long c = c0 + tid; c < c1; c += T) {
+                const ContactRec& R = A.c_rec[c];
+                const ContactStencil& st = A.c_st[c];
+                double acc[3] = {0.0, 0.0, 0.0};
+                for (int o = 0; o < 27; ++o) {
+                    const int sl = st.slot[o];
+                    if (sl < 0) continue;
+                    const double w = st.w[o];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) acc[a] = fma(w, ld_x(S(sl, kNtX + a)), acc[a]);
+                }
+                double u[3];
+                frame_project(R, acc, u);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Cw(c, kNtW)[a] = u[a];
+                const double* vc = A.c_dyn[c].vc[0];
+                store_coef(A.c_coef, c, ls_coef(params_of(R, A.h), vc, u));
+                const double* gc = Cw(c, kNtGc);
+                sums[3] += gc[0] * u[0] * u[0] + 2.0 * gc[1] * u[0] * u[1] + gc[2] * u[1] * u[1] + gc[3] * u[2] * u[2];
+            }
+            for (long long s = s0 + tid; s < s1; s += T) {
+                const SlotRec& Sr = A.s_rec[s];
+                const double* g = S(s, kNtG);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double xa = ld_x(S(s, kNtX + a));
+                    sums[0] += Sr.m * xa * xa;
+                    sums[1] += Sr.m * xa * (Sr.v[a] - Sr.vstar[a]);
+                    sums[2] += g[a] * xa;
+                }
+            }
+            if (!(ok = group_sum(sums, 4))) break;
+            const double Aq = sums[0], Bq = sums[1], d0 = sums[2], curv0 = sums[3];
+            if (!(d0 < 0.0)) break;
+            const double alpha0 = Aq + curv0 > 0.0 ? -d0 / (Aq + curv0) : 1.0;
+            // every block: the coefficients of all the environment's contacts
+            LsCoef lc[kLsPer];
+            const long long c_lds = ec0 + tid + (long long)kLsPer * T;
+            const bool use_lds = (long long)kLsPer * T < nc;
+#pragma unroll
+            for (int u = 0; u < kLsPer; ++u) {
+                const long long c = ec0 + tid + (long long)u * T;
+                lc[u] = c < ec1 ? load_coef(A.c_coef, c) : ls_coef_zero();
+            }
+            if (use_lds) ls_ovf[tid] = c_lds < ec1 ? load_coef(A.c_coef, c_lds) : ls_coef_zero();
+            auto eval = [&](double alpha, double* d2out) -> double {
+                double acc2[2] = {0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < kLsPer; ++u) {
+                    double d1, d2;
+                    ls_eval(lc[u], alpha, &d1, &d2);
+                    acc2[0] += d1;
+                    acc2[1] += d2;
+                }
+                if (use_lds) {
+                    double d1, d2;
+                    ls_eval(ls_ovf[tid], alpha, &d1, &d2);
+                    acc2[0] += d1;
+                    acc2[1] += d2;
+                    for (long long c = c_lds + T; c < ec1; c += T) {
+                        ls_eval(load_coef(A.c_coef, c), alpha, &d1, &d2);
+                        acc2[0] += d1;
+                        acc2[1] += d2;
+                    }
+                }
+                block_allsum<2>(acc2, rbuf, rpar);
+                *d2out = Aq + acc2[1];
+                return fma(Aq, alpha, Bq) + acc2[0];
+            };
+            const double alpha = exact_line_search(eval, alpha0, d0, A.ls_max_steps, &ls_total);
+            // (5) update the block's nodes and contacts
+            for (long long s = s0 + tid; s < s1; s += T) {
+                SlotRec& Sr = A.s_rec[s];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) Sr.v[a] = fma(alpha, ld_x(S(s, kNtX + a)), Sr.v[a]);
+            }
+            for (long long c = c0 + tid; c < c1; c += T) {
+                double* vc = A.c_dyn[c].vc[0];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) vc[a] = fma(alpha, Cw(c, kNtW)[a], vc[a]);
+            }
+            ++k;
+        }
+        // ---- outputs ----------------------------------------------------------------
+        for (long long s = s0 + tid; s < s1; s += T) {
+            const SlotRec& Sr = A.s_rec[s];
+            float4 g = A.vel[A.s_node[s]];
+            g.x = (float)Sr.v[0]; g.y = (float)Sr.v[1]; g.z = (float)Sr.v[2];
+            A.vel[A.s_node[s]] = g;
+        }
+        for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
+        __syncthreads();
+        for (long long c = c0 + tid; c < c1; c += T) contact_impulse_at(A, c, A.c_dyn[c].vc[0], racc);
+        __syncthreads();
+        for (int q = tid; q < A.n_rigid * 6; q += T)
+            if (racc[q] != 0.0) atomicAdd(&A.rigid_acc[q], racc[q]);
+        if (writer) {
+            write_stats(A, env, nc, ns, k, converged, ls_total, res, thr, tph, false, (int)G);
+            A.stats[(size_t)A.substep * A.n_envs + env].inner_iterations = cg_total;
+        }
+        __syncthreads();  // racc and the block sums are reused by the next environment
+        if (!ok) break;
+    }
+}
+
 hipError_t launch_qn(const Work& w, const float* x, int substep, double h, double eps_r,
                      double eps_a, int max_iter, int ls_max_steps, int blocks, int env_stride,
                      int timers, int slots_per_block, hipStream_t s) {
@@ -1634,6 +2017,8 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.env_ctr = w.env_ctr;
     A.n_envs = w.n_envs;
     A.env_stride = env_stride;
+    A.nt_slot = w.nt_slot;
+    A.nt_con = w.nt_con;
     A.cnt = w.cnt;
     void* args[] = {&A};
     auto launch = [&](const void* fn) -> hipError_t {
@@ -1644,6 +2029,10 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
         }
         return hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kQnThreads), args, 0, s);
     };
+    if (w.solver == kSolverNewton) {
+        A.env_pend = nullptr;
+        return launch((const void*)k_newton);
+    }
     if (w.qn_scatter && w.n_envs == 1) {
         // the one-barrier kernel, then the two-barrier kernel for what it left.
         // With several environments the second launch would start only after
@@ -1662,10 +2051,12 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
 int qn_max_blocks() {
     int per_cu = 0;
     int per_cu1 = 0;
+    int per_cu2 = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_qn<false>, kQnThreads, 0) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, (const void*)k_qn<true>, kQnThreads, 0) != hipSuccess)
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu1, (const void*)k_qn<true>, kQnThreads, 0) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, (const void*)k_newton, kQnThreads, 0) != hipSuccess)
         return 0;
-    per_cu = std::min(per_cu, per_cu1);
+    per_cu = std::min(per_cu, std::min(per_cu1, per_cu2));
     int dev = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;

@@ -35,31 +35,49 @@ __device__ __forceinline__ int cell_base(float x, float origin, float inv_dx, fl
 // ---------------------------------------------------------------------------
 // 3x3 SVD, F = U diag(s) V^T with det U = det V = +1, s sorted by decreasing
 // magnitude, s[2] carrying the sign of det F. Method of McAdams, Selle,
-// Tamstorf, Teran, Sifakis (2011): cyclic Jacobi eigen-analysis of F^T F for
-// V, ordering of the columns of F V by norm, then a Givens QR of F V for U and
-// s. Exact Jacobi and Givens rotations (sqrt-based) with a fixed sweep count.
+// Tamstorf, Teran, Sifakis (2011): cyclic Jacobi eigen-analysis of the
+// symmetric S = F^T F for V, ordering of the columns of F V by norm, then a
+// Givens QR of F V for U and s.
+//
+// Each Jacobi rotation in the (p, q) plane is the exact one that zeroes S_pq:
+// with theta = (S_qq - S_pp) / (2 S_pq), t = tan of the angle =
+// sign(theta) / (|theta| + sqrt(theta^2 + 1)) (the smaller root, |t| <= 1),
+// c = 1 / sqrt(1 + t^2), s = t c, the rotated matrix has S_pp - t S_pq and
+// S_qq + t S_pq on the diagonal, zero at (p, q), and the third row's entries
+// rotated by (c, s); only the six distinct entries of S are kept. Reciprocals
+// and square roots use the hardware's single-instruction approximations
+// (about one ulp): c and s stay normalised to rounding because c is the
+// reciprocal square root of 1 + t^2 and s = t c, so V stays orthogonal to
+// rounding whatever error the angle carries. Four cyclic sweeps.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void jacobi_rot(float S[9], float V[9], int p, int q) {
-    float apq = S[p * 3 + q];
-    if (fabsf(apq) < 1e-30f) return;
-    float app = S[p * 3 + p], aqq = S[q * 3 + q];
-    float theta = (aqq - app) / (2.0f * apq);
-    float t = copysignf(1.0f, theta) / (fabsf(theta) + sqrtf(theta * theta + 1.0f));
-    float c = rsqrtf(t * t + 1.0f);
-    float s = t * c;
-    // S <- J^T S J with J the rotation in the (p, q) plane
+constexpr float kSvdTiny = 5.9604645e-8f;  // 2^-24, the unit roundoff of float32
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// One Jacobi rotation of the symmetric matrix (spp, sqq, spq; spr, sqr the
+// entries of the third row) and of the columns p, q of V.
+template <int p, int q>
+__device__ __forceinline__ void sym_jacobi(float& spp, float& sqq, float& spq, float& spr, float& sqr, float V[9]) {
+    const float b = spq;
+    // an off-diagonal entry below the rounding of the smaller diagonal one
+    // moves no eigenvalue: no rotation (V then stays exactly orthogonal where
+    // F is a rotation to rounding, e.g. F = I)
+    const bool skip = !(fabsf(b) > kSvdTiny * fminf(fabsf(spp), fabsf(sqq))) || fabsf(b) < 1e-30f;
+    const float theta = (sqq - spp) * fast_rcp(2.0f * (skip ? 1.0f : b));
+    const float t0 = fast_rcp(fabsf(theta) + fast_sqrt(fmaf(theta, theta, 1.0f)));
+    const float t = skip ? 0.0f : copysignf(t0, theta);
+    const float c = skip ? 1.0f : fast_rsq(fmaf(t, t, 1.0f));
+    const float s = t * c;
+    spp = fmaf(-t, b, spp);
+    sqq = fmaf(t, b, sqq);
+    spq = 0.0f;
+    const float r0 = spr, r1 = sqr;
+    spr = c * r0 - s * r1;
+    sqr = s * r0 + c * r1;
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-        float skp = S[k * 3 + p], skq = S[k * 3 + q];
-        S[k * 3 + p] = c * skp - s * skq;
-        S[k * 3 + q] = s * skp + c * skq;
-    }
-    for (int k = 0; k < 3; ++k) {
-        float spk = S[p * 3 + k], sqk = S[q * 3 + k];
-        S[p * 3 + k] = c * spk - s * sqk;
-        S[q * 3 + k] = s * spk + c * sqk;
-    }
-    for (int k = 0; k < 3; ++k) {
-        float vkp = V[k * 3 + p], vkq = V[k * 3 + q];
+        const float vkp = V[k * 3 + p], vkq = V[k * 3 + q];
         V[k * 3 + p] = c * vkp - s * vkq;
         V[k * 3 + q] = s * vkp + c * vkq;
     }
@@ -80,9 +98,10 @@ __device__ __forceinline__ void swap_cols(float B[9], float V[9], int i, int j, 
 __device__ __forceinline__ void givens_qr(float B[9], float U[9], int i, int j, int col) {
     float a = B[i * 3 + col], b = B[j * 3 + col];
     float r2 = a * a + b * b;
-    if (r2 < 1e-38f) return;
-    float inv = rsqrtf(r2);
-    float c = a * inv, s = b * inv;
+    // nothing to zero below the rounding of the pivot
+    const bool skip = r2 < 1e-38f || !(fabsf(b) > kSvdTiny * fabsf(a));
+    float inv = fast_rsq(skip ? 1.0f : r2);
+    float c = skip ? 1.0f : a * inv, s = skip ? 0.0f : b * inv;
     for (int k = 0; k < 3; ++k) {
         float bi = B[i * 3 + k], bj = B[j * 3 + k];
         B[i * 3 + k] = c * bi + s * bj;
@@ -97,21 +116,20 @@ __device__ __forceinline__ void givens_qr(float B[9], float U[9], int i, int j, 
 }
 
 __device__ inline void svd3(const float F[9], float U[9], float s[3], float V[9]) {
-    // symmetric S = F^T F
-    float S[9];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            S[r * 3 + c] = F[0 * 3 + r] * F[0 * 3 + c] + F[1 * 3 + r] * F[1 * 3 + c] +
-                           F[2 * 3 + r] * F[2 * 3 + c];
+    // the six distinct entries of S = F^T F
+    float s00 = F[0] * F[0] + F[3] * F[3] + F[6] * F[6];
+    float s11 = F[1] * F[1] + F[4] * F[4] + F[7] * F[7];
+    float s22 = F[2] * F[2] + F[5] * F[5] + F[8] * F[8];
+    float s01 = F[0] * F[1] + F[3] * F[4] + F[6] * F[7];
+    float s02 = F[0] * F[2] + F[3] * F[5] + F[6] * F[8];
+    float s12 = F[1] * F[2] + F[4] * F[5] + F[7] * F[8];
 #pragma unroll
     for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0f : 0.0f;
-#pragma unroll 1
-    for (int sweep = 0; sweep < 6; ++sweep) {
-        jacobi_rot(S, V, 0, 1);
-        jacobi_rot(S, V, 0, 2);
-        jacobi_rot(S, V, 1, 2);
+#pragma unroll
+    for (int sweep = 0; sweep < 4; ++sweep) {
+        sym_jacobi<0, 1>(s00, s11, s01, s02, s12, V);
+        sym_jacobi<0, 2>(s00, s22, s02, s01, s12, V);
+        sym_jacobi<1, 2>(s11, s22, s12, s01, s02, V);
     }
     // B = F V; order columns by decreasing norm, keeping det V = +1
     float B[9];

@@ -51,6 +51,8 @@ struct SubstepStats {
     int converged;
     int ls_rounds;
     int pad;
+    int inner_iterations;  // exact-Newton variant: conjugate-gradient iterations
+    int pad2;
     double residual;
     double threshold;
     unsigned long long t_phase[8];  // solver wall-clock ticks: node gather, node solve, barrier, contact pass,
@@ -199,7 +201,24 @@ struct Work {
     double* qn_uacc;         // [3][3][cap_c] per-contact sums of the one-barrier form
     double* qn_vcblk;        // [kQnMaxGroup][6][kQnScatterMax] contact velocities per rank of the group
     int* qn_pend;            // [n_envs] environments the one-barrier solver kernel left to the other
+    int solver;              // MPM_SOLVER_QN or MPM_SOLVER_NEWTON
+    int sort_policy;         // kSortTiles, kSortTruncated or kSortNone
+    int transfer_blocks;     // blocks of the tiled P2G and G2P launches (each takes particle tiles in turn)
+    double* nt_slot;         // exact-Newton variant: [cap_s][kNtSlot] per contact-node vectors
+    double* nt_con;          // exact-Newton variant: [cap_c][kNtCon] per-contact terms
 };
+
+// The exact-Newton variant (the value of MPM_SOLVER_NEWTON) and its per-node and
+// per-contact words (see k_newton).
+constexpr int kSolverNewton = 1;
+// Sort policies: full keys once per host step with the LDS-tiled transfers
+// (the default), or the ablation arms: keys truncated to their top
+// kTruncBits bits once per host step, or no reordering; both arms use the
+// plain scatter and gather.
+constexpr int kSortTiles = 0, kSortTruncated = 1, kSortNone = 2;
+constexpr int kTruncBits = 10;
+constexpr int kNtSlot = 28;
+constexpr int kNtCon = 16;
 
 // One recorded substep of the differentiation tape.
 struct TapeStep {
@@ -209,7 +228,11 @@ struct TapeStep {
 };
 
 // ---- kernel launchers (return hipError_t of the launch) -------------------
-hipError_t launch_keys(const Work& w, const float* x, hipStream_t s);
+hipError_t launch_keys(const Work& w, const float* x, int shift, hipStream_t s);
+hipError_t launch_p2g_plain(const Work& w, const float* x, const float* v, hipStream_t s);
+hipError_t launch_g2p_plain(const Work& w, const float* x_in, const float* F_in, float* x_out, float* v_out,
+                            float* F_out, float* C_out, const int* pid_in, int* pid_out, double h, hipStream_t s);
+hipError_t launch_no_tiles(const Work& w, hipStream_t s);
 hipError_t radix_sort(const Work& w, unsigned* keys, unsigned* vals, unsigned* keys_tmp,
                       unsigned* vals_tmp, const unsigned* count_dev, long long count_host,
                       int bits, hipStream_t s, unsigned** keys_out, unsigned** vals_out);

@@ -61,7 +61,7 @@ __device__ __forceinline__ void stencil_base(const DevEnv& E, const float x[3], 
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
 k_keys(const float* __restrict__ x, long long P, const DevEnv* __restrict__ envs, int n_envs,
-       unsigned* __restrict__ keys, unsigned* __restrict__ idx, DevCounters* cnt) {
+       unsigned* __restrict__ keys, unsigned* __restrict__ idx, int shift, DevCounters* cnt) {
     long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P) return;
     const DevEnv& E = envs[env_of_particle(envs, n_envs, i)];
@@ -74,14 +74,14 @@ k_keys(const float* __restrict__ x, long long P, const DevEnv* __restrict__ envs
     unsigned tile = (unsigned)E.tile_base + (unsigned)(b[0] >> 2) +
                     (unsigned)E.ntile[0] * ((unsigned)(b[1] >> 2) + (unsigned)E.ntile[1] * (unsigned)(b[2] >> 2));
     unsigned cell = (unsigned)(b[0] & 3) | ((unsigned)(b[1] & 3) << 2) | ((unsigned)(b[2] & 3) << 4);
-    keys[i] = (tile << 6) | cell;
+    keys[i] = ((tile << 6) | cell) >> shift;
     idx[i] = (unsigned)i;
 }
 
-hipError_t launch_keys(const Work& w, const float* x, hipStream_t s) {
+hipError_t launch_keys(const Work& w, const float* x, int shift, hipStream_t s) {
     const unsigned blocks = (unsigned)((w.P + 255) / 256);
     hipLaunchKernelGGL(k_keys, dim3(blocks), dim3(256), 0, s, x, w.P, w.envs, w.n_envs, w.key_a,
-                       w.idx_a, w.cnt);
+                       w.idx_a, shift, w.cnt);
     return hipGetLastError();
 }
 
@@ -259,30 +259,86 @@ hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old) {
 }
 
 // ---------------------------------------------------------------------------
-// P2G: m_i += w m_p, p_i += w (m_p v_p + Q_p (x_i - x_p))
-//
-// One block per particle tile, one thread per (cell of the tile, component):
-// thread q*64 + c sums component q (0: mass, 1-3: momentum) of every particle
-// sorted into cell c over the 27 stencil nodes in registers (the particles of
-// a cell share one stencil), then adds its 27 sums into the tile's 8x8x8 LDS
-// node block; the 64 lanes of a wave hold 64 different cells, so those LDS
-// atomics never collide within an instruction. A particle whose stencil base
-// has drifted from its sort-time cell adds to the LDS block directly, or, if it
-// left the block, to the global accumulator. The block is stored atomic-free to
-// the tile's slot of the block buffer; the grid update sums the 8 blocks that
-// overlap each node in a fixed order.
+// P2G: m_i += w m_p, p_i += w (m_p v_p + Q_p (x_i - x_p))  (Eq. (6), Sec. V-A)
 // ---------------------------------------------------------------------------
 // P2G, one particle tile per block: 256 threads, thread (q, cell) with
 // component q = tid / 64 (mass, then the three momentum components) and cell
-// = tid % 64 of the 4x4x4 tile. Each thread walks the particles of its cell
-// (contiguous after the sort) and keeps in registers its component of the
-// contributions of those whose stencil base is still the cell; it then adds
-// its 27 sums into the tile's 8x8x8-node LDS block. The 64 lanes of a wave
-// own 64 different cells, so those atomics never collide. Particles that
-// drifted to another base since the sort are scattered directly, into LDS
-// when their stencil lies inside the block, else into the global accumulator
-// (activating the node tiles). The block is stored without atomics; the grid
-// update sums the overlapping blocks of every node.
+// = tid % 64 of the 4x4x4 tile.
+//  1. The cell ranges of the tile come from the sort-time keys (sorted, so a
+//     cell's particles are contiguous): the first and last particle of each
+//     run of equal keys write its bounds; no counting or scan.
+//  2. Each thread walks its cell's particles, loading the next particle while
+//     it computes the current one, and sums its component of the
+//     contributions of those whose stencil base is still the cell in 27
+//     registers (the particles of a cell share one stencil). A particle whose
+//     base has drifted since the sort is only queued: (particle, component)
+//     goes to a list in LDS, so no wave issues scattered atomics for the few
+//     lanes that meet one.
+//  3. The thread adds its 27 sums into the tile's 8x8x8-node LDS block; the 64
+//     lanes of a wave own 64 different cells, so the adds of one instruction
+//     never collide.
+//  4. All threads take the queued entries, one (particle, component) each,
+//     and add them into the LDS block, or, for a stencil outside the block, to
+//     the global accumulator (activating the node tiles it touches). A list
+//     that overflows leaves the rest to the walking thread, inline.
+//  5. The block is stored without atomics to the tile's slot of the block
+//     buffer; the grid update sums the overlapping blocks of every node.
+// (Staging the tile's particles in LDS before the walks, tried, was slower:
+// 189 against 162 us at 1M particles.)
+constexpr int kDriftMax = 1024;  // queued (particle, component) entries per tile
+
+// Component q of one particle's contribution to the 27 nodes of its stencil
+// (m_p, or m_p v_q + Q_q . (x_i - x_p)), added to the LDS block when the stencil
+// lies inside it, else to the global accumulator.
+__device__ __forceinline__ void p2g_scatter_one(const DevEnv& E, const float* __restrict__ x,
+                                                const float* __restrict__ v, const float* __restrict__ Q,
+                                                long long P, long long p, int q, int ox, int oy, int oz,
+                                                float (*sm)[kBN3], float4* __restrict__ acc,
+                                                unsigned* __restrict__ tile_flag, unsigned* __restrict__ active,
+                                                DevCounters* cnt, bool* clamped) {
+    const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
+    int b[3];
+    float f[3];
+    stencil_base(E, xp, b, f, clamped);
+    float wx[3], wy[3], wz[3];
+    bspline_w(f[0], wx);
+    bspline_w(f[1], wy);
+    bspline_w(f[2], wz);
+    const float dx = E.dx;
+    float base_val = E.m_p, qr0 = 0.f, qr1 = 0.f, qr2 = 0.f;
+    if (q > 0) {
+        base_val = E.m_p * v[(q - 1) * P + p];
+        qr0 = Q[(3 * (q - 1) + 0) * P + p];
+        qr1 = Q[(3 * (q - 1) + 1) * P + p];
+        qr2 = Q[(3 * (q - 1) + 2) * P + p];
+    }
+    const int lx = b[0] - ox, ly = b[1] - oy, lz = b[2] - oz;
+    const bool local = lx >= 0 && lx <= kBN - 3 && ly >= 0 && ly <= kBN - 3 && lz >= 0 && lz <= kBN - 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const float w = wx[a] * wy[bb] * wz[c];
+                const float val = w * (base_val + qr0 * (((float)a - f[0]) * dx) +
+                                       qr1 * (((float)bb - f[1]) * dx) + qr2 * (((float)c - f[2]) * dx));
+                if (local) {
+                    atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], val);
+                } else {
+                    float* g = reinterpret_cast<float*>(&acc[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]);
+                    atomicAdd(g + q, val);
+                }
+            }
+    if (!local && q == 0) {
+        // the drifted particle's nodes span up to 2x2x2 node tiles
+        for (int c = 0; c < 2; ++c)
+            for (int bb = 0; bb < 2; ++bb)
+                for (int a = 0; a < 2; ++a)
+                    activate_tile(node_tile(E, b[0] + 2 * a, b[1] + 2 * bb, b[2] + 2 * c), tile_flag, active, cnt);
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ Q,
       long long P, const DevEnv* __restrict__ envs, int n_envs, const unsigned* __restrict__ ptile_id,
@@ -290,27 +346,32 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
       float4* __restrict__ blkbuf, float4* __restrict__ acc, unsigned* __restrict__ tile_flag,
       unsigned* __restrict__ active, DevCounters* cnt) {
     __shared__ float sm[4][kBN3];
-    __shared__ unsigned ccount[64], cstart[64];
+    __shared__ unsigned cbeg[64], cend[64];
+    __shared__ unsigned drift[kDriftMax];
+    __shared__ unsigned n_drift;
     if (cnt->abort_step) return;
     const unsigned n_tiles = cnt->n_ptiles;
-    const int q = threadIdx.x >> 6, cell = threadIdx.x & 63;
+    // the component is uniform over a wave: scalar branches below
+    const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), cell = threadIdx.x & 63;
     const int cx = cell & 3, cy = (cell >> 2) & 3, cz = cell >> 4;
+    bool clamped = false;
     for (unsigned t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         for (int n = threadIdx.x; n < kBN3; n += blockDim.x) {
             sm[0][n] = 0.f; sm[1][n] = 0.f; sm[2][n] = 0.f; sm[3][n] = 0.f;
         }
-        if (threadIdx.x < 64) ccount[threadIdx.x] = 0u;
+        if (threadIdx.x < 64) {
+            cbeg[threadIdx.x] = 0u;
+            cend[threadIdx.x] = 0u;
+        }
+        if (threadIdx.x == 0) n_drift = 0u;
         __syncthreads();
         const unsigned gt = ptile_id[t];
         const long long pb = ptile_beg[t], pe = ptile_beg[t + 1];
-        for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) atomicAdd(&ccount[keys[p] & 63u], 1u);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned run = 0;
-            for (int c = 0; c < 64; ++c) {
-                cstart[c] = run;
-                run += ccount[c];
-            }
+        // 1. cell ranges: the bounds of every run of equal keys
+        for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) {
+            const unsigned k = keys[p];
+            if (p == pb || keys[p - 1] != k) cbeg[k & 63u] = (unsigned)(p - pb);
+            if (p == pe - 1 || keys[p + 1] != k) cend[k & 63u] = (unsigned)(p - pb + 1);
         }
         __syncthreads();
         const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
@@ -322,30 +383,53 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
         float sum[27];
 #pragma unroll
         for (int o = 0; o < 27; ++o) sum[o] = 0.f;
-        const unsigned cnt_c = ccount[cell];
-        const long long p0 = pb + cstart[cell];
-        bool clamped = false;
-        for (unsigned kk = 0; kk < cnt_c; ++kk) {
-            const long long p = p0 + kk;
-            const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
+        // 2. the walk over the cell's particles, the next one's loads issued first
+        const unsigned k0 = cbeg[cell], k1 = cend[cell];
+        bool any_same = false;
+        float nx0 = 0.f, nx1 = 0.f, nx2 = 0.f, nv = 0.f, nq0 = 0.f, nq1 = 0.f, nq2 = 0.f;
+        if (k0 < k1) {
+            const long long p = pb + k0;
+            nx0 = x[p]; nx1 = x[P + p]; nx2 = x[2 * P + p];
+            if (q > 0) {
+                nv = v[(q - 1) * P + p];
+                nq0 = Q[(3 * (q - 1) + 0) * P + p];
+                nq1 = Q[(3 * (q - 1) + 1) * P + p];
+                nq2 = Q[(3 * (q - 1) + 2) * P + p];
+            }
+        }
+        for (unsigned kk = k0; kk < k1; ++kk) {
+            const float xp[3] = {nx0, nx1, nx2};
+            const float vq = nv, q0 = nq0, q1 = nq1, q2 = nq2;
+            if (kk + 1 < k1) {
+                const long long pn = pb + kk + 1;
+                nx0 = x[pn]; nx1 = x[P + pn]; nx2 = x[2 * P + pn];
+                if (q > 0) {
+                    nv = v[(q - 1) * P + pn];
+                    nq0 = Q[(3 * (q - 1) + 0) * P + pn];
+                    nq1 = Q[(3 * (q - 1) + 1) * P + pn];
+                    nq2 = Q[(3 * (q - 1) + 2) * P + pn];
+                }
+            }
             int b[3];
             float f[3];
             stencil_base(E, xp, b, f, &clamped);
+            if (b[0] != nbx || b[1] != nby || b[2] != nbz) {
+                // drifted since the sort: queue (particle, component)
+                const unsigned slot = atomicAdd(&n_drift, 1u);
+                if (slot < (unsigned)kDriftMax) {
+                    drift[slot] = (kk << 2) | (unsigned)q;
+                } else {
+                    p2g_scatter_one(E, x, v, Q, P, pb + kk, q, ox, oy, oz, sm, acc, tile_flag, active, cnt,
+                                    &clamped);
+                }
+                continue;
+            }
+            any_same = true;
             float wx[3], wy[3], wz[3];
             bspline_w(f[0], wx);
             bspline_w(f[1], wy);
             bspline_w(f[2], wz);
-            // component q of the particle's contribution: m_p, or m_p v_q + Q_q . (x_i - x_p)
-            float base_val = mp, qr0 = 0.f, qr1 = 0.f, qr2 = 0.f;
-            if (q > 0) {
-                base_val = mp * v[(q - 1) * P + p];
-                qr0 = Q[(3 * (q - 1) + 0) * P + p];
-                qr1 = Q[(3 * (q - 1) + 1) * P + p];
-                qr2 = Q[(3 * (q - 1) + 2) * P + p];
-            }
-            const bool same = b[0] == nbx && b[1] == nby && b[2] == nbz;
-            const int lx = b[0] - ox, ly = b[1] - oy, lz = b[2] - oz;
-            const bool local = lx >= 0 && lx <= kBN - 3 && ly >= 0 && ly <= kBN - 3 && lz >= 0 && lz <= kBN - 3;
+            const float base_val = q > 0 ? mp * vq : mp;
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -354,27 +438,12 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                     for (int a = 0; a < 3; ++a) {
                         const int o = (c * 3 + bb) * 3 + a;
                         const float w = wx[a] * wy[bb] * wz[c];
-                        const float val = w * (base_val + qr0 * (((float)a - f[0]) * dx) +
-                                               qr1 * (((float)bb - f[1]) * dx) + qr2 * (((float)c - f[2]) * dx));
-                        if (same) {
-                            sum[o] += val;
-                        } else if (local) {
-                            atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], val);
-                        } else {
-                            float* g = reinterpret_cast<float*>(&acc[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]);
-                            atomicAdd(g + q, val);
-                        }
+                        sum[o] += w * (base_val + q0 * (((float)a - f[0]) * dx) + q1 * (((float)bb - f[1]) * dx) +
+                                       q2 * (((float)c - f[2]) * dx));
                     }
-            if (!local && q == 0) {
-                // the drifted particle's nodes span up to 2x2x2 node tiles
-                for (int c = 0; c < 2; ++c)
-                    for (int bb = 0; bb < 2; ++bb)
-                        for (int a = 0; a < 2; ++a)
-                            activate_tile(node_tile(E, b[0] + 2 * a, b[1] + 2 * bb, b[2] + 2 * c),
-                                          tile_flag, active, cnt);
-            }
         }
-        if (cnt_c > 0) {
+        // 3. the cell's sums into the LDS block
+        if (any_same) {
             const int lx = nbx - ox, ly = nby - oy, lz = nbz - oz;  // in [1, 4]
 #pragma unroll
             for (int c = 0; c < 3; ++c)
@@ -384,17 +453,26 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                     for (int a = 0; a < 3; ++a)
                         atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], sum[(c * 3 + bb) * 3 + a]);
         }
-        if (clamped) atomicOr(&cnt->flags, kFlagDomain);
         __syncthreads();
+        // 4. the queued drifted particles, one (particle, component) per thread
+        const unsigned nd = min(n_drift, (unsigned)kDriftMax);
+        for (unsigned i = threadIdx.x; i < nd; i += blockDim.x) {
+            const unsigned e = drift[i];
+            p2g_scatter_one(E, x, v, Q, P, pb + (e >> 2), (int)(e & 3u), ox, oy, oz, sm, acc, tile_flag, active,
+                            cnt, &clamped);
+        }
+        __syncthreads();
+        // 5. atomic-free block store
         float4* out = blkbuf + (size_t)t * kBN3;
         for (int n = threadIdx.x; n < kBN3; n += blockDim.x)
             out[n] = make_float4(sm[0][n], sm[1][n], sm[2][n], sm[3][n]);
         __syncthreads();
     }
+    if (clamped) atomicOr(&cnt->flags, kFlagDomain);
 }
 
 hipError_t launch_p2g(const Work& w, const float* x, const float* v, hipStream_t s) {
-    const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 8192);
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(w.n_tiles, w.transfer_blocks));
     hipLaunchKernelGGL(k_p2g, dim3(blocks), dim3(256), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs,
                        w.ptile_id, w.ptile_beg, w.keys_sorted, w.blkbuf, w.acc, w.tile_flag,
                        w.active_tiles, w.cnt);
@@ -514,13 +592,113 @@ hipError_t launch_grid_update(const Work& w, double h, hipStream_t s) {
 // G2P: v_p = sum w v_i, C_p = (4/dx^2) sum w v_i (x_i - x_p)^T,
 // F <- (I + h C) F, x <- x + h v_p; return map for sand; Q for the next P2G
 // ---------------------------------------------------------------------------
+// G2P of one particle p with stencil fractions f and weights w[axis][3]:
+// v_p = sum w v_i, C_p = D sum w v_i (x_i - x_p)^T, F <- (I + h C) F,
+// x <- x + h v_p, the return map for sand, and Q for the next P2G. near(a, b,
+// c) and far(a, b, c) return the velocity of stencil node (a, b, c), the
+// first used when `local` holds.
+template <typename NearV, typename FarV>
+__device__ __forceinline__ void g2p_particle(const DevEnv& E, long long P, long long p, const float xp[3],
+                                             const float f[3], const float* const w[3], const float Fp[9],
+                                             float hf, bool local, NearV near, FarV far, float* x_out,
+                                             float* v_out, float* F_out, float* C_out, float* Q, bool* bad_out) {
+    const float* wx = w[0];
+    const float* wy = w[1];
+    const float* wz = w[2];
+    const float dx = E.dx, D = E.D;
+    bool bad = false;
+    // v_p = sum w v_i and C_p = D sum w v_i (x_i - x_p)^T, summed axis by axis
+    // (the weights and offsets factor per axis): along x for each (y, z)
+    // row of the stencil, then along y, then along z
+    float wxd[3], wyd[3], wzd[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        wxd[a] = wx[a] * (((float)a - f[0]) * dx);
+        wyd[a] = wy[a] * (((float)a - f[1]) * dx);
+        wzd[a] = wz[a] * (((float)a - f[2]) * dx);
+    }
+    float vp[3] = {0.f, 0.f, 0.f};
+    float Cp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    auto gather = [&](auto node_v) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float q0[3] = {0.f, 0.f, 0.f}, q1[3] = {0.f, 0.f, 0.f}, q2[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb) {
+                float p0[3] = {0.f, 0.f, 0.f}, p1[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float4 g = node_v(a, bb, c);
+                    const float vi[3] = {g.x, g.y, g.z};
+#pragma unroll
+                    for (int r = 0; r < 3; ++r) {
+                        p0[r] = fmaf(wx[a], vi[r], p0[r]);
+                        p1[r] = fmaf(wxd[a], vi[r], p1[r]);
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 3; ++r) {
+                    q0[r] = fmaf(wy[bb], p0[r], q0[r]);
+                    q1[r] = fmaf(wy[bb], p1[r], q1[r]);
+                    q2[r] = fmaf(wyd[bb], p0[r], q2[r]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+                vp[r] = fmaf(wz[c], q0[r], vp[r]);
+                Cp[r * 3 + 0] = fmaf(wz[c], q1[r], Cp[r * 3 + 0]);
+                Cp[r * 3 + 1] = fmaf(wz[c], q2[r], Cp[r * 3 + 1]);
+                Cp[r * 3 + 2] = fmaf(wzd[c], q0[r], Cp[r * 3 + 2]);
+            }
+        }
+    };
+    if (local) {
+        gather(near);
+    } else {
+        gather(far);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Cp[k] *= D;
+    // F <- (I + h C) F
+    float Fn[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            Fn[r * 3 + c] = Fp[r * 3 + c] + hf * (Cp[r * 3 + 0] * Fp[0 * 3 + c] +
+                                                  Cp[r * 3 + 1] * Fp[1 * 3 + c] +
+                                                  Cp[r * 3 + 2] * Fp[2 * 3 + c]);
+    float U[9], s[3], V[9], tau[9];
+    svd3(Fn, U, s, V);
+    if (E.mat.type == 1) dp_return_map(E.mat, U, s, V, Fn);
+    kirchhoff_from_svd(E.mat, Fn, U, s, V, tau);
+    const float cq = hf * E.V0 * D;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        x_out[a * P + p] = xp[a] + hf * vp[a];
+        v_out[a * P + p] = vp[a];
+        bad |= !isfinite(vp[a]);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        F_out[k * P + p] = Fn[k];
+        Q[k * P + p] = E.m_p * Cp[k] - cq * tau[k];
+        bad |= !isfinite(Fn[k]);
+    }
+    if (C_out) {
+#pragma unroll
+        for (int k = 0; k < 9; ++k) C_out[k * P + p] = Cp[k];
+    }
+    *bad_out |= bad;
+}
+
 __global__ void __launch_bounds__(256)
 k_g2p(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F_out,
       float* __restrict__ C_out, float* __restrict__ Q, const int* __restrict__ pid_in,
       int* __restrict__ pid_out, long long P, const DevEnv* __restrict__ envs, int n_envs,
       const unsigned* __restrict__ ptile_id, const unsigned* __restrict__ ptile_beg,
       const float4* __restrict__ vel, double h, DevCounters* cnt) {
-    __shared__ float sv[3][kBN3];
+    __shared__ float4 sv[kBN3];  // node velocities of the tile's block (w unused)
     if (cnt->abort_step) return;
     const unsigned n_tiles = cnt->n_ptiles;
     const float hf = (float)h;
@@ -538,12 +716,9 @@ k_g2p(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F
             float4 vv = make_float4(0.f, 0.f, 0.f, 0.f);
             if (i >= 0 && j >= 0 && k >= 0 && i < E.dims[0] && j < E.dims[1] && k < E.dims[2])
                 vv = vel[node_index(E, i, j, k)];
-            sv[0][n] = vv.x;
-            sv[1][n] = vv.y;
-            sv[2][n] = vv.z;
+            sv[n] = vv;
         }
         __syncthreads();
-        const float dx = E.dx, D = E.D;
         for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) {
             float xp[3] = {x_in[p], x_in[P + p], x_in[2 * P + p]};
             float Fp[9];
@@ -559,66 +734,13 @@ k_g2p(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F
             bspline_w(f[2], wz);
             const int lx = b[0] - ox, ly = b[1] - oy, lz = b[2] - oz;
             const bool local = lx >= 0 && lx <= kBN - 3 && ly >= 0 && ly <= kBN - 3 && lz >= 0 && lz <= kBN - 3;
-            float vp[3] = {0.f, 0.f, 0.f};
-            float Cp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const float w = wx[a] * wy[bb] * wz[c];
-                        float vi[3];
-                        if (local) {
-                            const int n = ((lz + c) * kBN + (ly + bb)) * kBN + (lx + a);
-                            vi[0] = sv[0][n]; vi[1] = sv[1][n]; vi[2] = sv[2][n];
-                        } else {
-                            const float4 g = vel[node_index(E, b[0] + a, b[1] + bb, b[2] + c)];
-                            vi[0] = g.x; vi[1] = g.y; vi[2] = g.z;
-                        }
-                        const float d[3] = {((float)a - f[0]) * dx, ((float)bb - f[1]) * dx,
-                                            ((float)c - f[2]) * dx};
-#pragma unroll
-                        for (int r = 0; r < 3; ++r) {
-                            const float wv = w * vi[r];
-                            vp[r] += wv;
-                            Cp[r * 3 + 0] += wv * d[0];
-                            Cp[r * 3 + 1] += wv * d[1];
-                            Cp[r * 3 + 2] += wv * d[2];
-                        }
-                    }
-#pragma unroll
-            for (int k = 0; k < 9; ++k) Cp[k] *= D;
-            // F <- (I + h C) F
-            float Fn[9];
-#pragma unroll
-            for (int r = 0; r < 3; ++r)
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    Fn[r * 3 + c] = Fp[r * 3 + c] + hf * (Cp[r * 3 + 0] * Fp[0 * 3 + c] +
-                                                          Cp[r * 3 + 1] * Fp[1 * 3 + c] +
-                                                          Cp[r * 3 + 2] * Fp[2 * 3 + c]);
-            float U[9], s[3], V[9], tau[9];
-            svd3(Fn, U, s, V);
-            if (E.mat.type == 1) dp_return_map(E.mat, U, s, V, Fn);
-            kirchhoff_from_svd(E.mat, Fn, U, s, V, tau);
-            const float cq = hf * E.V0 * D;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                x_out[a * P + p] = xp[a] + hf * vp[a];
-                v_out[a * P + p] = vp[a];
-                bad |= !isfinite(vp[a]);
-            }
-#pragma unroll
-            for (int k = 0; k < 9; ++k) {
-                F_out[k * P + p] = Fn[k];
-                Q[k * P + p] = E.m_p * Cp[k] - cq * tau[k];
-                bad |= !isfinite(Fn[k]);
-            }
-            if (C_out) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) C_out[k * P + p] = Cp[k];
-            }
+            const float* wv[3] = {wx, wy, wz};
+            // a stencil that left the tile's block (drift of more than a cell) reads memory
+            g2p_particle(
+                E, P, p, xp, f, wv, Fp, hf, local,
+                [&](int a, int bb, int c) { return sv[((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)]; },
+                [&](int a, int bb, int c) { return vel[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]; }, x_out,
+                v_out, F_out, C_out, Q, &bad);
             if (pid_in && pid_out) pid_out[p] = pid_in[p];
         }
     }
@@ -628,10 +750,124 @@ k_g2p(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
                       float* v_out, float* F_out, float* C_out, const int* pid_in, int* pid_out,
                       double h, hipStream_t s) {
-    const unsigned blocks = (unsigned)std::min<long long>(w.n_tiles, 4096);
+    const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(w.n_tiles, w.transfer_blocks));
     hipLaunchKernelGGL(k_g2p, dim3(blocks), dim3(256), 0, s, x_in, F_in, x_out, v_out, F_out,
                        C_out, w.Q, pid_in, pid_out, w.P, w.envs, w.n_envs, w.ptile_id,
                        w.ptile_beg, w.vel, h, w.cnt);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sort-policy arms (the ablation of Sec. V-A's sorting): with the particles
+// ordered by truncated keys or not reordered at all there are no particle
+// tiles, so P2G is a plain scatter, one thread per particle and 27 x 4 float
+// atomics into the dense accumulator (activating the node tiles the stencil
+// touches, which the grid update then visits), and G2P a plain gather from
+// the dense node velocities; the per-particle arithmetic is the tiled
+// kernels'.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256)
+k_p2g_plain(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ Q,
+            long long P, const DevEnv* __restrict__ envs, int n_envs, float4* __restrict__ acc,
+            unsigned* __restrict__ tile_flag, unsigned* __restrict__ active, DevCounters* cnt) {
+    if (cnt->abort_step) return;
+    bool clamped = false;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (long long)gridDim.x * blockDim.x) {
+        const DevEnv& E = envs[env_of_particle(envs, n_envs, p)];
+        const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
+        int b[3];
+        float f[3];
+        stencil_base(E, xp, b, f, &clamped);
+        float wx[3], wy[3], wz[3];
+        bspline_w(f[0], wx);
+        bspline_w(f[1], wy);
+        bspline_w(f[2], wz);
+        const float dx = E.dx, mp = E.m_p;
+        float mv[3], Qp[9];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) mv[a] = mp * v[a * P + p];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Qp[k] = Q[k * P + p];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float w = wx[a] * wy[bb] * wz[c];
+                    const float d[3] = {((float)a - f[0]) * dx, ((float)bb - f[1]) * dx, ((float)c - f[2]) * dx};
+                    float* g = reinterpret_cast<float*>(&acc[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]);
+                    atomicAdd(g, w * mp);
+#pragma unroll
+                    for (int r = 0; r < 3; ++r)
+                        atomicAdd(g + 1 + r, w * (mv[r] + Qp[3 * r] * d[0] + Qp[3 * r + 1] * d[1] + Qp[3 * r + 2] * d[2]));
+                }
+        for (int c = 0; c < 2; ++c)
+            for (int bb = 0; bb < 2; ++bb)
+                for (int a = 0; a < 2; ++a) {
+                    const unsigned t = node_tile(E, b[0] + 2 * a, b[1] + 2 * bb, b[2] + 2 * c);
+                    if (tile_flag[t] == 0u) activate_tile(t, tile_flag, active, cnt);
+                }
+    }
+    if (clamped) atomicOr(&cnt->flags, kFlagDomain);
+}
+
+__global__ void __launch_bounds__(256)
+k_g2p_plain(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F_out,
+            float* __restrict__ C_out, float* __restrict__ Q, const int* __restrict__ pid_in,
+            int* __restrict__ pid_out, long long P, const DevEnv* __restrict__ envs, int n_envs,
+            const float4* __restrict__ vel, double h, DevCounters* cnt) {
+    if (cnt->abort_step) return;
+    const float hf = (float)h;
+    bool bad = false;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+         p += (long long)gridDim.x * blockDim.x) {
+        const DevEnv& E = envs[env_of_particle(envs, n_envs, p)];
+        float xp[3] = {x_in[p], x_in[P + p], x_in[2 * P + p]};
+        float Fp[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) Fp[k] = F_in[k * P + p];
+        int b[3];
+        float f[3];
+        bool clamped = false;
+        stencil_base(E, xp, b, f, &clamped);
+        float wx[3], wy[3], wz[3];
+        bspline_w(f[0], wx);
+        bspline_w(f[1], wy);
+        bspline_w(f[2], wz);
+        const float* wv[3] = {wx, wy, wz};
+        auto from_mem = [&](int a, int bb, int c) { return vel[node_index(E, b[0] + a, b[1] + bb, b[2] + c)]; };
+        g2p_particle(E, P, p, xp, f, wv, Fp, hf, false, from_mem, from_mem, x_out, v_out, F_out, C_out, Q, &bad);
+        if (pid_in && pid_out) pid_out[p] = pid_in[p];
+    }
+    if (bad) atomicOr(&cnt->flags, kFlagNan);
+}
+
+hipError_t launch_p2g_plain(const Work& w, const float* x, const float* v, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::min<long long>((w.P + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_p2g_plain, dim3(blocks), dim3(256), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs, w.acc,
+                       w.tile_flag, w.active_tiles, w.cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_g2p_plain(const Work& w, const float* x_in, const float* F_in, float* x_out, float* v_out,
+                            float* F_out, float* C_out, const int* pid_in, int* pid_out, double h, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::min<long long>((w.P + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_g2p_plain, dim3(blocks), dim3(256), 0, s, x_in, F_in, x_out, v_out, F_out, C_out, w.Q,
+                       pid_in, pid_out, w.P, w.envs, w.n_envs, w.vel, h, w.cnt);
+    return hipGetLastError();
+}
+
+// No particle tiles this host step (the sort-policy arms): the grid update
+// then visits only the node tiles the scatter activates.
+__global__ void k_no_tiles(DevCounters* cnt) {
+    cnt->n_ptiles = 0u;
+    cnt->n_ntiles = 0u;
+}
+
+hipError_t launch_no_tiles(const Work& w, hipStream_t s) {
+    hipLaunchKernelGGL(k_no_tiles, dim3(1), dim3(1), 0, s, w.cnt);
     return hipGetLastError();
 }
 
@@ -679,6 +915,7 @@ __global__ void k_clear_step(DevCounters* cnt, double* rigid_acc, int n_acc, Sub
     for (int i = t; i < n_st; i += blockDim.x) {
         SubstepStats z;
         z.n_contacts = z.n_slots = z.iterations = z.converged = z.ls_rounds = z.pad = 0;
+        z.inner_iterations = z.pad2 = 0;
         z.residual = z.threshold = 0.0;
         for (int q = 0; q < 8; ++q) z.t_phase[q] = 0ull;
         st[i] = z;

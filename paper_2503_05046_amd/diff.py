@@ -22,66 +22,30 @@ Every step of the computation runs in the HIP library.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 
-from . import inputs as I
 from . import mpm as M
 
 
-def _rotation(w, angle_scale: float) -> np.ndarray:
-    """Rotation by the angle |w| * angle_scale about w (Rodrigues)."""
-    w = np.asarray(w, np.float64)
-    wn = float(np.linalg.norm(w))
-    th = wn * angle_scale
-    if th == 0.0:
-        return np.eye(3)
-    k = w / wn
-    K = np.array([[0.0, -k[2], k[1]], [k[2], 0.0, -k[0]], [-k[1], k[0], 0.0]])
-    return np.eye(3) + math.sin(th) * K + (1.0 - math.cos(th)) * (K @ K)
-
-
 class RigidPath:
-    """Poses and twists of a scene's rigid bodies at every host step: static
-    bodies stay at their pose; kinematic bodies translate by N h V and turn
-    by N h w per host step, from their initial pose."""
+    """The initial pose and twist of a scene's rigid bodies. Host step j of a
+    kinematic body's path is its initial state advanced by j host steps of the
+    library's kinematic rule (mpm_set_rigid_state); static bodies stay put."""
 
     def __init__(self, scene):
         self.dT = scene.N * scene.h
-        self.bodies = [(np.array(r.R, np.float64).reshape(3, 3), np.array(r.t, np.float64),
-                        np.array(r.w, np.float64), r.motion) for r in scene.rigids]
+        self.bodies = [(tuple(r.R), tuple(r.t), tuple(r.V), tuple(r.w), r.motion) for r in scene.rigids]
 
-    def states(self, step: int, V, W=None) -> list:
-        out = []
-        for i, (R0, t0, w, motion) in enumerate(self.bodies):
-            s = M.RigidState()
-            if motion == I.KINEMATIC:
-                Vi = np.asarray(V[i], np.float64)
-                if W is not None:
-                    w = np.asarray(W[i], np.float64)
-                R = _rotation(w, step * self.dT) @ R0
-                t = t0 + step * self.dT * Vi
-                s.V[:] = list(Vi)
-                s.w[:] = list(w)
-            else:
-                R, t = R0, t0
-            s.R[:] = list(R.reshape(-1))
-            s.t[:] = list(t)
-            out.append(s)
-        return out
-
-
-def _left_jacobian(phi) -> np.ndarray:
-    """J(phi) = I + (1 - cos t)/t^2 [phi]x + (t - sin t)/t^3 [phi]x^2, t = |phi|:
-    Rot(phi + d) = Rot(J(phi) d) Rot(phi) to first order in d."""
-    phi = np.asarray(phi, np.float64)
-    t2 = float(phi @ phi)
-    t = math.sqrt(t2)
-    a = 0.5 - t2 / 24.0 if t < 1e-4 else (1.0 - math.cos(t)) / t2
-    b = 1.0 / 6.0 - t2 / 120.0 if t < 1e-4 else (t - math.sin(t)) / (t2 * t)
-    P = np.array([[0.0, -phi[2], phi[1]], [phi[2], 0.0, -phi[0]], [-phi[1], phi[0], 0.0]])
-    return np.eye(3) + a * P + b * (P @ P)
+    def state(self, i: int, V=None, W=None):
+        """Initial state of body i, with the linear (V) and angular (W)
+        velocity replaced when given."""
+        R, t, V0, w0, motion = self.bodies[i]
+        s = M.RigidState()
+        s.R[:] = list(R)
+        s.t[:] = list(t)
+        s.V[:] = list(V0 if V is None else (float(a) for a in V))
+        s.w[:] = list(w0 if W is None else (float(a) for a in W))
+        return s
 
 
 def _run(sim, path, n_steps, step0, x, v, F, C, V, W=None, record: bool = False) -> None:
@@ -89,8 +53,11 @@ def _run(sim, path, n_steps, step0, x, v, F, C, V, W=None, record: bool = False)
     sim.tape_reset(record)
     Vn = V.detach().cpu().numpy().astype(np.float64).reshape(-1, 3)
     Wn = None if W is None else W.detach().cpu().numpy().astype(np.float64).reshape(-1, 3)
+    for i in range(len(path.bodies)):
+        # the body's initial state, advanced to host step step0 by the library
+        sim.set_rigid_state(i, path.state(i, Vn[i], None if Wn is None else Wn[i]), step0)
     for j in range(n_steps):
-        status, _, _ = sim.step(path.states(step0 + j, Vn, Wn))
+        status, _, _ = sim.step()
         if status != M.MPM_OK:
             # a contact solve that stopped at its iteration cap: the implicit
             # differentiation of the recorded solve assumes its optimum
@@ -126,21 +93,15 @@ def _make_function():
                 if gt is None:
                     gt = torch.zeros_like(ref)
                 g.append(gt.detach().to(device=sim.device, dtype=torch.float32)[:, pid].contiguous())
+            # the library's adjoints of the twist of each body's initial state
+            # (the reference set in _run), through every host step up to the
+            # segment's end
             env_grads, rig = sim.backward(*g)
             dE = torch.tensor([e[0] for e in env_grads], dtype=E.dtype, device=E.device)
-            dV = rig["dV_kinematic"] + ctx.step0 * ctx.path.dT * rig["dt"]
-            dV = torch.from_numpy(dV).to(dtype=V.dtype, device=V.device)
+            dV = torch.from_numpy(rig["dV_kinematic"]).to(dtype=V.dtype, device=V.device)
             dW = None
             if W is not None:
-                # the segment's first pose is Rot(b w) R0, b = step0 N h; a
-                # change dw turns it by b J(b w) dw, which reaches the loss
-                # through the rotation adjoint dR of that pose
-                b = ctx.step0 * ctx.path.dT
-                Wn = W.detach().cpu().numpy().astype(np.float64).reshape(-1, 3)
-                dWn = rig["dw_kinematic"].copy()
-                for i in range(Wn.shape[0]):
-                    dWn[i] += b * _left_jacobian(b * Wn[i]).T @ rig["dR"][i]
-                dW = torch.from_numpy(dWn).to(dtype=W.dtype, device=W.device)
+                dW = torch.from_numpy(rig["dw_kinematic"]).to(dtype=W.dtype, device=W.device)
             out = [t.to(dtype=ref.dtype, device=ref.device) for t, ref in zip(g, (x, v, F, C))]
             return (None, None, None, None, *out, dE, dV, dW)
 

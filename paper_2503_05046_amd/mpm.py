@@ -22,9 +22,10 @@ MPM_OK, MPM_ENOCONV, MPM_EDOMAIN, MPM_ENAN, MPM_EINVAL, MPM_ENOMEM, MPM_EDEVICE 
 STATUS_NAMES = {0: "MPM_OK", 1: "MPM_ENOCONV", 2: "MPM_EDOMAIN", 3: "MPM_ENAN", 4: "MPM_EINVAL",
                 5: "MPM_ENOMEM", 6: "MPM_EDEVICE"}
 FLAG_NOCONV, FLAG_DOMAIN, FLAG_NAN, FLAG_CAPACITY = 1, 2, 4, 8
+SOLVER_QN, SOLVER_NEWTON = 0, 1
 
 EXPORTED = ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step", "mpm_step_graph",
-            "mpm_get_rigid_state", "mpm_profile", "mpm_destroy", "mpm_tape_reset",
+            "mpm_get_rigid_state", "mpm_set_rigid_state", "mpm_profile", "mpm_destroy", "mpm_tape_reset",
             "mpm_step_backward", "mpm_last_error")
 KERNEL_CLASSES = ("sort", "p2g", "grid", "register", "setup", "solve", "g2p")
 
@@ -45,7 +46,8 @@ class Desc(ct.Structure):
                 ("x", ct.c_void_p), ("v", ct.c_void_p), ("F", ct.c_void_p), ("C", ct.c_void_p),
                 ("pid", ct.c_void_p), ("max_contacts", ct.c_int64), ("workspace", ct.c_void_p),
                 ("workspace_bytes", ct.c_size_t), ("stream", ct.c_void_p),
-                ("tape_substeps", ct.c_int32), ("solver_slots_per_block", ct.c_int32)]
+                ("tape_substeps", ct.c_int32), ("solver_slots_per_block", ct.c_int32),
+                ("solver", ct.c_int32)]
 
 
 class EnvGrad(ct.Structure):
@@ -79,7 +81,7 @@ class StepStats(ct.Structure):
                 ("total_iterations", ct.c_int64), ("max_contacts", ct.c_int32),
                 ("iterations", ct.POINTER(ct.c_int32)), ("contacts", ct.POINTER(ct.c_int32)),
                 ("contact_nodes", ct.POINTER(ct.c_int32)), ("residual", ct.POINTER(ct.c_double)),
-                ("threshold", ct.POINTER(ct.c_double))]
+                ("threshold", ct.POINTER(ct.c_double)), ("total_inner_iterations", ct.c_int64)]
 
 
 class ProfileData(ct.Structure):
@@ -119,6 +121,7 @@ def load():
                                ct.POINTER(StepStats)]
         L.mpm_step_graph.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidImpulse), ct.POINTER(StepStats)]
         L.mpm_get_rigid_state.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidState)]
+        L.mpm_set_rigid_state.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(RigidState), ct.c_int32]
         L.mpm_profile.argtypes = [ct.c_void_p, ct.c_int32, ct.POINTER(ProfileData)]
         L.mpm_tape_reset.argtypes = [ct.c_void_p, ct.c_int32]
         L.mpm_step_backward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
@@ -127,7 +130,7 @@ def load():
         L.mpm_destroy.restype = None
         L.mpm_last_error.restype = ct.c_char_p
         for f in ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
-                  "mpm_get_rigid_state", "mpm_profile"):
+                  "mpm_get_rigid_state", "mpm_set_rigid_state", "mpm_profile"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -167,7 +170,7 @@ def env_descs(scene) -> ct.Array:
 
 
 def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 0,
-              tape_substeps: int = 0, solver_slots_per_block: int = 0) -> Desc:
+              tape_substeps: int = 0, solver_slots_per_block: int = 0, solver: int = SOLVER_QN) -> Desc:
     d = Desc()
     d.struct_size = ct.sizeof(Desc)
     d.n_envs = len(scene.envs)
@@ -180,6 +183,7 @@ def make_desc(scene, envs: ct.Array, max_contacts: int = 0, ls_max_steps: int = 
     d.max_contacts = max_contacts
     d.tape_substeps = tape_substeps
     d.solver_slots_per_block = solver_slots_per_block
+    d.solver = solver
     return d
 
 
@@ -234,7 +238,7 @@ def _stats_dict(st, bufs) -> dict:
     return dict(flags=st.flags, max_iterations=st.max_iterations,
                 total_iterations=st.total_iterations, max_contacts=st.max_contacts,
                 iterations=list(its), contacts=list(ncs), contact_nodes=list(nns),
-                residual=list(res), threshold=list(thr))
+                residual=list(res), threshold=list(thr), inner_iterations=st.total_inner_iterations)
 
 
 def mpm_step_graph(h, n_rigid: int, N: int, n_steps: int):
@@ -269,7 +273,7 @@ def mpm_step(h, n_rigid: int, N: int, states: Optional[Sequence[RigidState]] = N
     stats = dict(flags=st.flags, max_iterations=st.max_iterations,
                  total_iterations=st.total_iterations, max_contacts=st.max_contacts,
                  iterations=list(its), contacts=list(ncs), contact_nodes=list(nns),
-                 residual=list(res), threshold=list(thr))
+                 residual=list(res), threshold=list(thr), inner_iterations=st.total_inner_iterations)
     return status, out, stats
 
 
@@ -277,6 +281,10 @@ def mpm_get_rigid_state(h, rid: int) -> RigidState:
     s = RigidState()
     _check(load().mpm_get_rigid_state(h, rid, ct.byref(s)), "mpm_get_rigid_state")
     return s
+
+
+def mpm_set_rigid_state(h, rid: int, state: RigidState, host_steps: int = 0) -> None:
+    _check(load().mpm_set_rigid_state(h, rid, ct.byref(state), int(host_steps)), "mpm_set_rigid_state")
 
 
 def mpm_profile(h, enable: int) -> dict:
@@ -321,7 +329,7 @@ class Sim:
 
     def __init__(self, scene, device: str = "cuda:0", max_contacts: int = 0,
                  ls_max_steps: int = 0, track_ids: bool = True, tape_substeps: int = 0,
-                 solver_slots_per_block: int = 0):
+                 solver_slots_per_block: int = 0, solver: int = SOLVER_QN):
         import torch
         load()
         self.torch = torch
@@ -337,7 +345,7 @@ class Sim:
         self.pid = torch.arange(self.P, dtype=torch.int32, device=dev) if track_ids else None
         self._envs = env_descs(scene)
         self.desc = make_desc(scene, self._envs, max_contacts, ls_max_steps, tape_substeps,
-                              solver_slots_per_block)
+                              solver_slots_per_block, solver)
         self.ws_bytes = mpm_workspace_size(self.desc)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
         base = self.ws.data_ptr()
@@ -417,6 +425,11 @@ class Sim:
     def rigid_state(self, i: int) -> RigidState:
         return mpm_get_rigid_state(self.handle, self.rigid_ids[i])
 
+    def set_rigid_state(self, i: int, state: RigidState, host_steps: int = 0) -> None:
+        """Body i at `state` advanced by host_steps kinematic host steps (the
+        library's rule); `state` becomes its reference for the reverse pass."""
+        mpm_set_rigid_state(self.handle, self.rigid_ids[i], state, host_steps)
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             self.torch.cuda.synchronize(self.device)
@@ -431,3 +444,4 @@ class Sim:
             self.close()
         except Exception:
             pass
+
