@@ -233,3 +233,27 @@ def test_batched_envs_sharing_blocks(mpm, oracle, monkeypatch):
     _log("batched: 5 environments on 2 solver blocks, 2 substeps")
     contacts = _compare_envs(mpm, oracle, s)
     assert contacts.min() > 0
+
+
+@pytest.mark.parametrize("policy", ["truncated", "none"])
+def test_sort_policy_arms(mpm, oracle, monkeypatch, policy):
+    """The arms of the sort ablation (keys cut to their top 10 bits, or no
+    reordering, with the plain scatter and gather): a random state under a
+    moving box (contact in both substeps) and the cube in free fall over 10
+    substeps, against the oracle."""
+    monkeypatch.setenv("MPM_SORT_POLICY", policy)
+    s = I.tiny_random(P=600, seed=41, n=24, material=I.DRUCKER_PRAGER, with_box=True)
+    s.envs[0].eps_s = 1e-2
+    s.eps_r = 1e-10
+    s.max_iter = 400000
+    _log(f"sort policy {policy}: random state under a moving box")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, s)
+    assert min(sg[0]["contacts"]) > 0
+    e = field_errors(g, o, s.envs[0].dx)
+    assert max(e.values()) < 1e-5, e
+    assert impulse_error(ig, io, s.envs[0].m_p * s.P, s.h) < 1e-4
+    c = I.plain_cube(contact=False)
+    _log(f"sort policy {policy}: free fall, 10 substeps")
+    g, o, ig, io, sg, so = _run_both(mpm, oracle, c)
+    e = field_errors(g, o, c.envs[0].dx)
+    assert max(e.values()) < 1e-5, e
