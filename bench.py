@@ -286,30 +286,142 @@ def run_streaming_4m(args) -> dict:
 
 
 def run_gripper_dense(args) -> dict:
-    """Ten substeps (one host step) of the gripper started in dense contact
-    (both jaws 0.065 m inside the ellipsoid's tips: about 2e4 contacts)."""
+    """The gripper in dense contact: both jaws started 0.065 m inside the
+    ellipsoid's tips (about 2e4 particles inside the jaws), one substep from
+    that state (the host step of one substep). At the benchmark tolerance
+    eps_r = 1e-6 Algorithm 1 converges on this first substep; on the following
+    substeps of the violent expulsion the block-diagonal iteration needs more
+    than 2e5 iterations, so the line is the converged first substep, with the
+    tolerance sweep of the same substep beside it (iterations, time, and the
+    velocity change against the eps_r = 1e-6 result in the mass norm)."""
+    import numpy as np
     import torch
     from paper_2503_05046_amd import inputs as I
     from paper_2503_05046_amd import mpm as M
-    scene = I.gripper(overlap=0.065)
-    scene.max_iter = args.max_iter
-    sim = M.Sim(scene, device="cuda:0")
-    sim.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    status, imp, st = sim.step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    prof = sim.profile(0)
-    sim.close()
-    log(f"gripper dense: {dt * 1e3:.1f} ms, contacts {st['contacts']}, iterations {st['iterations']}")
-    return {"value": scene.P * scene.N / dt, "unit": "particle-substeps/s", "ms_per_host_step": 1e3 * dt,
-            "contacts_mean": sum(st["contacts"]) / scene.N, "contact_nodes_mean": sum(st["contact_nodes"]) / scene.N,
-            "iterations_per_substep": st["iterations"],
-            "us_per_iteration": (round(1e3 * prof["ms"]["solve"] / prof["solver_iterations"], 2)
-                                 if prof["solver_iterations"] else None),
-            "config": "gripper: 250000 elastic particles, 96^3 grid, two jaws closing at 0.05 m/s started "
-                      "0.065 m inside the tips, mu=0.8, h=1e-4 s, 10 substeps, eps_r=1e-6"}
+    base = I.gripper(overlap=0.065)
+    base.N = 1
+    out = {"config": "gripper: 250000 elastic particles, 96^3 grid, two jaws closing at 0.05 m/s started 0.065 m "
+                     "inside the tips, mu=0.8, h=1e-4 s, one substep from that state",
+           "sweep": []}
+    ref_v = None
+    for eps_r in (1e-6, 1e-5, 1e-4, 1e-3, 1e-2, 5e-2, 1e-1):
+        scene = base.copy()
+        scene.eps_r = eps_r
+        scene.max_iter = args.max_iter
+        sim = M.Sim(scene, device="cuda:0")
+        sim.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        status, imp, st = sim.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = sim.profile(0)
+        v = sim.state()["v"].astype(np.float64)
+        sim.close()
+        if ref_v is None:
+            ref_v = v
+        m_p = scene.envs[0].m_p
+        drift = float(np.sqrt(m_p * np.sum((v - ref_v) ** 2)))
+        row = {"eps_r": eps_r, "status": status, "iterations": st["iterations"][0], "seconds": round(dt, 4),
+               "us_per_iteration": (round(1e3 * prof["ms"]["solve"] / prof["solver_iterations"], 2)
+                                    if prof["solver_iterations"] else None),
+               "contacts": st["contacts"][0], "contact_nodes": st["contact_nodes"][0],
+               "dv_mass_norm_vs_1e-6": drift}
+        log(f"gripper dense, eps_r {eps_r:g}: {row}")
+        out["sweep"].append(row)
+        if eps_r == 1e-6:
+            out.update({"value": scene.P / dt, "unit": "particle-substeps/s", "seconds": dt,
+                        "contacts": st["contacts"][0], "contact_nodes": st["contact_nodes"][0],
+                        "iterations": st["iterations"][0], "us_per_iteration": row["us_per_iteration"],
+                        "status": status})
+    return out
+
+
+def run_solver_variants(args) -> dict:
+    """Algorithm 1 (block-diagonal quasi-Newton) against the exact-Newton study
+    variant (the full Hessian system by preconditioned conjugate gradients)
+    on one substep of two dense-contact states at eps_r = 1e-6: the granular
+    pour started with its bottom layer 0.7 mm inside the box tops at 1 m/s,
+    and the gripper with both jaws 0.065 m inside the ellipsoid. Both solves
+    stop at the same test; their results differ by less than the sum of their
+    thresholds in the mass norm."""
+    import numpy as np
+    import torch
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+    scenes = {"granular_pour": I.granular_pour(n_particles=args.particles, sink=0.5 / 128 + 7e-4),
+              "gripper": I.gripper(overlap=0.065)}
+    out = {}
+    for name, scene in scenes.items():
+        scene.N = 1
+        scene.max_iter = args.max_iter
+        rows = {}
+        vs = {}
+        for label, solver in (("quasi_newton", M.SOLVER_QN), ("exact_newton", M.SOLVER_NEWTON)):
+            sim = M.Sim(scene, device="cuda:0", solver=solver)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            status, imp, st = sim.step()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            vs[label] = sim.state()["v"].astype(np.float64)
+            sim.close()
+            rows[label] = {"status": status, "seconds": round(dt, 4), "iterations": st["iterations"][0],
+                           "cg_iterations": st["inner_iterations"], "contacts": st["contacts"][0],
+                           "contact_nodes": st["contact_nodes"][0], "threshold": st["threshold"][0],
+                           "residual": st["residual"][0]}
+            log(f"solver variants, {name}, {label}: {rows[label]}")
+        m_p = scene.envs[0].m_p
+        rows["dv_mass_norm"] = float(np.sqrt(m_p * np.sum((vs["quasi_newton"] - vs["exact_newton"]) ** 2)))
+        rows["threshold_sum"] = rows["quasi_newton"]["threshold"] + rows["exact_newton"]["threshold"]
+        rows["speedup_exact_over_qn"] = rows["quasi_newton"]["seconds"] / rows["exact_newton"]["seconds"]
+        out[name] = rows
+    return out
+
+
+def run_sort_policies(args) -> dict:
+    """The sort ablation of Sec. V-A on the granular pour before contact (host
+    steps 1-2 of the run, 20 substeps): full keys once per host step with the
+    LDS-tiled P2G and G2P (the library's default), full keys every substep
+    (one substep per host step), the paper's truncated 10-bit keys once per
+    host step, and no reordering; the last two with the plain scatter (27 x 4
+    float atomics per particle into the grid) and gather. Per-launch times from
+    the library's HIP events."""
+    import torch
+    from paper_2503_05046_amd import inputs as I
+    from paper_2503_05046_amd import mpm as M
+    arms = [("tiles, once per host step", None, 10), ("tiles, every substep", None, 1),
+            ("truncated 10-bit keys, once per host step", "truncated", 10), ("no sort", "none", 10)]
+    out = []
+    for label, policy, N in arms:
+        if policy is None:
+            os.environ.pop("MPM_SORT_POLICY", None)
+        else:
+            os.environ["MPM_SORT_POLICY"] = policy
+        scene = I.granular_pour(n_particles=args.particles)
+        scene.h, scene.N = scene.h, N
+        sim = M.Sim(scene, device="cuda:0")
+        sim.step()  # warm (no contact yet)
+        sim.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_host = 20 // N
+        for _ in range(n_host):
+            status, imp, st = sim.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = sim.profile(0)
+        sim.close()
+        k = kernel_table(prof, scene.P)
+        row = {"arm": label, "us_per_substep": round(1e6 * dt / 20, 1),
+               "sort_us_per_substep": round(1e3 * prof["ms"]["sort"] / 20, 1),
+               "p2g_us": k["p2g"]["us_per_launch"], "grid_us": k["grid"]["us_per_launch"],
+               "g2p_us": k["g2p"]["us_per_launch"], "contacts_max": st["max_contacts"]}
+        log(f"sort policy: {row}")
+        out.append(row)
+    os.environ.pop("MPM_SORT_POLICY", None)
+    return {"config": f"granular pour, {args.particles} particles, 128^3 grid, 20 substeps before contact",
+            "arms": out}
 
 
 def cpu_baseline(args) -> dict:
@@ -493,8 +605,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gripper,4m",
-                    help="comma-separated subset of plain, batched, fwd_bwd, gripper, 4m")
+    ap.add_argument("--forms", default="plain,batched,fwd_bwd,gripper,4m,variants,sort",
+                    help="comma-separated subset of plain, batched, fwd_bwd, gripper, 4m, variants, sort")
     ap.add_argument("--particles", type=int, default=1_000_000)
     ap.add_argument("--max-iter", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -542,6 +654,10 @@ def main() -> int:
         extra["batched"] = run_batched(args)
     if "fwd_bwd" in forms:
         extra["fwd_bwd"] = run_fwd_bwd(args)
+    if "variants" in forms:
+        extra["solver_variants"] = run_solver_variants(args)
+    if "sort" in forms:
+        extra["sort_policies"] = run_sort_policies(args)
     if extra:
         out["forms"] = extra
     if "plain" in forms and not args.no_cpu_baseline:
