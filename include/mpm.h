@@ -345,6 +345,41 @@ mpm_status mpm_tape_reset(mpm_handle* h, int32_t record);
 mpm_status mpm_step_backward(mpm_handle* h, float* gx, float* gv, float* gF, float* gC,
                              mpm_env_grad* env_grads, mpm_rigid_grad* rigid_grads);
 
+/* ---- One host step that allocates nothing ---------------------------------
+ * For callers that cannot allocate device or pinned memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * host step as mpm_create + mpm_add_rigid_sdf (n_rigid times) + mpm_step(in =
+ * NULL) + mpm_destroy on a fresh handle, without a handle: the particle state
+ * of desc (x, v, F, C, and pid when not NULL) is advanced by N substeps in place
+ * and reordered by cell as mpm_step does; the rigid bodies are frozen at the
+ * given poses and twists for the step and are not advanced afterwards (no state
+ * is kept: the caller integrates them). The workspace is an array of
+ * MPM_STATIC_SCRATCH_BYTES in device memory that the library defines: every GPU
+ * it runs on holds one until the process ends, and every call on that GPU
+ * shares it and overwrites what the previous call left there. The library
+ * calls no allocating routine (no hipMalloc, hipHostMalloc, hipFree, no stream
+ * or event creation); host staging is in fixed static arrays.
+ *   desc: as for mpm_create, except desc->workspace must be NULL and
+ *     workspace_bytes 0, tape_substeps 0, n_envs <= MPM_STATIC_MAX_ENVS,
+ *     N <= MPM_STATIC_MAX_SUBSTEPS; the stream must belong to the current
+ *     device.
+ *   rigids, rigid_env: host arrays of n_rigid descriptors and their environment
+ *     indices (0 <= n_rigid <= 256, at most 32 per environment, ordered by
+ *     environment, validated as in mpm_add_rigid_sdf).
+ *   out (may be NULL): impulses on the bodies, in the given order; st: as in mpm_step.
+ * Returns as mpm_step, plus MPM_ENOMEM (nothing launched) when the scene's
+ * workspace (mpm_workspace_size) exceeds MPM_STATIC_SCRATCH_BYTES. Calls on
+ * one GPU share its array, so two calls whose device work overlapped would
+ * race on it; the library prevents that within a process by serialising the
+ * calls on the host (one lock over all devices) and returning from each only
+ * after its stream has finished the step. Not usable while the caller's stream
+ * is being captured (the call synchronises it). */
+#define MPM_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+#define MPM_STATIC_MAX_ENVS 8
+#define MPM_STATIC_MAX_SUBSTEPS 64
+mpm_status mpm_step_static(const mpm_desc* desc, const mpm_rigid_desc* rigids, const int32_t* rigid_env,
+                           int32_t n_rigid, mpm_rigid_impulse* out, mpm_step_stats* st);
+
 /* Thread-local description of the last error on the calling thread. */
 const char* mpm_last_error(void);
 

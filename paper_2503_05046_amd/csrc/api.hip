@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1290,6 +1291,162 @@ mpm_status mpm_profile(mpm_handle* h, int32_t enable, mpm_profile_data* out) {
     h->prof = enable != 0;
     h->prof_phases = enable >= 2;
     return MPM_OK;
+}
+
+// ---- One host step without a handle and without allocation ----------------
+// The workspace is this file-scope device array: every GPU the library runs on
+// holds its own copy until the process ends. Host code never passes the
+// array's name to a kernel or copy (on the host it is only a stand-in for the
+// symbol): the first call on a device looks up the device's address with
+// hipGetSymbolAddress, with that device current, and every later use goes
+// through that address.
+}  // extern "C"
+
+namespace {
+constexpr size_t kStaticScratchBytes = (size_t)MPM_STATIC_SCRATCH_BYTES;
+constexpr int kStaticMaxEnvs = MPM_STATIC_MAX_ENVS;
+constexpr int kStaticMaxN = MPM_STATIC_MAX_SUBSTEPS;
+constexpr int kStaticMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+struct StaticDevice {
+    void* ptr = nullptr;  // device address of scratch on this device
+    int qn_cap = 0;       // co-resident solver blocks
+};
+StaticDevice g_static_dev[kStaticMaxDevices];
+// host staging of the calls (pageable, fixed size); calls are serialised
+struct StaticHost {
+    DevEnv env[kStaticMaxEnvs];
+    DevRigid rig[kMaxRigidTotal];
+    DevCounters cnt;
+    SubstepStats stats[kStaticMaxN * kStaticMaxEnvs];
+    double racc[6 * kMaxRigidTotal];
+    int2 qn_map[kMaxQnBlocks];
+    int env_qn[2 * kStaticMaxEnvs];
+    int env_slots[kStaticMaxEnvs];
+    int groups[kStaticMaxEnvs];
+};
+StaticHost g_static_host;
+std::mutex g_static_mutex;
+
+// The device's scratch address and solver capacity, looked up on the first
+// call on the device (with it current).
+mpm_status static_device(StaticDevice** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices) return fail(MPM_EDEVICE, "device %d beyond the static table", dev);
+    StaticDevice& S = g_static_dev[dev];
+    if (!S.ptr) {
+        void* ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr || ((uintptr_t)ptr) % kAlign) return fail(MPM_EDEVICE, "static scratch address is not usable");
+        const int cap = qn_max_blocks();
+        if (cap < 1) return fail(MPM_EDEVICE, "cannot size the cooperative solver launch");
+        S.qn_cap = std::min(cap, kMaxQnBlocks);
+        S.ptr = ptr;
+    }
+    *out = &S;
+    return MPM_OK;
+}
+
+mpm_status step_static_locked(const mpm_desc* desc, const mpm_rigid_desc* rigids, const int32_t* rigid_env,
+                              int32_t n_rigid, mpm_rigid_impulse* out, mpm_step_stats* st) {
+    Sizes z;
+    mpm_status vs = validate(desc, &z);
+    if (vs != MPM_OK) return vs;
+    if (!desc->x || !desc->v || !desc->F || !desc->C) return fail(MPM_EINVAL, "state pointers must be non-NULL");
+    if (desc->workspace || desc->workspace_bytes) return fail(MPM_EINVAL, "the static step takes no workspace");
+    if (desc->tape_substeps) return fail(MPM_EINVAL, "the static step records no tape");
+    if (desc->n_envs > kStaticMaxEnvs) return fail(MPM_EINVAL, "at most %d environments", kStaticMaxEnvs);
+    if (desc->N > kStaticMaxN) return fail(MPM_EINVAL, "at most %d substeps per host step", kStaticMaxN);
+    if (n_rigid < 0 || n_rigid > kMaxRigidTotal) return fail(MPM_EINVAL, "0 to %d rigid bodies", kMaxRigidTotal);
+    if (n_rigid > 0 && (!rigids || !rigid_env)) return fail(MPM_EINVAL, "rigid arrays are NULL");
+    int per_env = 0;
+    for (int i = 0; i < n_rigid; ++i) {
+        if (rigid_env[i] < 0 || rigid_env[i] >= desc->n_envs) return fail(MPM_EINVAL, "rigid %d: env out of range", i);
+        if (i > 0 && rigid_env[i] < rigid_env[i - 1])
+            return fail(MPM_EINVAL, "rigid bodies must be ordered by environment");
+        per_env = (i > 0 && rigid_env[i] == rigid_env[i - 1]) ? per_env + 1 : 1;
+        if (per_env > kMaxRigidPerEnv) return fail(MPM_EINVAL, "at most %d rigid bodies per environment", kMaxRigidPerEnv);
+        const mpm_status rs = check_rigid(&rigids[i]);
+        if (rs != MPM_OK) return rs;
+    }
+    Work W;
+    const size_t need = layout(z, nullptr, &W);
+    if (need > kStaticScratchBytes)
+        return fail(MPM_ENOMEM, "the step needs %zu bytes of workspace, the static array holds %zu", need,
+                    kStaticScratchBytes);
+    StaticDevice* S = nullptr;
+    const mpm_status ds = static_device(&S);
+    if (ds != MPM_OK) return ds;
+    layout(z, (char*)S->ptr, &W);
+    W.qn_blocks = S->qn_cap;
+    int spb = 0, cap = S->qn_cap;
+    solver_options(desc, &W, &spb, &cap);
+    StaticHost& H = g_static_host;
+    const int n_envs = desc->n_envs, N = desc->N;
+    StepCtx c;
+    c.w = &W;
+    c.d = desc;
+    c.key_bits = make_dev_envs(desc->envs, n_envs, H.env);
+    c.slots_per_block = spb;
+    c.rec = false;
+    c.tape_len = 0;
+    c.prof = nullptr;
+    c.phases = false;
+    for (int i = 0; i < n_rigid; ++i) place_dev_rigid(rigids[i], rigid_env[i], i, H.rig + i, H.env);
+    W.n_rigid = n_rigid;
+    for (int e = 0; e < n_envs; ++e) H.env_slots[e] = 0;  // no earlier step: groups from headroom alone
+    int env_stride = 0;
+    const int qn_blocks = plan_groups(n_envs, H.env_slots, spb, cap, H.groups, H.qn_map, H.env_qn, &env_stride);
+    hipStream_t s = (hipStream_t)desc->stream;
+    // everything a previous call left in the array is stale
+    HIP_TRY(init_workspace(W, H.env, s));
+    HIP_TRY(hipMemcpyAsync(W.rigids, H.rig, sizeof(DevRigid) * std::max(n_rigid, 1), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.qn_map, H.qn_map, sizeof(int2) * qn_blocks, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(W.env_qn, H.env_qn, sizeof(int) * 2 * n_envs, hipMemcpyHostToDevice, s));
+    int npair = 0;
+    mpm_status es = enqueue_host_step(c, qn_blocks, env_stride, false, npair, s);
+    if (es == MPM_OK) {
+        const hipError_t e1 = hipMemcpyAsync(&H.cnt, W.cnt, sizeof(DevCounters), hipMemcpyDeviceToHost, s);
+        const hipError_t e2 = hipMemcpyAsync(H.stats, W.sstats, sizeof(SubstepStats) * N * n_envs,
+                                             hipMemcpyDeviceToHost, s);
+        const hipError_t e3 = hipMemcpyAsync(H.racc, W.rigid_acc, sizeof(double) * 6 * std::max(n_rigid, 1),
+                                             hipMemcpyDeviceToHost, s);
+        if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess)
+            es = fail(MPM_EDEVICE, "copying the step's results failed");
+    }
+    // the call returns only after its device work: the next call reuses the array
+    const hipError_t se = hipStreamSynchronize(s);
+    if (es != MPM_OK) return es;
+    if (se != hipSuccess) return fail(MPM_EDEVICE, "hipStreamSynchronize failed: %s", hipGetErrorString(se));
+    const unsigned flags = H.cnt.flags;
+    if (H.cnt.abort_step && H.cnt.abort_substep > 0) {
+        // the step stopped early: the caller's C lags the state; rebuild it from Q
+        HIP_TRY(launch_recover_C(W, desc->F, desc->C, desc->h, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    }
+    if (out) {
+        for (int k = 0; k < n_rigid; ++k)
+            for (int a = 0; a < 3; ++a) {
+                out[k].impulse[a] = H.racc[6 * k + a];
+                out[k].torque[a] = H.racc[6 * k + 3 + a];
+            }
+    }
+    fill_step_stats(H.stats, N, n_envs, flags, st);
+    return step_status(flags, W.cap_c, H.cnt.n_contacts);
+}
+}  // namespace
+
+extern "C" {
+
+mpm_status mpm_step_static(const mpm_desc* desc, const mpm_rigid_desc* rigids, const int32_t* rigid_env,
+                           int32_t n_rigid, mpm_rigid_impulse* out, mpm_step_stats* st) {
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    return step_static_locked(desc, rigids, rigid_env, n_rigid, out, st);
 }
 
 void mpm_destroy(mpm_handle* h) {

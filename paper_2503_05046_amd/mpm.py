@@ -26,7 +26,7 @@ SOLVER_QN, SOLVER_NEWTON = 0, 1
 
 EXPORTED = ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step", "mpm_step_graph",
             "mpm_get_rigid_state", "mpm_set_rigid_state", "mpm_profile", "mpm_destroy", "mpm_tape_reset",
-            "mpm_step_backward", "mpm_last_error")
+            "mpm_step_backward", "mpm_step_static", "mpm_last_error")
 KERNEL_CLASSES = ("sort", "p2g", "grid", "register", "setup", "solve", "g2p")
 
 
@@ -126,11 +126,13 @@ def load():
         L.mpm_tape_reset.argtypes = [ct.c_void_p, ct.c_int32]
         L.mpm_step_backward.argtypes = [ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                         ct.POINTER(EnvGrad), ct.POINTER(RigidGrad)]
+        L.mpm_step_static.argtypes = [ct.POINTER(Desc), ct.POINTER(RigidDesc), ct.POINTER(ct.c_int32), ct.c_int32,
+                                      ct.POINTER(RigidImpulse), ct.POINTER(StepStats)]
         L.mpm_destroy.argtypes = [ct.c_void_p]
         L.mpm_destroy.restype = None
         L.mpm_last_error.restype = ct.c_char_p
         for f in ("mpm_workspace_size", "mpm_create", "mpm_add_rigid_sdf", "mpm_step",
-                  "mpm_get_rigid_state", "mpm_set_rigid_state", "mpm_profile"):
+                  "mpm_get_rigid_state", "mpm_set_rigid_state", "mpm_profile", "mpm_step_static"):
             getattr(L, f).restype = ct.c_int
         _lib = L
     return _lib
@@ -275,6 +277,20 @@ def mpm_step(h, n_rigid: int, N: int, states: Optional[Sequence[RigidState]] = N
                  iterations=list(its), contacts=list(ncs), contact_nodes=list(nns),
                  residual=list(res), threshold=list(thr), inner_iterations=st.total_inner_iterations)
     return status, out, stats
+
+
+def mpm_step_static(desc: Desc, rigids: Sequence[RigidDesc], rigid_env: Sequence[int], N: int):
+    """One host step without a handle, on the library's static workspace
+    (desc.workspace NULL). Returns (status, impulses [n_rigid, 6], stats dict)."""
+    n = len(rigids)
+    rig = (RigidDesc * max(1, n))(*rigids)
+    env = (ct.c_int32 * max(1, n))(*[int(e) for e in rigid_env])
+    imp = (RigidImpulse * max(1, n))()
+    st, bufs = _stats_buffers(N)
+    status = load().mpm_step_static(ct.byref(desc), rig, env, n, imp, ct.byref(st))
+    _check(status, "mpm_step_static", allow=(MPM_OK, MPM_ENOCONV))
+    out = np.array([[*imp[i].impulse, *imp[i].torque] for i in range(n)]).reshape(n, 6)
+    return status, out, _stats_dict(st, bufs)
 
 
 def mpm_get_rigid_state(h, rid: int) -> RigidState:
@@ -445,3 +461,47 @@ class Sim:
         except Exception:
             pass
 
+
+class StaticStep:
+    """A scene's particle arrays on one GPU, stepped by mpm_step_static (no
+    handle, no workspace: the library's static array). Rigid bodies stay at the
+    scene's poses."""
+
+    def __init__(self, scene, device: str = "cuda:0", max_contacts: int = 0, solver_slots_per_block: int = 0):
+        import torch
+        load()
+        self.torch = torch
+        self.scene = scene
+        self.device = torch.device(device)
+        dev = self.device
+        self.x = torch.from_numpy(np.ascontiguousarray(scene.x, np.float32)).to(dev)
+        self.v = torch.from_numpy(np.ascontiguousarray(scene.v, np.float32)).to(dev)
+        self.F = torch.from_numpy(np.ascontiguousarray(scene.F, np.float32)).to(dev)
+        self.C = torch.from_numpy(np.ascontiguousarray(scene.C, np.float32)).to(dev)
+        self.pid = torch.arange(scene.P, dtype=torch.int32, device=dev)
+        self._envs = env_descs(scene)
+        d = make_desc(scene, self._envs, max_contacts, 0, 0, solver_slots_per_block)
+        d.x, d.v, d.F, d.C = (t.data_ptr() for t in (self.x, self.v, self.F, self.C))
+        d.pid = self.pid.data_ptr()
+        d.workspace, d.workspace_bytes = None, 0
+        d.stream = torch.cuda.current_stream(dev).cuda_stream
+        self.desc = d
+        order = sorted(range(len(scene.rigids)), key=lambda i: scene.rigids[i].env)
+        self.order = order
+        self.rigids = [rigid_desc(scene.rigids[i]) for i in order]
+        self.rigid_env = [scene.rigids[i].env for i in order]
+
+    def step(self):
+        """One host step; impulses in the scene's rigid order."""
+        status, imp, st = mpm_step_static(self.desc, self.rigids, self.rigid_env, self.scene.N)
+        out = np.zeros_like(imp)
+        out[self.order] = imp
+        return status, out, st
+
+    def state(self) -> dict:
+        self.torch.cuda.synchronize(self.device)
+        out = {k: getattr(self, k).cpu().numpy() for k in ("x", "v", "F", "C")}
+        pid = self.pid.cpu().numpy()
+        inv = np.empty_like(pid)
+        inv[pid] = np.arange(pid.shape[0], dtype=pid.dtype)
+        return {k: a[:, inv] for k, a in out.items()}
