@@ -42,7 +42,7 @@ mpm_status fail(mpm_status st, const char* fmt, ...) {
     } while (0)
 
 constexpr int kMaxRigidTotal = 256;
-constexpr int kMaxQnBlocks = 1024;
+constexpr int kMaxQnBlocks = kQnMaxBlocks;
 constexpr int kQnItemsPerBlock = 128;  // contact nodes per solver block
 constexpr int kTransferBlocks = 4096;  // default blocks of the tiled P2G and G2P launches
 constexpr size_t kAlign = 256;
@@ -173,6 +173,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->partial = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
     w->partial_odd = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
     w->partial2 = L.take<double>(kMaxQnBlocks);
+    w->qn_lspart = L.take<double>((size_t)4 * kMaxQnBlocks);
     w->rigid_acc = L.take<double>(6 * kMaxRigidTotal);
     w->sstats = L.take<SubstepStats>((size_t)z.N * z.n_envs);
     w->env_pnorm = L.take<double>(z.n_envs);

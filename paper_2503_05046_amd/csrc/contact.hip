@@ -550,6 +550,7 @@ struct QnArgs {
     double* vc_blk;            // per group rank: [6][kScatterMax] v_c, u_c of the line search's contacts
     int timers;                // 1: the first block of each environment times the solver's phases
     int slots_per_block;       // contact nodes per block that set an environment's group size
+    double* ls_part;           // [2][kQnMaxBlocks][2] line-search sums of the distributed line search
     double* nt_slot;           // exact-Newton variant: per contact-node vectors
     double* nt_con;            // exact-Newton variant: per-contact terms
     DevCounters* cnt;
@@ -1148,6 +1149,7 @@ k_qn(QnArgs A) {
         }
 
         int k = 0, ls_total = 0, converged = 0;
+        unsigned ls_par = 0;  // buffer parity of the distributed line search
         double alpha_prev = 1.0, res = 0.0, thr = 0.0;
         // every thread's stores above (v_c^0, cleared sums, flags) acknowledged
         // before its block arrives
@@ -1358,6 +1360,11 @@ k_qn(QnArgs A) {
             LsCoef lc[kLsPer];
             const long long c_lds = ec0 + tid + (long long)kLsPer * T;
             const bool use_lds = (long long)kLsPer * T < nc;
+            // an environment with more contacts than a block's registers and LDS
+            // hold evaluates the line search distributed: each block sums its
+            // own contacts, and every evaluation meets at a group barrier (one
+            // barrier instead of every block streaming all coefficients)
+            const bool dist = !scatter && G > 1u && nc > (long long)(kLsPer + 1) * T;
             if (scatter) {
                 // ---- line-search set-up in every block, over all the environment's
                 // contacts (contact ec0 + i taken by thread i mod T): v_c^k from the
@@ -1488,13 +1495,15 @@ k_qn(QnArgs A) {
                 ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
                 if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
                 if (!ok) break;
-                // the coefficients the contact pass stored (coalesced loads)
+                // the coefficients the contact pass stored (coalesced loads): all
+                // the environment's, or with the distributed line search the block's own
+                const long long cl0 = dist ? c0 : ec0, cl1 = dist ? c1 : ec1;
 #pragma unroll
                 for (int u = 0; u < kLsPer; ++u) {
-                    const long long c = ec0 + tid + (long long)u * T;
-                    lc[u] = c < ec1 ? coef_of(c) : ls_coef_zero();
+                    const long long c = cl0 + tid + (long long)u * T;
+                    lc[u] = c < cl1 ? coef_of(c) : ls_coef_zero();
                 }
-                if (use_lds) ls_ovf[tid] = c_lds < ec1 ? coef_of(c_lds) : ls_coef_zero();
+                if (use_lds && !dist) ls_ovf[tid] = c_lds < ec1 ? coef_of(c_lds) : ls_coef_zero();
             }
             // phi''(0) - A summed over the group (wave 0; the one-barrier form
             // summed every contact in the block already), then the first trial
@@ -1521,7 +1530,14 @@ k_qn(QnArgs A) {
                     acc2[0] += d1;
                     acc2[1] += d2;
                 }
-                if (use_lds) {
+                if (dist) {
+                    double d1, d2;
+                    for (long long c = c0 + tid + (long long)kLsPer * T; c < c1; c += T) {
+                        ls_eval(coef_of(c), alpha, &d1, &d2);
+                        acc2[0] += d1;
+                        acc2[1] += d2;
+                    }
+                } else if (use_lds) {
                     double d1, d2;
                     ls_eval(ls_ovf[tid], alpha, &d1, &d2);
                     acc2[0] += d1;
@@ -1533,10 +1549,36 @@ k_qn(QnArgs A) {
                     }
                 }
                 block_allsum<2>(acc2, rbuf, rpar);
+                if (dist) {
+                    // the group's sums, in block order in every block (two buffers by
+                    // evaluation parity, as for the iteration's block sums)
+                    double* pb = A.ls_part + (size_t)(ls_par & 1u) * 2 * kQnMaxBlocks;
+                    ls_par ^= 1u;
+                    if (tid == 0) {
+                        st_x(&pb[2 * (first + rank)], acc2[0]);
+                        st_x(&pb[2 * (first + rank) + 1], acc2[1]);
+                    }
+                    if (!loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt)) {
+                        ok = false;
+                        return 0.0;  // stops the search; the solve then ends with the flag set
+                    }
+                    const int wv = tid >> 6, lane = tid & 63;
+                    if (wv < 2) {
+                        double a = 0.0;
+                        for (unsigned b = lane; b < G; b += 64) a += ld_x(&pb[2 * (first + b) + wv]);
+                        a = wave_sum(a);
+                        if (lane == 0) tot[wv] = a;
+                    }
+                    __syncthreads();
+                    acc2[0] = tot[0];
+                    acc2[1] = tot[1];
+                    __syncthreads();
+                }
                 *d2out = Aq + acc2[1];
                 return fma(Aq, alpha, Bq) + acc2[0];
             };
             const double alpha = exact_line_search(eval, alpha0, d0, A.ls_max_steps, &ls_total);
+            if (!ok) break;
             if (timer) { const unsigned long long t = wall_clock64(); tph[6] += t - tmark; tmark = t; }
             if (cmp) {
                 // by the node's first lane, which formed its dv and reads its
@@ -2019,6 +2061,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.env_stride = env_stride;
     A.nt_slot = w.nt_slot;
     A.nt_con = w.nt_con;
+    A.ls_part = w.qn_lspart;
     A.cnt = w.cnt;
     void* args[] = {&A};
     auto launch = [&](const void* fn) -> hipError_t {

@@ -206,6 +206,7 @@ struct Work {
     int transfer_blocks;     // blocks of the tiled P2G and G2P launches (each takes particle tiles in turn)
     double* nt_slot;         // exact-Newton variant: [cap_s][kNtSlot] per contact-node vectors
     double* nt_con;          // exact-Newton variant: [cap_c][kNtCon] per-contact terms
+    double* qn_lspart;       // [2][kQnMaxBlocks][2] per-block line-search sums of the distributed line search
 };
 
 // The exact-Newton variant (the value of MPM_SOLVER_NEWTON) and its per-node and
@@ -253,6 +254,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
                      int timers, int slots_per_block, hipStream_t s);
 int qn_max_blocks();
 constexpr int kQnMaxGroup = 128;  // blocks of one environment's group (partials staged in LDS)
+constexpr int kQnMaxBlocks = 1024;  // solver blocks a launch may have (capacity of the per-block buffers)
 hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float* x_out,
                       float* v_out, float* F_out, float* C_out, const int* pid_in,
                       int* pid_out, double h, hipStream_t s);

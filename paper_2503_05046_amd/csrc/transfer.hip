@@ -596,9 +596,10 @@ hipError_t launch_grid_update(const Work& w, double h, hipStream_t s) {
 // v_p = sum w v_i, C_p = D sum w v_i (x_i - x_p)^T, F <- (I + h C) F,
 // x <- x + h v_p, the return map for sand, and Q for the next P2G. near(a, b,
 // c) and far(a, b, c) return the velocity of stencil node (a, b, c), the
-// first used when `local` holds.
-template <typename NearV, typename FarV>
-__device__ __forceinline__ void g2p_particle(const DevEnv& E, long long P, long long p, const float xp[3],
+// first used when `local` holds. Idx: the index type of the particle arrays
+// (32-bit when every index fits, so stores take a scalar base and one offset).
+template <typename Idx, typename NearV, typename FarV>
+__device__ __forceinline__ void g2p_particle(const DevEnv& E, Idx P, Idx p, const float xp[3],
                                              const float f[3], const float* const w[3], const float Fp[9],
                                              float hf, bool local, NearV near, FarV far, float* x_out,
                                              float* v_out, float* F_out, float* C_out, float* Q, bool* bad_out) {
@@ -692,10 +693,11 @@ __device__ __forceinline__ void g2p_particle(const DevEnv& E, long long P, long 
     *bad_out |= bad;
 }
 
+template <typename Idx>
 __global__ void __launch_bounds__(256)
 k_g2p(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F_out,
       float* __restrict__ C_out, float* __restrict__ Q, const int* __restrict__ pid_in,
-      int* __restrict__ pid_out, long long P, const DevEnv* __restrict__ envs, int n_envs,
+      int* __restrict__ pid_out, Idx P, const DevEnv* __restrict__ envs, int n_envs,
       const unsigned* __restrict__ ptile_id, const unsigned* __restrict__ ptile_beg,
       const float4* __restrict__ vel, double h, DevCounters* cnt) {
     __shared__ float4 sv[kBN3];  // node velocities of the tile's block (w unused)
@@ -705,7 +707,7 @@ k_g2p(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F
     bool bad = false;
     for (unsigned t = blockIdx.x; t < n_tiles; t += gridDim.x) {
         const unsigned gt = ptile_id[t];
-        const long long pb = ptile_beg[t], pe = ptile_beg[t + 1];
+        const Idx pb = ptile_beg[t], pe = ptile_beg[t + 1];
         const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
         int tx, ty, tz;
         tile_coords(E, gt, &tx, &ty, &tz);
@@ -719,7 +721,7 @@ k_g2p(const float* x_in, const float* F_in, float* x_out, float* v_out, float* F
             sv[n] = vv;
         }
         __syncthreads();
-        for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) {
+        for (Idx p = pb + threadIdx.x; p < pe; p += blockDim.x) {
             float xp[3] = {x_in[p], x_in[P + p], x_in[2 * P + p]};
             float Fp[9];
 #pragma unroll
@@ -751,9 +753,14 @@ hipError_t launch_g2p(const Work& w, const float* x_in, const float* F_in, float
                       float* v_out, float* F_out, float* C_out, const int* pid_in, int* pid_out,
                       double h, hipStream_t s) {
     const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(w.n_tiles, w.transfer_blocks));
-    hipLaunchKernelGGL(k_g2p, dim3(blocks), dim3(256), 0, s, x_in, F_in, x_out, v_out, F_out,
-                       C_out, w.Q, pid_in, pid_out, w.P, w.envs, w.n_envs, w.ptile_id,
-                       w.ptile_beg, w.vel, h, w.cnt);
+    if (24 * w.P < (1ll << 32))
+        hipLaunchKernelGGL(k_g2p<unsigned>, dim3(blocks), dim3(256), 0, s, x_in, F_in, x_out, v_out, F_out,
+                           C_out, w.Q, pid_in, pid_out, (unsigned)w.P, w.envs, w.n_envs, w.ptile_id,
+                           w.ptile_beg, w.vel, h, w.cnt);
+    else
+        hipLaunchKernelGGL(k_g2p<long long>, dim3(blocks), dim3(256), 0, s, x_in, F_in, x_out, v_out, F_out,
+                           C_out, w.Q, pid_in, pid_out, w.P, w.envs, w.n_envs, w.ptile_id,
+                           w.ptile_beg, w.vel, h, w.cnt);
     return hipGetLastError();
 }
 
