@@ -189,6 +189,26 @@ __device__ __forceinline__ LsCoef load_coef(const double* __restrict__ buf, long
     return L;
 }
 
+// The same from a contact's line-search constants (eps_s^2, mu n0, phi0, d,
+// h k), with the same roundings.
+__device__ __forceinline__ LsCoef ls_coef_pre(double eps2, double mun0, double phi0, double d, double hk,
+                                              double h, const double vc[3], const double u[3]) {
+    LsCoef L;
+    L.q0 = vc[0] * vc[0] + vc[1] * vc[1] + eps2;
+    L.p0 = vc[0] * u[0] + vc[1] * u[1];
+    L.q2 = u[0] * u[0] + u[1] * u[1];
+    L.mun0 = mun0;
+    L.a0 = phi0 - h * vc[2];
+    L.a1 = h * u[2];
+    L.b0 = 1.0 - d * vc[2];
+    L.b1 = d * u[2];
+    const double hkuu = hk * u[2] * u[2];
+    L.kn = hk * u[2];
+    L.eh = hkuu * h;
+    L.ed = hkuu * d;
+    return L;
+}
+
 // Coefficients that contribute exactly zero (padding lanes).
 __device__ __forceinline__ LsCoef ls_coef_zero() {
     LsCoef L;
@@ -547,7 +567,8 @@ struct QnArgs {
     int compact;               // 0: no block takes the compact node pass
     int* env_pend;             // per environment: 1 when k_qn<true> left it to k_qn<false>
     double* u_acc;             // [3 buffers][3][cap] per-contact sums U_c of the one-barrier form
-    double* vc_blk;            // per group rank: [6][kScatterMax] v_c, u_c of the line search's contacts
+    double* vc_blk;            // per group rank: kQnRankWords doubles (see the one-barrier set-up)
+    double* ls_prm;            // [5][cap]: eps_s^2, mu n0, phi0, d, h k of every contact (one-barrier form)
     int timers;                // 1: the first block of each environment times the solver's phases
     int slots_per_block;       // contact nodes per block that set an environment's group size
     double* ls_part;           // [2][kQnMaxBlocks][2] line-search sums of the distributed line search
@@ -578,10 +599,14 @@ __device__ __forceinline__ void contact_velocity(const ContactDyn& D, int k, dou
 }
 
 // u = R_c^T U in the contact frame, with the same rounding wherever it is formed.
+__device__ __forceinline__ void frame_project(const double t1[3], const double t2[3], const double n[3],
+                                              const double U[3], double u[3]) {
+    u[0] = fma(t1[0], U[0], fma(t1[1], U[1], t1[2] * U[2]));
+    u[1] = fma(t2[0], U[0], fma(t2[1], U[1], t2[2] * U[2]));
+    u[2] = fma(n[0], U[0], fma(n[1], U[1], n[2] * U[2]));
+}
 __device__ __forceinline__ void frame_project(const ContactRec& R, const double U[3], double u[3]) {
-    u[0] = fma(R.t1[0], U[0], fma(R.t1[1], U[1], R.t1[2] * U[2]));
-    u[1] = fma(R.t2[0], U[0], fma(R.t2[1], U[1], R.t2[2] * U[2]));
-    u[2] = fma(R.n[0], U[0], fma(R.n[1], U[1], R.n[2] * U[2]));
+    frame_project(R.t1, R.t2, R.n, U, u);
 }
 
 // Sum of x over the 64 lanes of a wave, the same bits in every lane: DPP
@@ -621,28 +646,82 @@ __device__ __forceinline__ double wave_sum(double x) {
     return swap_add<true>(x); // the two halves
 }
 
-// Block-wide FP64 sums of NV values per thread over a block of NW waves,
+// The value x of the lane 32 (kHalf) or 16 lanes away (lane ^ 32, lane ^ 16)
+// by the permlane swaps: of the two results one is the lane's own value,
+// the other its partner's (told apart by comparing the bits).
+template <bool kHalf>
+__device__ __forceinline__ double lane_partner(double x) {
+    const long long b = __builtin_bit_cast(long long, x);
+    const unsigned lo = (unsigned)b, hi = (unsigned)(b >> 32);
+    const auto l = kHalf ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                         : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = kHalf ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                         : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    const bool first_is_own = l[0] == lo && h[0] == hi;
+    const unsigned plo = first_is_own ? l[1] : l[0], phi = first_is_own ? h[1] : h[0];
+    return __builtin_bit_cast(double, ((long long)phi << 32) | (long long)plo);
+}
+template <int kDist>
+__device__ __forceinline__ double lane_xor(double x) {
+    if constexpr (kDist == 32) return lane_partner<true>(x);
+    else if constexpr (kDist == 16) return lane_partner<false>(x);
+    else return dpp_move<0x128>(x);  // kDist == 8: row_ror:8
+}
+// One halving step of a multi-value wave reduction: the lanes with bit kDist
+// clear keep the first H values, the others the last H, each plus the
+// partner's copy of the same value.
+template <int kDist, int H, int P>
+__device__ __forceinline__ void split_step(double (&w)[P]) {
+    const bool up = (threadIdx.x & kDist) != 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const double send = up ? w[i] : w[H + i];
+        const double keep = up ? w[H + i] : w[i];
+        w[i] = keep + lane_xor<kDist>(send);
+    }
+}
+
+// Block-wide FP64 sums of NV <= 8 values per thread over a block of NW waves,
 // returned in every thread with the same bits in every thread (and in every
-// block that sums the same values): wave sums, one workgroup barrier, then
-// each thread adds the wave sums in wave order. buf holds 2 x 16 x NV doubles used alternately, so a
-// wave that runs ahead cannot overwrite sums another wave is still reading.
+// block that sums the same values). In each wave the values (padded to P, a
+// power of two) are first split across the lane halves, quarters and eighths
+// (lane ^ 32, ^ 16, ^ 8: each exchange moves half of the remaining values),
+// so that every group of 64 / P lanes ends with one value, which a butterfly
+// over the group completes (each step adds two equal-rank partial sums in
+// either order, so the group's lanes agree); one workgroup barrier, then each
+// thread adds the wave sums in wave order. buf holds 2 x 16 x NV doubles used
+// alternately, so a wave that runs ahead cannot overwrite sums another wave is
+// still reading.
 template <int NV, int NW = kQnThreads / 64>
 __device__ __forceinline__ void block_allsum(double (&v)[NV], double* buf, unsigned& parity) {
+    static_assert(NV >= 1 && NV <= 8, "up to eight values");
+    constexpr int P = NV == 1 ? 1 : NV == 2 ? 2 : NV <= 4 ? 4 : 8;
+    static_assert(NW * P <= 16 * NV, "wave sums fit the buffer");
     double* b = buf + (parity & 1u) * 16 * NV;
     parity ^= 1u;
-    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double w[P];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        const double ws = wave_sum(v[k]);
-        if ((threadIdx.x & 63) == 0) b[wave * NV + k] = ws;
-    }
+    for (int i = 0; i < P; ++i) w[i] = i < NV ? v[i] : 0.0;
+    int idx = 0;
+    if constexpr (P >= 2) { split_step<32, P / 2>(w); idx += (lane & 32) ? P / 2 : 0; }
+    if constexpr (P >= 4) { split_step<16, P / 4>(w); idx += (lane & 16) ? P / 4 : 0; }
+    if constexpr (P >= 8) { split_step<8, 1>(w); idx += (lane & 8) ? 1 : 0; }
+    double x = w[0];
+    x += dpp_move<0xB1>(x);   // quad_perm [1, 0, 3, 2]
+    x += dpp_move<0x4E>(x);   // quad_perm [2, 3, 0, 1]
+    x += dpp_move<0x141>(x);  // row_half_mirror
+    if constexpr (P <= 4) x += dpp_move<0x140>(x);  // row_mirror
+    if constexpr (P <= 2) x = swap_add<false>(x);   // rows 0 + 1, rows 2 + 3
+    if constexpr (P == 1) x = swap_add<true>(x);    // the two halves
+    if ((lane & (64 / P - 1)) == 0 && idx < NV) b[wave * P + idx] = x;
     __syncthreads();
     // NW is the block's wave count: a constant, so all the reads issue together
 #pragma unroll
     for (int k = 0; k < NV; ++k) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) t += b[w * NV + k];
+        for (int w2 = 0; w2 < NW; ++w2) t += b[w2 * P + k];
         v[k] = t;
     }
 }
@@ -947,7 +1026,7 @@ __device__ __forceinline__ bool loop_sync(unsigned* ctr, int rank, unsigned G, u
 
 constexpr int kEntBatch = 2;     // CSR entries per thread whose loads are issued together
 constexpr int kLsPer = 3;        // contacts per thread the line search keeps in registers
-constexpr int kUniqMax = 512;    // distinct contacts of a block's entries the compact node pass holds
+constexpr int kUniqMax = kQnUniqMax;  // distinct contacts of a block's entries the compact node pass holds
 constexpr int kEntMax = 2048;    // CSR entries of a block the compact node pass holds
 constexpr int kHashBits = 12;
 constexpr int kHash = 1 << kHashBits;  // open-addressing table that finds the distinct contacts
@@ -955,6 +1034,7 @@ static_assert(kHash * sizeof(int) <= 9 * kSlotChunk * sizeof(double), "hash tabl
 static_assert(9 * kUniqMax <= 11 * kQnThreads, "contact terms live in the line-search buffer");
 static_assert(kEntMax <= kHash / 2, "the hash table is at most half full");
 static_assert(kUniqMax <= 65536, "block-local contact indices are 16-bit");
+static_assert(kUniqMax <= kQnThreads, "at most one distinct contact per thread in the one-barrier set-up");
 constexpr int kEntPer = kEntMax / kQnThreads;  // entries per thread in the compact set-up
 // contacts of an environment the one-barrier form takes: each thread keeps
 // kLsPer in registers and one in LDS during the line search
@@ -993,7 +1073,7 @@ k_qn(QnArgs A) {
 
     DevCounters* cnt = A.cnt;
     const bool aborted = cnt->abort_step != 0u;
-    const int tid = threadIdx.x, T = blockDim.x;
+    const int tid = threadIdx.x, T = kQnThreads;  // the launch always takes kQnThreads
     const int2 me = A.qn_map[blockIdx.x];
     unsigned rpar = 0;  // parity of the block-sum buffer
     for (int env = me.x; env < A.n_envs; env += A.env_stride > 0 ? A.env_stride : A.n_envs) {
@@ -1046,6 +1126,18 @@ k_qn(QnArgs A) {
         double* partial_odd = A.partial_odd + (size_t)first * kQnSums;
 
         for (long long c = c0 + tid; c < c1; c += T) initial_contact_velocity(A, c);
+        if (kOne) {
+            // the line search's per-contact constants, read by every block of
+            // the group after the first barrier
+            for (long long c = c0 + tid; c < c1; c += T) {
+                const ContactRec& R = A.c_rec[c];
+                A.ls_prm[c] = R.eps_s * R.eps_s;
+                A.ls_prm[A.cap + c] = R.mun0;
+                A.ls_prm[2 * A.cap + c] = R.phi0;
+                A.ls_prm[3 * A.cap + c] = R.d;
+                A.ls_prm[4 * A.cap + c] = A.h * R.k;
+            }
+        }
 
         // Compact node pass: when the block's contact nodes fit one chunk, its
         // CSR entries number at most kEntMax, and they name at most kUniqMax distinct
@@ -1170,12 +1262,37 @@ k_qn(QnArgs A) {
         if (kOne && !all_compact) continue;  // left to k_qn<false>
         constexpr bool scatter = kOne;
         const bool cmp = kOne || compact;  // the compact node pass
-        double* vblk = A.vc_blk + (size_t)rank * 6 * kScatterMax;  // [6][kScatterMax]: v_c, u_c (rank < G <= kQnMaxGroup)
+        // The rank's scratch (rank < G <= kQnMaxGroup), in arrays of kQnThreads
+        // doubles so that a wave's loads are contiguous: [kLsPer + 1][6][T]
+        // v_c, u_c of the thread's line-search contacts ec0 + tid + u T, then
+        // [kQnRecWords][kUniqMax] the records of the block's distinct contacts
+        // (t1, t2, n, phi0, mu n0, k, d, eps_s), read only by the thread that
+        // wrote them.
+        static_assert(6 * (kLsPer + 1) * kQnThreads == 6 * kQnScatterMax, "rank scratch layout");
+        double* vblk = A.vc_blk + (size_t)rank * kQnRankWords;
+        double* crec = vblk + 6 * kQnScatterMax;
         if (scatter) {
             for (int t = tid; t < n_u; t += T) {
                 const int c = u_list[t];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) vcl[a * kUniqMax + t] = ld_x(&A.c_dyn[c].vc[0][a]);
+                const ContactRec& R = A.c_rec[c];
+                const double r[kQnRecWords] = {R.t1[0], R.t1[1], R.t1[2], R.t2[0], R.t2[1], R.t2[2],
+                                               R.n[0],  R.n[1],  R.n[2],  R.phi0,  R.mun0,  R.k,
+                                               R.d,     R.eps_s};
+#pragma unroll
+                for (int j = 0; j < kQnRecWords; ++j) crec[j * kUniqMax + t] = r[j];
+            }
+            // the line search's contacts start from v_c^0 with a zero step
+            for (int u = 0; u <= kLsPer; ++u) {
+                const long long c = ec0 + tid + (long long)u * T;
+                if (c >= ec1) break;
+                double* vb = vblk + u * 6 * kQnThreads + tid;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    vb[a * kQnThreads] = ld_x(&A.c_dyn[c].vc[0][a]);
+                    vb[(3 + a) * kQnThreads] = 0.0;
+                }
             }
             __syncthreads();
         }
@@ -1189,13 +1306,13 @@ k_qn(QnArgs A) {
             if (cmp) {
                 const int ls = tid >> lg_nl, sub = tid & (nl - 1);
                 const bool mine = ls < s1 - s0;    // a lane of contact node ls
-                const bool own = mine && sub == 0; // its first lane, which solves it
+                const bool own = mine && sub == 0; // its first lane, which keeps its results
                 SlotVals sv;
-                sv.m = own ? node_mv[0][ls] : 1.0;
+                sv.m = mine ? node_mv[0][ls] : 1.0;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) {
-                    sv.vs[a] = own ? node_mv[1 + a][ls] : 0.0;
-                    sv.v[a] = own ? node_v[a][ls] : 0.0;
+                    sv.vs[a] = mine ? node_mv[1 + a][ls] : 0.0;
+                    sv.v[a] = mine ? node_v[a][ls] : 0.0;
                 }
                 for (int t = tid; t < n_u; t += T) {
                     const unsigned c = (unsigned)u_list[t];
@@ -1209,7 +1326,17 @@ k_qn(QnArgs A) {
                     } else {
                         contact_velocity(A.c_dyn[c], k, alpha_prev, vc);
                     }
-                    contact_terms(A.c_rec[c], A.h, vc, rg, rgr);
+                    if (scatter) {
+                        // the record cached in the rank's scratch (coalesced loads)
+                        double r[kQnRecWords];
+#pragma unroll
+                        for (int j = 0; j < kQnRecWords; ++j) r[j] = crec[j * kUniqMax + t];
+                        ContactParams P;
+                        P.phi0 = r[9]; P.mun0 = r[10]; P.k = r[11]; P.d = r[12]; P.eps_s = r[13]; P.h = A.h;
+                        contact_terms(r, r + 3, r + 6, P, vc, rg, rgr);
+                    } else {
+                        contact_terms(A.c_rec[c], A.h, vc, rg, rgr);
+                    }
 #pragma unroll
                     for (int a = 0; a < 3; ++a) u_term[a * kUniqMax + t] = rg[a];
 #pragma unroll
@@ -1217,7 +1344,7 @@ k_qn(QnArgs A) {
                 }
                 __syncthreads();
                 // the nl lanes of a contact node add every nl-th of its entries'
-                // terms, then combine their sums by shuffles
+                // terms, then combine their sums by DPP exchanges
                 double j[3] = {0.0, 0.0, 0.0}, Hc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
                 if (mine) {
                     const int e1 = beg_l[ls + 1];
@@ -1231,33 +1358,54 @@ k_qn(QnArgs A) {
                         for (int q = 0; q < 6; ++q) Hc[q] = fma(w2, u_term[(3 + q) * kUniqMax + lc], Hc[q]);
                     }
                 }
-                for (int m = 1; m < nl; m <<= 1) {
+                // (DPP butterflies over the nl lanes: quad_perm [1, 0, 3, 2],
+                // [2, 3, 0, 1], then the other quad of the eight by
+                // row_half_mirror; each step adds two values in either order,
+                // so all nl lanes hold the same bits)
+                if (nl > 1) {
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) j[a] += __shfl_xor(j[a], m, 64);
+                    for (int a = 0; a < 3; ++a) j[a] += dpp_move<0xB1>(j[a]);
 #pragma unroll
-                    for (int q = 0; q < 6; ++q) Hc[q] += __shfl_xor(Hc[q], m, 64);
+                    for (int q = 0; q < 6; ++q) Hc[q] += dpp_move<0xB1>(Hc[q]);
+                }
+                if (nl > 2) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) j[a] += dpp_move<0x4E>(j[a]);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) Hc[q] += dpp_move<0x4E>(Hc[q]);
+                }
+                if (nl > 4) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) j[a] += dpp_move<0x141>(j[a]);
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) Hc[q] += dpp_move<0x141>(Hc[q]);
                 }
                 if (timer) { const unsigned long long t = wall_clock64(); tph[0] += t - tmark; tmark = t; }
+                // every lane of the node solves it (the same bits in each), so
+                // all of them hold dv for the scatter; its first lane keeps the sums
                 double dv[3] = {0.0, 0.0, 0.0};
-                if (own) {
-                    node_solve(sv, j, Hc, sums, dv);
-                    if (!scatter) {
-                        SlotRec& S = A.s_rec[s0 + ls];
-                        st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
-                    }
+                if (mine) {
+                    double ns[kQnSums];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) nacc[a][ls] = dv[a];  // kept for the update
+                    for (int q = 0; q < kQnSums; ++q) ns[q] = 0.0;
+                    node_solve(sv, j, Hc, ns, dv);
+                    if (own) {
+#pragma unroll
+                        for (int q = 0; q < kQnSums; ++q) sums[q] = ns[q];
+                        if (!scatter) {
+                            SlotRec& S = A.s_rec[s0 + ls];
+                            st_x(&S.dv[0], dv[0]); st_x(&S.dv[1], dv[1]); st_x(&S.dv[2], dv[2]);
+                        }
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) nacc[a][ls] = dv[a];  // kept for the update
+                    }
                 }
                 if (scatter) {
-                    // U_c += w dv over the node's entries: the node's lanes take
-                    // its dv from its first lane and add their entries into the
-                    // block's per-contact sums, which then go to the buffer of
-                    // this iteration; the next iteration's buffer is cleared for
-                    // the block's contacts
-                    const int src = (tid & 63) & ~(nl - 1);
-                    double d[3];
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) d[a] = __shfl(dv[a], src, 64);
+                    // U_c += w dv over the node's entries: the node's lanes add
+                    // their entries into the block's per-contact sums, which then
+                    // go to the buffer of this iteration; the next iteration's
+                    // buffer is cleared for the block's contacts
+                    const double d[3] = {dv[0], dv[1], dv[2]};
                     if (mine) {
                         const int e1 = beg_l[ls + 1];
                         for (int e = beg_l[ls] + sub; e < e1; e += nl) {
@@ -1268,12 +1416,15 @@ k_qn(QnArgs A) {
                         }
                     }
                     __syncthreads();
-                    double* U = A.u_acc + (size_t)buf * 3 * A.cap;
+                    double* U = A.u_acc + (size_t)buf * 3 * A.cap;  // [3][cap]
                     for (int t = tid; t < n_u; t += T) {
                         const long long c = u_list[t];
                         const double Uw[3] = {nacc[3][t], nacc[4][t], nacc[5][t]};
+                        double fr[9];
+#pragma unroll
+                        for (int j = 0; j < 9; ++j) fr[j] = crec[j * kUniqMax + t];
                         double uu[3];
-                        frame_project(A.c_rec[c], Uw, uu);
+                        frame_project(fr, fr + 3, fr + 6, Uw, uu);
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
                             __hip_atomic_fetch_add(&U[(size_t)a * A.cap + c], uu[a], __ATOMIC_RELAXED,
@@ -1354,7 +1505,10 @@ k_qn(QnArgs A) {
             const int wv = tid >> 6, lane = tid & 63;
             double ga = 0.0;
             if (G > 1u && wv < kQnSums) {
-                for (unsigned b = lane; b < G; b += 64) ga += ld_x(&part[(size_t)b * kQnSums + wv]);
+                // the first 64 blocks' sums without a loop, so that their loads
+                // overlap the set-up's
+                if ((unsigned)lane < G) ga = ld_x(&part[(size_t)lane * kQnSums + wv]);
+                for (unsigned b = lane + 64; b < G; b += 64) ga += ld_x(&part[(size_t)b * kQnSums + wv]);
             }
             double curv[1] = {0.0};
             LsCoef lc[kLsPer];
@@ -1370,38 +1524,73 @@ k_qn(QnArgs A) {
                 // contacts (contact ec0 + i taken by thread i mod T): v_c^k from the
                 // thread's own v_c^{k-1}, u_c^{k-1} (or the initial gather), u_c^k
                 // from the sums, the closed-form coefficients, and phi''(0)
+                // Every load is issued before the first store or use, with no
+                // branch between them, so the set-up waits for memory once:
+                // indices past the environment's contacts read a valid contact
+                // (and the rank's own scratch) and their values are discarded.
+                // U is [3][cap]: a wave's loads of one component cover 512 contiguous bytes
                 const double* U = A.u_acc + (size_t)buf * 3 * A.cap;
+                const long long clast = ec1 > 0 ? ec1 - 1 : 0;
+                // the loads of line-search contact ec0 + tid + u T
+                struct SetupIn {
+                    double uu[3], vo[3], uo[3], pr[5];
+                };
+                auto setup_load = [&](int u, SetupIn& in) {
+                    const long long c = ec0 + tid + (long long)u * T;
+                    const long long cc = c < ec1 ? c : clast;
+                    const double* vb = vblk + u * 6 * kQnThreads + tid;
 #pragma unroll
-                for (int u = 0; u <= kLsPer; ++u) {
+                    for (int a = 0; a < 3; ++a) {
+                        in.uu[a] = ld_x(&U[(size_t)a * A.cap + cc]);
+                        in.vo[a] = vb[a * kQnThreads];
+                        in.uo[a] = vb[(3 + a) * kQnThreads];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) in.pr[j] = A.ls_prm[(size_t)j * A.cap + cc];
+                };
+                // v_c^k = v_c^{k-1} + alpha_{k-1} u_c^{k-1} (at k = 0 the scratch
+                // holds v_c^0 and a zero u_c), stored with u_c^k for the next
+                // iteration; the coefficients and the contact's part of phi''(0)
+                auto setup_coef = [&](int u, const SetupIn& in) -> LsCoef {
                     const long long c = ec0 + tid + (long long)u * T;
                     LsCoef L = ls_coef_zero();
                     if (c < ec1) {
-                        double* vb = vblk + (c - ec0);
-                        double vc[3], uu[3];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) uu[a] = ld_x(&U[(size_t)a * A.cap + c]);
-#pragma unroll
-                        for (int a = 0; a < 3; ++a)
-                            vc[a] = k == 0 ? ld_x(&A.c_dyn[c].vc[0][a])
-                                           : fma(alpha_prev, vb[(3 + a) * kScatterMax], vb[a * kScatterMax]);
+                        double* vb = vblk + u * 6 * kQnThreads + tid;
+                        double vc[3];
 #pragma unroll
                         for (int a = 0; a < 3; ++a) {
-                            vb[a * kScatterMax] = vc[a];
-                            vb[(3 + a) * kScatterMax] = uu[a];
+                            vc[a] = fma(alpha_prev, in.uo[a], in.vo[a]);
+                            vb[a * kQnThreads] = vc[a];
+                            vb[(3 + a) * kQnThreads] = in.uu[a];
                         }
-                        L = ls_coef(params_of(A.c_rec[c], A.h), vc, uu);
+                        L = ls_coef_pre(in.pr[0], in.pr[1], in.pr[2], in.pr[3], in.pr[4], A.h, vc, in.uu);
                         double d1, d2;
                         ls_eval(L, 0.0, &d1, &d2);
                         curv[0] += d2;
                     }
-                    if (u < kLsPer) lc[u] = L;
-                    else if (use_lds) ls_ovf[tid] = L;
-                }
-                // u_c^k of the block's distinct contacts, for their velocities' update
-                for (int t = tid; t < n_u; t += T) {
-                    const long long c = u_list[t];
+                    return L;
+                };
+                SetupIn in[kLsPer];
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) nacc[6 + a][t] = ld_x(&U[(size_t)a * A.cap + c]);
+                for (int u = 0; u < kLsPer; ++u) setup_load(u, in[u]);
+                // u_c^k of the block's distinct contacts (at most one per
+                // thread), for their velocities' update
+                const bool has_u = tid < n_u;
+                const long long cu = has_u ? (long long)u_list[tid] : clast;
+                double un[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) un[a] = ld_x(&U[(size_t)a * A.cap + cu]);
+#pragma unroll
+                for (int u = 0; u < kLsPer; ++u) lc[u] = setup_coef(u, in[u]);
+                if (use_lds) {
+                    // contacts past kLsPer T (uniform branch: only large sets)
+                    SetupIn last;
+                    setup_load(kLsPer, last);
+                    ls_ovf[tid] = setup_coef(kLsPer, last);
+                }
+                if (has_u) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) nacc[6 + a][tid] = un[a];
                 }
             } else {
             // ---- contact pass: store v_c^k, u_c = R_c^T J dv, and u_c^T G(v_c^k) u_c
@@ -1625,8 +1814,8 @@ k_qn(QnArgs A) {
             for (int u = 0; u <= kLsPer; ++u) {
                 const long long c = ec0 + tid + (long long)u * T;
                 if (c < c0 || c >= c1) continue;
-                const double* vb = vblk + (c - ec0);
-                const double vc[3] = {vb[0], vb[kScatterMax], vb[2 * kScatterMax]};
+                const double* vb = vblk + u * 6 * kQnThreads + tid;
+                const double vc[3] = {vb[0], vb[kQnThreads], vb[2 * kQnThreads]};
                 contact_impulse_at(A, c, vc, racc);
             }
         } else {
@@ -2037,6 +2226,7 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
     A.compact = w.qn_compact;
     A.u_acc = w.qn_uacc;
     A.vc_blk = w.qn_vcblk;
+    A.ls_prm = w.qn_lsprm;
     A.timers = timers;
     A.slots_per_block = std::max(1, slots_per_block);
     A.s_node = w.s_node; A.s_beg = w.s_beg;

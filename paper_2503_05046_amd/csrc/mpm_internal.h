@@ -118,6 +118,14 @@ constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps e
 constexpr int kRigidGradStride = 12;
 // contacts of one environment the solver's one-barrier form takes
 constexpr int kQnScatterMax = 2048;
+// distinct contacts of one block's contact nodes in the compact node pass
+constexpr int kQnUniqMax = 512;
+// per distinct contact of a block of the one-barrier form: its frame (t1, t2,
+// n) and model parameters (phi0, mu n0, k, d, eps_s), kept in the rank's scratch
+constexpr int kQnRecWords = 14;
+// doubles of one group rank's scratch: v_c and u_c of the line search's
+// contacts, then the distinct contacts' records
+constexpr int kQnRankWords = 6 * kQnScatterMax + kQnRecWords * kQnUniqMax;
 
 // Pointers into the caller's workspace.
 struct Work {
@@ -199,7 +207,8 @@ struct Work {
     int qn_plain_launch;     // 1: launch the solver with hipLaunchKernel instead of the cooperative API
                              //    (the grid is still sized to the co-resident block count)
     double* qn_uacc;         // [3][3][cap_c] per-contact sums of the one-barrier form
-    double* qn_vcblk;        // [kQnMaxGroup][6][kQnScatterMax] contact velocities per rank of the group
+    double* qn_vcblk;        // [kQnMaxGroup][kQnRankWords] per rank of the group: contact velocities, records
+    double* qn_lsprm;        // [5][cap_c] per-contact line-search constants of the one-barrier form
     int* qn_pend;            // [n_envs] environments the one-barrier solver kernel left to the other
     int solver;              // MPM_SOLVER_QN or MPM_SOLVER_NEWTON
     int sort_policy;         // kSortTiles, kSortTruncated or kSortNone

@@ -274,9 +274,11 @@ hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old) {
 //     base has drifted since the sort is only queued: (particle, component)
 //     goes to a list in LDS, so no wave issues scattered atomics for the few
 //     lanes that meet one.
-//  3. The thread adds its 27 sums into the tile's 8x8x8-node LDS block; the 64
-//     lanes of a wave own 64 different cells, so the adds of one instruction
-//     never collide.
+//  3. Each wave reduces its 64 cells' sums to the 216 nodes they reach
+//     (DPP exchanges along x and y, a staging pass in LDS along z) and adds
+//     each node once into the tile's 8x8x8-node LDS block, without atomics
+//     (LDS float atomics, one per cell and stencil node, took about 40 % of
+//     the kernel's time).
 //  4. All threads take the queued entries, one (particle, component) each,
 //     and add them into the LDS block, or, for a stencil outside the block, to
 //     the global accumulator (activating the node tiles it touches). A list
@@ -339,6 +341,71 @@ __device__ __forceinline__ void p2g_scatter_one(const DevEnv& E, const float* __
     }
 }
 
+// A float from another lane of the wave by DPP (kCtrl: the DPP control);
+// lanes whose source lies outside their row read 0.
+template <int kCtrl>
+__device__ __forceinline__ float dpp_f(float x) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), kCtrl, 0xF, 0xF, false));
+}
+constexpr int kQuadUp1 = 0x90;   // quad_perm [0, 0, 1, 2]: lane i of a quad reads lane i - 1 (lane 0 itself)
+constexpr int kQuadUp2 = 0x40;   // quad_perm [0, 0, 0, 1]: lane i reads lane i - 2 (lanes 0, 1 lane 0)
+constexpr int kRowUp4 = 0x114;   // row_shr:4
+constexpr int kRowUp8 = 0x118;   // row_shr:8
+constexpr int kSpan = kTile + 2; // nodes a tile's cell stencils reach along an axis
+
+// Sum of the cells' stencil sums of one wave (lane = cell x + 4 y + 16 z of
+// the tile, sum[(c * 3 + b) * 3 + a] its weight on node cell + (a, b, c)) into
+// the LDS block, without atomics: the three axes are reduced in turn, x inside
+// each quad of lanes and y inside each row by DPP, which leaves in lane (x, y,
+// z) slot (i, j, c) the sum over x and y for node (x + i, y + j) at z offset c
+// (slots i > 0 valid in lanes x = 3 only, j > 0 in y = 3 only); z goes through
+// the wave's staging area (plain stores, then each node reads its three
+// z contributions). A node's value is added to the block non-atomically: only
+// this wave writes component q before the block's next barrier.
+__device__ __forceinline__ void p2g_cell_flush(float (&sum)[27], int cx, int cy, int cz, float* __restrict__ smq,
+                                               float* __restrict__ stage) {
+    const float mx1 = cx >= 1 ? 1.f : 0.f, mx2 = cx >= 2 ? 1.f : 0.f;
+#pragma unroll
+    for (int cb = 0; cb < 9; ++cb) {
+        float* r = &sum[cb * 3];
+        const float s1 = r[1], s2 = r[2];
+        r[0] = fmaf(mx2, dpp_f<kQuadUp2>(s2), fmaf(mx1, dpp_f<kQuadUp1>(s1), r[0]));
+        r[1] = fmaf(mx1, dpp_f<kQuadUp1>(s2), s1);
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            float* r0 = &sum[(c * 3 + 0) * 3 + i];
+            float* r1 = &sum[(c * 3 + 1) * 3 + i];
+            float* r2 = &sum[(c * 3 + 2) * 3 + i];
+            const float t1 = *r1, t2 = *r2;
+            *r0 += dpp_f<kRowUp4>(t1) + dpp_f<kRowUp8>(t2);
+            *r1 = t1 + dpp_f<kRowUp4>(t2);
+        }
+    // stage[c][z][y][x] over the 6 x 6 (x, y) nodes of each cell layer z
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if ((i == 0 || cx == kTile - 1) && (j == 0 || cy == kTile - 1))
+                    stage[((c * kTile + cz) * kSpan + cy + j) * kSpan + cx + i] = sum[(c * 3 + j) * 3 + i];
+    __builtin_amdgcn_wave_barrier();
+    const int lane = (cz * kTile + cy) * kTile + cx;
+    for (int n = lane; n < kSpan * kSpan * kSpan; n += 64) {
+        const int nx = n % kSpan, ny = (n / kSpan) % kSpan, nz = n / (kSpan * kSpan);
+        float v = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const int z = nz - c;
+            if (z >= 0 && z < kTile) v += stage[((c * kTile + z) * kSpan + ny) * kSpan + nx];
+        }
+        smq[((nz + 1) * kBN + ny + 1) * kBN + nx + 1] += v;
+    }
+}
+
 __global__ void __launch_bounds__(256)
 k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ Q,
       long long P, const DevEnv* __restrict__ envs, int n_envs, const unsigned* __restrict__ ptile_id,
@@ -346,6 +413,7 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
       float4* __restrict__ blkbuf, float4* __restrict__ acc, unsigned* __restrict__ tile_flag,
       unsigned* __restrict__ active, DevCounters* cnt) {
     __shared__ float sm[4][kBN3];
+    __shared__ float stage[4][3 * kTile * kSpan * kSpan];  // per wave: the cell flush's z staging
     __shared__ unsigned cbeg[64], cend[64];
     __shared__ unsigned drift[kDriftMax];
     __shared__ unsigned n_drift;
@@ -385,7 +453,6 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
         for (int o = 0; o < 27; ++o) sum[o] = 0.f;
         // 2. the walk over the cell's particles, the next one's loads issued first
         const unsigned k0 = cbeg[cell], k1 = cend[cell];
-        bool any_same = false;
         float nx0 = 0.f, nx1 = 0.f, nx2 = 0.f, nv = 0.f, nq0 = 0.f, nq1 = 0.f, nq2 = 0.f;
         if (k0 < k1) {
             const long long p = pb + k0;
@@ -424,7 +491,6 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                 }
                 continue;
             }
-            any_same = true;
             float wx[3], wy[3], wz[3];
             bspline_w(f[0], wx);
             bspline_w(f[1], wy);
@@ -442,17 +508,8 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                                        q2 * (((float)c - f[2]) * dx));
                     }
         }
-        // 3. the cell's sums into the LDS block
-        if (any_same) {
-            const int lx = nbx - ox, ly = nby - oy, lz = nbz - oz;  // in [1, 4]
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-                        atomicAdd(&sm[q][((lz + c) * kBN + (ly + bb)) * kBN + (lx + a)], sum[(c * 3 + bb) * 3 + a]);
-        }
+        // 3. the cells' sums into the LDS block (the whole wave, empty cells too)
+        p2g_cell_flush(sum, cx, cy, cz, sm[q], stage[q]);
         __syncthreads();
         // 4. the queued drifted particles, one (particle, component) per thread
         const unsigned nd = min(n_drift, (unsigned)kDriftMax);
