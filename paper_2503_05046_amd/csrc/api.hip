@@ -153,9 +153,9 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->c_dyn = L.take<ContactDyn>(C);
     w->c_coef = L.take<double>(11 * ((C + 63) / 64) * 64);
     // the solver's one-barrier form runs for handles of one environment only
-    w->qn_uacc = z.n_envs == 1 ? L.take<double>((size_t)9 * C) : nullptr;
+    w->qn_uacc = z.n_envs == 1 ? L.take<double>((size_t)9 * kQnScatterMax) : nullptr;
     w->qn_vcblk = z.n_envs == 1 ? L.take<double>((size_t)kQnMaxGroup * kQnRankWords) : nullptr;
-    w->qn_lsprm = z.n_envs == 1 ? L.take<double>((size_t)5 * C) : nullptr;
+    w->qn_lsprm = z.n_envs == 1 ? L.take<double>((size_t)5 * kQnScatterMax) : nullptr;
     w->qn_pend = L.take<int>(z.n_envs);
     // the exact-Newton variant's vectors, only when it is asked for
     w->nt_slot = z.solver == MPM_SOLVER_NEWTON ? L.take<double>((size_t)kNtSlot * z.cap_s) : nullptr;

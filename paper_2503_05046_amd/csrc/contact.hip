@@ -209,6 +209,23 @@ __device__ __forceinline__ LsCoef ls_coef_pre(double eps2, double mun0, double p
     return L;
 }
 
+// A line-search contact of the one-barrier form held in registers for the
+// whole solve: its contact velocity, the iteration's u_c and its constants.
+// The zero state (ls_state_zero) contributes exactly zero, as ls_coef_zero.
+struct LsState {
+    double vc[3], u[3], eps2, mun0, phi0, d, hk;
+};
+__device__ __forceinline__ LsState ls_state_zero() {
+    LsState S;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) S.vc[a] = S.u[a] = 0.0;
+    S.eps2 = 1.0; S.mun0 = 0.0; S.phi0 = -1.0; S.d = 0.0; S.hk = 0.0;
+    return S;
+}
+__device__ __forceinline__ LsCoef ls_coef_of(const LsState& S, double h) {
+    return ls_coef_pre(S.eps2, S.mun0, S.phi0, S.d, S.hk, h, S.vc, S.u);
+}
+
 // Coefficients that contribute exactly zero (padding lanes).
 __device__ __forceinline__ LsCoef ls_coef_zero() {
     LsCoef L;
@@ -566,9 +583,9 @@ struct QnArgs {
     int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
     int compact;               // 0: no block takes the compact node pass
     int* env_pend;             // per environment: 1 when k_qn<true> left it to k_qn<false>
-    double* u_acc;             // [3 buffers][3][cap] per-contact sums U_c of the one-barrier form
+    double* u_acc;             // [3 buffers][3][kQnScatterMax] per-contact sums U_c of the one-barrier form
     double* vc_blk;            // per group rank: kQnRankWords doubles (see the one-barrier set-up)
-    double* ls_prm;            // [5][cap]: eps_s^2, mu n0, phi0, d, h k of every contact (one-barrier form)
+    double* ls_prm;            // [5][kQnScatterMax]: eps_s^2, mu n0, phi0, d, h k per contact (one-barrier form)
     int timers;                // 1: the first block of each environment times the solver's phases
     int slots_per_block;       // contact nodes per block that set an environment's group size
     double* ls_part;           // [2][kQnMaxBlocks][2] line-search sums of the distributed line search
@@ -1131,11 +1148,12 @@ k_qn(QnArgs A) {
             // the group after the first barrier
             for (long long c = c0 + tid; c < c1; c += T) {
                 const ContactRec& R = A.c_rec[c];
-                A.ls_prm[c] = R.eps_s * R.eps_s;
-                A.ls_prm[A.cap + c] = R.mun0;
-                A.ls_prm[2 * A.cap + c] = R.phi0;
-                A.ls_prm[3 * A.cap + c] = R.d;
-                A.ls_prm[4 * A.cap + c] = A.h * R.k;
+                double* q = A.ls_prm + (c - ec0);
+                q[0] = R.eps_s * R.eps_s;
+                q[kQnScatterMax] = R.mun0;
+                q[2 * kQnScatterMax] = R.phi0;
+                q[3 * kQnScatterMax] = R.d;
+                q[4 * kQnScatterMax] = A.h * R.k;
             }
         }
 
@@ -1237,7 +1255,7 @@ k_qn(QnArgs A) {
             if (G > 1u && tid == 0) st_x(&partial2[rank], compact ? 1.0 : 0.0);
             for (long long c = c0 + tid; c < c1; c += T)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) st_x(&A.u_acc[(size_t)q * A.cap + c], 0.0);
+                for (int q = 0; q < 6; ++q) st_x(&A.u_acc[q * kQnScatterMax + (c - ec0)], 0.0);
         }
 
         int k = 0, ls_total = 0, converged = 0;
@@ -1297,6 +1315,31 @@ k_qn(QnArgs A) {
             __syncthreads();
         }
         int buf = 0;  // the iteration's buffer of the per-contact sums (k mod 3)
+        // One-barrier form: the thread's first kLsPer line-search contacts
+        // (ec0 + tid + u T) live in registers for the whole solve: v_c^0 and
+        // the constants loaded once, u_c^k loaded after each iteration's
+        // barrier, v_c^{k+1} = v_c^k + alpha_k u_c^k formed in the update. A
+        // contact past kLsPer T keeps v_c, u_c in the rank's scratch instead.
+        LsState st[kLsPer];
+#pragma unroll
+        for (int u = 0; u < kLsPer; ++u) {
+            st[u] = ls_state_zero();
+            const long long c = ec0 + tid + (long long)u * T;
+            if (scatter && c < ec1) {
+                const double* q = A.ls_prm + (c - ec0);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) st[u].vc[a] = ld_x(&A.c_dyn[c].vc[0][a]);
+                st[u].eps2 = q[0];
+                st[u].mun0 = q[kQnScatterMax];
+                st[u].phi0 = q[2 * kQnScatterMax];
+                st[u].d = q[3 * kQnScatterMax];
+                st[u].hk = q[4 * kQnScatterMax];
+            }
+        }
+        struct SetupIn {
+            double uu[3], vo[3], uo[3], pr[5];
+        };
+        const long long clast = nc > 0 ? ec1 - 1 : ec0;
         while (ok) {
             if (timer) tmark = wall_clock64();
             // ---- node pass: CSR entries spread over the threads, FP64 LDS sums ----
@@ -1416,7 +1459,7 @@ k_qn(QnArgs A) {
                         }
                     }
                     __syncthreads();
-                    double* U = A.u_acc + (size_t)buf * 3 * A.cap;  // [3][cap]
+                    double* U = A.u_acc + buf * 3 * kQnScatterMax;  // [3][kQnScatterMax]
                     for (int t = tid; t < n_u; t += T) {
                         const long long c = u_list[t];
                         const double Uw[3] = {nacc[3][t], nacc[4][t], nacc[5][t]};
@@ -1427,13 +1470,13 @@ k_qn(QnArgs A) {
                         frame_project(fr, fr + 3, fr + 6, Uw, uu);
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
-                            __hip_atomic_fetch_add(&U[(size_t)a * A.cap + c], uu[a], __ATOMIC_RELAXED,
+                            __hip_atomic_fetch_add(&U[a * kQnScatterMax + (c - ec0)], uu[a], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    double* Un = A.u_acc + (size_t)(buf == 2 ? 0 : buf + 1) * 3 * A.cap;
+                    double* Un = A.u_acc + (buf == 2 ? 0 : buf + 1) * 3 * kQnScatterMax;
                     for (long long c = c0 + tid; c < c1; c += T)
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) st_x(&Un[(size_t)a * A.cap + c], 0.0);
+                        for (int a = 0; a < 3; ++a) st_x(&Un[a * kQnScatterMax + (c - ec0)], 0.0);
                 }
             }
             for (long long sa = s0; sa < s1 && !cmp; sa += kSlotChunk) {
@@ -1521,72 +1564,75 @@ k_qn(QnArgs A) {
             const bool dist = !scatter && G > 1u && nc > (long long)(kLsPer + 1) * T;
             if (scatter) {
                 // ---- line-search set-up in every block, over all the environment's
-                // contacts (contact ec0 + i taken by thread i mod T): v_c^k from the
-                // thread's own v_c^{k-1}, u_c^{k-1} (or the initial gather), u_c^k
-                // from the sums, the closed-form coefficients, and phi''(0)
-                // Every load is issued before the first store or use, with no
-                // branch between them, so the set-up waits for memory once:
+                // contacts (contact ec0 + i taken by thread i mod T): u_c^k from the
+                // sums (v_c^k is already in the thread's registers), the
+                // closed-form coefficients, and phi''(0). Only the sums are read
+                // after the barrier, every load issued before the first use:
                 // indices past the environment's contacts read a valid contact
-                // (and the rank's own scratch) and their values are discarded.
-                // U is [3][cap]: a wave's loads of one component cover 512 contiguous bytes
-                const double* U = A.u_acc + (size_t)buf * 3 * A.cap;
-                const long long clast = ec1 > 0 ? ec1 - 1 : 0;
-                // the loads of line-search contact ec0 + tid + u T
-                struct SetupIn {
-                    double uu[3], vo[3], uo[3], pr[5];
-                };
-                auto setup_load = [&](int u, SetupIn& in) {
+                // and their values are discarded. U is [3][kQnScatterMax] by the
+                // environment's contact: a wave's loads of one component cover
+                // 512 contiguous bytes.
+                const double* U = A.u_acc + buf * 3 * kQnScatterMax;
+                // u_c^k of the register contacts and of the block's distinct
+                // contacts (at most one per thread, for their velocities' update),
+                // all loads issued together
+                double ul[kLsPer][3];
+#pragma unroll
+                for (int u = 0; u < kLsPer; ++u) {
                     const long long c = ec0 + tid + (long long)u * T;
                     const long long cc = c < ec1 ? c : clast;
-                    const double* vb = vblk + u * 6 * kQnThreads + tid;
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        in.uu[a] = ld_x(&U[(size_t)a * A.cap + cc]);
-                        in.vo[a] = vb[a * kQnThreads];
-                        in.uo[a] = vb[(3 + a) * kQnThreads];
-                    }
-#pragma unroll
-                    for (int j = 0; j < 5; ++j) in.pr[j] = A.ls_prm[(size_t)j * A.cap + cc];
-                };
-                // v_c^k = v_c^{k-1} + alpha_{k-1} u_c^{k-1} (at k = 0 the scratch
-                // holds v_c^0 and a zero u_c), stored with u_c^k for the next
-                // iteration; the coefficients and the contact's part of phi''(0)
-                auto setup_coef = [&](int u, const SetupIn& in) -> LsCoef {
-                    const long long c = ec0 + tid + (long long)u * T;
-                    LsCoef L = ls_coef_zero();
-                    if (c < ec1) {
-                        double* vb = vblk + u * 6 * kQnThreads + tid;
-                        double vc[3];
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            vc[a] = fma(alpha_prev, in.uo[a], in.vo[a]);
-                            vb[a * kQnThreads] = vc[a];
-                            vb[(3 + a) * kQnThreads] = in.uu[a];
-                        }
-                        L = ls_coef_pre(in.pr[0], in.pr[1], in.pr[2], in.pr[3], in.pr[4], A.h, vc, in.uu);
-                        double d1, d2;
-                        ls_eval(L, 0.0, &d1, &d2);
-                        curv[0] += d2;
-                    }
-                    return L;
-                };
-                SetupIn in[kLsPer];
-#pragma unroll
-                for (int u = 0; u < kLsPer; ++u) setup_load(u, in[u]);
-                // u_c^k of the block's distinct contacts (at most one per
-                // thread), for their velocities' update
+                    for (int a = 0; a < 3; ++a) ul[u][a] = ld_x(&U[a * kQnScatterMax + (cc - ec0)]);
+                }
                 const bool has_u = tid < n_u;
                 const long long cu = has_u ? (long long)u_list[tid] : clast;
                 double un[3];
 #pragma unroll
-                for (int a = 0; a < 3; ++a) un[a] = ld_x(&U[(size_t)a * A.cap + cu]);
+                for (int a = 0; a < 3; ++a) un[a] = ld_x(&U[a * kQnScatterMax + (cu - ec0)]);
 #pragma unroll
-                for (int u = 0; u < kLsPer; ++u) lc[u] = setup_coef(u, in[u]);
+                for (int u = 0; u < kLsPer; ++u) {
+                    const long long c = ec0 + tid + (long long)u * T;
+                    if (c < ec1) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) st[u].u[a] = ul[u][a];
+                    }
+                    // the coefficients, held for this iteration's line search
+                    lc[u] = ls_coef_of(st[u], A.h);
+                    double d1, d2;
+                    ls_eval(lc[u], 0.0, &d1, &d2);
+                    curv[0] += d2;
+                }
                 if (use_lds) {
-                    // contacts past kLsPer T (uniform branch: only large sets)
-                    SetupIn last;
-                    setup_load(kLsPer, last);
-                    ls_ovf[tid] = setup_coef(kLsPer, last);
+                    // the contact past kLsPer T (uniform branch: only large sets):
+                    // v_c^k = v_c^{k-1} + alpha_{k-1} u_c^{k-1} from the scratch (at
+                    // k = 0 it holds v_c^0 and a zero u_c), stored with u_c^k
+                    const long long c = ec0 + tid + (long long)kLsPer * T;
+                    const long long cc = c < ec1 ? c : clast;
+                    double* vb = vblk + kLsPer * 6 * kQnThreads + tid;
+                    double uu[3], vo[3], uo[3], pr[5];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        uu[a] = ld_x(&U[a * kQnScatterMax + (cc - ec0)]);
+                        vo[a] = vb[a * kQnThreads];
+                        uo[a] = vb[(3 + a) * kQnThreads];
+                    }
+#pragma unroll
+                    for (int j = 0; j < 5; ++j) pr[j] = A.ls_prm[j * kQnScatterMax + (cc - ec0)];
+                    LsCoef L = ls_coef_zero();
+                    if (c < ec1) {
+                        double vc[3];
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            vc[a] = fma(alpha_prev, uo[a], vo[a]);
+                            vb[a * kQnThreads] = vc[a];
+                            vb[(3 + a) * kQnThreads] = uu[a];
+                        }
+                        L = ls_coef_pre(pr[0], pr[1], pr[2], pr[3], pr[4], A.h, vc, uu);
+                        double d1, d2;
+                        ls_eval(L, 0.0, &d1, &d2);
+                        curv[0] += d2;
+                    }
+                    ls_ovf[tid] = L;
                 }
                 if (has_u) {
 #pragma unroll
@@ -1782,6 +1828,11 @@ k_qn(QnArgs A) {
 #pragma unroll
                         for (int a = 0; a < 3; ++a)
                             vcl[a * kUniqMax + t] = fma(alpha, nacc[6 + a][t], vcl[a * kUniqMax + t]);
+                    // the register contacts' v_c^{k+1} (zero states stay zero)
+#pragma unroll
+                    for (int u = 0; u < kLsPer; ++u)
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) st[u].vc[a] = fma(alpha, st[u].u[a], st[u].vc[a]);
                 }
             } else {
                 for (long long s = s0 + tid; s < s1; s += T) {
@@ -1809,14 +1860,21 @@ k_qn(QnArgs A) {
         for (int q = tid; q < A.n_rigid * 6; q += T) racc[q] = 0.0;
         __syncthreads();
         if (scatter) {
-            // v_c at the final iterate: the set-up of the last iteration stored it
-            // for the thread's line-search contacts; each block takes its own
-            for (int u = 0; u <= kLsPer; ++u) {
+            // v_c at the final iterate: in the registers of the thread's
+            // line-search contacts (the last, in the scratch, where the set-up
+            // of the last iteration stored it); each block takes its own
+#pragma unroll
+            for (int u = 0; u < kLsPer; ++u) {
                 const long long c = ec0 + tid + (long long)u * T;
-                if (c < c0 || c >= c1) continue;
-                const double* vb = vblk + u * 6 * kQnThreads + tid;
-                const double vc[3] = {vb[0], vb[kQnThreads], vb[2 * kQnThreads]};
-                contact_impulse_at(A, c, vc, racc);
+                if (c >= c0 && c < c1) contact_impulse_at(A, c, st[u].vc, racc);
+            }
+            {
+                const long long c = ec0 + tid + (long long)kLsPer * T;
+                if (c >= c0 && c < c1) {
+                    const double* vb = vblk + kLsPer * 6 * kQnThreads + tid;
+                    const double vc[3] = {vb[0], vb[kQnThreads], vb[2 * kQnThreads]};
+                    contact_impulse_at(A, c, vc, racc);
+                }
             }
         } else {
             for (long long c = c0 + tid; c < c1; c += T) contact_impulse(A, c, k, alpha_prev, racc);
