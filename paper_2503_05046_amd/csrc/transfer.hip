@@ -271,7 +271,9 @@ hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old) {
 //     it computes the current one, and sums its component of the
 //     contributions of those whose stencil base is still the cell in 27
 //     registers (the particles of a cell share one stencil). A particle whose
-//     base has drifted since the sort is only queued: (particle, component)
+//     base has drifted since the sort into another cell of the tile is listed
+//     for that cell, whose threads then walk it too (2b), so it needs no
+//     atomics; one that left the tile is only queued: (particle, component)
 //     goes to a list in LDS, so no wave issues scattered atomics for the few
 //     lanes that meet one.
 //  3. Each wave reduces its 64 cells' sums to the 216 nodes they reach
@@ -286,8 +288,9 @@ hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old) {
 //  5. The block is stored without atomics to the tile's slot of the block
 //     buffer; the grid update sums the overlapping blocks of every node.
 // (Staging the tile's particles in LDS before the walks, tried, was slower:
-// 189 against 162 us at 1M particles.)
+// 189 against 162 us at 1M particles, and 1005 against 574 us at 4M.)
 constexpr int kDriftMax = 1024;  // queued (particle, component) entries per tile
+constexpr int kDinCap = 16;      // particles that drifted into a cell of the tile, listed per cell
 
 // Component q of one particle's contribution to the 27 nodes of its stencil
 // (m_p, or m_p v_q + Q_q . (x_i - x_p)), added to the LDS block when the stencil
@@ -417,6 +420,8 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
     __shared__ unsigned cbeg[64], cend[64];
     __shared__ unsigned drift[kDriftMax];
     __shared__ unsigned n_drift;
+    __shared__ unsigned din[64][kDinCap];  // per cell: tile-relative particles that drifted into it
+    __shared__ unsigned din_cnt[64];
     if (cnt->abort_step) return;
     const unsigned n_tiles = cnt->n_ptiles;
     // the component is uniform over a wave: scalar branches below
@@ -430,6 +435,7 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
         if (threadIdx.x < 64) {
             cbeg[threadIdx.x] = 0u;
             cend[threadIdx.x] = 0u;
+            din_cnt[threadIdx.x] = 0u;
         }
         if (threadIdx.x == 0) n_drift = 0u;
         __syncthreads();
@@ -464,6 +470,33 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                 nq2 = Q[(3 * (q - 1) + 2) * P + p];
             }
         }
+        // component q of a particle whose stencil base is this cell, into the sums
+        auto accumulate = [&](const float xp[3], const float f[3], float vq, float q0, float q1, float q2) {
+            float wx[3], wy[3], wz[3];
+            bspline_w(f[0], wx);
+            bspline_w(f[1], wy);
+            bspline_w(f[2], wz);
+            const float base_val = q > 0 ? mp * vq : mp;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const int o = (c * 3 + bb) * 3 + a;
+                        const float w = wx[a] * wy[bb] * wz[c];
+                        sum[o] += w * (base_val + q0 * (((float)a - f[0]) * dx) + q1 * (((float)bb - f[1]) * dx) +
+                                       q2 * (((float)c - f[2]) * dx));
+                    }
+        };
+        auto queue_drift = [&](unsigned kk, int qq) {
+            const unsigned slot = atomicAdd(&n_drift, 1u);
+            if (slot < (unsigned)kDriftMax) {
+                drift[slot] = (kk << 2) | (unsigned)qq;
+            } else {
+                p2g_scatter_one(E, x, v, Q, P, pb + kk, qq, ox, oy, oz, sm, acc, tile_flag, active, cnt, &clamped);
+            }
+        };
         for (unsigned kk = k0; kk < k1; ++kk) {
             const float xp[3] = {nx0, nx1, nx2};
             const float vq = nv, q0 = nq0, q1 = nq1, q2 = nq2;
@@ -481,32 +514,43 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
             float f[3];
             stencil_base(E, xp, b, f, &clamped);
             if (b[0] != nbx || b[1] != nby || b[2] != nbz) {
-                // drifted since the sort: queue (particle, component)
-                const unsigned slot = atomicAdd(&n_drift, 1u);
-                if (slot < (unsigned)kDriftMax) {
-                    drift[slot] = (kk << 2) | (unsigned)q;
+                // drifted since the sort: into another cell of the tile, listed
+                // there (by the mass wave, for all four components), else queued
+                const int rx = b[0] - (nbx - cx), ry = b[1] - (nby - cy), rz = b[2] - (nbz - cz);
+                if (rx >= 0 && rx < kTile && ry >= 0 && ry < kTile && rz >= 0 && rz < kTile) {
+                    if (q == 0) {
+                        const int to = (rz * kTile + ry) * kTile + rx;
+                        const unsigned slot = atomicAdd(&din_cnt[to], 1u);
+                        if (slot < (unsigned)kDinCap) {
+                            din[to][slot] = kk;
+                        } else {
+                            for (int qq = 0; qq < 4; ++qq) queue_drift(kk, qq);
+                        }
+                    }
                 } else {
-                    p2g_scatter_one(E, x, v, Q, P, pb + kk, q, ox, oy, oz, sm, acc, tile_flag, active, cnt,
-                                    &clamped);
+                    queue_drift(kk, q);
                 }
                 continue;
             }
-            float wx[3], wy[3], wz[3];
-            bspline_w(f[0], wx);
-            bspline_w(f[1], wy);
-            bspline_w(f[2], wz);
-            const float base_val = q > 0 ? mp * vq : mp;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-#pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const int o = (c * 3 + bb) * 3 + a;
-                        const float w = wx[a] * wy[bb] * wz[c];
-                        sum[o] += w * (base_val + q0 * (((float)a - f[0]) * dx) + q1 * (((float)bb - f[1]) * dx) +
-                                       q2 * (((float)c - f[2]) * dx));
-                    }
+            accumulate(xp, f, vq, q0, q1, q2);
+        }
+        __syncthreads();
+        // 2b. the particles that drifted into this cell from another of the tile
+        const unsigned n_in = min(din_cnt[cell], (unsigned)kDinCap);
+        for (unsigned i = 0; i < n_in; ++i) {
+            const long long p = pb + din[cell][i];
+            const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
+            float vq = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
+            if (q > 0) {
+                vq = v[(q - 1) * P + p];
+                q0 = Q[(3 * (q - 1) + 0) * P + p];
+                q1 = Q[(3 * (q - 1) + 1) * P + p];
+                q2 = Q[(3 * (q - 1) + 2) * P + p];
+            }
+            int b[3];
+            float f[3];
+            stencil_base(E, xp, b, f, &clamped);
+            accumulate(xp, f, vq, q0, q1, q2);
         }
         // 3. the cells' sums into the LDS block (the whole wave, empty cells too)
         p2g_cell_flush(sum, cx, cy, cz, sm[q], stage[q]);
