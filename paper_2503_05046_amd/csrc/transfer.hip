@@ -471,23 +471,35 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
             }
         }
         // component q of a particle whose stencil base is this cell, into the sums
+        // (the node's term w_a w_b w_c (base + q0 dx_a + q1 dy_b + q2 dz_c) is
+        // formed as (w_b w_c) (w_a s_bc + w_a q0 dx_a), s_bc = base + q1 dy_b +
+        // q2 dz_c: two FMAs per node)
         auto accumulate = [&](const float xp[3], const float f[3], float vq, float q0, float q1, float q2) {
             float wx[3], wy[3], wz[3];
             bspline_w(f[0], wx);
             bspline_w(f[1], wy);
             bspline_w(f[2], wz);
             const float base_val = q > 0 ? mp * vq : mp;
+            float hx[3], sy[3];
 #pragma unroll
-            for (int c = 0; c < 3; ++c)
+            for (int a = 0; a < 3; ++a) {
+                hx[a] = wx[a] * (q0 * (((float)a - f[0]) * dx));
+                sy[a] = fmaf(q1, ((float)a - f[1]) * dx, base_val);
+            }
 #pragma unroll
-                for (int bb = 0; bb < 3; ++bb)
+            for (int c = 0; c < 3; ++c) {
+                const float dz = q2 * (((float)c - f[2]) * dx);
+#pragma unroll
+                for (int bb = 0; bb < 3; ++bb) {
+                    const float t = wy[bb] * wz[c];
+                    const float sbc = sy[bb] + dz;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         const int o = (c * 3 + bb) * 3 + a;
-                        const float w = wx[a] * wy[bb] * wz[c];
-                        sum[o] += w * (base_val + q0 * (((float)a - f[0]) * dx) + q1 * (((float)bb - f[1]) * dx) +
-                                       q2 * (((float)c - f[2]) * dx));
+                        sum[o] = fmaf(t, fmaf(wx[a], sbc, hx[a]), sum[o]);
                     }
+                }
+            }
         };
         auto queue_drift = [&](unsigned kk, int qq) {
             const unsigned slot = atomicAdd(&n_drift, 1u);
