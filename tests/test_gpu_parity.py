@@ -231,6 +231,42 @@ def _compare_envs(mpm, oracle, s):
     return contacts
 
 
+def _combine(scenes):
+    """Single-environment scenes as the environments of one batched scene
+    (same h and N)."""
+    import dataclasses
+    envs, rigids, base = [], [], 0
+    for e, sc in enumerate(scenes):
+        assert len(sc.envs) == 1 and sc.h == scenes[0].h and sc.N == scenes[0].N
+        envs.append(dataclasses.replace(sc.envs[0], p_begin=base, p_end=base + sc.P))
+        rigids += [dataclasses.replace(r, env=e) for r in sc.rigids]
+        base += sc.P
+    cat = [np.ascontiguousarray(np.concatenate([getattr(sc, k) for sc in scenes], axis=1))
+           for k in ("x", "v", "F", "C")]
+    return I.Scene("mixed", scenes[0].h, scenes[0].N, envs, rigids, *cat)
+
+
+def test_batched_mixed_one_and_two_barrier_forms(mpm, oracle):
+    """A batched handle whose first environment has more contacts than the
+    one-barrier form takes (a slab pressed into a plane, 2,304 contacts) beside
+    two small ones in contact: the one-barrier kernel solves the small ones and
+    leaves the slab to the two-barrier kernel launched after it; every
+    environment matches the oracle run on it alone."""
+    slab = I.slab_on_plane(48, 2, (0.0, 0.0, 0.0), 0.5, seed=57, n=48, penetration=2e-5)
+    rng = np.random.default_rng(57)
+    slab.v = rng.normal(0.0, 1e-3, slab.v.shape).astype(np.float32)
+    small = _batched_contact_scene(4, 21, penetrating=(0, 1, 3))
+    parts = [slab] + [I.single_env(small, e) for e in (0, 1)]
+    for sc in parts:
+        sc.N = 1
+    s = _combine(parts)
+    s.eps_r = 1e-10
+    s.max_iter = 400000
+    _log("batched, mixed forms: the dense slab and two small environments, 1 substep")
+    contacts = _compare_envs(mpm, oracle, s)
+    assert contacts[0] > 2304
+
+
 def test_batched_envs_solve_independently(mpm, oracle):
     """Four environments of different size and material in one handle, one of
     them without contact: each matches the oracle run on it alone (its own
