@@ -152,12 +152,10 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->c_st = L.take<ContactStencil>(C);
     w->c_dyn = L.take<ContactDyn>(C);
     w->c_coef = L.take<double>(11 * ((C + 63) / 64) * 64);
-    // the solver's one-barrier form: per environment its per-contact sums and
-    // line-search constants, per solver block its scratch (one environment's
-    // group has at most kQnMaxGroup blocks)
-    w->qn_uacc = L.take<double>((size_t)z.n_envs * 9 * kQnScatterMax);
-    w->qn_vcblk = L.take<double>((size_t)(z.n_envs == 1 ? kQnMaxGroup : kMaxQnBlocks) * kQnRankWords);
-    w->qn_lsprm = L.take<double>((size_t)z.n_envs * 5 * kQnScatterMax);
+    // the solver's one-barrier form runs for handles of one environment only
+    w->qn_uacc = z.n_envs == 1 ? L.take<double>((size_t)9 * kQnScatterMax) : nullptr;
+    w->qn_vcblk = z.n_envs == 1 ? L.take<double>((size_t)kQnMaxGroup * kQnRankWords) : nullptr;
+    w->qn_lsprm = z.n_envs == 1 ? L.take<double>((size_t)5 * kQnScatterMax) : nullptr;
     w->qn_pend = L.take<int>(z.n_envs);
     // the exact-Newton variant's vectors, only when it is asked for
     w->nt_slot = z.solver == MPM_SOLVER_NEWTON ? L.take<double>((size_t)kNtSlot * z.cap_s) : nullptr;

@@ -583,9 +583,9 @@ struct QnArgs {
     int env_stride;            // > 0: block b solves environments b, b + stride, ... alone
     int compact;               // 0: no block takes the compact node pass
     int* env_pend;             // per environment: 1 when k_qn<true> left it to k_qn<false>
-    double* u_acc;             // per environment [3 buffers][3][kQnScatterMax]: the one-barrier form's sums U_c
-    double* vc_blk;            // per solver block: kQnRankWords doubles (see the one-barrier set-up)
-    double* ls_prm;            // per environment [5][kQnScatterMax]: eps_s^2, mu n0, phi0, d, h k per contact
+    double* u_acc;             // [3 buffers][3][kQnScatterMax] per-contact sums U_c of the one-barrier form
+    double* vc_blk;            // per group rank: kQnRankWords doubles (see the one-barrier set-up)
+    double* ls_prm;            // [5][kQnScatterMax]: eps_s^2, mu n0, phi0, d, h k per contact (one-barrier form)
     int timers;                // 1: the first block of each environment times the solver's phases
     int slots_per_block;       // contact nodes per block that set an environment's group size
     double* ls_part;           // [2][kQnMaxBlocks][2] line-search sums of the distributed line search
@@ -1119,10 +1119,6 @@ k_qn(QnArgs A) {
         const long long ec0 = A.env_range[4 * env], ec1 = A.env_range[4 * env + 1];
         const long long es0 = A.env_range[4 * env + 2], es1 = A.env_range[4 * env + 3];
         const long long nc = ec1 - ec0, ns = es1 - es0;
-        // the one-barrier form's per-environment arrays (indexed by the
-        // environment's contact: it has at most kQnScatterMax)
-        double* const u_acc = A.u_acc + (size_t)env * 9 * kQnScatterMax;
-        double* const ls_prm = A.ls_prm + (size_t)env * 5 * kQnScatterMax;
         const unsigned G = (unsigned)std::min<long long>(
             G_launch, std::max<long long>(1, (ns + A.slots_per_block - 1) / A.slots_per_block));
         if ((unsigned)rank >= G) continue;
@@ -1152,7 +1148,7 @@ k_qn(QnArgs A) {
             // the group after the first barrier
             for (long long c = c0 + tid; c < c1; c += T) {
                 const ContactRec& R = A.c_rec[c];
-                double* q = ls_prm + (c - ec0);
+                double* q = A.ls_prm + (c - ec0);
                 q[0] = R.eps_s * R.eps_s;
                 q[kQnScatterMax] = R.mun0;
                 q[2 * kQnScatterMax] = R.phi0;
@@ -1259,7 +1255,7 @@ k_qn(QnArgs A) {
             if (G > 1u && tid == 0) st_x(&partial2[rank], compact ? 1.0 : 0.0);
             for (long long c = c0 + tid; c < c1; c += T)
 #pragma unroll
-                for (int q = 0; q < 6; ++q) st_x(&u_acc[q * kQnScatterMax + (c - ec0)], 0.0);
+                for (int q = 0; q < 6; ++q) st_x(&A.u_acc[q * kQnScatterMax + (c - ec0)], 0.0);
         }
 
         int k = 0, ls_total = 0, converged = 0;
@@ -1291,7 +1287,7 @@ k_qn(QnArgs A) {
         // (t1, t2, n, phi0, mu n0, k, d, eps_s), read only by the thread that
         // wrote them.
         static_assert(6 * (kLsPer + 1) * kQnThreads == 6 * kQnScatterMax, "rank scratch layout");
-        double* vblk = A.vc_blk + (size_t)(first + rank) * kQnRankWords;  // the block's own
+        double* vblk = A.vc_blk + (size_t)rank * kQnRankWords;
         double* crec = vblk + 6 * kQnScatterMax;
         if (scatter) {
             for (int t = tid; t < n_u; t += T) {
@@ -1330,7 +1326,7 @@ k_qn(QnArgs A) {
             st[u] = ls_state_zero();
             const long long c = ec0 + tid + (long long)u * T;
             if (scatter && c < ec1) {
-                const double* q = ls_prm + (c - ec0);
+                const double* q = A.ls_prm + (c - ec0);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) st[u].vc[a] = ld_x(&A.c_dyn[c].vc[0][a]);
                 st[u].eps2 = q[0];
@@ -1463,7 +1459,7 @@ k_qn(QnArgs A) {
                         }
                     }
                     __syncthreads();
-                    double* U = u_acc + buf * 3 * kQnScatterMax;  // [3][kQnScatterMax]
+                    double* U = A.u_acc + buf * 3 * kQnScatterMax;  // [3][kQnScatterMax]
                     for (int t = tid; t < n_u; t += T) {
                         const long long c = u_list[t];
                         const double Uw[3] = {nacc[3][t], nacc[4][t], nacc[5][t]};
@@ -1477,7 +1473,7 @@ k_qn(QnArgs A) {
                             __hip_atomic_fetch_add(&U[a * kQnScatterMax + (c - ec0)], uu[a], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    double* Un = u_acc + (buf == 2 ? 0 : buf + 1) * 3 * kQnScatterMax;
+                    double* Un = A.u_acc + (buf == 2 ? 0 : buf + 1) * 3 * kQnScatterMax;
                     for (long long c = c0 + tid; c < c1; c += T)
 #pragma unroll
                         for (int a = 0; a < 3; ++a) st_x(&Un[a * kQnScatterMax + (c - ec0)], 0.0);
@@ -1576,7 +1572,7 @@ k_qn(QnArgs A) {
                 // and their values are discarded. U is [3][kQnScatterMax] by the
                 // environment's contact: a wave's loads of one component cover
                 // 512 contiguous bytes.
-                const double* U = u_acc + buf * 3 * kQnScatterMax;
+                const double* U = A.u_acc + buf * 3 * kQnScatterMax;
                 // u_c^k of the register contacts and of the block's distinct
                 // contacts (at most one per thread, for their velocities' update),
                 // all loads issued together
@@ -1621,7 +1617,7 @@ k_qn(QnArgs A) {
                         uo[a] = vb[(3 + a) * kQnThreads];
                     }
 #pragma unroll
-                    for (int j = 0; j < 5; ++j) pr[j] = ls_prm[j * kQnScatterMax + (cc - ec0)];
+                    for (int j = 0; j < 5; ++j) pr[j] = A.ls_prm[j * kQnScatterMax + (cc - ec0)];
                     LsCoef L = ls_coef_zero();
                     if (c < ec1) {
                         double vc[3];
@@ -2328,10 +2324,11 @@ hipError_t launch_qn(const Work& w, const float* x, int substep, double h, doubl
         A.env_pend = nullptr;
         return launch((const void*)k_newton);
     }
-    if (w.qn_scatter) {
-        // the one-barrier kernel, then the two-barrier kernel for what it left
-        // (with several environments the second launch starts only after the
-        // first kernel's slowest environment)
+    if (w.qn_scatter && w.n_envs == 1) {
+        // the one-barrier kernel, then the two-barrier kernel for what it left.
+        // With several environments the second launch would start only after
+        // the first kernel's slowest environment, so the batched form keeps the
+        // two-barrier kernel for all of them.
         A.env_pend = w.qn_pend;
         const hipError_t e = launch((const void*)k_qn<true>);
         if (e != hipSuccess) return e;

@@ -206,9 +206,9 @@ struct Work {
     int qn_scatter;          // 1: environments that fit take the solver's one-barrier form
     int qn_plain_launch;     // 1: launch the solver with hipLaunchKernel instead of the cooperative API
                              //    (the grid is still sized to the co-resident block count)
-    double* qn_uacc;         // [n_envs][3][3][kQnScatterMax] per-contact sums of the one-barrier form
-    double* qn_vcblk;        // per solver block [kQnRankWords]: contact velocities, records
-    double* qn_lsprm;        // [n_envs][5][kQnScatterMax] per-contact line-search constants (one-barrier form)
+    double* qn_uacc;         // [3][3][kQnScatterMax] per-contact sums of the one-barrier form
+    double* qn_vcblk;        // [kQnMaxGroup][kQnRankWords] per rank of the group: contact velocities, records
+    double* qn_lsprm;        // [5][kQnScatterMax] per-contact line-search constants of the one-barrier form
     int* qn_pend;            // [n_envs] environments the one-barrier solver kernel left to the other
     int solver;              // MPM_SOLVER_QN or MPM_SOLVER_NEWTON
     int sort_policy;         // kSortTiles, kSortTruncated or kSortNone

@@ -246,12 +246,11 @@ def _combine(scenes):
     return I.Scene("mixed", scenes[0].h, scenes[0].N, envs, rigids, *cat)
 
 
-def test_batched_mixed_one_and_two_barrier_forms(mpm, oracle):
-    """A batched handle whose first environment has more contacts than the
-    one-barrier form takes (a slab pressed into a plane, 2,304 contacts) beside
-    two small ones in contact: the one-barrier kernel solves the small ones and
-    leaves the slab to the two-barrier kernel launched after it; every
-    environment matches the oracle run on it alone."""
+def test_batched_dense_and_small_environments(mpm, oracle):
+    """A batched handle whose first environment is a slab pressed into a plane
+    (2,304 contacts: its group evaluates the line search distributed) beside
+    two small ones in contact: every environment matches the oracle run on it
+    alone."""
     slab = I.slab_on_plane(48, 2, (0.0, 0.0, 0.0), 0.5, seed=57, n=48, penetration=2e-5)
     rng = np.random.default_rng(57)
     slab.v = rng.normal(0.0, 1e-3, slab.v.shape).astype(np.float32)
@@ -262,7 +261,7 @@ def test_batched_mixed_one_and_two_barrier_forms(mpm, oracle):
     s = _combine(parts)
     s.eps_r = 1e-10
     s.max_iter = 400000
-    _log("batched, mixed forms: the dense slab and two small environments, 1 substep")
+    _log("batched: the dense slab and two small environments, 1 substep")
     contacts = _compare_envs(mpm, oracle, s)
     assert contacts[0] > 2304
 

@@ -84,6 +84,20 @@ def test_static_step_matches_handle_two_calls(mpm):
     _compare(mpm, _tiny(), "second call, smaller scene")
 
 
+def test_static_step_batched(mpm):
+    """Three environments in one static call (a batched handle's solver
+    path), against a handle."""
+    s = I.batched(n_envs=3, seed=21, p_min=300, p_max=1500, n=24, N=2)
+    for e in (0, 2):
+        env = s.envs[e]
+        s.x[2, env.p_begin:env.p_end] -= np.float32(1.5 * env.dx)
+    for env in s.envs:
+        env.eps_s = 1e-2
+    s.eps_r = 1e-10
+    s.max_iter = 200000
+    _compare(mpm, s, "batched call, three environments")
+
+
 def test_static_step_refuses_oversized_scene(mpm):
     """A scene whose workspace exceeds the static array is refused with
     MPM_ENOMEM before any device work (the pointers are never read)."""
