@@ -189,41 +189,54 @@ __device__ __forceinline__ LsCoef load_coef(const double* __restrict__ buf, long
     return L;
 }
 
-// The same from a contact's line-search constants (eps_s^2, mu n0, phi0, d,
-// h k), with the same roundings.
-__device__ __forceinline__ LsCoef ls_coef_pre(double eps2, double mun0, double phi0, double d, double hk,
-                                              double h, const double vc[3], const double u[3]) {
-    LsCoef L;
-    L.q0 = vc[0] * vc[0] + vc[1] * vc[1] + eps2;
-    L.p0 = vc[0] * u[0] + vc[1] * u[1];
-    L.q2 = u[0] * u[0] + u[1] * u[1];
-    L.mun0 = mun0;
-    L.a0 = phi0 - h * vc[2];
-    L.a1 = h * u[2];
-    L.b0 = 1.0 - d * vc[2];
-    L.b1 = d * u[2];
-    const double hkuu = hk * u[2] * u[2];
-    L.kn = hk * u[2];
-    L.eh = hkuu * h;
-    L.ed = hkuu * d;
-    return L;
+// The one-barrier form's line search keeps its contacts in registers in a
+// compact form: one environment's contacts share eps_s, d and h k (copied
+// from the environment at registration), so only what differs per contact is
+// held, and a1 = h u_n, b1 = d u_n, h k u_n are formed at each evaluation
+// from the block-uniform constants (LsUni).
+struct LsUni {
+    double eps2, h, d, hk;
+};
+// A value equal in every lane of the wave, moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double x) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)b);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
-
-// A line-search contact of the one-barrier form held in registers for the
-// whole solve: its contact velocity, the iteration's u_c and its constants.
-// The zero state (ls_state_zero) contributes exactly zero, as ls_coef_zero.
+// A line-search contact held in registers for the whole solve: its contact
+// velocity, the iteration's u_c, mu n0 and phi0. The zero state
+// (ls_state_zero) contributes exactly zero.
 struct LsState {
-    double vc[3], u[3], eps2, mun0, phi0, d, hk;
+    double vc[3], u[3], mun0, phi0;
 };
 __device__ __forceinline__ LsState ls_state_zero() {
     LsState S;
 #pragma unroll
     for (int a = 0; a < 3; ++a) S.vc[a] = S.u[a] = 0.0;
-    S.eps2 = 1.0; S.mun0 = 0.0; S.phi0 = -1.0; S.d = 0.0; S.hk = 0.0;
+    S.mun0 = 0.0;
+    S.phi0 = -1.0;
     return S;
 }
-__device__ __forceinline__ LsCoef ls_coef_of(const LsState& S, double h) {
-    return ls_coef_pre(S.eps2, S.mun0, S.phi0, S.d, S.hk, h, S.vc, S.u);
+// The iteration's coefficients of such a contact (LsCoef's q0, p0, q2, mun0,
+// a0, b0 with the same roundings, and u_n).
+struct LsCoefC {
+    double q0, p0, q2, mun0, a0, b0, un;
+};
+__device__ __forceinline__ LsCoefC ls_coefc(const LsUni& E, double mun0, double phi0, const double vc[3],
+                                            const double u[3]) {
+    LsCoefC L;
+    L.q0 = vc[0] * vc[0] + vc[1] * vc[1] + E.eps2;
+    L.p0 = vc[0] * u[0] + vc[1] * u[1];
+    L.q2 = u[0] * u[0] + u[1] * u[1];
+    L.mun0 = mun0;
+    L.a0 = phi0 - E.h * vc[2];
+    L.b0 = 1.0 - E.d * vc[2];
+    L.un = u[2];
+    return L;
+}
+__device__ __forceinline__ LsCoefC ls_coefc_of(const LsState& S, const LsUni& E) {
+    return ls_coefc(E, S.mun0, S.phi0, S.vc, S.u);
 }
 
 // Coefficients that contribute exactly zero (padding lanes).
@@ -250,6 +263,62 @@ __device__ __forceinline__ void ls_eval(const LsCoef& L, double alpha, double* d
     }
     *d1 = e1;
     *d2 = e2;
+}
+
+// phi' and phi'' of one contact's terms added to d[0..1], from either form of
+// the coefficients (the full form gives ls_eval's values).
+__device__ __forceinline__ void ls_eval2(const LsCoef& L, const LsUni&, double alpha, double (&d)[2]) {
+    double d1, d2;
+    ls_eval(L, alpha, &d1, &d2);
+    d[0] += d1;
+    d[1] += d2;
+}
+__device__ __forceinline__ void ls_eval2(const LsCoefC& L, const LsUni& E, double alpha, double (&d)[2]) {
+    const double pa = fma(alpha, L.q2, L.p0);
+    const double s2 = fma(alpha, pa + L.p0, L.q0);
+    const double is = inv_sqrt(s2);
+    const double cs = L.mun0 * is;
+    const double pis = pa * is;
+    double e1 = cs * pa;
+    double e2 = cs * fma(-pis, pis, L.q2);
+    const double a1 = E.h * L.un, b1 = E.d * L.un;
+    const double a = fma(-alpha, a1, L.a0), b = fma(-alpha, b1, L.b0);
+    if (a > 0.0 && b > 0.0) {
+        const double kn = E.hk * L.un;
+        e1 -= kn * a * b;
+        e2 += kn * fma(a1, b, b1 * a);
+    }
+    d[0] += e1;
+    d[1] += e2;
+}
+// The same for a compact contact with the next two derivatives, added to
+// d[0..3] (phi', phi'', phi''', phi''''). Along the line s(alpha) =
+// |v_t + alpha u_t|^2 + eps^2 has s'' = 2 q2 and a constant q0 q2 - p0^2, so
+// the friction term's curvature e2 = mu n0 (q0 q2 - p0^2) / s^(3/2)
+// differentiates to e3 = -3 e2 pa / s and e4 = -3 e2 (q2 - 5 pa^2 / s) / s;
+// the active normal term is a quadratic in alpha (e3 = -2 h k u_n a1 b1,
+// e4 = 0).
+__device__ __forceinline__ void ls_eval4(const LsCoefC& L, const LsUni& E, double alpha, double (&d)[4]) {
+    const double pa = fma(alpha, L.q2, L.p0);
+    const double s2 = fma(alpha, pa + L.p0, L.q0);
+    const double is = inv_sqrt(s2);
+    const double cs = L.mun0 * is;
+    const double pis = pa * is;
+    const double f2 = cs * fma(-pis, pis, L.q2);
+    double e1 = cs * pa, e2 = f2;
+    double e3 = -3.0 * f2 * (pis * is);
+    const double e4 = -3.0 * f2 * (is * is) * fma(-5.0 * pis, pis, L.q2);
+    const double a1 = E.h * L.un, b1 = E.d * L.un, kn = E.hk * L.un;
+    const double a = fma(-alpha, a1, L.a0), b = fma(-alpha, b1, L.b0);
+    if (a > 0.0 && b > 0.0) {
+        e1 -= kn * a * b;
+        e2 += kn * fma(a1, b, b1 * a);
+        e3 -= 2.0 * kn * (a1 * b1);
+    }
+    d[0] += e1;
+    d[1] += e2;
+    d[2] += e3;
+    d[3] += e4;
 }
 
 // ---------------------------------------------------------------------------
@@ -806,7 +875,7 @@ __device__ __forceinline__ SlotVals slot_vals(const SlotRec& S) {
 // node's share of the iteration sums.
 __device__ __forceinline__ void node_solve(const SlotVals& S, const double j[3], const double Hc[6],
                                            double sums[kQnSums], double dv[3]) {
-    const double m = S.m, inv_m = 1.0 / m;
+    const double m = S.m, inv_m = rcp_nr(m);
     const double H[6] = {m + Hc[0], Hc[1], Hc[2], m + Hc[3], Hc[4], m + Hc[5]};  // 00 01 02 11 12 22
     double g[3];
 #pragma unroll
@@ -889,6 +958,18 @@ __device__ __forceinline__ void contact_impulse(const QnArgs& A, long long c, in
     contact_impulse_at(A, c, vc, racc);
 }
 
+// The line search's first trial step from alpha = 0, given f = phi'(0) and
+// f1..f3 = phi'', phi''', phi'''' there (f1 > 0): Householder's third-order
+// step, written in t = f / f1, r2 = f2 / f1, r3 = f3 / f1 so that no power of
+// the derivatives can leave the exponent range; Newton's step -t where its
+// denominator is not positive. With f2 = f3 = 0 it is Newton's step.
+__device__ __forceinline__ double ls_first_step(double f, double f1, double f2, double f3) {
+    const double r = rcp_nr(f1);
+    const double t = f * r, r2 = f2 * r, r3 = f3 * r;
+    const double den = fma(t, fma(t, r3 * (1.0 / 6.0), -r2), 1.0);
+    return den > 0.0 ? -t * fma(-0.5 * t, r2, 1.0) * rcp_nr(den) : -t;
+}
+
 // Exact line search: the root of phi'(alpha) for alpha > 0 (phi is convex
 // with phi'(0) = d0 < 0). Safeguarded 1-D Newton from alpha0: while no point
 // with phi' >= 0 is known the step only grows (Newton, or doubling when
@@ -912,7 +993,7 @@ __device__ double exact_line_search(Eval eval, double alpha0, double d0, int max
             bracketed = true;
         }
         if (bracketed && hi - lo <= 1e-12 * hi) break;
-        double an = dd > 0.0 ? alpha - da / dd : -1.0;
+        double an = dd > 0.0 ? alpha - da * rcp_nr(dd) : -1.0;
         if (bracketed) {
             if (!(an > lo && an < hi) || fabs(da) > 0.5 * prev) an = 0.5 * (lo + hi);
         } else if (!(an > alpha)) {
@@ -1070,7 +1151,9 @@ k_qn(QnArgs A) {
     // line-search contacts beyond the registers; in the compact node pass, the
     // terms of the block's distinct contacts ([9][kUniqMax])
     __shared__ double ovf_raw[11 * kQnThreads];
-    LsCoef* ls_ovf = reinterpret_cast<LsCoef*>(ovf_raw);
+    using LsC = std::conditional_t<kOne, LsCoefC, LsCoef>;  // a line-search contact's coefficients
+    static_assert(sizeof(LsC) <= 11 * sizeof(double), "line-search LDS contacts");
+    LsC* ls_ovf = reinterpret_cast<LsC*>(ovf_raw);
     double* u_term = ovf_raw;
     __shared__ double nacc[9][kSlotChunk];  // j (3) and R G R^T (6) of a chunk of owned slots
     __shared__ unsigned short ent_c[kEntMax];  // compact pass: block-local contact of each entry
@@ -1321,6 +1404,14 @@ k_qn(QnArgs A) {
         // barrier, v_c^{k+1} = v_c^k + alpha_k u_c^k formed in the update. A
         // contact past kLsPer T keeps v_c, u_c in the rank's scratch instead.
         LsState st[kLsPer];
+        // the environment's eps_s^2, d and h k (equal for all its contacts), as
+        // block-uniform values
+        LsUni lsu{1.0, A.h, 0.0, 0.0};
+        if (scatter && nc > 0) {
+            lsu.eps2 = uniform_f64(A.ls_prm[0]);
+            lsu.d = uniform_f64(A.ls_prm[3 * kQnScatterMax]);
+            lsu.hk = uniform_f64(A.ls_prm[4 * kQnScatterMax]);
+        }
 #pragma unroll
         for (int u = 0; u < kLsPer; ++u) {
             st[u] = ls_state_zero();
@@ -1329,11 +1420,8 @@ k_qn(QnArgs A) {
                 const double* q = A.ls_prm + (c - ec0);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) st[u].vc[a] = ld_x(&A.c_dyn[c].vc[0][a]);
-                st[u].eps2 = q[0];
                 st[u].mun0 = q[kQnScatterMax];
                 st[u].phi0 = q[2 * kQnScatterMax];
-                st[u].d = q[3 * kQnScatterMax];
-                st[u].hk = q[4 * kQnScatterMax];
             }
         }
         struct SetupIn {
@@ -1553,8 +1641,8 @@ k_qn(QnArgs A) {
                 if ((unsigned)lane < G) ga = ld_x(&part[(size_t)lane * kQnSums + wv]);
                 for (unsigned b = lane + 64; b < G; b += 64) ga += ld_x(&part[(size_t)b * kQnSums + wv]);
             }
-            double curv[1] = {0.0};
-            LsCoef lc[kLsPer];
+            double curv[3] = {0.0, 0.0, 0.0};  // phi'' - A, phi''', phi'''' at alpha = 0
+            LsC lc[kLsPer];
             const long long c_lds = ec0 + tid + (long long)kLsPer * T;
             const bool use_lds = (long long)kLsPer * T < nc;
             // an environment with more contacts than a block's registers and LDS
@@ -1562,7 +1650,7 @@ k_qn(QnArgs A) {
             // own contacts, and every evaluation meets at a group barrier (one
             // barrier instead of every block streaming all coefficients)
             const bool dist = !scatter && G > 1u && nc > (long long)(kLsPer + 1) * T;
-            if (scatter) {
+            if constexpr (scatter) {
                 // ---- line-search set-up in every block, over all the environment's
                 // contacts (contact ec0 + i taken by thread i mod T): u_c^k from the
                 // sums (v_c^k is already in the thread's registers), the
@@ -1597,10 +1685,11 @@ k_qn(QnArgs A) {
                         for (int a = 0; a < 3; ++a) st[u].u[a] = ul[u][a];
                     }
                     // the coefficients, held for this iteration's line search
-                    lc[u] = ls_coef_of(st[u], A.h);
-                    double d1, d2;
-                    ls_eval(lc[u], 0.0, &d1, &d2);
-                    curv[0] += d2;
+                    lc[u] = ls_coefc_of(st[u], lsu);
+                    double z[4] = {0.0, 0.0, 0.0, 0.0};
+                    ls_eval4(lc[u], lsu, 0.0, z);
+#pragma unroll
+                    for (int q = 0; q < 3; ++q) curv[q] += z[1 + q];
                 }
                 if (use_lds) {
                     // the contact past kLsPer T (uniform branch: only large sets):
@@ -1609,16 +1698,16 @@ k_qn(QnArgs A) {
                     const long long c = ec0 + tid + (long long)kLsPer * T;
                     const long long cc = c < ec1 ? c : clast;
                     double* vb = vblk + kLsPer * 6 * kQnThreads + tid;
-                    double uu[3], vo[3], uo[3], pr[5];
+                    double uu[3], vo[3], uo[3];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         uu[a] = ld_x(&U[a * kQnScatterMax + (cc - ec0)]);
                         vo[a] = vb[a * kQnThreads];
                         uo[a] = vb[(3 + a) * kQnThreads];
                     }
-#pragma unroll
-                    for (int j = 0; j < 5; ++j) pr[j] = A.ls_prm[j * kQnScatterMax + (cc - ec0)];
-                    LsCoef L = ls_coef_zero();
+                    const double mun0 = A.ls_prm[kQnScatterMax + (cc - ec0)];
+                    const double phi0 = A.ls_prm[2 * kQnScatterMax + (cc - ec0)];
+                    LsCoefC L = ls_coefc_of(ls_state_zero(), lsu);
                     if (c < ec1) {
                         double vc[3];
 #pragma unroll
@@ -1627,10 +1716,11 @@ k_qn(QnArgs A) {
                             vb[a * kQnThreads] = vc[a];
                             vb[(3 + a) * kQnThreads] = uu[a];
                         }
-                        L = ls_coef_pre(pr[0], pr[1], pr[2], pr[3], pr[4], A.h, vc, uu);
-                        double d1, d2;
-                        ls_eval(L, 0.0, &d1, &d2);
-                        curv[0] += d2;
+                        L = ls_coefc(lsu, mun0, phi0, vc, uu);
+                        double z[4] = {0.0, 0.0, 0.0, 0.0};
+                        ls_eval4(L, lsu, 0.0, z);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q) curv[q] += z[1 + q];
                     }
                     ls_ovf[tid] = L;
                 }
@@ -1707,7 +1797,7 @@ k_qn(QnArgs A) {
                 const double a = wave_sum(ga);
                 if (lane == 0) tot[wv] = a;
             }
-            block_allsum<1>(curv, rbuf, rpar);  // its workgroup barrier also publishes tot
+            block_allsum<3>(curv, rbuf, rpar);  // its workgroup barrier also publishes tot
             if (G > 1u) {
 #pragma unroll
                 for (int q = 0; q < kQnSums; ++q) sums[q] = tot[q];
@@ -1725,7 +1815,7 @@ k_qn(QnArgs A) {
             // all the evaluations, the next T in LDS, and any beyond are formed
             // from memory at each evaluation.
             auto coef_of = [&](long long c) -> LsCoef { return load_coef(A.c_coef, c); };
-            if (!scatter) {
+            if constexpr (!scatter) {
                 if (G > 1u && tid == 0) st_x(&partial2[rank], curv[0]);
                 ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
                 if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
@@ -1754,34 +1844,22 @@ k_qn(QnArgs A) {
                 __syncthreads();
                 curv0 = tot[0];
             }
-            const double alpha0 = Aq + curv0 > 0.0 ? -d0 / (Aq + curv0) : alpha_prev;
+            // (the third-order step where the one-barrier form summed phi''' and
+            // phi'''' at 0; the two-barrier form's contact pass leaves them zero,
+            // and its first step is Newton's)
+            const double alpha0 = Aq + curv0 > 0.0 ? ls_first_step(d0, Aq + curv0, curv[1], curv[2]) : alpha_prev;
             if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
             auto eval = [&](double alpha, double* d2out) -> double {
                 double acc2[2] = {0.0, 0.0};
 #pragma unroll
-                for (int u = 0; u < kLsPer; ++u) {
-                    double d1, d2;
-                    ls_eval(lc[u], alpha, &d1, &d2);
-                    acc2[0] += d1;
-                    acc2[1] += d2;
-                }
+                for (int u = 0; u < kLsPer; ++u) ls_eval2(lc[u], lsu, alpha, acc2);
                 if (dist) {
-                    double d1, d2;
-                    for (long long c = c0 + tid + (long long)kLsPer * T; c < c1; c += T) {
-                        ls_eval(coef_of(c), alpha, &d1, &d2);
-                        acc2[0] += d1;
-                        acc2[1] += d2;
-                    }
+                    for (long long c = c0 + tid + (long long)kLsPer * T; c < c1; c += T)
+                        ls_eval2(coef_of(c), lsu, alpha, acc2);
                 } else if (use_lds) {
-                    double d1, d2;
-                    ls_eval(ls_ovf[tid], alpha, &d1, &d2);
-                    acc2[0] += d1;
-                    acc2[1] += d2;
-                    for (long long c = c_lds + T; c < ec1; c += T) {
-                        ls_eval(coef_of(c), alpha, &d1, &d2);
-                        acc2[0] += d1;
-                        acc2[1] += d2;
-                    }
+                    // (the one-barrier form holds at most (kLsPer + 1) T contacts)
+                    ls_eval2(ls_ovf[tid], lsu, alpha, acc2);
+                    for (long long c = c_lds + T; c < ec1; c += T) ls_eval2(coef_of(c), lsu, alpha, acc2);
                 }
                 block_allsum<2>(acc2, rbuf, rpar);
                 if (dist) {

@@ -30,6 +30,16 @@ __device__ __forceinline__ double inv_sqrt(double x) {
     return y;
 }
 
+// 1/x for normal x > 0: the hardware estimate refined by two Newton steps
+// r <- r + r (1 - x r) (each step squares the relative error); a short
+// dependency chain where the IEEE-exact quotient is not needed.
+__device__ __forceinline__ double rcp_nr(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
+
 // The normal impulse is active while both factors (phi0 - h vn) and
 // (1 - d vn) are positive; the friction terms share one reciprocal square root.
 __device__ __forceinline__ void contact_model(const ContactParams& P, const double vc[3],
