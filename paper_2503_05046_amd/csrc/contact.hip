@@ -1075,10 +1075,10 @@ __device__ __forceinline__ bool group_sync(unsigned* bar, unsigned G, unsigned* 
 
 // Barrier of the iteration loop, for data exchanged through ld_x / st_x.
 // Arrivals are spread over kCtrLanes counters that only grow (a block adds to
-// counter rank mod kCtrLanes, each in its own cache line, so fewer blocks
-// contend for one); the i-th barrier after the start of the solve completes
-// when their sum reaches its value at the start plus i * G. Eight lanes of the
-// first wave poll the counters together. Each thread waits for its own stores
+// counter rank mod kCtrLanes, each in its own cache line, so groups of up to
+// kCtrLanes blocks never contend for one); the i-th barrier after the start of
+// the solve completes when their sum reaches its value at the start plus i *
+// G. The lanes of the first wave poll the counters together, one each. Each thread waits for its own stores
 // to be acknowledged before the block arrives. Same time limit as group_sync.
 __device__ __forceinline__ unsigned ctr_sum(unsigned* ctr) {
     const int lane = threadIdx.x & 63;

@@ -110,7 +110,7 @@ struct DevCounters {
 };
 
 constexpr int kBarStride = 16;     // unsigned words between the barrier counters of two environments
-constexpr int kCtrLanes = 8;       // loop-barrier arrival counters per environment (block rank mod 8)
+constexpr int kCtrLanes = 64;      // loop-barrier arrival counters per environment (block rank mod 64)
 constexpr int kCtrStride = 32;     // unsigned words between two of them (separate 128-byte lines)
 constexpr int kMaxRigidTape = 256;  // rigid bodies per handle (the tape keeps each host step's table)
 // adjoints per rigid body and recorded host step: V, t, w (through the
