@@ -105,6 +105,30 @@ def copy_calibration(n_bytes: int) -> int:
     return 0
 
 
+# Bandwidth of a plain device-to-device copy measured on this GPU at start-up
+# (read plus write bytes over event time, the best of several copies of 1
+# GiB): the rate a streaming kernel can reach here, beside the vendor peak.
+_COPY_PEAK_GBS = None
+
+
+def stream_copy_peak(n_bytes: int = 1 << 30, reps: int = 10) -> float:
+    import torch
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = 0.0
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        best = max(best, 2.0 * n_bytes / (a.elapsed_time(b) * 1e-3) / 1e9)
+    del src, dst
+    torch.cuda.empty_cache()
+    return best
+
+
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -149,8 +173,29 @@ def kernel_table(prof: dict, P: int) -> dict:
             gbs = algo_bytes[k] / (ms[k] * 1e-3) / 1e9
             e["algo_GBps"] = round(gbs, 1)
             e["frac_hbm_peak"] = round(gbs / HBM_PEAK_GBS, 4)
+            if _COPY_PEAK_GBS:
+                e["frac_copy_peak"] = round(gbs / _COPY_PEAK_GBS, 4)
         kernels[k] = e
     return kernels
+
+
+def substep_hbm(kernels: dict, prof: dict, P: int) -> dict:
+    """The whole substep: the algorithmic bytes of P2G, G2P, the sort and the
+    solve (the grid sweep's are not counted) over the event time of every
+    kernel class, as a fraction of HBM peak."""
+    launches = prof["launches"]
+    algo = (P2G_BYTES_PER_PARTICLE * P * launches["p2g"] + G2P_BYTES_PER_PARTICLE * P * launches["g2p"] +
+            SORT_BYTES_PER_PARTICLE * P * launches["sort"] +
+            SOLVE_BYTES_PER_CONTACT_ITER * prof["solver_contact_iters"] +
+            SOLVE_BYTES_PER_NODE_ITER * prof["solver_node_iters"] +
+            SOLVE_BYTES_PER_CONTACT_ROUND * prof["solver_contact_rounds"])
+    ms = sum(e["ms_total"] for e in kernels.values())
+    gbs = algo / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    out = {"algo_bytes": algo, "ms_total": round(ms, 3), "algo_GBps": round(gbs, 1),
+           "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 5)}
+    if _COPY_PEAK_GBS:
+        out["frac_copy_peak"] = round(gbs / _COPY_PEAK_GBS, 5)
+    return out
 
 
 def add_profiles(a: dict, b: dict) -> dict:
@@ -240,6 +285,7 @@ def run_plain(args) -> dict:
     for s in sims:
         s.close()
     kernels = kernel_table(prof, P)
+    whole = substep_hbm(kernels, prof, P)
     solver = solver_summary(stats, prof, phase_prof)
     dominant = max(kernels, key=lambda k: kernels[k]["ms_total"])
     dom = kernels[dominant]
@@ -260,7 +306,7 @@ def run_plain(args) -> dict:
                    f"past host step {RUN_HOST_STEPS - 1} the window continues on a fresh copy of "
                    f"the initial state"),
         "host_step_ms": [round(t, 1) for t in step_ms],
-        "roofline": roofline, "kernels": kernels, "solver": solver, "scene": scene,
+        "roofline": roofline, "kernels": kernels, "substep_hbm": whole, "solver": solver, "scene": scene,
     }
 
 
@@ -629,6 +675,9 @@ def main() -> int:
     forms = set(f.strip() for f in args.forms.split(",") if f.strip())
 
     out = {"metric": "particle-substeps/s (plain substep at contact residual 1e-6)"}
+    global _COPY_PEAK_GBS
+    _COPY_PEAK_GBS = stream_copy_peak()
+    log(f"device copy: {_COPY_PEAK_GBS:.0f} GB/s (read + write)")
     if "plain" in forms:
         r = run_plain(args)
         scene = r.pop("scene")
@@ -642,7 +691,8 @@ def main() -> int:
                                     f"host step"),
                        "particles": scene.P, "substeps_per_step": scene.N, "parallelism": "single GPU",
                        "window": r["window"]},
-            "roofline": r["roofline"], "kernels": r["kernels"], "solver": r["solver"],
+            "roofline": r["roofline"], "kernels": r["kernels"], "substep_hbm": r["substep_hbm"],
+            "solver": r["solver"],
             "host_step_ms": r["host_step_ms"],
         })
     extra = {}
@@ -660,6 +710,7 @@ def main() -> int:
         extra["sort_policies"] = run_sort_policies(args)
     if extra:
         out["forms"] = extra
+    out["stream_copy_GBps"] = round(_COPY_PEAK_GBS, 1)
     if "plain" in forms and not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(out), flush=True)
