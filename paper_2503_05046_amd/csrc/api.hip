@@ -253,6 +253,12 @@ void solver_options(const mpm_desc* desc, Work* w, int* slots_per_block, int* qn
     // MPM_TRANSFER_BLOCKS: blocks of the tiled P2G and G2P launches
     const char* tb = getenv("MPM_TRANSFER_BLOCKS");
     w->transfer_blocks = (tb && atoi(tb) > 0) ? atoi(tb) : kTransferBlocks;
+    // MPM_P2G_WALKS=1 or 2 fixes the tiled P2G's walks per (component, cell);
+    // otherwise they follow the particle density (p2g_adapt)
+    const char* pw = getenv("MPM_P2G_WALKS");
+    const int pwv = pw ? atoi(pw) : 0;
+    w->p2g_walks_fixed = (pwv == 1 || pwv == 2) ? 1 : 0;
+    w->p2g_walks = pwv == 2 ? 2 : 1;
     // MPM_SORT_POLICY=truncated or none selects an arm of the sort ablation
     const char* sp = getenv("MPM_SORT_POLICY");
     w->sort_policy = !sp ? kSortTiles
@@ -473,7 +479,7 @@ struct mpm_handle {
     hipEvent_t gevent = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
-    int graph_steps = 0, graph_qn_blocks = 0, graph_stride = 0, graph_nr = -1;
+    int graph_steps = 0, graph_qn_blocks = 0, graph_stride = 0, graph_nr = -1, graph_walks = 0;
 };
 
 namespace {
@@ -1019,6 +1025,7 @@ mpm_status mpm_step(mpm_handle* h, const mpm_rigid_state* in, mpm_rigid_impulse*
     HIP_TRY(hipMemcpyAsync(h->h_stats, W.sstats, sizeof(SubstepStats) * N * n_envs, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    p2g_adapt(W, h->h_cnt->n_ptiles);
     const mpm_desc& d = h->d;
     // host side of the split: advance kinematic bodies with their twist, and
     // integrate dynamic bodies from this step's impulses (device order k)
@@ -1057,7 +1064,8 @@ mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out
     int env_stride = 0;
     const int qn_blocks = plan_solver(h, &env_stride);
     if (h->graph_exec && (h->graph_steps != n_steps || h->graph_qn_blocks != qn_blocks ||
-                          h->graph_stride != env_stride || h->graph_nr != nr)) {
+                          h->graph_stride != env_stride || h->graph_nr != nr ||
+                          h->graph_walks != W.p2g_walks)) {
         HIP_TRY(hipGraphExecDestroy(h->graph_exec));
         HIP_TRY(hipGraphDestroy(h->graph));
         h->graph_exec = nullptr;
@@ -1095,6 +1103,7 @@ mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out
         h->graph_steps = n_steps;
         h->graph_qn_blocks = qn_blocks;
         h->graph_stride = env_stride;
+        h->graph_walks = W.p2g_walks;
         h->graph_nr = nr;
     }
     HIP_TRY(hipGraphLaunch(h->graph_exec, s));
@@ -1103,6 +1112,7 @@ mpm_status mpm_step_graph(mpm_handle* h, int32_t n_steps, mpm_rigid_impulse* out
     HIP_TRY(hipMemcpyAsync(h->h_racc, W.rigid_acc, sizeof(double) * 6 * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->h_rigids, W.rigids, sizeof(DevRigid) * std::max(nr, 1), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    p2g_adapt(W, h->h_cnt->n_ptiles);  // a change records the graph again at the next call
     // the host's rigid state takes the device's kinematic advance
     for (int k = 0; k < nr; ++k) {
         HostRigid& q = h->rigids[order[k]];

@@ -213,6 +213,8 @@ struct Work {
     int solver;              // MPM_SOLVER_QN or MPM_SOLVER_NEWTON
     int sort_policy;         // kSortTiles, kSortTruncated or kSortNone
     int transfer_blocks;     // blocks of the tiled P2G and G2P launches (each takes particle tiles in turn)
+    int p2g_walks;           // walks per (component, cell) of the tiled P2G: 1 or 2
+    int p2g_walks_fixed;     // nonzero: p2g_walks was set at creation and is not adapted
     double* nt_slot;         // exact-Newton variant: [cap_s][kNtSlot] per contact-node vectors
     double* nt_con;          // exact-Newton variant: [cap_c][kNtCon] per-contact terms
     double* qn_lspart;       // [2][kQnMaxBlocks][2] per-block line-search sums of the distributed line search
@@ -254,6 +256,7 @@ hipError_t launch_scan_blocks(unsigned* data, int n_items, unsigned* total, hipS
 hipError_t launch_tile_list(const Work& w, const unsigned* sorted_keys, hipStream_t s);
 hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old);
 hipError_t launch_p2g(const Work& w, const float* x, const float* v, hipStream_t s);
+void p2g_adapt(Work& w, unsigned n_ptiles);  // the tiled P2G's walks for the next host step
 hipError_t launch_grid_update(const Work& w, double h, hipStream_t s);
 hipError_t launch_registration(const Work& w, const float* x, const float* v, double h,
                                int substep, hipStream_t s);

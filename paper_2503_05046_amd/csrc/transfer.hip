@@ -409,7 +409,8 @@ __device__ __forceinline__ void p2g_cell_flush(float (&sum)[27], int cx, int cy,
     }
 }
 
-__global__ void __launch_bounds__(256)
+template <int kP2gSplit>  // walks per (component, cell): a block is 4 x kP2gSplit waves
+__global__ void __launch_bounds__(256 * kP2gSplit)
 k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ Q,
       long long P, const DevEnv* __restrict__ envs, int n_envs, const unsigned* __restrict__ ptile_id,
       const unsigned* __restrict__ ptile_beg, const unsigned* __restrict__ keys,
@@ -420,12 +421,16 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
     __shared__ unsigned cbeg[64], cend[64];
     __shared__ unsigned drift[kDriftMax];
     __shared__ unsigned n_drift;
-    __shared__ unsigned din[64][kDinCap];  // per cell: tile-relative particles that drifted into it
-    __shared__ unsigned din_cnt[64];
+    __shared__ unsigned din[kP2gSplit][64][kDinCap];  // per walk and cell: tile-relative particles that drifted into it
+    __shared__ unsigned din_cnt[kP2gSplit][64];
+    __shared__ float comb[kP2gSplit > 1 ? (kP2gSplit - 1) * 4 : 1][kP2gSplit > 1 ? 27 : 1][64];  // the later walks' sums
     if (cnt->abort_step) return;
     const unsigned n_tiles = cnt->n_ptiles;
-    // the component is uniform over a wave: scalar branches below
-    const int q = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), cell = threadIdx.x & 63;
+    // the component and the walk are uniform over a wave: scalar branches below.
+    // Walk `part` of a (component, cell) takes every kP2gSplit-th of the cell's
+    // particles; the walks' sums are added in walk order before the flush.
+    const int q = __builtin_amdgcn_readfirstlane((int)((threadIdx.x >> 6) & 3u)), cell = threadIdx.x & 63;
+    const int part = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 8));
     const int cx = cell & 3, cy = (cell >> 2) & 3, cz = cell >> 4;
     bool clamped = false;
     for (unsigned t = blockIdx.x; t < n_tiles; t += gridDim.x) {
@@ -435,7 +440,8 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
         if (threadIdx.x < 64) {
             cbeg[threadIdx.x] = 0u;
             cend[threadIdx.x] = 0u;
-            din_cnt[threadIdx.x] = 0u;
+#pragma unroll
+            for (int h = 0; h < kP2gSplit; ++h) din_cnt[h][threadIdx.x] = 0u;
         }
         if (threadIdx.x == 0) n_drift = 0u;
         __syncthreads();
@@ -458,7 +464,7 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
 #pragma unroll
         for (int o = 0; o < 27; ++o) sum[o] = 0.f;
         // 2. the walk over the cell's particles, the next one's loads issued first
-        const unsigned k0 = cbeg[cell], k1 = cend[cell];
+        const unsigned k0 = cbeg[cell] + (unsigned)part, k1 = cend[cell];
         float nx0 = 0.f, nx1 = 0.f, nx2 = 0.f, nv = 0.f, nq0 = 0.f, nq1 = 0.f, nq2 = 0.f;
         if (k0 < k1) {
             const long long p = pb + k0;
@@ -509,11 +515,11 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                 p2g_scatter_one(E, x, v, Q, P, pb + kk, qq, ox, oy, oz, sm, acc, tile_flag, active, cnt, &clamped);
             }
         };
-        for (unsigned kk = k0; kk < k1; ++kk) {
+        for (unsigned kk = k0; kk < k1; kk += kP2gSplit) {
             const float xp[3] = {nx0, nx1, nx2};
             const float vq = nv, q0 = nq0, q1 = nq1, q2 = nq2;
-            if (kk + 1 < k1) {
-                const long long pn = pb + kk + 1;
+            if (kk + kP2gSplit < k1) {
+                const long long pn = pb + kk + kP2gSplit;
                 nx0 = x[pn]; nx1 = x[P + pn]; nx2 = x[2 * P + pn];
                 if (q > 0) {
                     nv = v[(q - 1) * P + pn];
@@ -532,9 +538,9 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                 if (rx >= 0 && rx < kTile && ry >= 0 && ry < kTile && rz >= 0 && rz < kTile) {
                     if (q == 0) {
                         const int to = (rz * kTile + ry) * kTile + rx;
-                        const unsigned slot = atomicAdd(&din_cnt[to], 1u);
+                        const unsigned slot = atomicAdd(&din_cnt[part][to], 1u);
                         if (slot < (unsigned)kDinCap) {
-                            din[to][slot] = kk;
+                            din[part][to][slot] = kk;
                         } else {
                             for (int qq = 0; qq < 4; ++qq) queue_drift(kk, qq);
                         }
@@ -548,9 +554,9 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
         }
         __syncthreads();
         // 2b. the particles that drifted into this cell from another of the tile
-        const unsigned n_in = min(din_cnt[cell], (unsigned)kDinCap);
+        const unsigned n_in = min(din_cnt[part][cell], (unsigned)kDinCap);
         for (unsigned i = 0; i < n_in; ++i) {
-            const long long p = pb + din[cell][i];
+            const long long p = pb + din[part][cell][i];
             const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
             float vq = 0.f, q0 = 0.f, q1 = 0.f, q2 = 0.f;
             if (q > 0) {
@@ -564,8 +570,22 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
             stencil_base(E, xp, b, f, &clamped);
             accumulate(xp, f, vq, q0, q1, q2);
         }
-        // 3. the cells' sums into the LDS block (the whole wave, empty cells too)
-        p2g_cell_flush(sum, cx, cy, cz, sm[q], stage[q]);
+        // 3. the later walks' sums added to the first's in walk order, then the
+        // cells' sums into the LDS block (the first walk's whole wave, empty
+        // cells too)
+        if constexpr (kP2gSplit > 1) {
+            if (part > 0) {
+#pragma unroll
+                for (int o = 0; o < 27; ++o) comb[(part - 1) * 4 + q][o][cell] = sum[o];
+            }
+            __syncthreads();
+            if (part == 0) {
+                for (int h = 1; h < kP2gSplit; ++h)
+#pragma unroll
+                    for (int o = 0; o < 27; ++o) sum[o] += comb[(h - 1) * 4 + q][o][cell];
+            }
+        }
+        if (part == 0) p2g_cell_flush(sum, cx, cy, cz, sm[q], stage[q]);
         __syncthreads();
         // 4. the queued drifted particles, one (particle, component) per thread
         const unsigned nd = min(n_drift, (unsigned)kDriftMax);
@@ -586,10 +606,27 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
 
 hipError_t launch_p2g(const Work& w, const float* x, const float* v, hipStream_t s) {
     const unsigned blocks = (unsigned)std::max<long long>(1, std::min<long long>(w.n_tiles, w.transfer_blocks));
-    hipLaunchKernelGGL(k_p2g, dim3(blocks), dim3(256), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs,
-                       w.ptile_id, w.ptile_beg, w.keys_sorted, w.blkbuf, w.acc, w.tile_flag,
-                       w.active_tiles, w.cnt);
+    if (w.p2g_walks == 2)
+        hipLaunchKernelGGL(k_p2g<2>, dim3(blocks), dim3(512), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs,
+                           w.ptile_id, w.ptile_beg, w.keys_sorted, w.blkbuf, w.acc, w.tile_flag,
+                           w.active_tiles, w.cnt);
+    else
+        hipLaunchKernelGGL(k_p2g<1>, dim3(blocks), dim3(256), 0, s, x, v, w.Q, w.P, w.envs, w.n_envs,
+                           w.ptile_id, w.ptile_beg, w.keys_sorted, w.blkbuf, w.acc, w.tile_flag,
+                           w.active_tiles, w.cnt);
     return hipGetLastError();
+}
+
+// The tiled P2G's walks per (component, cell) for the next host step, from
+// the particles per non-empty tile of the last sort: one walk per (component,
+// cell) up to 16 particles per cell on average, two beyond (each walk then
+// takes every other particle of the cell, and the block has twice the waves).
+// Measured on the granular pour: at about 7 particles per cell one walk is
+// faster (79 against 94 us at 1M particles), at about 28 two are (378
+// against 661 us at 4M).
+void p2g_adapt(Work& w, unsigned n_ptiles) {
+    if (w.p2g_walks_fixed || n_ptiles == 0u) return;
+    w.p2g_walks = (double)w.P > 16.0 * 64.0 * (double)n_ptiles ? 2 : 1;
 }
 
 // ---------------------------------------------------------------------------

@@ -100,15 +100,18 @@ def test_one_substep_random_state(mpm, oracle, material):
     assert impulse_error(ig, io, m_tot, s.h) < 1e-4
 
 
+@pytest.mark.parametrize("walks", ["1", "2"])
 @pytest.mark.parametrize("material", [I.FIXED_COROTATED, I.DRUCKER_PRAGER])
-def test_dense_tiles_free_motion(mpm, oracle, material):
-    """About 40 particles per cell (P2G walks such dense tiles from LDS,
-    staged a chunk at a time): two free-motion substeps of a random state
+def test_dense_tiles_free_motion(mpm, oracle, material, walks, monkeypatch):
+    """About 40 particles per cell (long P2G walks; with two walks per
+    component and cell, each takes every other particle and their sums are
+    added before the flush): two free-motion substeps of a random state
     against the oracle."""
+    monkeypatch.setenv("MPM_P2G_WALKS", walks)
     s = I.tiny_random(P=20000, seed=17, n=32, material=material, with_box=False)
     s.rigids = []
     s.N = 2
-    _log(f"dense tiles, material {material}")
+    _log(f"dense tiles, material {material}, {walks} P2G walks")
     g, o, ig, io, sg, so = _run_both(mpm, oracle, s)
     assert sg[0]["max_contacts"] == 0
     e = field_errors(g, o, s.envs[0].dx)
