@@ -291,6 +291,7 @@ hipError_t launch_tile_maps(const Work& w, hipStream_t s, bool clear_old) {
 // 189 against 162 us at 1M particles, and 1005 against 574 us at 4M.)
 constexpr int kDriftMax = 1024;  // queued (particle, component) entries per tile
 constexpr int kDinCap = 16;      // particles that drifted into a cell of the tile, listed per cell
+constexpr int kPreCap = 1024;    // particles of a tile whose stencil base P2G forms once, in its first pass
 
 // Component q of one particle's contribution to the 27 nodes of its stencil
 // (m_p, or m_p v_q + Q_q . (x_i - x_p)), added to the LDS block when the stencil
@@ -410,7 +411,7 @@ __device__ __forceinline__ void p2g_cell_flush(float (&sum)[27], int cx, int cy,
 }
 
 template <int kP2gSplit>  // walks per (component, cell): a block is 4 x kP2gSplit waves
-__global__ void __launch_bounds__(256 * kP2gSplit)
+__global__ void __launch_bounds__(256 * kP2gSplit, 4)
 k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __restrict__ Q,
       long long P, const DevEnv* __restrict__ envs, int n_envs, const unsigned* __restrict__ ptile_id,
       const unsigned* __restrict__ ptile_beg, const unsigned* __restrict__ keys,
@@ -424,6 +425,9 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
     __shared__ unsigned din[kP2gSplit][64][kDinCap];  // per walk and cell: tile-relative particles that drifted into it
     __shared__ unsigned din_cnt[kP2gSplit][64];
     __shared__ float comb[kP2gSplit > 1 ? (kP2gSplit - 1) * 4 : 1][kP2gSplit > 1 ? 27 : 1][64];  // the later walks' sums
+    // the first kPreCap particles of the tile: the offset f of their stencil
+    // base and that base as a cell of the tile (64: outside the tile)
+    __shared__ float4 pinfo[kPreCap];
     if (cnt->abort_step) return;
     const unsigned n_tiles = cnt->n_ptiles;
     // the component and the walk are uniform over a wave: scalar branches below.
@@ -447,18 +451,32 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
         __syncthreads();
         const unsigned gt = ptile_id[t];
         const long long pb = ptile_beg[t], pe = ptile_beg[t + 1];
-        // 1. cell ranges: the bounds of every run of equal keys
+        const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
+        int tx, ty, tz;
+        tile_coords(E, gt, &tx, &ty, &tz);
+        // a stencil base as a cell of this tile, 64 when it lies outside
+        auto tile_cell = [&](const int b[3]) -> int {
+            const int rx = b[0] - tx * kTile, ry = b[1] - ty * kTile, rz = b[2] - tz * kTile;
+            return (rx >= 0 && rx < kTile && ry >= 0 && ry < kTile && rz >= 0 && rz < kTile)
+                       ? (rz * kTile + ry) * kTile + rx : 64;
+        };
+        // 1. cell ranges: the bounds of every run of equal keys; and each of
+        // the first kPreCap particles' stencil base, formed once for the four
+        // components
         for (long long p = pb + threadIdx.x; p < pe; p += blockDim.x) {
             const unsigned k = keys[p];
             if (p == pb || keys[p - 1] != k) cbeg[k & 63u] = (unsigned)(p - pb);
             if (p == pe - 1 || keys[p + 1] != k) cend[k & 63u] = (unsigned)(p - pb + 1);
+            if (p - pb < kPreCap) {
+                const float xp[3] = {x[p], x[P + p], x[2 * P + p]};
+                int b[3];
+                float f[3];
+                stencil_base(E, xp, b, f, &clamped);
+                pinfo[p - pb] = make_float4(f[0], f[1], f[2], __int_as_float(tile_cell(b)));
+            }
         }
         __syncthreads();
-        const DevEnv& E = envs[env_of_tile(envs, n_envs, (int)gt)];
-        int tx, ty, tz;
-        tile_coords(E, gt, &tx, &ty, &tz);
         const int ox = tx * kTile - 1, oy = ty * kTile - 1, oz = tz * kTile - 1;
-        const int nbx = tx * kTile + cx, nby = ty * kTile + cy, nbz = tz * kTile + cz;  // this cell's base
         const float dx = E.dx, mp = E.m_p;
         float sum[27];
 #pragma unroll
@@ -468,7 +486,7 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
         float nx0 = 0.f, nx1 = 0.f, nx2 = 0.f, nv = 0.f, nq0 = 0.f, nq1 = 0.f, nq2 = 0.f;
         if (k0 < k1) {
             const long long p = pb + k0;
-            nx0 = x[p]; nx1 = x[P + p]; nx2 = x[2 * P + p];
+            if (k0 >= (unsigned)kPreCap) { nx0 = x[p]; nx1 = x[P + p]; nx2 = x[2 * P + p]; }
             if (q > 0) {
                 nv = v[(q - 1) * P + p];
                 nq0 = Q[(3 * (q - 1) + 0) * P + p];
@@ -520,7 +538,7 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
             const float vq = nv, q0 = nq0, q1 = nq1, q2 = nq2;
             if (kk + kP2gSplit < k1) {
                 const long long pn = pb + kk + kP2gSplit;
-                nx0 = x[pn]; nx1 = x[P + pn]; nx2 = x[2 * P + pn];
+                if (kk + kP2gSplit >= (unsigned)kPreCap) { nx0 = x[pn]; nx1 = x[P + pn]; nx2 = x[2 * P + pn]; }
                 if (q > 0) {
                     nv = v[(q - 1) * P + pn];
                     nq0 = Q[(3 * (q - 1) + 0) * P + pn];
@@ -528,16 +546,22 @@ k_p2g(const float* __restrict__ x, const float* __restrict__ v, const float* __r
                     nq2 = Q[(3 * (q - 1) + 2) * P + pn];
                 }
             }
-            int b[3];
             float f[3];
-            stencil_base(E, xp, b, f, &clamped);
-            if (b[0] != nbx || b[1] != nby || b[2] != nbz) {
+            int to;
+            if (kk < (unsigned)kPreCap) {
+                const float4 in = pinfo[kk];
+                f[0] = in.x; f[1] = in.y; f[2] = in.z;
+                to = __float_as_int(in.w);
+            } else {
+                int b[3];
+                stencil_base(E, xp, b, f, &clamped);
+                to = tile_cell(b);
+            }
+            if (to != cell) {
                 // drifted since the sort: into another cell of the tile, listed
                 // there (by the mass wave, for all four components), else queued
-                const int rx = b[0] - (nbx - cx), ry = b[1] - (nby - cy), rz = b[2] - (nbz - cz);
-                if (rx >= 0 && rx < kTile && ry >= 0 && ry < kTile && rz >= 0 && rz < kTile) {
+                if (to < 64) {
                     if (q == 0) {
-                        const int to = (rz * kTile + ry) * kTile + rx;
                         const unsigned slot = atomicAdd(&din_cnt[part][to], 1u);
                         if (slot < (unsigned)kDinCap) {
                             din[part][to][slot] = kk;
