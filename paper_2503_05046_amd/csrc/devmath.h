@@ -184,6 +184,24 @@ struct Material {
 };
 
 // Kirchhoff stress tau = P F^T from an SVD of F.
+// Hencky stress tau = U (2 mu eps + la tr(eps) I) U^T from the left singular
+// vectors U and the Hencky strain eps = ln s.
+__device__ __forceinline__ void hencky_tau(const Material& m, const float U[9], float e0, float e1, float e2,
+                                           float tau[9]) {
+    float tr = e0 + e1 + e2;
+    float d0 = 2.0f * m.mu * e0 + m.la * tr, d1 = 2.0f * m.mu * e1 + m.la * tr,
+          d2 = 2.0f * m.mu * e2 + m.la * tr;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = r; c < 3; ++c) {
+            float v = U[r * 3 + 0] * d0 * U[c * 3 + 0] + U[r * 3 + 1] * d1 * U[c * 3 + 1] +
+                      U[r * 3 + 2] * d2 * U[c * 3 + 2];
+            tau[r * 3 + c] = v;
+            tau[c * 3 + r] = v;
+        }
+}
+
 __device__ __forceinline__ void kirchhoff_from_svd(const Material& m, const float F[9],
                                                    const float U[9], const float s[3],
                                                    const float V[9], float tau[9]) {
@@ -212,28 +230,17 @@ __device__ __forceinline__ void kirchhoff_from_svd(const Material& m, const floa
         tau[4] += vol;
         tau[8] += vol;
     } else {
-        // Hencky: tau = U (2 mu eps + la tr(eps) I) U^T, eps = ln s
-        float e0 = logf(fmaxf(s[0], 1e-6f)), e1 = logf(fmaxf(s[1], 1e-6f)),
-              e2 = logf(fmaxf(s[2], 1e-6f));
-        float tr = e0 + e1 + e2;
-        float d0 = 2.0f * m.mu * e0 + m.la * tr, d1 = 2.0f * m.mu * e1 + m.la * tr,
-              d2 = 2.0f * m.mu * e2 + m.la * tr;
-#pragma unroll
-        for (int r = 0; r < 3; ++r)
-#pragma unroll
-            for (int c = r; c < 3; ++c) {
-                float v = U[r * 3 + 0] * d0 * U[c * 3 + 0] + U[r * 3 + 1] * d1 * U[c * 3 + 1] +
-                          U[r * 3 + 2] * d2 * U[c * 3 + 2];
-                tau[r * 3 + c] = v;
-                tau[c * 3 + r] = v;
-            }
+        // Hencky: eps = ln s
+        hencky_tau(m, U, logf(fmaxf(s[0], 1e-6f)), logf(fmaxf(s[1], 1e-6f)), logf(fmaxf(s[2], 1e-6f)), tau);
     }
 }
 
 // Drucker-Prager return map in Hencky strain (zero cohesion, no hardening),
-// applied to the singular values; F is rebuilt as U exp(eps) V^T.
+// applied to the singular values; F is rebuilt as U exp(eps) V^T, and the
+// projected eps is returned (the Hencky stress's strain, without taking the
+// logarithm of exp(eps) again).
 __device__ __forceinline__ void dp_return_map(const Material& m, float U[9], float s[3],
-                                              const float V[9], float F[9]) {
+                                              const float V[9], float F[9], float eps[3]) {
     float e[3] = {logf(fmaxf(s[0], 1e-6f)), logf(fmaxf(s[1], 1e-6f)), logf(fmaxf(s[2], 1e-6f))};
     float tr = e[0] + e[1] + e[2];
     if (tr >= 0.0f) {
@@ -252,6 +259,9 @@ __device__ __forceinline__ void dp_return_map(const Material& m, float U[9], flo
     s[0] = expf(e[0]);
     s[1] = expf(e[1]);
     s[2] = expf(e[2]);
+    eps[0] = e[0];
+    eps[1] = e[1];
+    eps[2] = e[2];
 #pragma unroll
     for (int r = 0; r < 3; ++r)
 #pragma unroll

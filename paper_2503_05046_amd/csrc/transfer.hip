@@ -845,8 +845,13 @@ __device__ __forceinline__ void g2p_particle(const DevEnv& E, Idx P, Idx p, cons
                                                   Cp[r * 3 + 2] * Fp[2 * 3 + c]);
     float U[9], s[3], V[9], tau[9];
     svd3(Fn, U, s, V);
-    if (E.mat.type == 1) dp_return_map(E.mat, U, s, V, Fn);
-    kirchhoff_from_svd(E.mat, Fn, U, s, V, tau);
+    if (E.mat.type == 1) {
+        float eps[3];
+        dp_return_map(E.mat, U, s, V, Fn, eps);
+        hencky_tau(E.mat, U, eps[0], eps[1], eps[2], tau);
+    } else {
+        kirchhoff_from_svd(E.mat, Fn, U, s, V, tau);
+    }
     const float cq = hf * E.V0 * D;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
