@@ -173,7 +173,7 @@ size_t layout(const Sizes& z, char* base, Work* w) {
     w->blk = L.take<unsigned>(256 * kSortBlocks + 2 * kSortBlocks);
     w->partial = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
     w->partial_odd = L.take<double>((size_t)kMaxQnBlocks * kQnSums);
-    w->partial2 = L.take<double>(kMaxQnBlocks);
+    w->partial2 = L.take<double>(3 * kMaxQnBlocks);
     w->qn_lspart = L.take<double>((size_t)4 * kMaxQnBlocks);
     w->rigid_acc = L.take<double>(6 * kMaxRigidTotal);
     w->sstats = L.take<SubstepStats>((size_t)z.N * z.n_envs);

@@ -265,6 +265,22 @@ __device__ __forceinline__ void ls_eval(const LsCoef& L, double alpha, double* d
     *d2 = e2;
 }
 
+// phi''' and phi'''' of a contact's terms at alpha from its full coefficients
+// (the derivatives as in ls_eval4 below), added to d[0..1].
+__device__ __forceinline__ void ls_eval34(const LsCoef& L, double alpha, double (&d)[2]) {
+    const double pa = fma(alpha, L.q2, L.p0);
+    const double s2 = fma(alpha, pa + L.p0, L.q0);
+    const double is = inv_sqrt(s2);
+    const double pis = pa * is;
+    const double f2 = L.mun0 * is * fma(-pis, pis, L.q2);
+    double e3 = -3.0 * f2 * (pis * is);
+    const double e4 = -3.0 * f2 * (is * is) * fma(-5.0 * pis, pis, L.q2);
+    const double a = fma(-alpha, L.a1, L.a0), b = fma(-alpha, L.b1, L.b0);
+    if (a > 0.0 && b > 0.0) e3 -= fma(L.eh, L.b1, L.ed * L.a1);
+    d[0] += e3;
+    d[1] += e4;
+}
+
 // phi' and phi'' of one contact's terms added to d[0..1], from either form of
 // the coefficients (the full form gives ls_eval's values).
 __device__ __forceinline__ void ls_eval2(const LsCoef& L, const LsUni&, double alpha, double (&d)[2]) {
@@ -635,7 +651,7 @@ struct QnArgs {
     SlotRec* s_rec;
     double* partial;        // per block: the node pass's sums
     double* partial_odd;    // the same for odd iterations of the one-barrier form
-    double* partial2;       // per block: the contact pass's share of phi''(0)
+    double* partial2;       // [3][kQnMaxBlocks] per block: the contact pass's shares of phi''(0) - A, phi''', phi''''
     double* rigid_acc;
     int n_rigid;
     SubstepStats* stats;
@@ -1786,10 +1802,15 @@ k_qn(QnArgs A) {
                         u[2] = fr[6] * sacc[0] + fr[7] * sacc[1] + fr[8] * sacc[2];
 #pragma unroll
                         for (int a = 0; a < 3; ++a) st_x(&D.uc[k & 1][a], u[a]);
-                        store_coef(A.c_coef, c, ls_coef(Pc, vc, u));
+                        const LsCoef Lc = ls_coef(Pc, vc, u);
+                        store_coef(A.c_coef, c, Lc);
                         double g[3], g00, g01, g11, gnn;
                         contact_model(Pc, vc, g, &g00, &g01, &g11, &gnn);
                         curv[0] += g00 * u[0] * u[0] + 2.0 * g01 * u[0] * u[1] + g11 * u[1] * u[1] + gnn * u[2] * u[2];
+                        double z[2] = {0.0, 0.0};
+                        ls_eval34(Lc, 0.0, z);
+                        curv[1] += z[0];
+                        curv[2] += z[1];
                     }
                 }
             }
@@ -1816,7 +1837,10 @@ k_qn(QnArgs A) {
             // from memory at each evaluation.
             auto coef_of = [&](long long c) -> LsCoef { return load_coef(A.c_coef, c); };
             if constexpr (!scatter) {
-                if (G > 1u && tid == 0) st_x(&partial2[rank], curv[0]);
+                if (G > 1u && tid == 0) {
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) st_x(&partial2[j * kQnMaxBlocks + rank], curv[j]);
+                }
                 ok = loop_sync(ctr, rank, G, &ltarget, &s_ok, cnt);
                 if (timer) { const unsigned long long t = wall_clock64(); tph[4] += t - tmark; tmark = t; }
                 if (!ok) break;
@@ -1830,24 +1854,25 @@ k_qn(QnArgs A) {
                 }
                 if (use_lds && !dist) ls_ovf[tid] = c_lds < ec1 ? coef_of(c_lds) : ls_coef_zero();
             }
-            // phi''(0) - A summed over the group (wave 0; the one-barrier form
-            // summed every contact in the block already), then the first trial
-            // step: the Newton step of phi' from alpha = 0
-            double curv0 = curv[0];
+            // phi''(0) - A, phi''' and phi'''' at 0 summed over the group (waves 0
+            // to 2, in block order; the one-barrier form summed every contact in
+            // the block already), then the first trial step: the third-order
+            // step of phi' from alpha = 0
+            double curv0 = curv[0], curv1 = curv[1], curv2 = curv[2];
             if (G > 1u && !scatter) {
-                if (tid < 64) {
+                const int wv = tid >> 6, lane = tid & 63;
+                if (wv < 3) {
                     double a = 0.0;
-                    for (unsigned b = tid; b < G; b += 64) a += ld_x(&partial2[b]);
+                    for (unsigned b = lane; b < G; b += 64) a += ld_x(&partial2[wv * kQnMaxBlocks + b]);
                     a = wave_sum(a);
-                    if (tid == 0) tot[0] = a;
+                    if (lane == 0) tot[wv] = a;
                 }
                 __syncthreads();
                 curv0 = tot[0];
+                curv1 = tot[1];
+                curv2 = tot[2];
             }
-            // (the third-order step where the one-barrier form summed phi''' and
-            // phi'''' at 0; the two-barrier form's contact pass leaves them zero,
-            // and its first step is Newton's)
-            const double alpha0 = Aq + curv0 > 0.0 ? ls_first_step(d0, Aq + curv0, curv[1], curv[2]) : alpha_prev;
+            const double alpha0 = Aq + curv0 > 0.0 ? ls_first_step(d0, Aq + curv0, curv1, curv2) : alpha_prev;
             if (timer) { const unsigned long long t = wall_clock64(); tph[5] += t - tmark; tmark = t; }
             auto eval = [&](double alpha, double* d2out) -> double {
                 double acc2[2] = {0.0, 0.0};

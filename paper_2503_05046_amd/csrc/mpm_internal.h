@@ -165,7 +165,7 @@ struct Work {
     unsigned* blk;           // [kSortBlocks * 256 + 2 * kSortBlocks] histograms / block sums
     double* partial;         // [solver blocks][kQnSums]
     double* partial_odd;     // [solver blocks][kQnSums] odd iterations of the one-barrier form
-    double* partial2;        // [solver blocks]
+    double* partial2;        // [3][solver blocks]
     double* rigid_acc;       // [n_rigid][6] FP64 impulse accumulators
     SubstepStats* sstats;    // [N][n_envs]
     // per-environment contact solve
