@@ -238,13 +238,16 @@ __device__ __forceinline__ void kirchhoff_from_svd(const Material& m, const floa
 // Drucker-Prager return map in Hencky strain (zero cohesion, no hardening),
 // applied to the singular values; F is rebuilt as U exp(eps) V^T, and the
 // projected eps is returned (the Hencky stress's strain, without taking the
-// logarithm of exp(eps) again).
-__device__ __forceinline__ void dp_return_map(const Material& m, float U[9], float s[3],
+// logarithm of exp(eps) again). Returns true in tension, where eps = 0 and
+// s = 1 exactly (no exponentials to take).
+__device__ __forceinline__ bool dp_return_map(const Material& m, float U[9], float s[3],
                                               const float V[9], float F[9], float eps[3]) {
     float e[3] = {logf(fmaxf(s[0], 1e-6f)), logf(fmaxf(s[1], 1e-6f)), logf(fmaxf(s[2], 1e-6f))};
     float tr = e[0] + e[1] + e[2];
-    if (tr >= 0.0f) {
+    const bool tension = tr >= 0.0f;
+    if (tension) {
         e[0] = e[1] = e[2] = 0.0f;  // tension: cone tip
+        s[0] = s[1] = s[2] = 1.0f;
     } else {
         float dv[3] = {e[0] - tr / 3.0f, e[1] - tr / 3.0f, e[2] - tr / 3.0f};
         float nd = sqrtf(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
@@ -255,10 +258,10 @@ __device__ __forceinline__ void dp_return_map(const Material& m, float U[9], flo
             e[1] -= r * dv[1];
             e[2] -= r * dv[2];
         }
+        s[0] = expf(e[0]);
+        s[1] = expf(e[1]);
+        s[2] = expf(e[2]);
     }
-    s[0] = expf(e[0]);
-    s[1] = expf(e[1]);
-    s[2] = expf(e[2]);
     eps[0] = e[0];
     eps[1] = e[1];
     eps[2] = e[2];
@@ -268,6 +271,7 @@ __device__ __forceinline__ void dp_return_map(const Material& m, float U[9], flo
         for (int c = 0; c < 3; ++c)
             F[r * 3 + c] = U[r * 3 + 0] * s[0] * V[c * 3 + 0] + U[r * 3 + 1] * s[1] * V[c * 3 + 1] +
                            U[r * 3 + 2] * s[2] * V[c * 3 + 2];
+    return tension;
 }
 
 }  // namespace mpm

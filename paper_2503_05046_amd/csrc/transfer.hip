@@ -847,8 +847,12 @@ __device__ __forceinline__ void g2p_particle(const DevEnv& E, Idx P, Idx p, cons
     svd3(Fn, U, s, V);
     if (E.mat.type == 1) {
         float eps[3];
-        dp_return_map(E.mat, U, s, V, Fn, eps);
-        hencky_tau(E.mat, U, eps[0], eps[1], eps[2], tau);
+        if (dp_return_map(E.mat, U, s, V, Fn, eps)) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) tau[k] = 0.0f;  // tension: eps = 0, no stress
+        } else {
+            hencky_tau(E.mat, U, eps[0], eps[1], eps[2], tau);
+        }
     } else {
         kirchhoff_from_svd(E.mat, Fn, U, s, V, tau);
     }
