@@ -184,6 +184,35 @@ struct Material {
 };
 
 // Kirchhoff stress tau = P F^T from an SVD of F.
+// The rotation of F near a rotation (polar decomposition F = R S), by three
+// steps of Newton's iteration R <- (R + R^-T) / 2 (R^-T = cofactor(R) / det R),
+// which converges quadratically from F; returns false, leaving R unspecified,
+// when R^T R is not the identity within 1e-5 after them (F far from a
+// rotation: the caller takes the SVD instead).
+__device__ __forceinline__ bool polar_rotation_near(const float F[9], float R[9]) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) R[k] = F[k];
+#pragma unroll
+    for (int it = 0; it < 3; ++it) {
+        const float c[9] = {R[4] * R[8] - R[5] * R[7], R[5] * R[6] - R[3] * R[8], R[3] * R[7] - R[4] * R[6],
+                            R[2] * R[7] - R[1] * R[8], R[0] * R[8] - R[2] * R[6], R[1] * R[6] - R[0] * R[7],
+                            R[1] * R[5] - R[2] * R[4], R[2] * R[3] - R[0] * R[5], R[0] * R[4] - R[1] * R[3]};
+        const float d = R[0] * c[0] + R[1] * c[1] + R[2] * c[2];
+        const float h = 0.5f / d;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) R[k] = fmaf(c[k], h, 0.5f * R[k]);
+    }
+    float err = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = a; b < 3; ++b) {
+            const float g = R[a] * R[b] + R[3 + a] * R[3 + b] + R[6 + a] * R[6 + b] - (a == b ? 1.0f : 0.0f);
+            err = fmaxf(err, fabsf(g));
+        }
+    return err < 1e-5f;  // false for a NaN too
+}
+
 // Hencky stress tau = U (2 mu eps + la tr(eps) I) U^T from the left singular
 // vectors U and the Hencky strain eps = ln s.
 __device__ __forceinline__ void hencky_tau(const Material& m, const float U[9], float e0, float e1, float e2,

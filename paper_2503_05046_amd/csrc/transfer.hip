@@ -844,17 +844,38 @@ __device__ __forceinline__ void g2p_particle(const DevEnv& E, Idx P, Idx p, cons
                                                   Cp[r * 3 + 1] * Fp[1 * 3 + c] +
                                                   Cp[r * 3 + 2] * Fp[2 * 3 + c]);
     float U[9], s[3], V[9], tau[9];
-    svd3(Fn, U, s, V);
+    // Drucker-Prager sand in tension (J = det F >= 1: the Hencky strain's trace
+    // is not negative) returns to the cone tip: zero strain, F its rotation,
+    // no stress. After such a substep F is a rotation up to h C, so the
+    // rotation comes from a few Newton steps of the polar decomposition; F
+    // farther from a rotation, and compression, take the SVD.
+    bool done = false;
     if (E.mat.type == 1) {
-        float eps[3];
-        if (dp_return_map(E.mat, U, s, V, Fn, eps)) {
+        const float J = Fn[0] * (Fn[4] * Fn[8] - Fn[5] * Fn[7]) - Fn[1] * (Fn[3] * Fn[8] - Fn[5] * Fn[6]) +
+                        Fn[2] * (Fn[3] * Fn[7] - Fn[4] * Fn[6]);
+        float R[9];
+        if (J >= 1.0f && polar_rotation_near(Fn, R)) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) tau[k] = 0.0f;  // tension: eps = 0, no stress
-        } else {
-            hencky_tau(E.mat, U, eps[0], eps[1], eps[2], tau);
+            for (int k = 0; k < 9; ++k) {
+                Fn[k] = R[k];
+                tau[k] = 0.0f;
+            }
+            done = true;
         }
-    } else {
-        kirchhoff_from_svd(E.mat, Fn, U, s, V, tau);
+    }
+    if (!done) {
+        svd3(Fn, U, s, V);
+        if (E.mat.type == 1) {
+            float eps[3];
+            if (dp_return_map(E.mat, U, s, V, Fn, eps)) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) tau[k] = 0.0f;  // tension: eps = 0, no stress
+            } else {
+                hencky_tau(E.mat, U, eps[0], eps[1], eps[2], tau);
+            }
+        } else {
+            kirchhoff_from_svd(E.mat, Fn, U, s, V, tau);
+        }
     }
     const float cq = hf * E.V0 * D;
 #pragma unroll
